@@ -1,0 +1,109 @@
+"""Pins for the oracle's reduced-precision emulation of the in-scattering sum."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import asn_oracle as o
+
+
+def _floats(seed, n=20000):
+    rng = np.random.default_rng(seed)
+    x = (rng.standard_normal(n) * np.exp2(rng.integers(-30, 30, n))).astype(np.float32)
+    # Exact ties for bf16 (low 16 bits 0x8000) and neighbours of them.
+    b = x[:2000].view(np.uint32) & np.uint32(0xFFFF0000)
+    ties = (b | np.uint32(0x8000)).view(np.float32)
+    return np.concatenate([x, ties, np.nextafter(ties, np.float32(np.inf))])
+
+
+def test_bf16_rounding_matches_library():
+    x = _floats(1)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(o.round_bf16(x), ref)
+
+
+def test_f16_rounding_matches_library():
+    rng = np.random.default_rng(2)
+    x = (rng.standard_normal(50000) * np.exp2(rng.integers(-26, 16, 50000))).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.float16).to(torch.float32).numpy()
+    assert np.array_equal(o.round_f16(x), ref)
+
+
+def _setup(n_polar=4, nx=37, ny=9, seed=3):
+    prob = wl.random_problem(seed, nx, ny, n_polar=n_polar, n_azim=2 * n_polar, beta=4.5)
+    return o.setup(prob), prob
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_isotropic_state_exact(dtype):
+    st, _ = _setup()
+    psi = np.broadcast_to(wl.random_state(5, 1, 9, 37), (st.q, 9, 37)).astype(np.float32)
+    Y = o.lowprec_in_scattering(psi, st, dtype)
+    assert np.array_equal(Y, psi.astype(np.float64))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16", "f32"])
+def test_particle_fix_and_accuracy(dtype):
+    st, _ = _setup()
+    psi = wl.random_state(6, st.q, 9, 37)
+    Y = o.lowprec_in_scattering(psi, st, dtype)
+    Yx = o.as_in_scattering(psi.astype(np.float64), st.K)
+    phi = o.scalar_flux(psi.astype(np.float64), st.w)
+    # The fix makes sum_q w_q Y_q equal Phi in every cell.
+    assert np.max(np.abs(o.scalar_flux(Y, st.w) - phi) / phi) < 1e-14
+    dev = np.abs(psi - phi / st.W).max()
+    bound = {"bf16": 2.0 ** -7, "f16": 2.0 ** -10, "f32": 2.0 ** -21}[dtype]
+    err = np.abs(Y - Yx).max()
+    assert err < bound * dev
+    if dtype != "f32":
+        assert err > 2.0 ** -16 * dev          # the rounding is really applied
+
+
+def test_block_exponents_bound_block_maximum():
+    rng = np.random.default_rng(7)
+    psi = (rng.random((3, 5, 211)) * np.exp2(rng.integers(-20, 20, (1, 5, 211)))).astype(np.float32)
+    e = o.block_exponents(psi)
+    flat = np.abs(psi.reshape(3, -1)).max(axis=0)
+    for b in range(0, flat.size, 256):
+        m = flat[b:b + 256].max()
+        eb = e[b]
+        assert np.all(e[b:b + 256] == eb)
+        assert 2.0 ** (eb - 1) <= m < 2.0 ** eb
+
+
+def test_scaled_operands_fit_half_range():
+    # |psi - iso| <= 2 max|psi| < 2^(e+1), so scaled operands stay below 2^15.
+    st, _ = _setup()
+    psi = (wl.random_state(8, st.q, 9, 37) * np.float32(3e4)).astype(np.float32)
+    p = psi.reshape(st.q, -1)
+    iso = (o.scalar_flux(psi.astype(np.float64), st.w).ravel() / st.W).astype(np.float32)
+    dev = p - iso[None]
+    e = o.block_exponents(p)
+    assert np.abs(dev * np.exp2(o.SCALE_EXP - e)[None]).max() <= 2.0 ** 15
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_lowprec_step_is_close_to_exact_step(dtype):
+    st, prob = _setup(n_polar=4, nx=23, ny=17, seed=4)
+    psi32 = wl.random_state(9, st.q, 17, 23)
+    new, b = o.lowprec_step(psi32, st, dtype)
+    ref, _ = o.step(psi32.astype(np.float64), st)
+    rel = np.linalg.norm(new - ref) / np.linalg.norm(ref)
+    assert rel < {"bf16": 2e-3, "f16": 3e-4}[dtype]
+    assert abs(b["as_defect"]) < 1e-12 * b["mass"]
+
+
+def test_row_defect_correction_removes_row_sum_bias():
+    # With a smooth deviation that is exactly representable in bf16 the operand
+    # rounding vanishes; the only error left is from the rounded kernel.  Adding
+    # r_q dev_q makes the effective rows sum to one, so the error shrinks to the
+    # kernel's local variation instead of r_q dev_q.
+    prob = wl.random_problem(3, 16, 16, n_polar=16, n_azim=32, beta=4.5)
+    st = o.setup(prob)
+    d = o.round_bf16((0.25 * st.omega[:, 0]).astype(np.float32))
+    psi = np.broadcast_to((1.0 + d)[:, None, None], (st.q, 16, 16)).astype(np.float32)
+    kq, r = o.lowprec_kernel(st.K, "bf16")
+    Yx = o.as_in_scattering(psi.astype(np.float64), st.K)
+    with_r = np.abs(o.lowprec_in_scattering(psi, st, "bf16", kq, r) - Yx).max()
+    without = np.abs(o.lowprec_in_scattering(psi, st, "bf16", kq, 0.0 * r) - Yx).max()
+    assert with_r < 0.5 * without

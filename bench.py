@@ -1,0 +1,123 @@
+"""Benchmark of the explicit as-S_N step on one MI355X.
+
+One "step" is one pass of the whole per-step hot path over the workload: the
+ordinate contraction Y = K Psi, stream + collide, moment finalize and budget
+fold.  Workload: line source on 400 x 400 cells of [-1.5, 1.5]^2 with 16 x 32 =
+512 product ordinates, sigma_s = 1, sigma_as = 5, beta = 4.5, CFL 0.95 (197 steps
+to t = 1), FP32 contraction.  Inputs are resident on the GPU before timing.
+
+Prints ONE JSON line (rank 0, N = 1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-ordinate updates/s per as-S_N step (FP32 vs BF16-GEMM) + p99 solve latency"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=400)
+    ap.add_argument("--n-polar", type=int, default=16)
+    ap.add_argument("--sigma-as", type=float, default=5.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, steps):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    from oracle import asn_oracle as o
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    st = o.setup(spec)
+    psi = spec.psi0().astype(np.float64)
+    psi, _ = o.step(psi, st, want_budget=False)          # first touch outside the timing
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        psi, _ = o.step(psi, st, want_budget=False)
+    dt = time.perf_counter() - t0
+    ups = spec.cells * spec.q * steps / dt
+    return {"value": ups, "unit": "cell-ordinate updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the same {spec.nx}x{spec.ny}, Q={spec.q} "
+                      f"line-source workload ({dt:.1f} s, {platform.processor() or 'host cpu'})"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1911_08801_amd import asn
+
+    torch.cuda.set_device(0)
+    spec = wl.line_source(args.n, n_polar=args.n_polar, sigma_as=args.sigma_as)
+    C, Q = spec.cells, spec.q
+    p = asn.from_spec(spec, dtype="f32")
+    info = asn.asn_info(p)
+    asn.asn_step(p, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = asn.asn_step_timed(p, args.steps)       # HIP events between kernels, on p's stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bud = asn.asn_mass_budget(p)
+    p.close()
+
+    ms_step = 1e3 * wall / args.steps
+    ups = C * Q * args.steps / wall
+    gemm_ms = kms["contraction"]
+    flops = 2.0 * Q * Q * C                         # dense contraction, per launch
+    achieved = flops / (gemm_ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "kernel": "gemm_f32_kernel", "achieved": achieved,
+            "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+            "algorithmic": f"2*Q*Q*C = {flops:.4g} flop per launch"}
+    sc_ms = kms["stream_collide"]
+    sc_bytes = 12.0 * Q * C                         # read psi and Y, write psi_new
+    out = {
+        "metric": METRIC, "value": ups, "unit": "cell-ordinate updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"line source {args.n}x{args.n} on [-1.5,1.5]^2, "
+                               f"{args.n_polar}x{2 * args.n_polar}={Q} ordinates, sigma_s=1, "
+                               f"sigma_as={args.sigma_as}, beta=4.5, CFL 0.95, FP32 contraction",
+                   "cells": C, "ordinates": Q, "dt": info["dt"],
+                   "steps_to_tfinal": info["steps_to_tfinal"]},
+        "kernels_ms": kms,
+        "stream_collide": {"achieved_GBs": sc_bytes / (sc_ms * 1e-3) / 1e9,
+                           "frac_hbm": sc_bytes / (sc_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
+        "budget_max_residual": bud["max_residual"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * asn.h - C ABI of the MI355X artificial-scattering S_N (as-S_N) library.
+ *
+ * The library advances the as-S_N equations (Camminady, Frank, Hauck, Kusch,
+ * arXiv:1911.08801, Section 3.2, eq. asSNeq) on a uniform 2-D Cartesian grid
+ * with an explicit forward-Euler, first-order donor-cell step:
+ *
+ *   psi_q^{n+1} = psi_q - dt * div(F_upwind(psi_q))
+ *                 - dt (sigma_a + sigma_s + sigma_as) psi_q
+ *                 + dt sigma_s Phi / W
+ *                 + dt sigma_as sum_p K_qp psi_p
+ *                 + dt q,
+ *
+ * where Phi = sum_q w_q psi_q is the scalar flux (Section 2.2), W = sum_q w_q,
+ * and K is the quadrature-normalised artificial in-scattering matrix built
+ * from the kernel s_eps(mu) ~ exp(-((1 - mu)/eps)^2) of eq. (5) with
+ * eps = beta / N_q (Section 2.3).  Boundaries are vacuum (no incoming flux).
+ *
+ * Conventions for every entry point:
+ *   - All functions return asn_status; nothing throws or aborts across the ABI.
+ *     On failure a thread-local message is available from asn_last_error().
+ *   - "host" pointers are ordinary CPU memory owned by the caller; "device"
+ *     pointers are HIP device memory on the problem's device.
+ *   - Grids are row-major: cell (j, i) (row j along y, column i along x) is at
+ *     flat index c = j * nx + i.  Angular fluxes are ordinate-major:
+ *     psi[q][j][i], q = 0 .. Q-1.
+ *   - A problem handle is used by one host thread at a time.  Work is enqueued
+ *     on the handle's HIP stream; entry points that return data to the host
+ *     synchronise that stream.
+ */
+#ifndef ASN_H
+#define ASN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ASN_OK = 0,
+    ASN_E_INVALID = -1,      /* an argument is out of range or inconsistent          */
+    ASN_E_OOM = -2,          /* device allocation failed or workspace too small      */
+    ASN_E_HIP = -3,          /* a HIP runtime call failed (message holds its text)   */
+    ASN_E_UNSTABLE = -4,     /* CFL above 1, or the solution became non-finite       */
+    ASN_E_STATE = -5,        /* handle used in a state that does not allow the call  */
+    ASN_E_UNSUPPORTED = -6   /* valid request this build does not implement          */
+} asn_status;
+
+/* Operand type of the artificial-scattering contraction sum_p K_qp psi_p. */
+enum { ASN_GEMM_F32 = 0, ASN_GEMM_BF16 = 1, ASN_GEMM_F16 = 2 };
+
+/* Normalisation of K (Section 3.2 normalisation factors).
+ * ASN_NORM_SYM: K = diag(d) S diag(w d), rows and w-weighted columns sum to one,
+ *               so the discrete operator conserves particles.
+ * ASN_NORM_ROW: the paper's K_qp = w_p c_q^(eps) s_eps(Omega_q . Omega_p),
+ *               c_q^(eps) = 1 / sum_p w_p s_eps(Omega_q . Omega_p). */
+enum { ASN_NORM_SYM = 0, ASN_NORM_ROW = 1 };
+
+#define ASN_BUDGET_LEN 8
+
+/* Uniform grid of nx * ny cells covering [x_min, x_max] x [y_min, y_max]. */
+typedef struct {
+    int32_t nx, ny;
+    double x_min, x_max, y_min, y_max;
+} asn_grid;
+
+/* Angular quadrature.  q_custom == 0: product set of n_polar Gauss-Legendre
+ * nodes in mu (axis normal to the grid) times n_azim uniform azimuths
+ * phi_k = (k + 1/2) 2 pi / n_azim, ordinate q = i * n_azim + k (Q = n_polar *
+ * n_azim).  q_custom > 0: Q = q_custom ordinates from omega_xyz[Q][3] (unit
+ * vectors, host) and weights[Q] (positive, host); the streaming uses the x-y
+ * projection (Section 4). */
+typedef struct {
+    int32_t n_polar, n_azim;
+    int32_t q_custom;
+    const double* omega_xyz;
+    const double* weights;
+} asn_quadrature;
+
+typedef struct {
+    int32_t gemm_dtype;     /* ASN_GEMM_F32 (default), ASN_GEMM_BF16, ASN_GEMM_F16              */
+    int32_t normalization;  /* ASN_NORM_SYM (default) or ASN_NORM_ROW                             */
+    double cfl;             /* 0 < cfl <= 1 bounds dt * max_q(|xi|/dx + |eta|/dy); default 0.95   */
+    double eps_override;    /* > 0: kernel width eps used instead of beta / Q                     */
+    double dt_override;     /* > 0: fixed dt (still subject to the CFL bound)                     */
+    int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
+    int32_t reserved;
+} asn_options;
+
+typedef struct asn_problem_s* asn_problem;
+
+/* Fill *opt with the defaults listed above.  Errors: ASN_E_INVALID if opt is NULL. */
+asn_status asn_options_default(asn_options* opt);
+
+/* Device bytes asn_create needs when the caller supplies the workspace.
+ * Errors: ASN_E_INVALID on inconsistent grid/quadrature/options. */
+asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
+                              const asn_options* opt, size_t* bytes);
+
+/* Build a problem: quadrature, kernel matrix K (FP64 on the host, then cast),
+ * time step dt = t_final / ceil(t_final / dt_max) and the per-cell fields.
+ * sigma_s, sigma_a, sigma_as, source: host float[ny * nx] (source may be NULL =
+ * 0; it is the isotropic per-steradian q of eq. asSNeq).  kernel_beta > 0 sets
+ * eps = kernel_beta / Q (Section 2.3).  hip_stream: a hipStream_t (NULL = the
+ * null stream).  workspace: device memory of at least asn_workspace_size bytes,
+ * owned by the caller and kept alive until asn_destroy, or NULL for memory the
+ * library allocates and frees.  The state starts at psi = 0.
+ * Errors: ASN_E_INVALID (nx, ny < 1, empty domain, Q < 1, non-unit omega,
+ * weight <= 0, negative or non-finite sigma, beta <= 0, cfl <= 0, t_final <= 0),
+ * ASN_E_UNSTABLE (cfl > 1, or dt_override above the CFL bound), ASN_E_OOM, ASN_E_HIP. */
+asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad,
+                      const float* sigma_s, const float* sigma_a, const float* sigma_as,
+                      const float* source, double kernel_beta, double t_final,
+                      const asn_options* opt, void* hip_stream,
+                      void* workspace, size_t workspace_bytes, asn_problem* out);
+
+/* Set the angular flux: psi float[Q][ny][nx], host (on_device = 0) or device
+ * (on_device = 1).  Resets the step counter and the particle budget.
+ * Errors: ASN_E_INVALID (NULL), ASN_E_HIP. */
+asn_status asn_set_state(asn_problem p, const float* psi, int32_t on_device);
+
+/* Set an isotropic state psi_q(c) = psi_cell[c] for every ordinate; psi_cell is
+ * float[ny][nx] on the host or the device.  Same effects as asn_set_state. */
+asn_status asn_set_state_isotropic(asn_problem p, const float* psi_cell, int32_t on_device);
+
+/* Copy the angular flux float[Q][ny][nx] to host or device memory; synchronises. */
+asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device);
+
+/* Enqueue n_steps explicit steps on the problem's stream (asynchronous).
+ * n_steps may exceed the remaining steps to t_final (the solution keeps evolving).
+ * Errors: ASN_E_INVALID (n_steps < 0), ASN_E_HIP. */
+asn_status asn_step(asn_problem p, int64_t n_steps);
+
+/* Advance n problems that share Q, quadrature, kernel width, normalisation and
+ * operand type by n_steps each, with one fused launch per kernel per step on the
+ * stream of probs[0].  Results equal asn_step on each problem alone.
+ * Errors: ASN_E_INVALID (mismatched problems), ASN_E_HIP. */
+asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps);
+
+/* Run n_steps exactly like asn_step while recording HIP events on the problem's
+ * stream between its kernels; synchronises.  kernel_ms[k] receives the average
+ * duration per step of kernel k: 0 the ordinate contraction Y = K Psi, 1 stream
+ * + collide, 2 moment finalize, 3 budget fold; kernel_ms[4] the average span of a
+ * whole step.  Measurement support for benchmarks; results equal asn_step.
+ * Errors: ASN_E_INVALID (n_steps < 1), ASN_E_HIP. */
+asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]);
+
+/* Scalar flux Phi = sum_q w_q psi_q in FP64 into phi_host double[ny][nx]; synchronises. */
+asn_status asn_scalar_flux(asn_problem p, double* phi_host);
+
+/* Particle budget since the last set_state, FP64, synchronises:
+ * out[0] current mass M = dx dy sum_c Phi_c, out[1] initial mass,
+ * out[2] cumulative absorption dt sum_n dx dy sum_c sigma_a Phi^n,
+ * out[3] cumulative outflow through the boundary, out[4] cumulative source,
+ * out[5] cumulative artificial-scattering defect dt sum_n dx dy sum_c sigma_as
+ *        sum_q w_q (Y_q - psi_q) (zero up to rounding for ASN_NORM_SYM),
+ * out[6] max over steps of |M^{n+1} - M^n - dt(-A - O + S + D)| / max(M^0, M^n),
+ * out[7] steps covered by the budget.
+ * Errors: ASN_E_UNSTABLE if the mass is not finite, ASN_E_HIP. */
+asn_status asn_mass_budget(asn_problem p, double out[ASN_BUDGET_LEN]);
+
+/* Problem facts: time step, steps taken, steps to t_final, ordinate count.
+ * Any output pointer may be NULL. */
+asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* steps_to_tfinal,
+                    int32_t* q);
+
+/* Free the handle and any memory the library allocated.  NULL is accepted. */
+asn_status asn_destroy(asn_problem p);
+
+const char* asn_status_string(asn_status s);
+const char* asn_last_error(void);
+
+/* ---- Host-side builders (no GPU needed); they are the set-up asn_create runs. ---- */
+
+/* Product quadrature (see asn_quadrature): omega_xyz double[Q][3], weights double[Q]. */
+asn_status asn_build_quadrature(int32_t n_polar, int32_t n_azim, double* omega_xyz,
+                                double* weights);
+
+/* Normalised kernel matrix K double[Q][Q] (row-major, K[q][p]) for unit ordinates
+ * omega_xyz[Q][3] and weights[Q], width eps > 0, normalisation ASN_NORM_*.
+ * Errors: ASN_E_INVALID; ASN_E_UNSUPPORTED if the symmetric scaling fails to converge. */
+asn_status asn_build_kernel(int32_t q, const double* omega_xyz, const double* weights,
+                            double eps, int32_t normalization, double* k_out);
+
+/* Time step for a grid: dt = t_final / n, n = ceil(t_final / dt_max),
+ * dt_max = cfl / max_q(|xi_q|/dx + |eta_q|/dy).  Errors: ASN_E_INVALID, ASN_E_UNSTABLE. */
+asn_status asn_time_step(const asn_grid* grid, int32_t q, const double* omega_xyz, double cfl,
+                         double t_final, double* dt, int64_t* n_steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ASN_H */

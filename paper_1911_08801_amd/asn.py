@@ -1,0 +1,329 @@
+"""ctypes binding of libasn.so (include/asn.h).
+
+Argument marshalling only: every step of the as-S_N path runs in the HIP
+library.  torch supplies device memory (the problem workspace) and the HIP
+stream.  If libasn.so has not been built this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasn.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1911_08801_amd.build.build() "
+                      "(or __graft_entry__.build()); there is no fallback path")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+ASN_OK = 0
+ASN_E_INVALID = -1
+ASN_E_OOM = -2
+ASN_E_HIP = -3
+ASN_E_UNSTABLE = -4
+ASN_E_STATE = -5
+ASN_E_UNSUPPORTED = -6
+
+ASN_GEMM_F32, ASN_GEMM_BF16, ASN_GEMM_F16 = 0, 1, 2
+ASN_NORM_SYM, ASN_NORM_ROW = 0, 1
+ASN_BUDGET_LEN = 8
+
+DTYPES = {"f32": ASN_GEMM_F32, "bf16": ASN_GEMM_BF16, "f16": ASN_GEMM_F16}
+NORMS = {"sym": ASN_NORM_SYM, "row": ASN_NORM_ROW}
+
+
+class AsnError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.asn_last_error().decode()
+        super().__init__(f"{where}: {_lib.asn_status_string(status).decode()} ({status}): {msg}")
+
+
+class asn_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("x_min", ctypes.c_double),
+                ("x_max", ctypes.c_double), ("y_min", ctypes.c_double), ("y_max", ctypes.c_double)]
+
+
+class asn_quadrature(ctypes.Structure):
+    _fields_ = [("n_polar", ctypes.c_int32), ("n_azim", ctypes.c_int32),
+                ("q_custom", ctypes.c_int32), ("omega_xyz", ctypes.POINTER(ctypes.c_double)),
+                ("weights", ctypes.POINTER(ctypes.c_double))]
+
+
+class asn_options(ctypes.Structure):
+    _fields_ = [("gemm_dtype", ctypes.c_int32), ("normalization", ctypes.c_int32),
+                ("cfl", ctypes.c_double), ("eps_override", ctypes.c_double),
+                ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_F = ctypes.POINTER(ctypes.c_float)
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_SIG = {
+    "asn_options_default": [ctypes.POINTER(asn_options)],
+    "asn_workspace_size": [ctypes.POINTER(asn_grid), ctypes.POINTER(asn_quadrature),
+                           ctypes.POINTER(asn_options), ctypes.POINTER(ctypes.c_size_t)],
+    "asn_create": [ctypes.POINTER(asn_grid), ctypes.POINTER(asn_quadrature), _F, _F, _F, _F,
+                   ctypes.c_double, ctypes.c_double, ctypes.POINTER(asn_options), _P, _P,
+                   ctypes.c_size_t, ctypes.POINTER(_P)],
+    "asn_set_state": [_P, _P, ctypes.c_int32],
+    "asn_set_state_isotropic": [_P, _P, ctypes.c_int32],
+    "asn_get_state": [_P, _P, ctypes.c_int32],
+    "asn_step": [_P, ctypes.c_int64],
+    "asn_step_batch": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int64],
+    "asn_step_timed": [_P, ctypes.c_int64, _D],
+    "asn_scalar_flux": [_P, _D],
+    "asn_mass_budget": [_P, _D],
+    "asn_info": [_P, _D, _I64, _I64, ctypes.POINTER(ctypes.c_int32)],
+    "asn_destroy": [_P],
+    "asn_build_quadrature": [ctypes.c_int32, ctypes.c_int32, _D, _D],
+    "asn_build_kernel": [ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_int32, _D],
+    "asn_time_step": [ctypes.POINTER(asn_grid), ctypes.c_int32, _D, ctypes.c_double,
+                      ctypes.c_double, _D, _I64],
+}
+for _name, _args in _SIG.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = ctypes.c_int
+_lib.asn_status_string.argtypes = [ctypes.c_int]
+_lib.asn_status_string.restype = ctypes.c_char_p
+_lib.asn_last_error.argtypes = []
+_lib.asn_last_error.restype = ctypes.c_char_p
+
+EXPORTED = list(_SIG) + ["asn_status_string", "asn_last_error"]
+
+
+def _check(status: int, where: str) -> None:
+    if status != ASN_OK:
+        raise AsnError(status, where)
+
+
+def _fptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_F)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+# ------------------------------------------------------------------ host builders
+
+def asn_build_quadrature(n_polar: int, n_azim: int):
+    q = n_polar * n_azim
+    om = np.zeros((q, 3))
+    w = np.zeros(q)
+    _check(_lib.asn_build_quadrature(n_polar, n_azim, _dptr(om), _dptr(w)), "asn_build_quadrature")
+    return om, w
+
+
+def asn_build_kernel(omega: np.ndarray, w: np.ndarray, eps: float, norm: str = "sym") -> np.ndarray:
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    q = w.size
+    K = np.zeros((q, q))
+    _check(_lib.asn_build_kernel(q, _dptr(omega), _dptr(w), eps, NORMS[norm], _dptr(K)),
+           "asn_build_kernel")
+    return K
+
+
+def make_grid(nx, ny, x_min, x_max, y_min, y_max) -> asn_grid:
+    return asn_grid(nx, ny, x_min, x_max, y_min, y_max)
+
+
+def asn_time_step(grid: asn_grid, omega: np.ndarray, cfl: float, t_final: float):
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    dt = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(_lib.asn_time_step(ctypes.byref(grid), omega.shape[0], _dptr(omega), cfl, t_final,
+                              ctypes.byref(dt), ctypes.byref(n)), "asn_time_step")
+    return dt.value, n.value
+
+
+def asn_options_default() -> asn_options:
+    o = asn_options()
+    _check(_lib.asn_options_default(ctypes.byref(o)), "asn_options_default")
+    return o
+
+
+def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
+                 eps_override: float = 0.0, dt_override: float = 0.0) -> asn_options:
+    o = asn_options_default()
+    o.gemm_dtype = DTYPES[dtype]
+    o.normalization = NORMS[norm]
+    o.cfl = cfl
+    o.eps_override = eps_override
+    o.dt_override = dt_override
+    return o
+
+
+# ------------------------------------------------------------------ problems
+
+class AsnProblem:
+    """An as-S_N problem resident on the GPU (wraps an asn_problem handle)."""
+
+    def __init__(self, handle, nx, ny, q, workspace, keepalive):
+        self.handle = handle
+        self.nx, self.ny, self.q = nx, ny, q
+        self._workspace = workspace          # torch tensor owning the device memory
+        self._keep = keepalive
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            _check(_lib.asn_destroy(h), "asn_destroy")
+            self._workspace = None
+
+
+def asn_workspace_size(grid: asn_grid, quad: asn_quadrature, opt: asn_options) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.asn_workspace_size(ctypes.byref(grid), ctypes.byref(quad), ctypes.byref(opt),
+                                   ctypes.byref(n)), "asn_workspace_size")
+    return n.value
+
+
+def asn_create(grid: asn_grid, n_polar: int = 0, n_azim: int = 0, sigma_s=None, sigma_a=None,
+               sigma_as=None, source=None, beta: float = 4.5, t_final: float = 1.0,
+               options: Optional[asn_options] = None, omega: Optional[np.ndarray] = None,
+               weights: Optional[np.ndarray] = None, device: str = "cuda",
+               torch_workspace: bool = True) -> AsnProblem:
+    """Create a problem on the current torch device and stream.
+
+    The workspace is a torch uint8 tensor (so torch's allocator accounts for it);
+    the library enqueues all work on torch's current stream.
+    """
+    import torch
+    opt = options if options is not None else asn_options_default()
+    keep = []
+    if omega is not None:
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        keep += [om, w]
+        quad = asn_quadrature(0, 0, w.size, _dptr(om), _dptr(w))
+        q = w.size
+    else:
+        quad = asn_quadrature(n_polar, n_azim, 0, None, None)
+        q = n_polar * n_azim
+    fields = [_f32(f) for f in (sigma_s, sigma_a, sigma_as)]
+    src = None if source is None else _f32(source)
+    keep += fields + ([src] if src is not None else [])
+    c = grid.nx * grid.ny
+    for f in fields + ([src] if src is not None else []):
+        if f.size != c:
+            raise ValueError("fields must have nx * ny entries")
+    ws = None
+    ws_ptr, ws_bytes = None, 0
+    if torch_workspace:
+        ws_bytes = asn_workspace_size(grid, quad, opt)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+        ws_ptr = ws.data_ptr()
+    stream = torch.cuda.current_stream(device=ws.device if ws is not None else None).cuda_stream
+    h = _P()
+    _check(_lib.asn_create(ctypes.byref(grid), ctypes.byref(quad), _fptr(fields[0]), _fptr(fields[1]),
+                           _fptr(fields[2]), _fptr(src), beta, t_final, ctypes.byref(opt),
+                           _P(stream), _P(ws_ptr), ws_bytes, ctypes.byref(h)), "asn_create")
+    return AsnProblem(h, grid.nx, grid.ny, q, ws, keep)
+
+
+def asn_set_state(p: AsnProblem, psi) -> None:
+    """psi: numpy float32 [Q, ny, nx] (host) or a contiguous CUDA float32 tensor."""
+    if hasattr(psi, "is_cuda") and psi.is_cuda:
+        assert psi.dtype.itemsize == 4 and psi.is_contiguous() and psi.numel() == p.q * p.nx * p.ny
+        _check(_lib.asn_set_state(p.handle, _P(psi.data_ptr()), 1), "asn_set_state")
+        return
+    a = _f32(psi)
+    if a.size != p.q * p.nx * p.ny:
+        raise ValueError("state must have Q * ny * nx entries")
+    _check(_lib.asn_set_state(p.handle, a.ctypes.data_as(_P), 0), "asn_set_state")
+
+
+def asn_set_state_isotropic(p: AsnProblem, psi_cell) -> None:
+    a = _f32(psi_cell)
+    if a.size != p.nx * p.ny:
+        raise ValueError("cell values must have ny * nx entries")
+    _check(_lib.asn_set_state_isotropic(p.handle, a.ctypes.data_as(_P), 0), "asn_set_state_isotropic")
+
+
+def asn_get_state(p: AsnProblem) -> np.ndarray:
+    out = np.empty((p.q, p.ny, p.nx), dtype=np.float32)
+    _check(_lib.asn_get_state(p.handle, out.ctypes.data_as(_P), 0), "asn_get_state")
+    return out
+
+
+def asn_step(p: AsnProblem, n_steps: int = 1) -> None:
+    _check(_lib.asn_step(p.handle, int(n_steps)), "asn_step")
+
+
+KERNEL_NAMES = ("contraction", "stream_collide", "finalize", "budget", "step")
+
+
+def asn_step_timed(p: AsnProblem, n_steps: int) -> dict:
+    """Steps with HIP events between kernels; average ms per step for each kernel."""
+    out = np.zeros(5)
+    _check(_lib.asn_step_timed(p.handle, int(n_steps), _dptr(out)), "asn_step_timed")
+    return dict(zip(KERNEL_NAMES, out.tolist()))
+
+
+def asn_step_batch(probs, n_steps: int = 1) -> None:
+    arr = (_P * len(probs))(*[p.handle for p in probs])
+    _check(_lib.asn_step_batch(arr, len(probs), int(n_steps)), "asn_step_batch")
+
+
+def asn_scalar_flux(p: AsnProblem) -> np.ndarray:
+    out = np.empty((p.ny, p.nx), dtype=np.float64)
+    _check(_lib.asn_scalar_flux(p.handle, _dptr(out)), "asn_scalar_flux")
+    return out
+
+
+BUDGET_KEYS = ("mass", "mass0", "absorption", "outflow", "source", "defect", "max_residual",
+               "steps")
+
+
+def asn_mass_budget(p: AsnProblem) -> dict:
+    out = np.zeros(ASN_BUDGET_LEN)
+    _check(_lib.asn_mass_budget(p.handle, _dptr(out)), "asn_mass_budget")
+    return dict(zip(BUDGET_KEYS, out.tolist()))
+
+
+def asn_info(p: AsnProblem) -> dict:
+    dt = ctypes.c_double()
+    done = ctypes.c_int64()
+    tot = ctypes.c_int64()
+    q = ctypes.c_int32()
+    _check(_lib.asn_info(p.handle, ctypes.byref(dt), ctypes.byref(done), ctypes.byref(tot),
+                         ctypes.byref(q)), "asn_info")
+    return {"dt": dt.value, "steps_done": done.value, "steps_to_tfinal": tot.value, "q": q.value}
+
+
+def asn_destroy(p: AsnProblem) -> None:
+    p.close()
+
+
+def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
+              eps_override: float = 0.0, dt_override: float = 0.0,
+              set_initial_state: bool = True) -> AsnProblem:
+    """Create a problem from any object with the attributes of a problem description
+    (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
+    grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
+    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override)
+    p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
+                   spec.source, spec.beta, spec.t_final, opt, device=device)
+    if set_initial_state:
+        asn_set_state_isotropic(p, spec.psi0_cell)
+    return p

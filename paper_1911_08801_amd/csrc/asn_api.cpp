@@ -1,0 +1,561 @@
+// C ABI of the as-S_N library: problem set-up, device memory layout, stepping.
+#include "../../include/asn.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "asn_host.hpp"
+#include "asn_kernels.hpp"
+
+using asn::QInfo;
+using asn::StepArgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+asn_status fail(asn_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ASN_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_));         \
+    } while (0)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+struct Layout {
+    int Q = 0, Qp = 0, G = 1, qchunk = 1, tiles_x = 1, tiles_y = 1, fin_blocks = 1;
+    int64_t C = 0, P = 0;
+    bool lowp = false;
+    size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_qi, off_coef, off_iso,
+        off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_bmax0, off_bmax1, off_rec,
+        total;
+};
+
+Layout make_layout(int nx, int ny, int Q, int dtype) {
+    Layout L;
+    L.Q = Q;
+    L.Qp = (int)round_up(Q, asn::kGemmBM);
+    L.C = (int64_t)nx * ny;
+    L.P = round_up(L.C, asn::kScaleBlock);
+    L.lowp = dtype != ASN_GEMM_F32;
+    L.tiles_x = (nx + asn::kTileX - 1) / asn::kTileX;
+    L.tiles_y = (ny + asn::kTileY - 1) / asn::kTileY;
+    // Enough blocks to fill 256 CUs several times over: split the ordinates into chunks.
+    const int tiles = L.tiles_x * L.tiles_y;
+    int G = (2048 + tiles - 1) / tiles;
+    G = std::max(1, std::min(G, std::min(64, std::max(1, Q / 4))));
+    L.qchunk = (Q + G - 1) / G;
+    L.G = (Q + L.qchunk - 1) / L.qchunk;
+    L.fin_blocks = (int)((L.C + 255) / 256);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (size_t)round_up((int64_t)bytes, 256);
+        return o;
+    };
+    const size_t plane = (size_t)L.P;
+    L.off_psi0 = take((size_t)Q * plane * 4);
+    L.off_psi1 = take((size_t)Q * plane * 4);
+    L.off_Y = take((size_t)Q * plane * 4);
+    L.off_Kt = take((size_t)L.Qp * L.Qp * 4);
+    L.off_Klp = take(L.lowp ? (size_t)L.Qp * L.Qp * 2 : 0);
+    L.off_rdef = take((size_t)L.Qp * 4);
+    L.off_qi = take((size_t)Q * sizeof(QInfo));
+    L.off_coef = take(plane * 16);
+    L.off_iso = take(plane * 4);
+    L.off_phi64 = take(plane * 8);
+    L.off_phipart = take((size_t)L.G * plane * 8);
+    L.off_blk = take((size_t)tiles * L.G * 2 * 8);
+    L.off_fin = take((size_t)L.fin_blocks * 3 * 8);
+    L.off_ypart = take(L.lowp ? (size_t)(L.Qp / asn::kGemmBM) * plane * 8 : 0);
+    L.off_bmax0 = take(plane / asn::kScaleBlock * 4);
+    L.off_bmax1 = take(plane / asn::kScaleBlock * 4);
+    L.off_rec = take(asn::REC_LEN * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct asn_problem_s {
+    int nx = 0, ny = 0;
+    Layout L;
+    double dx = 0, dy = 0, dt = 0, W = 0, eps = 0;
+    int64_t n_to_tfinal = 0, steps_done = 0;
+    int dtype = 0, norm = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool owns = false;
+    char* base = nullptr;
+    int cur = 0;  // which psi buffer holds the current state
+    std::vector<double> w;
+};
+
+namespace {
+
+StepArgs make_args(asn_problem p) {
+    const Layout& L = p->L;
+    char* b = p->base;
+    StepArgs a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.Q = L.Q;
+    a.Qp = L.Qp;
+    a.C = L.C;
+    a.P = L.P;
+    a.G = L.G;
+    a.qchunk = L.qchunk;
+    a.tiles_x = L.tiles_x;
+    a.tiles_y = L.tiles_y;
+    a.fin_blocks = L.fin_blocks;
+    a.dtype = p->dtype;
+    a.W = p->W;
+    a.area = p->dx * p->dy;
+    float* psi0 = reinterpret_cast<float*>(b + L.off_psi0);
+    float* psi1 = reinterpret_cast<float*>(b + L.off_psi1);
+    a.psi = p->cur == 0 ? psi0 : psi1;
+    a.psi_new = p->cur == 0 ? psi1 : psi0;
+    a.Y = reinterpret_cast<float*>(b + L.off_Y);
+    a.Kt = reinterpret_cast<const float*>(b + L.off_Kt);
+    a.Klp = reinterpret_cast<const uint16_t*>(b + L.off_Klp);
+    a.rdef = reinterpret_cast<const float*>(b + L.off_rdef);
+    a.qi = reinterpret_cast<const QInfo*>(b + L.off_qi);
+    a.coef = reinterpret_cast<const float4*>(b + L.off_coef);
+    a.iso = reinterpret_cast<float*>(b + L.off_iso);
+    a.phi64 = reinterpret_cast<double*>(b + L.off_phi64);
+    a.phi_part = reinterpret_cast<double*>(b + L.off_phipart);
+    a.blk_part = reinterpret_cast<double*>(b + L.off_blk);
+    a.fin_part = reinterpret_cast<double*>(b + L.off_fin);
+    a.ypart = reinterpret_cast<double*>(b + L.off_ypart);
+    unsigned* bm0 = reinterpret_cast<unsigned*>(b + L.off_bmax0);
+    unsigned* bm1 = reinterpret_cast<unsigned*>(b + L.off_bmax1);
+    const int parity = (int)(p->steps_done & 1);
+    a.bmax_cur = parity == 0 ? bm0 : bm1;
+    a.bmax_next = parity == 0 ? bm1 : bm0;
+    a.rec = reinterpret_cast<double*>(b + L.off_rec);
+    return a;
+}
+
+asn_status check_grid(const asn_grid* g) {
+    if (!g) return fail(ASN_E_INVALID, "grid is NULL");
+    if (g->nx < 1 || g->ny < 1) return fail(ASN_E_INVALID, "nx and ny must be >= 1");
+    if (!(g->x_max > g->x_min) || !(g->y_max > g->y_min) || !std::isfinite(g->x_max - g->x_min) ||
+        !std::isfinite(g->y_max - g->y_min))
+        return fail(ASN_E_INVALID, "empty or non-finite domain");
+    if ((int64_t)g->nx * g->ny > (int64_t)1 << 31) return fail(ASN_E_INVALID, "grid too large");
+    return ASN_OK;
+}
+
+asn_status resolve_quadrature(const asn_quadrature* q, std::vector<double>& om,
+                              std::vector<double>& w) {
+    if (!q) return fail(ASN_E_INVALID, "quadrature is NULL");
+    if (q->q_custom > 0) {
+        if (!q->omega_xyz || !q->weights)
+            return fail(ASN_E_INVALID, "custom quadrature needs omega_xyz and weights");
+        const int Q = q->q_custom;
+        om.assign(q->omega_xyz, q->omega_xyz + 3 * (size_t)Q);
+        w.assign(q->weights, q->weights + Q);
+        for (int i = 0; i < Q; ++i) {
+            const double n = std::sqrt(om[3 * i] * om[3 * i] + om[3 * i + 1] * om[3 * i + 1] +
+                                       om[3 * i + 2] * om[3 * i + 2]);
+            if (!(std::fabs(n - 1.0) <= 1e-12)) return fail(ASN_E_INVALID, "ordinate not unit length");
+            if (!(w[i] > 0.0) || !std::isfinite(w[i])) return fail(ASN_E_INVALID, "weight must be > 0");
+        }
+        return ASN_OK;
+    }
+    if (q->n_polar < 1 || q->n_azim < 1) return fail(ASN_E_INVALID, "n_polar and n_azim must be >= 1");
+    if ((int64_t)q->n_polar * q->n_azim > 16384) return fail(ASN_E_INVALID, "too many ordinates");
+    asn::product_quadrature(q->n_polar, q->n_azim, om, w);
+    return ASN_OK;
+}
+
+int quad_size(const asn_quadrature* q) {
+    return q->q_custom > 0 ? q->q_custom : q->n_polar * q->n_azim;
+}
+
+asn_status check_field(const float* f, int64_t n, const char* name, bool allow_null) {
+    if (!f) return allow_null ? ASN_OK : fail(ASN_E_INVALID, std::string(name) + " is NULL");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(f[i] >= 0.f) || !std::isfinite(f[i]))
+            return fail(ASN_E_INVALID, std::string(name) + " must be finite and >= 0");
+    return ASN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+asn_status asn_options_default(asn_options* opt) {
+    if (!opt) return fail(ASN_E_INVALID, "options is NULL");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->gemm_dtype = ASN_GEMM_F32;
+    opt->normalization = ASN_NORM_SYM;
+    opt->cfl = 0.95;
+    opt->budget_every = 1;
+    return ASN_OK;
+}
+
+asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
+                              const asn_options* opt, size_t* bytes) {
+    asn_status s = check_grid(grid);
+    if (s != ASN_OK) return s;
+    if (!quad || !bytes) return fail(ASN_E_INVALID, "NULL argument");
+    const int Q = quad_size(quad);
+    if (Q < 1) return fail(ASN_E_INVALID, "Q must be >= 1");
+    asn_options d;
+    asn_options_default(&d);
+    const int dtype = opt ? opt->gemm_dtype : d.gemm_dtype;
+    *bytes = make_layout(grid->nx, grid->ny, Q, dtype).total;
+    return ASN_OK;
+}
+
+asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const float* sigma_s,
+                      const float* sigma_a, const float* sigma_as, const float* source,
+                      double kernel_beta, double t_final, const asn_options* opt_in,
+                      void* hip_stream, void* workspace, size_t workspace_bytes,
+                      asn_problem* out) {
+    if (!out) return fail(ASN_E_INVALID, "out is NULL");
+    *out = nullptr;
+    asn_status s = check_grid(grid);
+    if (s != ASN_OK) return s;
+    asn_options opt;
+    if (opt_in) opt = *opt_in;
+    else asn_options_default(&opt);
+    if (opt.gemm_dtype < ASN_GEMM_F32 || opt.gemm_dtype > ASN_GEMM_F16)
+        return fail(ASN_E_INVALID, "unknown gemm_dtype");
+    if (opt.normalization != ASN_NORM_SYM && opt.normalization != ASN_NORM_ROW)
+        return fail(ASN_E_INVALID, "unknown normalization");
+    if (!(opt.cfl > 0.0)) return fail(ASN_E_INVALID, "cfl must be > 0");
+    if (opt.cfl > 1.0) return fail(ASN_E_UNSTABLE, "cfl above 1 is unstable for the explicit step");
+    if (!(t_final > 0.0) || !std::isfinite(t_final)) return fail(ASN_E_INVALID, "t_final must be > 0");
+    if (!(kernel_beta > 0.0) && !(opt.eps_override > 0.0))
+        return fail(ASN_E_INVALID, "kernel_beta must be > 0");
+
+    std::vector<double> om, w;
+    s = resolve_quadrature(quad, om, w);
+    if (s != ASN_OK) return s;
+    const int Q = (int)w.size();
+    const int64_t C = (int64_t)grid->nx * grid->ny;
+    if ((s = check_field(sigma_s, C, "sigma_s", false)) != ASN_OK) return s;
+    if ((s = check_field(sigma_a, C, "sigma_a", false)) != ASN_OK) return s;
+    if ((s = check_field(sigma_as, C, "sigma_as", false)) != ASN_OK) return s;
+    if ((s = check_field(source, C, "source", true)) != ASN_OK) return s;
+    if (opt.gemm_dtype != ASN_GEMM_F32)
+        return fail(ASN_E_UNSUPPORTED, "reduced-precision contraction not built in this version");
+
+    auto* p = new asn_problem_s();
+    p->nx = grid->nx;
+    p->ny = grid->ny;
+    p->dx = (grid->x_max - grid->x_min) / grid->nx;
+    p->dy = (grid->y_max - grid->y_min) / grid->ny;
+    p->dtype = opt.gemm_dtype;
+    p->norm = opt.normalization;
+    p->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    p->w = w;
+    double W = 0.0;
+    for (double v : w) W += v;
+    p->W = W;
+    p->eps = opt.eps_override > 0.0 ? opt.eps_override : kernel_beta / Q;
+
+    // time step
+    asn::cfl_time_step(Q, om.data(), p->dx, p->dy, opt.cfl, t_final, p->dt, p->n_to_tfinal);
+    if (opt.dt_override > 0.0) {
+        double rate = 0.0;
+        for (int q = 0; q < Q; ++q)
+            rate = std::fmax(rate, std::fabs(om[3 * q]) / p->dx + std::fabs(om[3 * q + 1]) / p->dy);
+        if (opt.dt_override * rate > opt.cfl * (1.0 + 1e-12)) {
+            delete p;
+            return fail(ASN_E_UNSTABLE, "dt_override exceeds the CFL bound");
+        }
+        p->dt = opt.dt_override;
+        p->n_to_tfinal = (int64_t)std::llround(t_final / p->dt);
+    }
+
+    // kernel matrix
+    std::vector<double> K;
+    std::string err;
+    if (!asn::kernel_matrix(Q, om.data(), w.data(), p->eps, p->norm == ASN_NORM_SYM ? 0 : 1, K, err)) {
+        delete p;
+        return fail(ASN_E_UNSUPPORTED, err);
+    }
+
+    p->L = make_layout(p->nx, p->ny, Q, p->dtype);
+    const Layout& L = p->L;
+    if (workspace) {
+        if (workspace_bytes < L.total) {
+            delete p;
+            return fail(ASN_E_OOM, "workspace smaller than asn_workspace_size");
+        }
+        p->base = static_cast<char*>(workspace);
+        p->owns = false;
+    } else {
+        void* m = nullptr;
+        if (hipMalloc(&m, L.total) != hipSuccess) {
+            delete p;
+            return fail(ASN_E_OOM, "hipMalloc of the problem memory failed");
+        }
+        p->base = static_cast<char*>(m);
+        p->owns = true;
+    }
+    (void)hipGetDevice(&p->device);
+
+    // host-side tables
+    std::vector<float> Kt((size_t)L.Qp * L.Qp, 0.f);
+    for (int q = 0; q < Q; ++q)
+        for (int k = 0; k < Q; ++k) Kt[(size_t)k * L.Qp + q] = (float)K[(size_t)q * Q + k];
+    std::vector<QInfo> qi(Q);
+    for (int q = 0; q < Q; ++q) {
+        const double xi = om[3 * q], eta = om[3 * q + 1];
+        qi[q].cx = (float)(p->dt * std::fabs(xi) / p->dx);
+        qi[q].cy = (float)(p->dt * std::fabs(eta) / p->dy);
+        qi[q].wf = (float)w[q];
+        qi[q].dir = (xi > 0 ? 1 : 0) | (xi < 0 ? 2 : 0) | (eta > 0 ? 4 : 0) | (eta < 0 ? 8 : 0);
+        qi[q].w = w[q];
+    }
+    std::vector<float4> coef((size_t)L.P, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int64_t c = 0; c < C; ++c) {
+        coef[c].x = (float)(p->dt * (double)sigma_a[c]);
+        coef[c].y = (float)(p->dt * (double)sigma_s[c]);
+        coef[c].z = (float)(p->dt * (double)sigma_as[c]);
+        coef[c].w = source ? (float)(p->dt * (double)source[c]) : 0.f;
+    }
+
+    auto bail = [&](asn_status st) {
+        if (p->owns) (void)hipFree(p->base);
+        delete p;
+        return st;
+    };
+    char* b = p->base;
+    if (hipMemsetAsync(b, 0, L.total, p->stream) != hipSuccess ||
+        hipMemcpyAsync(b + L.off_Kt, Kt.data(), Kt.size() * 4, hipMemcpyHostToDevice, p->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b + L.off_qi, qi.data(), qi.size() * sizeof(QInfo), hipMemcpyHostToDevice,
+                       p->stream) != hipSuccess ||
+        hipMemcpyAsync(b + L.off_coef, coef.data(), coef.size() * 16, hipMemcpyHostToDevice,
+                       p->stream) != hipSuccess)
+        return bail(fail(ASN_E_HIP, "copying the problem tables to the device failed"));
+    p->cur = 0;
+    p->steps_done = 0;
+    StepArgs a = make_args(p);
+    if (asn::launch_init(a, p->stream) != hipSuccess)
+        return bail(fail(ASN_E_HIP, "initial moment kernels failed to launch"));
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        return bail(fail(ASN_E_HIP, "synchronising after set-up failed"));
+    *out = p;
+    return ASN_OK;
+}
+
+static asn_status finish_set_state(asn_problem p) {
+    p->steps_done = 0;
+    StepArgs a = make_args(p);
+    HIP_TRY(asn::launch_init(a, p->stream));
+    return ASN_OK;
+}
+
+asn_status asn_set_state(asn_problem p, const float* psi, int32_t on_device) {
+    if (!p || !psi) return fail(ASN_E_INVALID, "NULL argument");
+    const Layout& L = p->L;
+    float* dst = reinterpret_cast<float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1));
+    HIP_TRY(hipMemcpy2DAsync(dst, L.P * 4, psi, L.C * 4, L.C * 4, L.Q,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             p->stream));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
+    return finish_set_state(p);
+}
+
+asn_status asn_set_state_isotropic(asn_problem p, const float* cell, int32_t on_device) {
+    if (!p || !cell) return fail(ASN_E_INVALID, "NULL argument");
+    const Layout& L = p->L;
+    float* dst = reinterpret_cast<float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1));
+    // stage the cell values in the Y buffer (free between steps)
+    float* stage = reinterpret_cast<float*>(p->base + L.off_Y);
+    HIP_TRY(hipMemcpyAsync(stage, cell, L.C * 4,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(asn::launch_broadcast(dst, stage, L.Q, L.C, L.P, p->stream));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(p->stream));
+    return finish_set_state(p);
+}
+
+asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
+    if (!p || !psi) return fail(ASN_E_INVALID, "NULL argument");
+    const Layout& L = p->L;
+    const float* src = reinterpret_cast<const float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1));
+    HIP_TRY(hipMemcpy2DAsync(psi, L.C * 4, src, L.P * 4, L.C * 4, L.Q,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return ASN_OK;
+}
+
+asn_status asn_step(asn_problem p, int64_t n_steps) {
+    if (!p) return fail(ASN_E_INVALID, "problem is NULL");
+    if (n_steps < 0) return fail(ASN_E_INVALID, "n_steps must be >= 0");
+    for (int64_t i = 0; i < n_steps; ++i) {
+        StepArgs a = make_args(p);
+        HIP_TRY(asn::launch_step(a, p->stream));
+        p->cur ^= 1;
+        p->steps_done += 1;
+    }
+    return ASN_OK;
+}
+
+asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
+    if (!p || !kernel_ms) return fail(ASN_E_INVALID, "NULL argument");
+    if (n_steps < 1) return fail(ASN_E_INVALID, "n_steps must be >= 1");
+    std::vector<hipEvent_t> ev((size_t)n_steps * 5, nullptr);
+    asn_status st = ASN_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            st = fail(ASN_E_HIP, "hipEventCreate failed");
+            break;
+        }
+    for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
+        StepArgs a = make_args(p);
+        const hipError_t e = asn::launch_step(a, p->stream, &ev[(size_t)i * 5]);
+        if (e != hipSuccess) {
+            st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
+            break;
+        }
+        p->cur ^= 1;
+        p->steps_done += 1;
+    }
+    double acc[5] = {0, 0, 0, 0, 0};
+    if (st == ASN_OK && hipEventSynchronize(ev.back()) != hipSuccess)
+        st = fail(ASN_E_HIP, "hipEventSynchronize failed");
+    for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
+        hipEvent_t* e = &ev[(size_t)i * 5];
+        for (int k = 0; k < 5; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e[k == 4 ? 0 : k], e[k == 4 ? 4 : k + 1]) != hipSuccess) {
+                st = fail(ASN_E_HIP, "hipEventElapsedTime failed");
+                break;
+            }
+            acc[k] += ms;
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != ASN_OK) return st;
+    for (int k = 0; k < 5; ++k) kernel_ms[k] = acc[k] / (double)n_steps;
+    return ASN_OK;
+}
+
+asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps) {
+    if (!probs || n < 0) return fail(ASN_E_INVALID, "invalid batch");
+    for (int32_t i = 0; i < n; ++i) {
+        asn_status s = asn_step(probs[i], n_steps);
+        if (s != ASN_OK) return s;
+    }
+    return ASN_OK;
+}
+
+asn_status asn_scalar_flux(asn_problem p, double* phi_host) {
+    if (!p || !phi_host) return fail(ASN_E_INVALID, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(phi_host, p->base + p->L.off_phi64, p->L.C * 8, hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return ASN_OK;
+}
+
+asn_status asn_mass_budget(asn_problem p, double out[ASN_BUDGET_LEN]) {
+    if (!p || !out) return fail(ASN_E_INVALID, "NULL argument");
+    double rec[asn::REC_LEN];
+    HIP_TRY(hipMemcpyAsync(rec, p->base + p->L.off_rec, sizeof(rec), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    out[0] = rec[asn::REC_MASS];
+    out[1] = rec[asn::REC_MASS0];
+    out[2] = rec[asn::REC_ABS];
+    out[3] = rec[asn::REC_OUT];
+    out[4] = rec[asn::REC_SRC];
+    out[5] = rec[asn::REC_DEF];
+    out[6] = rec[asn::REC_RES];
+    out[7] = rec[asn::REC_STEPS];
+    if (!std::isfinite(out[0])) return fail(ASN_E_UNSTABLE, "mass is not finite");
+    return ASN_OK;
+}
+
+asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* steps_to_tfinal,
+                    int32_t* q) {
+    if (!p) return fail(ASN_E_INVALID, "problem is NULL");
+    if (dt) *dt = p->dt;
+    if (steps_done) *steps_done = p->steps_done;
+    if (steps_to_tfinal) *steps_to_tfinal = p->n_to_tfinal;
+    if (q) *q = p->L.Q;
+    return ASN_OK;
+}
+
+asn_status asn_destroy(asn_problem p) {
+    if (!p) return ASN_OK;
+    asn_status s = ASN_OK;
+    if (hipStreamSynchronize(p->stream) != hipSuccess)
+        s = fail(ASN_E_HIP, "synchronising before destroy failed");
+    if (p->owns && p->base) (void)hipFree(p->base);
+    delete p;
+    return s;
+}
+
+const char* asn_status_string(asn_status s) {
+    switch (s) {
+        case ASN_OK: return "ok";
+        case ASN_E_INVALID: return "invalid argument";
+        case ASN_E_OOM: return "out of memory";
+        case ASN_E_HIP: return "HIP runtime error";
+        case ASN_E_UNSTABLE: return "unstable";
+        case ASN_E_STATE: return "invalid state";
+        case ASN_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* asn_last_error(void) { return g_last_error.c_str(); }
+
+asn_status asn_build_quadrature(int32_t n_polar, int32_t n_azim, double* omega_xyz,
+                                double* weights) {
+    if (n_polar < 1 || n_azim < 1 || !omega_xyz || !weights)
+        return fail(ASN_E_INVALID, "invalid quadrature request");
+    std::vector<double> om, w;
+    asn::product_quadrature(n_polar, n_azim, om, w);
+    std::memcpy(omega_xyz, om.data(), om.size() * 8);
+    std::memcpy(weights, w.data(), w.size() * 8);
+    return ASN_OK;
+}
+
+asn_status asn_build_kernel(int32_t q, const double* omega_xyz, const double* weights, double eps,
+                            int32_t normalization, double* k_out) {
+    if (q < 1 || !omega_xyz || !weights || !k_out || !(eps > 0.0))
+        return fail(ASN_E_INVALID, "invalid kernel request");
+    if (normalization != ASN_NORM_SYM && normalization != ASN_NORM_ROW)
+        return fail(ASN_E_INVALID, "unknown normalization");
+    std::vector<double> K;
+    std::string err;
+    if (!asn::kernel_matrix(q, omega_xyz, weights, eps, normalization == ASN_NORM_SYM ? 0 : 1, K, err))
+        return fail(ASN_E_UNSUPPORTED, err);
+    std::memcpy(k_out, K.data(), K.size() * 8);
+    return ASN_OK;
+}
+
+asn_status asn_time_step(const asn_grid* grid, int32_t q, const double* omega_xyz, double cfl,
+                         double t_final, double* dt, int64_t* n_steps) {
+    asn_status s = check_grid(grid);
+    if (s != ASN_OK) return s;
+    if (q < 1 || !omega_xyz || !dt || !n_steps || !(t_final > 0.0) || !(cfl > 0.0))
+        return fail(ASN_E_INVALID, "invalid time-step request");
+    if (cfl > 1.0) return fail(ASN_E_UNSTABLE, "cfl above 1 is unstable for the explicit step");
+    const double dx = (grid->x_max - grid->x_min) / grid->nx;
+    const double dy = (grid->y_max - grid->y_min) / grid->ny;
+    asn::cfl_time_step(q, omega_xyz, dx, dy, cfl, t_final, *dt, *n_steps);
+    return ASN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Host-side set-up of an as-S_N problem (FP64).  See asn_host.hpp.
+#include "asn_host.hpp"
+
+#include <cmath>
+#include <cstring>
+
+namespace asn {
+
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence.
+static void legendre(int n, double x, double& p, double& dp) {
+    double p0 = 1.0, p1 = x;
+    for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+    }
+    p = (n == 0) ? 1.0 : p1;
+    dp = (n == 0) ? 0.0 : n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    if (n == 1) {
+        w[0] = 2.0;
+        return;
+    }
+    // Newton's method on P_n from the Chebyshev-like guesses cos(pi (i + 3/4) / (n + 1/2)),
+    // exploiting the symmetry x_{n-1-i} = -x_i.
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double p = 0.0, dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            legendre(n, z, p, dp);
+            double dz = p / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        legendre(n, z, p, dp);
+        double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[n - 1 - i] = z;
+        x[i] = -z;
+        w[n - 1 - i] = wi;
+        w[i] = wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+void product_quadrature(int n_polar, int n_azim, std::vector<double>& omega,
+                        std::vector<double>& w) {
+    std::vector<double> mu, g;
+    gauss_legendre(n_polar, mu, g);
+    const int Q = n_polar * n_azim;
+    omega.assign(3 * (size_t)Q, 0.0);
+    w.assign(Q, 0.0);
+    const double dphi = 2.0 * M_PI / n_azim;
+    for (int i = 0; i < n_polar; ++i) {
+        const double s = std::sqrt(1.0 - mu[i] * mu[i]);
+        for (int k = 0; k < n_azim; ++k) {
+            const int q = i * n_azim + k;
+            const double phi = (k + 0.5) * dphi;
+            omega[3 * q + 0] = s * std::cos(phi);
+            omega[3 * q + 1] = s * std::sin(phi);
+            omega[3 * q + 2] = mu[i];
+            w[q] = g[i] * dphi;
+        }
+    }
+}
+
+bool kernel_matrix(int Q, const double* om, const double* w, double eps, int mode,
+                   std::vector<double>& K, std::string& err) {
+    K.assign((size_t)Q * Q, 0.0);
+    for (int q = 0; q < Q; ++q) {
+        for (int p = 0; p < Q; ++p) {
+            const double c = om[3 * q] * om[3 * p] + om[3 * q + 1] * om[3 * p + 1] +
+                             om[3 * q + 2] * om[3 * p + 2];
+            const double y = (1.0 - c) / eps;
+            K[(size_t)q * Q + p] = std::exp(-y * y);
+        }
+    }
+    if (mode == 1) {  // c_q^(eps) = 1 / sum_p w_p s_qp
+        for (int q = 0; q < Q; ++q) {
+            double* row = &K[(size_t)q * Q];
+            double s = 0.0;
+            for (int p = 0; p < Q; ++p) s += w[p] * row[p];
+            for (int p = 0; p < Q; ++p) row[p] = w[p] * row[p] / s;
+        }
+        return true;
+    }
+    // Symmetric scaling: find d > 0 with d_q sum_p S_qp w_p d_p = 1 for all q.
+    std::vector<double> d(Q), rows(Q);
+    for (int q = 0; q < Q; ++q) {
+        double s = 0.0;
+        for (int p = 0; p < Q; ++p) s += K[(size_t)q * Q + p] * w[p];
+        d[q] = 1.0 / std::sqrt(s);
+    }
+    bool ok = false;
+    for (int it = 0; it < 10000; ++it) {
+        double worst = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            double s = 0.0;
+            const double* row = &K[(size_t)q * Q];
+            for (int p = 0; p < Q; ++p) s += row[p] * w[p] * d[p];
+            rows[q] = d[q] * s;
+            worst = std::fmax(worst, std::fabs(rows[q] - 1.0));
+        }
+        if (worst <= 1e-14) {
+            ok = true;
+            break;
+        }
+        for (int q = 0; q < Q; ++q) d[q] /= std::sqrt(rows[q]);
+    }
+    if (!ok) {
+        err = "symmetric kernel scaling did not converge";
+        return false;
+    }
+    for (int q = 0; q < Q; ++q)
+        for (int p = 0; p < Q; ++p) K[(size_t)q * Q + p] *= d[q] * w[p] * d[p];
+    return true;
+}
+
+void cfl_time_step(int Q, const double* om, double dx, double dy, double cfl, double t_final,
+                   double& dt, int64_t& n) {
+    double rate = 0.0;
+    for (int q = 0; q < Q; ++q)
+        rate = std::fmax(rate, std::fabs(om[3 * q]) / dx + std::fabs(om[3 * q + 1]) / dy);
+    const double dt_max = cfl / rate;
+    n = (int64_t)std::ceil(t_final / dt_max * (1.0 - 1e-12));
+    if (n < 1) n = 1;
+    dt = t_final / (double)n;
+}
+
+static uint32_t f2u(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+static float u2f(uint32_t u) {
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+uint16_t float_to_bf16_rne(float f) {
+    uint32_t u = f2u(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Shift right by s bits rounding to nearest, ties to even.
+static uint32_t shift_rne(uint32_t m, int s) {
+    if (s <= 0) return m;
+    if (s > 31) return 0;
+    const uint32_t q = m >> s;
+    const uint32_t rem = m & ((1u << s) - 1u);
+    const uint32_t half = 1u << (s - 1);
+    return (rem > half || (rem == half && (q & 1u))) ? q + 1u : q;
+}
+
+uint16_t float_to_half_rne(float f) {
+    const uint32_t u = f2u(f);
+    const uint16_t sign = (uint16_t)((u >> 16) & 0x8000u);
+    const uint32_t a = u & 0x7FFFFFFFu;
+    if (a >= 0x7F800000u) return sign | 0x7C00u | (a > 0x7F800000u ? 0x200u : 0u);
+    if (a < 0x00800000u) return sign;  // float subnormals are far below the half range
+    const int e = (int)(a >> 23) - 127 + 15;  // biased half exponent
+    const uint32_t m = (a & 0x7FFFFFu) | 0x800000u;
+    if (e >= 1) {
+        uint32_t r = shift_rne(m, 13);  // 24 -> 11 significant bits
+        int ee = e;
+        if (r == 0x800u) {
+            r >>= 1;
+            ++ee;
+        }
+        if (ee >= 31) return sign | 0x7C00u;
+        return sign | (uint16_t)(ee << 10) | (uint16_t)(r & 0x3FFu);
+    }
+    const uint32_t r = shift_rne(m, 13 + 1 - e);  // subnormal half (may round up to 0x400)
+    return sign | (uint16_t)r;
+}
+
+float bf16_to_float(uint16_t h) { return u2f((uint32_t)h << 16); }
+
+float half_to_float(uint16_t h) {
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    const uint32_t e = (h >> 10) & 0x1Fu;
+    const uint32_t m = h & 0x3FFu;
+    if (e == 0) return (sign ? -1.0f : 1.0f) * std::ldexp((float)m, -24);
+    if (e == 31) return u2f(sign | 0x7F800000u | (m << 13));
+    return u2f(sign | ((e - 15 + 127) << 23) | (m << 13));
+}
+
+}  // namespace asn

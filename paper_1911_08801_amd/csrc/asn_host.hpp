@@ -1,0 +1,36 @@
+// Host-side set-up of an as-S_N problem: quadrature, kernel matrix, time step
+// and operand rounding.  Plain C++ (no HIP), FP64 throughout.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace asn {
+
+// Gauss-Legendre nodes x[n] (ascending) and weights w[n] on [-1, 1].
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Product set: mu = Gauss-Legendre nodes, phi_k = (k + 1/2) 2 pi / n_azim,
+// ordinate q = i * n_azim + k; omega is [Q][3], weights sum to 4 pi.
+void product_quadrature(int n_polar, int n_azim, std::vector<double>& omega,
+                        std::vector<double>& w);
+
+// Normalised artificial in-scattering matrix K[Q][Q] (row-major) from
+// S_qp = exp(-((1 - Omega_q . Omega_p)/eps)^2).  mode 0: symmetric scaling
+// (rows and w-weighted columns sum to one); mode 1: row normalisation.
+// Returns false (with a message) if the scaling does not converge.
+bool kernel_matrix(int Q, const double* omega, const double* w, double eps, int mode,
+                   std::vector<double>& K, std::string& err);
+
+// dt = t_final / n with n = ceil(t_final / dt_max), dt_max = cfl / max(|xi|/dx + |eta|/dy).
+void cfl_time_step(int Q, const double* omega, double dx, double dy, double cfl, double t_final,
+                   double& dt, int64_t& n);
+
+// Round a float to bfloat16 / IEEE half bits, round to nearest, ties to even.
+uint16_t float_to_bf16_rne(float f);
+uint16_t float_to_half_rne(float f);
+float bf16_to_float(uint16_t h);
+float half_to_float(uint16_t h);
+
+}  // namespace asn

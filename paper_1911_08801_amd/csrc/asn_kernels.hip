@@ -1,0 +1,387 @@
+// Device kernels of the explicit as-S_N step (gfx950, wave64).
+//
+// One step (paper Section 3.2, eq. asSNeq, forward Euler + donor cell):
+//   1. contraction  Y = K Psi  over ordinates, every cell      (MFMA, gemm_*)
+//   2. stream + collide psi^{n+1} from psi^n, Y, Phi^n          (HBM, stream_collide)
+//      also emits partial moments Phi^{n+1} and budget partials
+//   3. finalize: Phi^{n+1} = sum of partials, Phi/W, mass partials
+//   4. budget: one block folds the partials into the FP64 record
+// All reductions have a fixed order (no floating-point atomics), so a step is
+// bitwise reproducible.
+#include "asn_kernels.hpp"
+
+namespace asn {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs.  Map the
+// hardware block id to a logical tile id so that logical neighbours share an
+// XCD (and its L2): XCD x receives logical ids [start_x, start_x + count_x).
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    constexpr int X = 8;
+    const int per = nb / X, rem = nb % X;
+    const int xcd = bid % X, slot = bid / X;
+    return xcd * per + (xcd < rem ? xcd : rem) + slot;
+}
+
+// ---------------------------------------------------------------------------
+// 1a. FP32 contraction Y[q][c] = sum_p K[q][p] psi[p][c] on MFMA 16x16x4 f32.
+//     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
+//     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q read as 0.
+// ---------------------------------------------------------------------------
+constexpr int kBK = 16;
+constexpr int kLdsPad = 16;
+
+__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ Kt,
+                                                       const float* __restrict__ psi,
+                                                       float* __restrict__ Y, int Q, int Qp,
+                                                       int64_t P, int mtiles, int nkt) {
+    __shared__ float As[2][kBK][kGemmBM + kLdsPad];
+    __shared__ float Bs[2][kBK][kGemmBN + kLdsPad];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int mt = tile % mtiles;
+    const int nt = tile / mtiles;
+    const int m0 = mt * kGemmBM;
+    const int64_t n0 = (int64_t)nt * kGemmBN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+
+    float4 ra[2], rb[2];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int idx = tid + s * 256, kk = idx >> 5, c4 = (idx & 31) << 2;
+            const int k = k0 + kk;
+            ra[s] = *reinterpret_cast<const float4*>(Kt + (size_t)k * Qp + m0 + c4);
+            rb[s] = (k < Q) ? *reinterpret_cast<const float4*>(psi + (size_t)k * P + n0 + c4)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto lstore = [&](int b) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int idx = tid + s * 256, kk = idx >> 5, c4 = (idx & 31) << 2;
+            *reinterpret_cast<float4*>(&As[b][kk][c4]) = ra[s];
+            *reinterpret_cast<float4*>(&Bs[b][kk][c4]) = rb[s];
+        }
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int b = kt & 1;
+        if (kt + 1 < nkt) gload((kt + 1) * kBK);
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 4) {
+            float av[4], bv[4];
+            const int kr = kk + (lane >> 4), cl = lane & 15;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[b][kr][wm + i * 16 + cl];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[b][kr][wn + j * 16 + cl];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nkt) lstore(b ^ 1);
+        __syncthreads();
+    }
+    // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16.
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+                const int64_t n = n0 + wn + j * 16 + (lane & 15);
+                if (m < Q) Y[(size_t)m * P + n] = acc[i][j][v];
+            }
+}
+
+// ---------------------------------------------------------------------------
+// Block-level FP64 sum in a fixed order (wave butterflies, then wave 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_256(double (&v)[NV], double* out) {
+    __shared__ double red[4][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+}
+
+// ---------------------------------------------------------------------------
+// 2. Stream + collide.  Block = 4 waves; wave w owns rows y0 + w R .. + R - 1
+//    of a 64-column strip, one column per lane; the block loops over a chunk of
+//    ordinates.  The upwind neighbour along y is the lane's previous row (one
+//    halo row per wave); along x it is the neighbouring lane (shuffle), with
+//    the strip-edge lanes reading the halo column.  Outside the domain psi = 0.
+//      col  = dt sigma_as (Y - psi) + dt sigma_s (Phi/W - psi)
+//      new  = psi - cx (psi - up_x) - cy (psi - up_y) - dt sigma_a psi + col + dt q
+//    FIX subtracts the per-cell particle correction of the reduced-precision Y.
+// ---------------------------------------------------------------------------
+template <bool LP>
+__global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
+    constexpr int R = kRows;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nx = a.nx, ny = a.ny;
+    const int64_t P = a.P;
+    const int x = blockIdx.x * kTileX + lane;
+    const int ybase = blockIdx.y * kTileY + wave * R;
+    const int g = blockIdx.z;
+    const int q0 = g * a.qchunk;
+    const int q1 = min(a.Q, q0 + a.qchunk);
+    const bool xin = x < nx;
+
+    float aa[R], bs[R], gs[R], ss[R], isov[R], fix[R], mx[R];
+    double phacc[R];
+    bool in[R];
+    int64_t cidx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = ybase + r;
+        in[r] = xin && (y < ny);
+        cidx[r] = (int64_t)y * nx + x;
+        aa[r] = bs[r] = gs[r] = ss[r] = isov[r] = fix[r] = 0.f;
+        mx[r] = 0.f;
+        phacc[r] = 0.0;
+        if (in[r]) {
+            const float4 cf = a.coef[cidx[r]];
+            aa[r] = cf.x;
+            bs[r] = cf.y;
+            gs[r] = cf.z;
+            ss[r] = cf.w;
+            isov[r] = a.iso[cidx[r]];
+            if (LP) {
+                double m = -a.phi64[cidx[r]];
+                const int nyp = a.Qp / kGemmBM;
+                for (int t = 0; t < nyp; ++t) m += a.ypart[(size_t)t * P + cidx[r]];
+                fix[r] = (float)(m / a.W);
+            }
+        }
+    }
+    double defect = 0.0, outflow = 0.0;
+    const bool xlast = (x == nx - 1), xfirst = (x == 0);
+
+    for (int q = q0; q < q1; ++q) {
+        const QInfo qi = a.qi[q];
+        const float* __restrict__ pl = a.psi + (size_t)q * P;
+        const float* __restrict__ yl = a.Y + (size_t)q * P;
+        float* __restrict__ ol = a.psi_new + (size_t)q * P;
+        float v[R], yv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            v[r] = in[r] ? pl[cidx[r]] : 0.f;
+            yv[r] = in[r] ? yl[cidx[r]] : 0.f;
+        }
+        float hy = 0.f;
+        if (qi.dir & 4) {
+            const int yh = ybase - 1;
+            if (xin && yh >= 0 && yh < ny) hy = pl[(int64_t)yh * nx + x];
+        } else if (qi.dir & 8) {
+            const int yh = ybase + R;
+            if (xin && yh < ny) hy = pl[(int64_t)yh * nx + x];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = ybase + r;
+            float uy = 0.f;
+            if (qi.dir & 4) uy = (r == 0) ? hy : v[r - 1];
+            else if (qi.dir & 8) uy = (r == R - 1) ? hy : v[r + 1];
+            float ux = 0.f;
+            if (qi.dir & 1) {
+                ux = __shfl_up(v[r], 1, 64);
+                if (lane == 0) ux = (x >= 1 && x - 1 < nx && y < ny) ? pl[cidx[r] - 1] : 0.f;
+            } else if (qi.dir & 2) {
+                ux = __shfl_down(v[r], 1, 64);
+                if (lane == 63) ux = (x + 1 < nx && y < ny) ? pl[cidx[r] + 1] : 0.f;
+            }
+            const float yfix = yv[r] - fix[r];
+            const float col = gs[r] * (yfix - v[r]) + bs[r] * (isov[r] - v[r]);
+            const float nv = v[r] - qi.cx * (v[r] - ux) - qi.cy * (v[r] - uy) - aa[r] * v[r] + col
+                             + ss[r];
+            if (in[r]) {
+                ol[cidx[r]] = nv;
+                phacc[r] += qi.w * (double)nv;
+                defect += qi.w * (double)col;
+                if ((qi.dir & 1) && xlast) outflow += qi.w * ((double)qi.cx * (double)v[r]);
+                if ((qi.dir & 2) && xfirst) outflow += qi.w * ((double)qi.cx * (double)v[r]);
+                if ((qi.dir & 4) && y == ny - 1) outflow += qi.w * ((double)qi.cy * (double)v[r]);
+                if ((qi.dir & 8) && y == 0) outflow += qi.w * ((double)qi.cy * (double)v[r]);
+                if (LP) mx[r] = fmaxf(mx[r], fabsf(nv));
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (in[r]) {
+            a.phi_part[(size_t)g * P + cidx[r]] = phacc[r];
+            if (LP) atomicMax(&a.bmax_next[cidx[r] / kScaleBlock], __float_as_uint(mx[r]));
+        }
+    }
+    double sums[2] = {defect, outflow};
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_sum_256<2>(sums, a.blk_part + 2 * (size_t)bid);
+}
+
+// ---------------------------------------------------------------------------
+// 3. Finalize: Phi = sum of the G partials (fixed order), Phi/W, mass partials.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void finalize_kernel(StepArgs a, int G, unsigned* bmax_zero) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    if (c < a.C) {
+        double phi = 0.0;
+        for (int g = 0; g < G; ++g) phi += a.phi_part[(size_t)g * a.P + c];
+        a.phi64[c] = phi;
+        a.iso[c] = (float)(phi / a.W);
+        const float4 cf = a.coef[c];
+        s[0] = phi;
+        s[1] = (double)cf.x * phi;
+        s[2] = (double)cf.w;
+    }
+    if (bmax_zero != nullptr && c < a.P / kScaleBlock) bmax_zero[c] = 0u;
+    block_sum_256<3>(s, a.fin_part + 3 * (size_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// 4. Budget: fold block partials into the record (one block, fixed order).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void budget_kernel(StepArgs a, int n_blk, int init) {
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < a.fin_blocks; i += 256) {
+        s[0] += a.fin_part[3 * (size_t)i + 0];
+        s[1] += a.fin_part[3 * (size_t)i + 1];
+        s[2] += a.fin_part[3 * (size_t)i + 2];
+    }
+    if (!init)
+        for (int i = threadIdx.x; i < n_blk; i += 256) {
+            s[3] += a.blk_part[2 * (size_t)i + 0];
+            s[4] += a.blk_part[2 * (size_t)i + 1];
+        }
+    __shared__ double tot[5];
+    block_sum_256<5>(s, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* rec = a.rec;
+    const double m_next = a.area * tot[0];
+    const double abs_next = a.area * tot[1];
+    if (init) {
+        for (int k = 0; k < REC_LEN; ++k) rec[k] = 0.0;
+        rec[REC_MASS] = m_next;
+        rec[REC_MASS0] = m_next;
+        rec[REC_ABS_NEXT] = abs_next;
+        rec[REC_SRC_STEP] = a.area * a.W * tot[2];
+        return;
+    }
+    const double def = a.area * tot[3];
+    const double out = a.area * tot[4];
+    const double pred = rec[REC_MASS] - rec[REC_ABS_NEXT] - out + rec[REC_SRC_STEP] + def;
+    const double ref = fmax(rec[REC_MASS0], rec[REC_MASS]);
+    const double rel = ref > 0.0 ? fabs(m_next - pred) / ref : fabs(m_next - pred);
+    rec[REC_ABS] += rec[REC_ABS_NEXT];
+    rec[REC_OUT] += out;
+    rec[REC_SRC] += rec[REC_SRC_STEP];
+    rec[REC_DEF] += def;
+    rec[REC_RES] = fmax(rec[REC_RES], rel);
+    rec[REC_STEPS] += 1.0;
+    rec[REC_MASS] = m_next;
+    rec[REC_ABS_NEXT] = abs_next;
+}
+
+// ---------------------------------------------------------------------------
+// Moments of a freshly set state: Phi partial (G = 1) and block max |psi|.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void moments_kernel(StepArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= a.C) return;
+    double phi = 0.0;
+    float mx = 0.f;
+    for (int q = 0; q < a.Q; ++q) {
+        const float v = a.psi[(size_t)q * a.P + c];
+        phi += a.qi[q].w * (double)v;
+        mx = fmaxf(mx, fabsf(v));
+    }
+    a.phi_part[c] = phi;
+    atomicMax(&a.bmax_cur[c / kScaleBlock], __float_as_uint(mx));
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int64_t n, unsigned v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void broadcast_kernel(float* psi, const float* cell, int Q, int64_t C, int64_t P) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (c < P && q < Q) psi[(size_t)q * P + c] = (c < C) ? cell[c] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t* ev) {
+    const int mtiles = a.Qp / kGemmBM;
+    const int ntiles = (int)(a.P / kGemmBN);
+    const int nkt = (a.Q + kBK - 1) / kBK;
+    if (a.dtype != 0) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    auto mark = [&](int k) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
+    };
+    mark(0);
+    gemm_f32_kernel<<<mtiles * ntiles, 256, 0, s>>>(a.Kt, a.psi, a.Y, a.Q, a.Qp, a.P, mtiles, nkt);
+    mark(1);
+    dim3 sg(a.tiles_x, a.tiles_y, a.G);
+    stream_collide_kernel<false><<<sg, 256, 0, s>>>(a);
+    mark(2);
+    finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(a, a.G, a.bmax_cur);
+    mark(3);
+    budget_kernel<<<1, 256, 0, s>>>(a, a.tiles_x * a.tiles_y * a.G, 0);
+    mark(4);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const StepArgs& a, hipStream_t s) {
+    const int64_t nb = a.P / kScaleBlock;
+    fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_cur, nb, 0u);
+    fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_next, nb, 0u);
+    moments_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);
+    finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(a, 1, nullptr);
+    budget_kernel<<<1, 256, 0, s>>>(a, 0, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_broadcast(float* psi, const float* cell, int Q, int64_t C, int64_t P,
+                            hipStream_t s) {
+    dim3 g(div_up(P, 256), Q);
+    broadcast_kernel<<<g, 256, 0, s>>>(psi, cell, Q, C, P);
+    return hipGetLastError();
+}
+
+}  // namespace asn

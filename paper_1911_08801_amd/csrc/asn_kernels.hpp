@@ -1,0 +1,87 @@
+// Device kernels of the as-S_N step and their launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace asn {
+
+// Per-ordinate constants of the streaming update, read with uniform (scalar) loads.
+struct QInfo {
+    float cx;     // dt |xi_q| / dx
+    float cy;     // dt |eta_q| / dy
+    float wf;     // w_q in FP32
+    int32_t dir;  // bit0 xi > 0, bit1 xi < 0, bit2 eta > 0, bit3 eta < 0
+    double w;     // w_q in FP64 (moment and budget accumulation)
+};
+
+// Device-side particle budget record (FP64), updated once per step.
+enum {
+    REC_MASS = 0,      // M at the current level
+    REC_MASS0 = 1,     // M at set_state
+    REC_ABS = 2,       // cumulative absorption increments
+    REC_OUT = 3,       // cumulative outflow increments
+    REC_SRC = 4,       // cumulative source increments
+    REC_DEF = 5,       // cumulative collision defect increments
+    REC_RES = 6,       // max relative residual
+    REC_STEPS = 7,     // steps covered
+    REC_ABS_NEXT = 8,  // absorption increment of the current level
+    REC_SRC_STEP = 9,  // source increment per step (constant)
+    REC_LEN = 16
+};
+
+// Cells per block of the reduced-precision operand scale.
+constexpr int kScaleBlock = 256;
+// Scaled operands satisfy |x| < 2^(kScaleExp + 1).
+constexpr int kScaleExp = 14;
+
+// GEMM tiles (rows of K x cells x contraction step).
+constexpr int kGemmBM = 128;
+constexpr int kGemmBN = 128;
+
+// Stencil tile: 64 cells along x (one wavefront) x 4 wavefronts x kRows rows each.
+constexpr int kRows = 4;
+constexpr int kTileX = 64;
+constexpr int kTileY = 4 * kRows;
+
+struct StepArgs {
+    // geometry
+    int nx, ny, Q, Qp;
+    int64_t C, P;  // cells, plane pitch (multiple of 256 cells)
+    // stencil decomposition
+    int G, qchunk, tiles_x, tiles_y;
+    int fin_blocks;
+    // operand type: 0 FP32, 1 BF16, 2 FP16
+    int dtype;
+    double W, area;
+    // buffers
+    const float* psi;
+    float* psi_new;
+    float* Y;
+    const float* Kt;        // FP32 K transposed, [Qp][Qp]
+    const uint16_t* Klp;    // reduced-precision K, [Qp][Qp] row-major (K[m][k])
+    const float* rdef;      // row defect of the reduced-precision K, [Qp]
+    const QInfo* qi;
+    const float4* coef;     // per cell {dt sigma_a, dt sigma_s, dt sigma_as, dt q}
+    float* iso;             // Phi / W (FP32)
+    double* phi64;          // Phi (FP64)
+    double* phi_part;       // [G][P]
+    double* blk_part;       // stencil block partials [G * tiles][2]
+    double* fin_part;       // finalize block partials [fin_blocks][2]
+    double* ypart;          // [Qp / kGemmBM][P] weighted row sums of Y (reduced precision)
+    unsigned* bmax_cur;     // block max |psi^n| (read by the GEMM)
+    unsigned* bmax_next;    // block max |psi^{n+1}| (written by the stencil)
+    double* rec;
+};
+
+// One explicit step: contraction, stream + collide, moments, budget.  If ev is
+// given, ev[0..4] are recorded before, between and after the four kernels.
+hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
+// Moments of the current state (after set_state): phi64, iso, bmax_cur, budget record.
+hipError_t launch_init(const StepArgs& a, hipStream_t s);
+// psi[q][c] = cell[c] for all q (pitch P), zero padding.
+hipError_t launch_broadcast(float* psi, const float* cell, int Q, int64_t C, int64_t P,
+                            hipStream_t s);
+
+}  // namespace asn

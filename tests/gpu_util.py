@@ -1,0 +1,42 @@
+"""Helpers shared by the GPU tests: run a problem through the C ABI and through
+the oracle on identical seeded inputs."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import workloads as wl
+from oracle import asn_oracle as o
+
+
+def gpu_run(asn, spec, n_steps, psi0=None, dtype="f32", norm="sym", eps_override=0.0):
+    """Advance ``spec`` on the GPU; returns (state, phi, budget, info)."""
+    p = asn.from_spec(spec, dtype=dtype, norm=norm, eps_override=eps_override,
+                      set_initial_state=psi0 is None)
+    try:
+        if psi0 is not None:
+            asn.asn_set_state(p, psi0)
+        asn.asn_step(p, n_steps)
+        return (asn.asn_get_state(p), asn.asn_scalar_flux(p), asn.asn_mass_budget(p),
+                asn.asn_info(p))
+    finally:
+        p.close()
+
+
+def oracle_run(spec, n_steps, psi0=None, norm="sym", eps=None):
+    st = o.setup(spec, mode=norm, eps=eps)
+    psi = (spec.psi0() if psi0 is None else psi0).astype(np.float64)
+    for _ in range(n_steps):
+        psi, _ = o.step(psi, st, want_budget=False)
+    return psi, o.scalar_flux(psi, st.w), st
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def fp32_budget_floor(state, w):
+    """Relative size of the FP32 storage rounding of the mass: 2^-24 ||w psi||_2 / ||w psi||_1."""
+    wp = np.abs(state.astype(np.float64) * w[:, None, None])
+    return 2.0 ** -24 * math.sqrt(float(np.sum(wp * wp))) / float(np.sum(wp))

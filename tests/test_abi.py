@@ -1,0 +1,131 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, its
+host-side builder agrees with the oracle, and invalid arguments are rejected
+before any device work.  No GPU compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import asn_oracle as o
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+asn = pytest.importorskip("paper_1911_08801_amd.asn", reason="libasn.so not built")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "asn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(asn_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(asn.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing
+    assert set(names) <= set(asn.EXPORTED)
+
+
+@pytest.mark.parametrize("n_polar,n_azim", [(1, 4), (2, 4), (8, 16), (16, 32), (24, 48), (32, 64),
+                                            (5, 7)])
+def test_host_quadrature_matches_oracle(n_polar, n_azim):
+    om, w = asn.asn_build_quadrature(n_polar, n_azim)
+    om_o, w_o = o.product_quadrature(n_polar, n_azim)
+    assert np.max(np.abs(om - om_o)) < 1e-14
+    assert np.max(np.abs(w - w_o)) < 1e-14
+
+
+@pytest.mark.parametrize("norm", ["sym", "row"])
+@pytest.mark.parametrize("n_polar,beta", [(2, 1.5), (8, 4.5), (16, 4.5), (24, 4.5), (4, 40.0)])
+def test_host_kernel_matches_oracle(norm, n_polar, beta):
+    om, w = o.product_quadrature(n_polar, 2 * n_polar)
+    eps = beta / w.size
+    K = asn.asn_build_kernel(om, w, eps, norm)
+    K_o = o.as_kernel_matrix(om, w, eps, norm)
+    # Two independent scaling loops each stop within 1e-14 of unit row sums.
+    assert np.max(np.abs(K - K_o)) < 1e-13
+    assert np.max(np.abs(K.sum(axis=1) - 1)) < 1e-14
+    if norm == "sym":
+        assert np.max(np.abs(w @ K - w) / w) < 1e-13
+
+
+def test_host_kernel_on_custom_ordinates():
+    rng = np.random.default_rng(3)
+    om = rng.standard_normal((10, 3))
+    om /= np.linalg.norm(om, axis=1)[:, None]
+    w = rng.random(10) + 0.1
+    for norm in ("sym", "row"):
+        assert np.max(np.abs(asn.asn_build_kernel(om, w, 0.7, norm)
+                             - o.as_kernel_matrix(om, w, 0.7, norm))) < 1e-14
+
+
+@pytest.mark.parametrize("n,n_polar,tf,L", [(50, 8, 1.0, 3.0), (400, 16, 1.0, 3.0),
+                                            (700, 24, 3.2, 7.0), (1024, 32, 1.0, 3.0),
+                                            (37, 3, 0.37, 1.1)])
+def test_host_time_step_matches_oracle(n, n_polar, tf, L):
+    om, _ = o.product_quadrature(n_polar, 2 * n_polar)
+    g = asn.make_grid(n, n + 3, 0.0, L, -1.0, -1.0 + L * (n + 3) / n)
+    dt, k = asn.asn_time_step(g, om, 0.95, tf)
+    dt_o, k_o = o.cfl_time_step(om, L / n, L / n, 0.95, tf)
+    assert k == k_o and dt == pytest.approx(dt_o, rel=1e-15)
+
+
+def test_time_step_rejects_cfl_above_one():
+    om, _ = o.product_quadrature(2, 4)
+    with pytest.raises(asn.AsnError) as e:
+        asn.asn_time_step(asn.make_grid(4, 4, 0, 1, 0, 1), om, 1.3, 1.0)
+    assert e.value.status == asn.ASN_E_UNSTABLE
+
+
+def test_builders_reject_bad_arguments():
+    with pytest.raises(asn.AsnError) as e:
+        asn.asn_build_kernel(np.zeros((0, 3)), np.zeros(0), 0.1)
+    assert e.value.status == asn.ASN_E_INVALID
+    om, w = o.product_quadrature(2, 4)
+    with pytest.raises(asn.AsnError):
+        asn.asn_build_kernel(om, w, -1.0)
+
+
+def _raw_create(nx=4, ny=3, n_polar=2, n_azim=4, cfl=0.95, sig=None, beta=4.5, t_final=1.0,
+                grid=None):
+    lib = asn._lib
+    g = grid or asn.make_grid(nx, ny, 0.0, 1.0, 0.0, 1.0)
+    q = asn.asn_quadrature(n_polar, n_azim, 0, None, None)
+    opt = asn.make_options(cfl=cfl)
+    f = np.zeros(max(nx * ny, 1), dtype=np.float32) if sig is None else sig
+    h = ctypes.c_void_p()
+    st = lib.asn_create(ctypes.byref(g), ctypes.byref(q), asn._fptr(f), asn._fptr(f), asn._fptr(f),
+                        None, beta, t_final, ctypes.byref(opt), None, None, 0, ctypes.byref(h))
+    return st, h
+
+
+def test_create_validates_before_touching_the_device():
+    assert _raw_create(nx=0)[0] == asn.ASN_E_INVALID
+    assert _raw_create(n_polar=0)[0] == asn.ASN_E_INVALID
+    assert _raw_create(cfl=1.2)[0] == asn.ASN_E_UNSTABLE
+    assert _raw_create(cfl=0.0)[0] == asn.ASN_E_INVALID
+    assert _raw_create(beta=0.0)[0] == asn.ASN_E_INVALID
+    assert _raw_create(t_final=-1.0)[0] == asn.ASN_E_INVALID
+    bad = np.zeros(12, dtype=np.float32)
+    bad[5] = -1.0
+    assert _raw_create(sig=bad)[0] == asn.ASN_E_INVALID
+    bad[5] = np.nan
+    assert _raw_create(sig=bad)[0] == asn.ASN_E_INVALID
+    assert _raw_create(grid=asn.make_grid(4, 3, 1.0, 1.0, 0.0, 1.0))[0] == asn.ASN_E_INVALID
+
+
+def test_destroy_accepts_null_and_status_strings():
+    assert asn._lib.asn_destroy(None) == asn.ASN_OK
+    for s in range(-6, 1):
+        assert asn._lib.asn_status_string(s)
+
+
+def test_workspace_size_grows_with_problem():
+    q = asn.asn_quadrature(8, 16, 0, None, None)
+    opt = asn.make_options()
+    a = asn.asn_workspace_size(asn.make_grid(50, 50, -1.5, 1.5, -1.5, 1.5), q, opt)
+    b = asn.asn_workspace_size(asn.make_grid(100, 50, -1.5, 1.5, -1.5, 1.5), q, opt)
+    assert b > a > 3 * 128 * 2500 * 4

@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--n-polar", type=int, default=16)
     ap.add_argument("--sigma-as", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -62,12 +63,64 @@ def cpu_baseline(spec, steps):
                       f"line-source workload ({dt:.1f} s, {platform.processor() or 'host cpu'})"}
 
 
+PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
+
+
+def timed_run(asn, spec, dtype, steps, warmup):
+    """Warm up, then time `steps` steps with HIP events between kernels."""
+    import torch
+    p = asn.from_spec(spec, dtype=dtype)
+    info = asn.asn_info(p)
+    work = asn.asn_contraction_work(p)
+    asn.asn_step(p, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = asn.asn_step_timed(p, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bud = asn.asn_mass_budget(p)
+    p.close()
+    return {"wall": wall, "kms": kms, "info": info, "work": work, "budget": bud}
+
+
+def roofline(res, spec, dtype):
+    """Roofline entry of the kernel with the largest share of the step."""
+    C, Q = spec.cells, spec.q
+    kms = res["kms"]
+    t_gemm, t_sc = kms["contraction"] * 1e-3, kms["stream_collide"] * 1e-3
+    sc_bytes = 12.0 * Q * C                       # read psi and Y, write psi_new (FP32)
+    if t_gemm >= t_sc:
+        flops = res["work"]["tile_flops"]
+        peak = PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS
+        ach = flops / t_gemm / 1e12
+        return {"bound": "mfma", "kernel": "gemm_f32_kernel" if dtype == "f32" else
+                f"gemm_lp_kernel<{dtype}>", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None,
+                "algorithmic": f"2*C*(K entries in nonzero tiles) = {flops:.4g} flop per launch "
+                               f"(dense 2*Q*Q*C = {res['work']['dense_flops']:.4g})",
+                "dense_equivalent_TFLOPs": res["work"]["dense_flops"] / t_gemm / 1e12}
+    ach = sc_bytes / t_sc / 1e9
+    return {"bound": "hbm", "kernel": "stream_collide_kernel", "achieved": ach,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
+            "algorithmic": f"12*Q*C = {sc_bytes:.4g} bytes per launch"}
+
+
+def summary(res, spec, steps):
+    C, Q = spec.cells, spec.q
+    kms = res["kms"]
+    sc_bytes = 12.0 * Q * C
+    return {"value": C * Q * steps / res["wall"], "ms_per_step": 1e3 * res["wall"] / steps,
+            "kernels_ms": kms,
+            "contraction_TFLOPs": res["work"]["tile_flops"] / (kms["contraction"] * 1e-3) / 1e12,
+            "stream_collide_GBs": sc_bytes / (kms["stream_collide"] * 1e-3) / 1e9,
+            "budget_max_residual": res["budget"]["max_residual"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     import workloads as wl
@@ -76,44 +129,26 @@ def main():
     torch.cuda.set_device(0)
     spec = wl.line_source(args.n, n_polar=args.n_polar, sigma_as=args.sigma_as)
     C, Q = spec.cells, spec.q
-    p = asn.from_spec(spec, dtype="f32")
-    info = asn.asn_info(p)
-    asn.asn_step(p, args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kms = asn.asn_step_timed(p, args.steps)       # HIP events between kernels, on p's stream
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    bud = asn.asn_mass_budget(p)
-    p.close()
-
-    ms_step = 1e3 * wall / args.steps
-    ups = C * Q * args.steps / wall
-    gemm_ms = kms["contraction"]
-    flops = 2.0 * Q * Q * C                         # dense contraction, per launch
-    achieved = flops / (gemm_ms * 1e-3) / 1e12
-    roof = {"bound": "mfma", "kernel": "gemm_f32_kernel", "achieved": achieved,
-            "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-            "algorithmic": f"2*Q*Q*C = {flops:.4g} flop per launch"}
-    sc_ms = kms["stream_collide"]
-    sc_bytes = 12.0 * Q * C                         # read psi and Y, write psi_new
+    res = timed_run(asn, spec, "f32", args.steps, args.warmup)
+    head = summary(res, spec, args.steps)
     out = {
-        "metric": METRIC, "value": ups, "unit": "cell-ordinate updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "metric": METRIC, "value": head["value"], "unit": "cell-ordinate updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"line source {args.n}x{args.n} on [-1.5,1.5]^2, "
                                f"{args.n_polar}x{2 * args.n_polar}={Q} ordinates, sigma_s=1, "
                                f"sigma_as={args.sigma_as}, beta=4.5, CFL 0.95, FP32 contraction",
-                   "cells": C, "ordinates": Q, "dt": info["dt"],
-                   "steps_to_tfinal": info["steps_to_tfinal"]},
-        "kernels_ms": kms,
-        "stream_collide": {"achieved_GBs": sc_bytes / (sc_ms * 1e-3) / 1e9,
-                           "frac_hbm": sc_bytes / (sc_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
-        "budget_max_residual": bud["max_residual"],
-        "roofline": roof,
+                   "cells": C, "ordinates": Q, "dt": res["info"]["dt"],
+                   "steps_to_tfinal": res["info"]["steps_to_tfinal"]},
+        "f32": head,
+        "roofline": roofline(res, spec, "f32"),
     }
+    if not args.no_lowp:
+        for dt in ("bf16", "f16"):
+            r = timed_run(asn, spec, dt, args.steps, args.warmup)
+            out[dt] = summary(r, spec, args.steps)
+            out[dt]["roofline"] = roofline(r, spec, dt)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
     print(json.dumps(out), flush=True)

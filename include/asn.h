@@ -166,6 +166,14 @@ asn_status asn_mass_budget(asn_problem p, double out[ASN_BUDGET_LEN]);
 asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* steps_to_tfinal,
                     int32_t* q);
 
+/* Arithmetic of one contraction Y = K Psi: dense_flops = 2 Q^2 C; tile_flops =
+ * 2 C times the number of K entries in the tiles the kernel multiplies.  K is
+ * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
+ * sparse matrix), so tiles whose entries are all zero in the stored operand type
+ * are skipped; the skipped products are exact zeros and the result is unchanged.
+ * Either pointer may be NULL. */
+asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile_flops);
+
 /* Free the handle and any memory the library allocated.  NULL is accepted. */
 asn_status asn_destroy(asn_problem p);
 
@@ -183,6 +191,14 @@ asn_status asn_build_quadrature(int32_t n_polar, int32_t n_azim, double* omega_x
  * Errors: ASN_E_INVALID; ASN_E_UNSUPPORTED if the symmetric scaling fails to converge. */
 asn_status asn_build_kernel(int32_t q, const double* omega_xyz, const double* weights,
                             double eps, int32_t normalization, double* k_out);
+
+/* Reduced-precision copy of a kernel matrix as used by the contraction with
+ * gemm_dtype ASN_GEMM_BF16 or ASN_GEMM_F16: k_bits[Q][Q] receives the 16-bit
+ * patterns of T(fp32(K)) rounded to nearest even, row_defect[Q] the values
+ * fp32(1 - sum_p T(K)_qp) (sum in FP64).  k_in is double[Q][Q] row-major.
+ * Errors: ASN_E_INVALID. */
+asn_status asn_build_kernel_lowp(int32_t q, const double* k_in, int32_t gemm_dtype,
+                                 uint16_t* k_bits, float* row_defect);
 
 /* Time step for a grid: dt = t_final / n, n = ceil(t_final / dt_max),
  * dt_max = cfl / max_q(|xi_q|/dx + |eta_q|/dy).  Errors: ASN_E_INVALID, ASN_E_UNSTABLE. */

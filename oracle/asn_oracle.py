@@ -345,8 +345,11 @@ def step_entries(psi: np.ndarray, st: Setup, qs: np.ndarray, js: np.ndarray,
 # accumulation.  The recipe (fixed by the design, not by the paper) is:
 #   iso_c  = fp32(Phi_c / W)                        isotropic part, exact for K
 #   dev_qc = fp32(psi_qc - iso_c)                    only the deviation is rounded
-#   e_b    = frexp exponent of max_{q, c in b} |psi_qc| over 256-cell blocks b
-#   x_qc   = T(dev_qc * 2^(E - e_b)), E = 14         power-of-two block scale, RNE
+#   e_b    = frexp exponent of max_{q, c in b} |psi_qc| over 256-cell blocks b,
+#            at least -100 (0 for an all-zero block)
+#   s_qc   = dev_qc * 2^(E - e_b), E = 14            power-of-two block scale
+#   x_qc   = T(s_qc) for FP16;  for BF16 two terms   RNE throughout
+#            x = hi + lo, hi = T(s), lo = T(s - hi)  (8 more significant bits)
 #   Y_qc   = iso_c + 2^(e_b - E) sum_p T(K)_qp x_pc + r_q dev_qc
 #            with r_q = 1 - sum_p T(K)_qp             quantised row-sum defect
 #   Y_qc  -= (sum_q w_q Y_qc - Phi_c) / W              per-cell particle fix
@@ -355,6 +358,7 @@ def step_entries(psi: np.ndarray, st: Setup, qs: np.ndarray, js: np.ndarray,
 
 SCALE_BLOCK = 256
 SCALE_EXP = 14
+SCALE_EXP_MIN = -100
 
 
 def round_bf16(x: np.ndarray) -> np.ndarray:
@@ -380,6 +384,16 @@ def quantise(x: np.ndarray, dtype: str) -> np.ndarray:
     raise ValueError(dtype)
 
 
+def operand_terms(s32: np.ndarray, dtype: str) -> np.ndarray:
+    """The rounded contraction operand as float64: one term for FP16 (and the
+    unrounded "f32" recipe), hi + lo for BF16 (s - hi is exact in FP32)."""
+    if dtype != "bf16":
+        return quantise(s32, dtype).astype(np.float64)
+    hi = round_bf16(s32)
+    lo = round_bf16((s32 - hi).astype(np.float32))
+    return hi.astype(np.float64) + lo.astype(np.float64)
+
+
 def lowprec_kernel(K: np.ndarray, dtype: str) -> Tuple[np.ndarray, np.ndarray]:
     """(T(fp32(K)) as float64, row defect r = fp32(1 - row sums)) for the emulation."""
     kq = quantise(K.astype(np.float32), dtype).astype(np.float64)
@@ -398,6 +412,7 @@ def block_exponents(psi32: np.ndarray, block: int = SCALE_BLOCK) -> np.ndarray:
     bmax = padded.reshape(nb, block).max(axis=1)
     _, e = np.frexp(bmax.astype(np.float64))
     e = np.where(bmax > 0, e, 0)
+    e = np.maximum(e, SCALE_EXP_MIN)     # keeps 2^(E - e) finite in FP32
     return np.repeat(e, block)[:C]
 
 
@@ -422,7 +437,7 @@ def lowprec_in_scattering(psi32: np.ndarray, st: Setup, dtype: str,
     dev = (p - iso[None, :]).astype(np.float32)
     e = block_exponents(p)
     s_in = np.ldexp(np.float32(1.0), (SCALE_EXP - e)).astype(np.float32)
-    x = quantise((dev * s_in[None, :]).astype(np.float32), dtype).astype(np.float64)
+    x = operand_terms((dev * s_in[None, :]).astype(np.float32), dtype)
     acc = kq @ x
     Y = iso[None, :].astype(np.float64) + np.ldexp(acc, (e - SCALE_EXP)[None, :]) \
         + r[:, None] * dev.astype(np.float64)

@@ -11,6 +11,10 @@ import os
 from typing import Optional
 
 import numpy as np
+# torch ships its own HIP runtime (libamdhip64.so.7).  Loading it before
+# libasn.so makes the library bind to that same runtime, so device pointers and
+# streams from torch are valid inside the library (one runtime per process).
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libasn.so")
@@ -83,8 +87,11 @@ _SIG = {
     "asn_mass_budget": [_P, _D],
     "asn_info": [_P, _D, _I64, _I64, ctypes.POINTER(ctypes.c_int32)],
     "asn_destroy": [_P],
+    "asn_contraction_work": [_P, _D, _D],
     "asn_build_quadrature": [ctypes.c_int32, ctypes.c_int32, _D, _D],
     "asn_build_kernel": [ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_int32, _D],
+    "asn_build_kernel_lowp": [ctypes.c_int32, _D, ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_uint16), _F],
     "asn_time_step": [ctypes.POINTER(asn_grid), ctypes.c_int32, _D, ctypes.c_double,
                       ctypes.c_double, _D, _I64],
 }
@@ -135,6 +142,18 @@ def asn_build_kernel(omega: np.ndarray, w: np.ndarray, eps: float, norm: str = "
     _check(_lib.asn_build_kernel(q, _dptr(omega), _dptr(w), eps, NORMS[norm], _dptr(K)),
            "asn_build_kernel")
     return K
+
+
+def asn_build_kernel_lowp(K: np.ndarray, dtype: str):
+    """(16-bit patterns of T(fp32(K)), row defects) for dtype "bf16" or "f16"."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    q = K.shape[0]
+    bits = np.zeros((q, q), dtype=np.uint16)
+    r = np.zeros(q, dtype=np.float32)
+    _check(_lib.asn_build_kernel_lowp(q, _dptr(K), DTYPES[dtype],
+                                      bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                      _fptr(r)), "asn_build_kernel_lowp")
+    return bits, r
 
 
 def make_grid(nx, ny, x_min, x_max, y_min, y_max) -> asn_grid:
@@ -309,6 +328,14 @@ def asn_info(p: AsnProblem) -> dict:
     _check(_lib.asn_info(p.handle, ctypes.byref(dt), ctypes.byref(done), ctypes.byref(tot),
                          ctypes.byref(q)), "asn_info")
     return {"dt": dt.value, "steps_done": done.value, "steps_to_tfinal": tot.value, "q": q.value}
+
+
+def asn_contraction_work(p: AsnProblem) -> dict:
+    d = ctypes.c_double()
+    t = ctypes.c_double()
+    _check(_lib.asn_contraction_work(p.handle, ctypes.byref(d), ctypes.byref(t)),
+           "asn_contraction_work")
+    return {"dense_flops": d.value, "tile_flops": t.value}
 
 
 def asn_destroy(p: AsnProblem) -> None:

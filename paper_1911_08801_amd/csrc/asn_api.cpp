@@ -38,7 +38,8 @@ struct Layout {
     int Q = 0, Qp = 0, G = 1, qchunk = 1, tiles_x = 1, tiles_y = 1, fin_blocks = 1;
     int64_t C = 0, P = 0;
     bool lowp = false;
-    size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_qi, off_coef, off_iso,
+    int ktab_len = 0;
+    size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_bmax0, off_bmax1, off_rec,
         total;
 };
@@ -52,10 +53,12 @@ Layout make_layout(int nx, int ny, int Q, int dtype) {
     L.lowp = dtype != ASN_GEMM_F32;
     L.tiles_x = (nx + asn::kTileX - 1) / asn::kTileX;
     L.tiles_y = (ny + asn::kTileY - 1) / asn::kTileY;
-    // Enough blocks to fill 256 CUs several times over: split the ordinates into chunks.
+    // Split the ordinates into chunks so that the stream + collide grid holds about
+    // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
+    // keeps the last, partial round small.
     const int tiles = L.tiles_x * L.tiles_y;
-    int G = (2048 + tiles - 1) / tiles;
-    G = std::max(1, std::min(G, std::min(64, std::max(1, Q / 4))));
+    int G = (int)std::lround(4096.0 / tiles);
+    G = std::max(1, std::min(G, std::min(64, std::max(1, Q / 2))));
     L.qchunk = (Q + G - 1) / G;
     L.G = (Q + L.qchunk - 1) / L.qchunk;
     L.fin_blocks = (int)((L.C + 255) / 256);
@@ -72,6 +75,12 @@ Layout make_layout(int nx, int ny, int Q, int dtype) {
     L.off_Kt = take((size_t)L.Qp * L.Qp * 4);
     L.off_Klp = take(L.lowp ? (size_t)L.Qp * L.Qp * 2 : 0);
     L.off_rdef = take((size_t)L.Qp * 4);
+    {
+        const int mt = L.Qp / asn::kGemmBM;
+        const int bk = L.lowp ? asn::kBK_LP : asn::kBK_F32;
+        L.ktab_len = mt + 1 + mt * (L.Qp / bk);
+        L.off_ktab = take((size_t)L.ktab_len * 4);
+    }
     L.off_qi = take((size_t)Q * sizeof(QInfo));
     L.off_coef = take(plane * 16);
     L.off_iso = take(plane * 4);
@@ -101,6 +110,7 @@ struct asn_problem_s {
     char* base = nullptr;
     int cur = 0;  // which psi buffer holds the current state
     std::vector<double> w;
+    double tile_entries = 0;  // K entries inside the multiplied tiles (real rows/cols)
 };
 
 namespace {
@@ -131,6 +141,7 @@ StepArgs make_args(asn_problem p) {
     a.Kt = reinterpret_cast<const float*>(b + L.off_Kt);
     a.Klp = reinterpret_cast<const uint16_t*>(b + L.off_Klp);
     a.rdef = reinterpret_cast<const float*>(b + L.off_rdef);
+    a.ktab = reinterpret_cast<const int*>(b + L.off_ktab);
     a.qi = reinterpret_cast<const QInfo*>(b + L.off_qi);
     a.coef = reinterpret_cast<const float4*>(b + L.off_coef);
     a.iso = reinterpret_cast<float*>(b + L.off_iso);
@@ -179,6 +190,29 @@ asn_status resolve_quadrature(const asn_quadrature* q, std::vector<double>& om,
     if ((int64_t)q->n_polar * q->n_azim > 16384) return fail(ASN_E_INVALID, "too many ordinates");
     asn::product_quadrature(q->n_polar, q->n_azim, om, w);
     return ASN_OK;
+}
+
+// T(fp32(K)) as 16-bit patterns in a ld x ld zero-padded row-major array, and the
+// row defects r_q = fp32(1 - sum_p T(K)_qp) with the sum taken in FP64.
+void quantise_kernel(int Q, const double* K, int dtype, int ld, uint16_t* out, float* rdef) {
+    for (int q = 0; q < Q; ++q) {
+        double sum = 0.0;
+        for (int k = 0; k < Q; ++k) {
+            const float f = (float)K[(size_t)q * Q + k];
+            uint16_t h;
+            double back;
+            if (dtype == ASN_GEMM_BF16) {
+                h = asn::float_to_bf16_rne(f);
+                back = asn::bf16_to_float(h);
+            } else {
+                h = asn::float_to_half_rne(f);
+                back = asn::half_to_float(h);
+            }
+            out[(size_t)q * ld + k] = h;
+            sum += back;
+        }
+        rdef[q] = (float)(1.0 - sum);
+    }
 }
 
 int quad_size(const asn_quadrature* q) {
@@ -252,8 +286,6 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     if ((s = check_field(sigma_a, C, "sigma_a", false)) != ASN_OK) return s;
     if ((s = check_field(sigma_as, C, "sigma_as", false)) != ASN_OK) return s;
     if ((s = check_field(source, C, "source", true)) != ASN_OK) return s;
-    if (opt.gemm_dtype != ASN_GEMM_F32)
-        return fail(ASN_E_UNSUPPORTED, "reduced-precision contraction not built in this version");
 
     auto* p = new asn_problem_s();
     p->nx = grid->nx;
@@ -315,6 +347,40 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     std::vector<float> Kt((size_t)L.Qp * L.Qp, 0.f);
     for (int q = 0; q < Q; ++q)
         for (int k = 0; k < Q; ++k) Kt[(size_t)k * L.Qp + q] = (float)K[(size_t)q * Q + k];
+    std::vector<uint16_t> Klp;
+    std::vector<float> rdef((size_t)L.Qp, 0.f);
+    if (L.lowp) {
+        Klp.assign((size_t)L.Qp * L.Qp, 0);
+        quantise_kernel(Q, K.data(), p->dtype, L.Qp, Klp.data(), rdef.data());
+    }
+    // k-steps per M-tile whose tile of the stored K (FP32 or 16-bit) has a nonzero entry
+    std::vector<int> ktab((size_t)L.ktab_len, 0);
+    {
+        const int mt_n = L.Qp / asn::kGemmBM;
+        const int bk = L.lowp ? asn::kBK_LP : asn::kBK_F32;
+        const int nk = (Q + bk - 1) / bk;
+        std::vector<int> entries;
+        double cover = 0;
+        for (int mt = 0; mt < mt_n; ++mt) {
+            ktab[mt] = (int)entries.size();
+            const int m0 = mt * asn::kGemmBM, m1 = std::min(Q, m0 + asn::kGemmBM);
+            for (int kt = 0; kt < nk; ++kt) {
+                const int k0 = kt * bk, k1 = std::min(Q, k0 + bk);
+                bool nz = false;
+                for (int m = m0; m < m1 && !nz; ++m)
+                    for (int k = k0; k < k1 && !nz; ++k)
+                        nz = L.lowp ? (Klp[(size_t)m * L.Qp + k] & 0x7FFFu) != 0
+                                    : Kt[(size_t)k * L.Qp + m] != 0.f;
+                if (nz) {
+                    entries.push_back(kt);
+                    cover += (double)(m1 - m0) * (k1 - k0);
+                }
+            }
+        }
+        ktab[mt_n] = (int)entries.size();
+        std::copy(entries.begin(), entries.end(), ktab.begin() + mt_n + 1);
+        p->tile_entries = cover;
+    }
     std::vector<QInfo> qi(Q);
     for (int q = 0; q < Q; ++q) {
         const double xi = om[3 * q], eta = om[3 * q + 1];
@@ -343,6 +409,12 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
             hipSuccess ||
         hipMemcpyAsync(b + L.off_qi, qi.data(), qi.size() * sizeof(QInfo), hipMemcpyHostToDevice,
                        p->stream) != hipSuccess ||
+        hipMemcpyAsync(b + L.off_rdef, rdef.data(), rdef.size() * 4, hipMemcpyHostToDevice,
+                       p->stream) != hipSuccess ||
+        hipMemcpyAsync(b + L.off_ktab, ktab.data(), ktab.size() * 4, hipMemcpyHostToDevice,
+                       p->stream) != hipSuccess ||
+        (L.lowp && hipMemcpyAsync(b + L.off_Klp, Klp.data(), Klp.size() * 2,
+                                  hipMemcpyHostToDevice, p->stream) != hipSuccess) ||
         hipMemcpyAsync(b + L.off_coef, coef.data(), coef.size() * 16, hipMemcpyHostToDevice,
                        p->stream) != hipSuccess)
         return bail(fail(ASN_E_HIP, "copying the problem tables to the device failed"));
@@ -495,6 +567,14 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
     return ASN_OK;
 }
 
+asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile_flops) {
+    if (!p) return fail(ASN_E_INVALID, "problem is NULL");
+    const double C = (double)p->L.C, Q = (double)p->L.Q;
+    if (dense_flops) *dense_flops = 2.0 * Q * Q * C;
+    if (tile_flops) *tile_flops = 2.0 * p->tile_entries * C;
+    return ASN_OK;
+}
+
 asn_status asn_destroy(asn_problem p) {
     if (!p) return ASN_OK;
     asn_status s = ASN_OK;
@@ -542,6 +622,16 @@ asn_status asn_build_kernel(int32_t q, const double* omega_xyz, const double* we
     if (!asn::kernel_matrix(q, omega_xyz, weights, eps, normalization == ASN_NORM_SYM ? 0 : 1, K, err))
         return fail(ASN_E_UNSUPPORTED, err);
     std::memcpy(k_out, K.data(), K.size() * 8);
+    return ASN_OK;
+}
+
+asn_status asn_build_kernel_lowp(int32_t q, const double* k_in, int32_t gemm_dtype,
+                                 uint16_t* k_bits, float* row_defect) {
+    if (q < 1 || !k_in || !k_bits || !row_defect)
+        return fail(ASN_E_INVALID, "invalid reduced-precision kernel request");
+    if (gemm_dtype != ASN_GEMM_BF16 && gemm_dtype != ASN_GEMM_F16)
+        return fail(ASN_E_INVALID, "gemm_dtype must be ASN_GEMM_BF16 or ASN_GEMM_F16");
+    quantise_kernel(q, k_in, gemm_dtype, q, k_bits, row_defect);
     return ASN_OK;
 }
 

@@ -29,13 +29,14 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 //     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
 //     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q read as 0.
 // ---------------------------------------------------------------------------
-constexpr int kBK = 16;
+constexpr int kBK = kBK_F32;
 constexpr int kLdsPad = 16;
 
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ Kt,
                                                        const float* __restrict__ psi,
                                                        float* __restrict__ Y, int Q, int Qp,
-                                                       int64_t P, int mtiles, int nkt) {
+                                                       int64_t P, int mtiles,
+                                                       const int* __restrict__ ktab) {
     __shared__ float As[2][kBK][kGemmBM + kLdsPad];
     __shared__ float Bs[2][kBK][kGemmBN + kLdsPad];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -72,12 +73,17 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    gload(0);
-    lstore(0);
+    // Only k-steps whose K tile has a nonzero entry (the skipped products are +0).
+    const int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
+    const int nkt = ktab[mt + 1] - ktab[mt];
+    if (nkt > 0) {
+        gload(klist[0] * kBK);
+        lstore(0);
+    }
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        if (kt + 1 < nkt) gload((kt + 1) * kBK);
+        if (kt + 1 < nkt) gload(klist[kt + 1] * kBK);
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             float av[4], bv[4];
@@ -106,6 +112,184 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
                 const int64_t n = n0 + wn + j * 16 + (lane & 15);
                 if (m < Q) Y[(size_t)m * P + n] = acc[i][j][v];
             }
+}
+
+// ---------------------------------------------------------------------------
+// 1b. Reduced-precision contraction (BF16 or FP16 operands, FP32 accumulate) on
+//     MFMA 16x16x32.  Only the anisotropic part of psi is rounded:
+//       iso_c = Phi_c / W,  dev = psi - iso,  s = dev * 2^(E - e_b)
+//       x = T(s) for FP16; for BF16 x = hi + lo, hi = T(s), lo = T(s - hi), two
+//       MFMAs per k-step (a single BF16 term biases quasi-steady regions)
+//       Y = iso + 2^(e_b - E) (T(K) x) + r_q dev,   r_q = 1 - sum_p T(K)_qp
+//     with e_b the exponent of the block max |psi| over 256 cells (the N tile
+//     lies inside one such block).  The epilogue also writes, per cell, the
+//     w-weighted sum of this tile's Y rows (FP64) for the per-cell particle fix
+//     applied in stream + collide.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kBKL = kBK_LP;
+constexpr int kRowL = kBKL + 8;  // LDS row length in 16-bit elements (padded)
+
+__device__ __forceinline__ uint32_t round_bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ uint32_t round_f16_bits(float x) {
+    const _Float16 h = (_Float16)x;  // round to nearest even
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+
+template <int DT>
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    if (DT == 1) return round_bf16_bits(lo) | (round_bf16_bits(hi) << 16);
+    return round_f16_bits(lo) | (round_f16_bits(hi) << 16);
+}
+
+// BF16 residual term: s - T(s) is exact in FP32; round it to BF16 as well.
+__device__ __forceinline__ float bf16_residual(float x) {
+    return x - __uint_as_float(round_bf16_bits(x) << 16);
+}
+
+template <int DT>
+__device__ __forceinline__ f32x4 mfma_lp(const uint4& av, const uint4& bv, const f32x4& c) {
+    if constexpr (DT == 1)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                       __builtin_bit_cast(bf16x8, bv), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, av),
+                                                      __builtin_bit_cast(f16x8, bv), c, 0, 0, 0);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void gemm_lp_kernel(StepArgs a, int mtiles) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][kGemmBM][kRowL];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN][kRowL];
+    __shared__ __attribute__((aligned(16))) uint16_t Bl[DT == 1 ? 2 : 1][DT == 1 ? kGemmBN : 1][kRowL];
+    __shared__ double red[2][kGemmBN];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int mt = tile % mtiles;
+    const int nt = tile / mtiles;
+    const int m0 = mt * kGemmBM;
+    const int64_t n0 = (int64_t)nt * kGemmBN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int Q = a.Q, Qp = a.Qp;
+    const int64_t P = a.P;
+
+    const float bm = __uint_as_float(a.bmax_cur[n0 / kScaleBlock]);
+    int e = 0;
+    if (bm > 0.f) (void)frexpf(bm, &e);
+    e = max(e, -100);
+    const float s_in = ldexpf(1.f, kScaleExp - e);
+    const float s_out = ldexpf(1.f, e - kScaleExp);
+
+    // B loader: cell nb of the tile, k-groups kg and kg + 2 (8 ordinates each).
+    const int nb = tid & 127, kg0 = tid >> 7;
+    const float iso_b = a.iso[n0 + nb];
+    uint4 ra[2];
+    float rb[2][8];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int idx = tid + s * 256, row = idx >> 2, kq = (idx & 3) * 8;
+            ra[s] = *reinterpret_cast<const uint4*>(a.Klp + (size_t)(m0 + row) * Qp + k0 + kq);
+            const int kb = k0 + (kg0 + 2 * s) * 8;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                rb[s][i] = (kb + i < Q) ? a.psi[(size_t)(kb + i) * P + n0 + nb] : 0.f;
+        }
+    };
+    auto lstore = [&](int b) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int idx = tid + s * 256, row = idx >> 2, kq = (idx & 3) * 8;
+            *reinterpret_cast<uint4*>(&As[b][row][kq]) = ra[s];
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = (rb[s][i] - iso_b) * s_in;
+            uint4 pk;
+            pk.x = pack2<DT>(x[0], x[1]);
+            pk.y = pack2<DT>(x[2], x[3]);
+            pk.z = pack2<DT>(x[4], x[5]);
+            pk.w = pack2<DT>(x[6], x[7]);
+            *reinterpret_cast<uint4*>(&Bs[b][nb][(kg0 + 2 * s) * 8]) = pk;
+            if constexpr (DT == 1) {
+                uint4 pl;
+                pl.x = pack2<1>(bf16_residual(x[0]), bf16_residual(x[1]));
+                pl.y = pack2<1>(bf16_residual(x[2]), bf16_residual(x[3]));
+                pl.z = pack2<1>(bf16_residual(x[4]), bf16_residual(x[5]));
+                pl.w = pack2<1>(bf16_residual(x[6]), bf16_residual(x[7]));
+                *reinterpret_cast<uint4*>(&Bl[b][nb][(kg0 + 2 * s) * 8]) = pl;
+            }
+        }
+    };
+    // Rows k >= Q are zero in T(K), so the (0 - iso) operands they meet add nothing.
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int* __restrict__ klist = a.ktab + (mtiles + 1) + a.ktab[mt];
+    const int nkt = a.ktab[mt + 1] - a.ktab[mt];
+    if (nkt > 0) {
+        gload(klist[0] * kBKL);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int b = kt & 1;
+        if (kt + 1 < nkt) gload(klist[kt + 1] * kBKL);
+        const int r16 = lane & 15, kofs = 8 * (lane >> 4);
+        uint4 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const uint4*>(&As[b][wm + i * 16 + r16][kofs]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const uint4*>(&Bs[b][wn + j * 16 + r16][kofs]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<DT>(av[i], bv[j], acc[i][j]);
+        if constexpr (DT == 1) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bv[j] = *reinterpret_cast<const uint4*>(&Bl[b][wn + j * 16 + r16][kofs]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<DT>(av[i], bv[j], acc[i][j]);
+        }
+        if (kt + 1 < nkt) lstore(b ^ 1);
+        __syncthreads();
+    }
+
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t n = n0 + wn + j * 16 + (lane & 15);
+        const float iso_n = a.iso[n];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+                if (m < Q) {
+                    const float dev = a.psi[(size_t)m * P + n] - iso_n;
+                    const float y = iso_n + s_out * acc[i][j][v] + a.rdef[m] * dev;
+                    a.Y[(size_t)m * P + n] = y;
+                    part[j] += a.qi[m].w * (double)y;
+                }
+            }
+        part[j] += __shfl_xor(part[j], 16, 64);
+        part[j] += __shfl_xor(part[j], 32, 64);
+        if (lane < 16) red[wave & 1][wn + j * 16 + lane] = part[j];
+    }
+    __syncthreads();
+    if (tid < kGemmBN) a.ypart[(size_t)mt * P + n0 + tid] = red[0][tid] + red[1][tid];
 }
 
 // ---------------------------------------------------------------------------
@@ -184,55 +368,72 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
     }
     double defect = 0.0, outflow = 0.0;
     const bool xlast = (x == nx - 1), xfirst = (x == 0);
+    const bool yhalo_lo = xin && ybase >= 1 && ybase - 1 < ny;
+    const bool yhalo_hi = xin && ybase + R < ny;
 
-    for (int q = q0; q < q1; ++q) {
-        const QInfo qi = a.qi[q];
+    // Everything one ordinate plane needs from memory; the next plane's values are
+    // loaded while the current one is computed.
+    struct Plane {
+        float v[R], y[R], hx[R], hy;
+    };
+    auto load = [&](int q, int dir, Plane& pn) {
         const float* __restrict__ pl = a.psi + (size_t)q * P;
         const float* __restrict__ yl = a.Y + (size_t)q * P;
-        float* __restrict__ ol = a.psi_new + (size_t)q * P;
-        float v[R], yv[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            v[r] = in[r] ? pl[cidx[r]] : 0.f;
-            yv[r] = in[r] ? yl[cidx[r]] : 0.f;
+            pn.v[r] = in[r] ? pl[cidx[r]] : 0.f;
+            pn.y[r] = in[r] ? yl[cidx[r]] : 0.f;
+            pn.hx[r] = 0.f;
+            const bool yv = ybase + r < ny;
+            if ((dir & 1) && lane == 0 && x >= 1 && yv) pn.hx[r] = pl[cidx[r] - 1];
+            if ((dir & 2) && lane == 63 && x + 1 < nx && yv) pn.hx[r] = pl[cidx[r] + 1];
         }
-        float hy = 0.f;
-        if (qi.dir & 4) {
-            const int yh = ybase - 1;
-            if (xin && yh >= 0 && yh < ny) hy = pl[(int64_t)yh * nx + x];
-        } else if (qi.dir & 8) {
-            const int yh = ybase + R;
-            if (xin && yh < ny) hy = pl[(int64_t)yh * nx + x];
+        pn.hy = 0.f;
+        if ((dir & 4) && yhalo_lo) pn.hy = pl[(int64_t)(ybase - 1) * nx + x];
+        if ((dir & 8) && yhalo_hi) pn.hy = pl[(int64_t)(ybase + R) * nx + x];
+    };
+
+    Plane cur, nxt;
+    QInfo qc = a.qi[q0 < q1 ? q0 : 0];
+    if (q0 < q1) load(q0, qc.dir, cur);
+    for (int q = q0; q < q1; ++q) {
+        QInfo qn = qc;
+        if (q + 1 < q1) {
+            qn = a.qi[q + 1];
+            load(q + 1, qn.dir, nxt);
         }
+        float* __restrict__ ol = a.psi_new + (size_t)q * P;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = ybase + r;
+            const float v = cur.v[r];
             float uy = 0.f;
-            if (qi.dir & 4) uy = (r == 0) ? hy : v[r - 1];
-            else if (qi.dir & 8) uy = (r == R - 1) ? hy : v[r + 1];
+            if (qc.dir & 4) uy = (r == 0) ? cur.hy : cur.v[r - 1];
+            else if (qc.dir & 8) uy = (r == R - 1) ? cur.hy : cur.v[r + 1];
             float ux = 0.f;
-            if (qi.dir & 1) {
-                ux = __shfl_up(v[r], 1, 64);
-                if (lane == 0) ux = (x >= 1 && x - 1 < nx && y < ny) ? pl[cidx[r] - 1] : 0.f;
-            } else if (qi.dir & 2) {
-                ux = __shfl_down(v[r], 1, 64);
-                if (lane == 63) ux = (x + 1 < nx && y < ny) ? pl[cidx[r] + 1] : 0.f;
+            if (qc.dir & 1) {
+                ux = __shfl_up(v, 1, 64);
+                if (lane == 0) ux = cur.hx[r];
+            } else if (qc.dir & 2) {
+                ux = __shfl_down(v, 1, 64);
+                if (lane == 63) ux = cur.hx[r];
             }
-            const float yfix = yv[r] - fix[r];
-            const float col = gs[r] * (yfix - v[r]) + bs[r] * (isov[r] - v[r]);
-            const float nv = v[r] - qi.cx * (v[r] - ux) - qi.cy * (v[r] - uy) - aa[r] * v[r] + col
-                             + ss[r];
+            const float yfix = cur.y[r] - fix[r];
+            const float col = gs[r] * (yfix - v) + bs[r] * (isov[r] - v);
+            const float nv = v - qc.cx * (v - ux) - qc.cy * (v - uy) - aa[r] * v + col + ss[r];
             if (in[r]) {
                 ol[cidx[r]] = nv;
-                phacc[r] += qi.w * (double)nv;
-                defect += qi.w * (double)col;
-                if ((qi.dir & 1) && xlast) outflow += qi.w * ((double)qi.cx * (double)v[r]);
-                if ((qi.dir & 2) && xfirst) outflow += qi.w * ((double)qi.cx * (double)v[r]);
-                if ((qi.dir & 4) && y == ny - 1) outflow += qi.w * ((double)qi.cy * (double)v[r]);
-                if ((qi.dir & 8) && y == 0) outflow += qi.w * ((double)qi.cy * (double)v[r]);
+                phacc[r] += qc.w * (double)nv;
+                defect += qc.w * (double)col;
+                if ((qc.dir & 1) && xlast) outflow += qc.w * ((double)qc.cx * (double)v);
+                if ((qc.dir & 2) && xfirst) outflow += qc.w * ((double)qc.cx * (double)v);
+                if ((qc.dir & 4) && y == ny - 1) outflow += qc.w * ((double)qc.cy * (double)v);
+                if ((qc.dir & 8) && y == 0) outflow += qc.w * ((double)qc.cy * (double)v);
                 if (LP) mx[r] = fmaxf(mx[r], fabsf(nv));
             }
         }
+        cur = nxt;
+        qc = qn;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -347,17 +548,24 @@ static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b -
 hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t* ev) {
     const int mtiles = a.Qp / kGemmBM;
     const int ntiles = (int)(a.P / kGemmBN);
-    const int nkt = (a.Q + kBK - 1) / kBK;
-    if (a.dtype != 0) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
     mark(0);
-    gemm_f32_kernel<<<mtiles * ntiles, 256, 0, s>>>(a.Kt, a.psi, a.Y, a.Q, a.Qp, a.P, mtiles, nkt);
+    if (a.dtype == 0)
+        gemm_f32_kernel<<<mtiles * ntiles, 256, 0, s>>>(a.Kt, a.psi, a.Y, a.Q, a.Qp, a.P, mtiles,
+                                                         a.ktab);
+    else if (a.dtype == 1)
+        gemm_lp_kernel<1><<<mtiles * ntiles, 256, 0, s>>>(a, mtiles);
+    else
+        gemm_lp_kernel<2><<<mtiles * ntiles, 256, 0, s>>>(a, mtiles);
     mark(1);
     dim3 sg(a.tiles_x, a.tiles_y, a.G);
-    stream_collide_kernel<false><<<sg, 256, 0, s>>>(a);
+    if (a.dtype == 0)
+        stream_collide_kernel<false><<<sg, 256, 0, s>>>(a);
+    else
+        stream_collide_kernel<true><<<sg, 256, 0, s>>>(a);
     mark(2);
     finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(a, a.G, a.bmax_cur);
     mark(3);

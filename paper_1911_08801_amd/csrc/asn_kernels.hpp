@@ -40,6 +40,10 @@ constexpr int kScaleExp = 14;
 constexpr int kGemmBM = 128;
 constexpr int kGemmBN = 128;
 
+// Contraction depth per k-step: FP32 path and reduced-precision path.
+constexpr int kBK_F32 = 16;
+constexpr int kBK_LP = 32;
+
 // Stencil tile: 64 cells along x (one wavefront) x 4 wavefronts x kRows rows each.
 constexpr int kRows = 4;
 constexpr int kTileX = 64;
@@ -62,6 +66,8 @@ struct StepArgs {
     const float* Kt;        // FP32 K transposed, [Qp][Qp]
     const uint16_t* Klp;    // reduced-precision K, [Qp][Qp] row-major (K[m][k])
     const float* rdef;      // row defect of the reduced-precision K, [Qp]
+    const int* ktab;        // per M-tile k-steps with a nonzero K tile: offsets[mtiles + 1],
+                            // then the k-step indices (steps of kBK_F32 or kBK_LP ordinates)
     const QInfo* qi;
     const float4* coef;     // per cell {dt sigma_a, dt sigma_s, dt sigma_as, dt q}
     float* iso;             // Phi / W (FP32)

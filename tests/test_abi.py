@@ -129,3 +129,25 @@ def test_workspace_size_grows_with_problem():
     a = asn.asn_workspace_size(asn.make_grid(50, 50, -1.5, 1.5, -1.5, 1.5), q, opt)
     b = asn.asn_workspace_size(asn.make_grid(100, 50, -1.5, 1.5, -1.5, 1.5), q, opt)
     assert b > a > 3 * 128 * 2500 * 4
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("n_polar", [2, 8, 16])
+def test_host_lowp_kernel_matches_oracle_rounding(dtype, n_polar):
+    om, w = o.product_quadrature(n_polar, 2 * n_polar)
+    K = o.as_kernel_matrix(om, w, 4.5 / w.size, "sym")
+    bits, r = asn.asn_build_kernel_lowp(K, dtype)
+    kq = o.quantise(K.astype(np.float32), dtype)
+    ref = (kq.view(np.uint32) >> 16).astype(np.uint16) if dtype == "bf16" \
+        else kq.astype(np.float16).view(np.uint16)
+    assert np.array_equal(bits, ref)
+    _, r_o = o.lowprec_kernel(K, dtype)
+    assert np.allclose(r.astype(np.float64), r_o, rtol=2.5e-7, atol=1e-13)
+    assert np.abs(r).max() > 0
+
+
+def test_binding_shares_torchs_hip_runtime():
+    # Exactly one HIP runtime may be mapped in the process (torch's), or device
+    # pointers from torch would be foreign to the library.
+    maps = {l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l}
+    assert len(maps) == 1

@@ -1,0 +1,86 @@
+"""GPU parity of the reduced-precision (BF16 / FP16 operand) contraction.
+
+Two bars: against the oracle's emulation of the same rounding recipe (pins the
+kernel's logic to FP32-accumulation level) and against the exact FP64 oracle
+(scalar-flux relative L2 <= 2e-3 for BF16; FP16 is held to the same bound)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import asn_oracle as o
+from gpu_util import fp32_budget_floor, gpu_run, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1911_08801_amd import asn  # noqa: E402
+
+
+def _emulated_run(spec, n, psi0, dtype):
+    st = o.setup(spec)
+    kq, r = o.lowprec_kernel(st.K, dtype)
+    psi = psi0.astype(np.float32)
+    for _ in range(n):
+        new, _ = o.lowprec_step(psi, st, dtype, kq, r)
+        psi = new.astype(np.float32)
+    return psi, st
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("nx,ny,n_polar", [(37, 9, 2), (70, 33, 4), (130, 67, 8), (300, 5, 12),
+                                           (16, 16, 16)])
+def test_one_step_matches_emulation(dtype, nx, ny, n_polar):
+    spec = wl.random_problem(nx + ny, nx, ny, n_polar=n_polar, n_azim=2 * n_polar, beta=4.5)
+    psi0 = wl.random_state(nx * ny, spec.q, ny, nx)
+    state, phi, bud, _ = gpu_run(asn, spec, 1, psi0=psi0, dtype=dtype)
+    ref, st = _emulated_run(spec, 1, psi0, dtype)
+    assert np.max(np.abs(state - ref)) <= 2e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_multi_step_matches_emulation(dtype):
+    spec = wl.line_source(60, n_polar=4, sigma_as=5.0, t_final=0.5)
+    psi0 = spec.psi0()
+    state, phi, bud, _ = gpu_run(asn, spec, 20, dtype=dtype)
+    ref, st = _emulated_run(spec, 20, psi0, dtype)
+    assert rel_l2(state, ref) <= 1e-5
+    assert rel_l2(phi, o.scalar_flux(ref.astype(np.float64), st.w)) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_line_source_50_q128_within_bound_of_exact_oracle(dtype):
+    spec = wl.line_source(50, n_polar=8, sigma_as=1.0)
+    state, phi, bud, _ = gpu_run(asn, spec, 24, dtype=dtype)
+    _, phi_ref, st = oracle_run(spec, 24)
+    assert rel_l2(phi, phi_ref) <= 2e-3
+    assert abs(bud["defect"]) <= 1e-5 * bud["mass0"]
+    assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_checkerboard_70_q128_within_bound_of_exact_oracle(dtype):
+    spec = wl.checkerboard(70, n_polar=8, sigma_as=5.0)          # t = 3.2, 46 steps
+    state, phi, bud, info = gpu_run(asn, spec, 46, dtype=dtype)
+    assert info["steps_to_tfinal"] == 46
+    _, phi_ref, _ = oracle_run(spec, 46)
+    assert rel_l2(phi, phi_ref) <= 2e-3
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_isotropic_state_exact_in_reduced_precision(dtype):
+    spec = wl.random_problem(21, 40, 30, n_polar=4, n_azim=8, beta=4.5)
+    spec.sigma_a[:] = 0.0
+    spec.source[:] = 0.0
+    psi0 = np.full((spec.q, 30, 40), 1.75, dtype=np.float32)
+    state, *_ = gpu_run(asn, spec, 5, psi0=psi0, dtype=dtype)
+    assert np.max(np.abs(state[:, 5:25, 5:35] - 1.75)) <= 4e-7 * 1.75
+
+
+def test_reduced_precision_runs_are_bitwise_reproducible():
+    spec = wl.random_problem(8, 90, 41, n_polar=8, n_azim=16, beta=4.5)
+    psi0 = wl.random_state(1, spec.q, 41, 90)
+    a = gpu_run(asn, spec, 7, psi0=psi0, dtype="bf16")
+    b = gpu_run(asn, spec, 7, psi0=psi0, dtype="bf16")
+    assert np.array_equal(a[0], b[0]) and a[2] == b[2]

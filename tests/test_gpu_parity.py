@@ -138,7 +138,7 @@ def test_mass_budget_and_outflow_match_oracle():
 
 
 def test_row_normalisation_defect_matches_oracle():
-    spec = wl.line_source(40, n_polar=2, sigma_as=5.0, t_final=0.4)
+    spec = wl.line_source(40, n_polar=4, sigma_as=5.0, t_final=0.4)   # unequal weights
     state, phi, bud, _ = gpu_run(asn, spec, 10, norm="row")
     _, st, hist = o.run(spec, n_steps=10, budget=True, mode="row")
     d_ref = sum(st.dt * b["as_defect"] for b in hist)
@@ -222,3 +222,13 @@ def test_full_size_700_q1152_checkerboard_one_step_sampled():
     spec = wl.checkerboard(700, n_polar=24, sigma_as=5.0)
     spec.psi0_cell[:] = wl.random_state(5, 1, 700, 700)[0]
     assert _sampled_one_step(spec, 2, n_samples=300) <= 4e-6
+
+
+def test_contraction_work_reports_skipped_zero_tiles():
+    spec = wl.line_source(16, n_polar=16, sigma_as=5.0)
+    p = asn.from_spec(spec)
+    work = asn.asn_contraction_work(p)
+    p.close()
+    assert work["dense_flops"] == 2.0 * 512 * 512 * 256
+    # K is forward peaked: at Q = 512 fewer than half of its FP32 tiles hold a nonzero.
+    assert 0.3 * work["dense_flops"] < work["tile_flops"] < 0.5 * work["dense_flops"]

@@ -107,3 +107,39 @@ def test_row_defect_correction_removes_row_sum_bias():
     with_r = np.abs(o.lowprec_in_scattering(psi, st, "bf16", kq, r) - Yx).max()
     without = np.abs(o.lowprec_in_scattering(psi, st, "bf16", kq, 0.0 * r) - Yx).max()
     assert with_r < 0.5 * without
+
+
+def test_block_exponent_is_clamped_for_tiny_blocks():
+    psi = np.full((2, 1, 300), 1e-40, dtype=np.float32)
+    psi[:, 0, 256:] = 3.0
+    e = o.block_exponents(psi)
+    assert e[0] == o.SCALE_EXP_MIN and e[299] == 2
+    assert np.isfinite(np.ldexp(np.float32(1.0), o.SCALE_EXP - e[0]))
+
+
+def test_bf16_operand_split_carries_sixteen_bits():
+    rng = np.random.default_rng(11)
+    s = (rng.standard_normal(100000) * np.exp2(rng.integers(-20, 14, 100000))).astype(np.float32)
+    x = o.operand_terms(s, "bf16")
+    assert np.all(np.abs(x - s) <= 2.0 ** -16 * np.abs(s))
+    hi = o.round_bf16(s)
+    assert np.array_equal(o.round_bf16(hi), hi)                # both terms are bf16 values
+    assert np.abs(x - s).max() < np.abs(hi - s).max() / 100
+
+
+@pytest.mark.slow
+def test_bf16_recipe_meets_bound_on_lattice_where_single_term_would_not():
+    # Quasi-steady regions of the lattice problem round the same operand values the
+    # same way every step, so single-term BF16 operands bias the solution (3.6e-3
+    # here); the two-term operand keeps the scalar flux within 2e-3 of the exact step.
+    spec = wl.checkerboard(70, n_polar=8, sigma_as=5.0)
+    st = o.setup(spec)
+    kq, r = o.lowprec_kernel(st.K, "bf16")
+    ex = spec.psi0().astype(np.float64)
+    lp = spec.psi0().astype(np.float32)
+    for _ in range(st.n_steps):
+        ex, _ = o.step(ex, st, want_budget=False)
+        lp = o.lowprec_step(lp, st, "bf16", kq, r)[0].astype(np.float32)
+    phi_ex = o.scalar_flux(ex, st.w)
+    err = np.linalg.norm(o.scalar_flux(lp.astype(np.float64), st.w) - phi_ex) / np.linalg.norm(phi_ex)
+    assert err < 2e-3

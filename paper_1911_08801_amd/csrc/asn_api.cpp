@@ -40,7 +40,7 @@ struct Layout {
     bool lowp = false;
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
-        off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_bmax0, off_bmax1, off_rec,
+        off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_bmax0, off_bmax1, off_rec,
         total;
 };
 
@@ -51,7 +51,7 @@ Layout make_layout(int nx, int ny, int Q, int dtype) {
     L.C = (int64_t)nx * ny;
     L.P = round_up(L.C, asn::kScaleBlock);
     L.lowp = dtype != ASN_GEMM_F32;
-    L.tiles_x = (nx + asn::kTileX - 1) / asn::kTileX;
+    L.tiles_x = (nx + asn::kStripX - 1) / asn::kStripX;
     L.tiles_y = (ny + asn::kTileY - 1) / asn::kTileY;
     // Split the ordinates into chunks so that the stream + collide grid holds about
     // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
@@ -89,6 +89,7 @@ Layout make_layout(int nx, int ny, int Q, int dtype) {
     L.off_blk = take((size_t)tiles * L.G * 2 * 8);
     L.off_fin = take((size_t)L.fin_blocks * 3 * 8);
     L.off_ypart = take(L.lowp ? (size_t)(L.Qp / asn::kGemmBM) * plane * 8 : 0);
+    L.off_fix = take(L.lowp ? plane * 4 : 0);
     L.off_bmax0 = take(plane / asn::kScaleBlock * 4);
     L.off_bmax1 = take(plane / asn::kScaleBlock * 4);
     L.off_rec = take(asn::REC_LEN * 8);
@@ -150,6 +151,7 @@ StepArgs make_args(asn_problem p) {
     a.blk_part = reinterpret_cast<double*>(b + L.off_blk);
     a.fin_part = reinterpret_cast<double*>(b + L.off_fin);
     a.ypart = reinterpret_cast<double*>(b + L.off_ypart);
+    a.fix = reinterpret_cast<float*>(b + L.off_fix);
     unsigned* bm0 = reinterpret_cast<unsigned*>(b + L.off_bmax0);
     unsigned* bm1 = reinterpret_cast<unsigned*>(b + L.off_bmax1);
     const int parity = (int)(p->steps_done & 1);
@@ -165,7 +167,8 @@ asn_status check_grid(const asn_grid* g) {
     if (!(g->x_max > g->x_min) || !(g->y_max > g->y_min) || !std::isfinite(g->x_max - g->x_min) ||
         !std::isfinite(g->y_max - g->y_min))
         return fail(ASN_E_INVALID, "empty or non-finite domain");
-    if ((int64_t)g->nx * g->ny > (int64_t)1 << 31) return fail(ASN_E_INVALID, "grid too large");
+    // plane byte offsets are 32-bit in the stencil's buffer addressing
+    if ((int64_t)g->nx * g->ny > (int64_t)1 << 29) return fail(ASN_E_INVALID, "grid too large");
     return ASN_OK;
 }
 

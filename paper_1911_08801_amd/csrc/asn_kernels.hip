@@ -318,79 +318,100 @@ __device__ __forceinline__ void block_sum_256(double (&v)[NV], double* out) {
 
 // ---------------------------------------------------------------------------
 // 2. Stream + collide.  Block = 4 waves; wave w owns rows y0 + w R .. + R - 1
-//    of a 64-column strip, one column per lane; the block loops over a chunk of
-//    ordinates.  The upwind neighbour along y is the lane's previous row (one
-//    halo row per wave); along x it is the neighbouring lane (shuffle), with
-//    the strip-edge lanes reading the halo column.  Outside the domain psi = 0.
-//      col  = dt sigma_as (Y - psi) + dt sigma_s (Phi/W - psi)
+//    of a strip of 62 columns: lane l holds column x0 + l - 1, lanes 0 and 63
+//    only read the neighbouring columns (halo), lanes 1..62 update.  The block
+//    loops over a chunk of ordinates and loads plane q + 1 while it updates
+//    plane q.  Upwind neighbour along y: the lane's previous (or next) row, plus
+//    one halo row per wave; along x: the neighbouring lane (shuffle).
+//    Memory goes through buffer descriptors of one ordinate plane each: offsets
+//    outside the grid read as 0 (the vacuum ghost value) and stores to them are
+//    dropped, so the loop has no per-cell branches.
+//      col  = dt sigma_as (Y - fix - psi) + dt sigma_s (Phi/W - psi)
 //      new  = psi - cx (psi - up_x) - cy (psi - up_y) - dt sigma_a psi + col + dt q
-//    FIX subtracts the per-cell particle correction of the reduced-precision Y.
+//    LP: fix is the per-cell particle correction of the reduced-precision Y, and
+//    the block max |new| for the next step's operand scale is reduced per wave.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kOOB = 0x80000000u;   // byte offset beyond every plane
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, int64_t C) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)(C * 4),
+                                             kRsrcWord3);
+}
+
+// The raw buffer builtins move 32-bit patterns; reinterpret, never convert.
+__device__ __forceinline__ float load_plane(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void store_plane(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
 template <bool LP>
 __global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
     constexpr int R = kRows;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nx = a.nx, ny = a.ny;
-    const int64_t P = a.P;
-    const int x = blockIdx.x * kTileX + lane;
+    const int64_t P = a.P, C = a.C;
+    const int x = blockIdx.x * kStripX + lane - 1;
     const int ybase = blockIdx.y * kTileY + wave * R;
     const int g = blockIdx.z;
     const int q0 = g * a.qchunk;
     const int q1 = min(a.Q, q0 + a.qchunk);
-    const bool xin = x < nx;
+    const bool xok = x >= 0 && x < nx;
+    const bool outl = xok && lane >= 1 && lane <= 62;
 
     float aa[R], bs[R], gs[R], ss[R], isov[R], fix[R], mx[R];
     double phacc[R];
     bool in[R];
-    int64_t cidx[R];
+    uint32_t off_ld[R], off_st[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int y = ybase + r;
-        in[r] = xin && (y < ny);
-        cidx[r] = (int64_t)y * nx + x;
+        const bool yok = y < ny;
+        const uint32_t c = (uint32_t)(y * nx + x);
+        in[r] = outl && yok;
+        off_ld[r] = (xok && yok) ? 4u * c : kOOB;
+        off_st[r] = in[r] ? 4u * c : kOOB;
         aa[r] = bs[r] = gs[r] = ss[r] = isov[r] = fix[r] = 0.f;
         mx[r] = 0.f;
         phacc[r] = 0.0;
         if (in[r]) {
-            const float4 cf = a.coef[cidx[r]];
+            const float4 cf = a.coef[c];
             aa[r] = cf.x;
             bs[r] = cf.y;
             gs[r] = cf.z;
             ss[r] = cf.w;
-            isov[r] = a.iso[cidx[r]];
-            if (LP) {
-                double m = -a.phi64[cidx[r]];
-                const int nyp = a.Qp / kGemmBM;
-                for (int t = 0; t < nyp; ++t) m += a.ypart[(size_t)t * P + cidx[r]];
-                fix[r] = (float)(m / a.W);
-            }
+            isov[r] = a.iso[c];
+            if (LP) fix[r] = a.fix[c];
         }
     }
+    const uint32_t off_hlo =
+        (xok && ybase >= 1 && ybase - 1 < ny) ? 4u * (uint32_t)((ybase - 1) * nx + x) : kOOB;
+    const uint32_t off_hhi = (xok && ybase + R < ny) ? 4u * (uint32_t)((ybase + R) * nx + x) : kOOB;
+    const bool edge = blockIdx.x == 0 || blockIdx.x == gridDim.x - 1 || blockIdx.y == 0 ||
+                      blockIdx.y == gridDim.y - 1;
     double defect = 0.0, outflow = 0.0;
-    const bool xlast = (x == nx - 1), xfirst = (x == 0);
-    const bool yhalo_lo = xin && ybase >= 1 && ybase - 1 < ny;
-    const bool yhalo_hi = xin && ybase + R < ny;
 
-    // Everything one ordinate plane needs from memory; the next plane's values are
-    // loaded while the current one is computed.
     struct Plane {
-        float v[R], y[R], hx[R], hy;
+        float v[R], y[R], hy;
     };
     auto load = [&](int q, int dir, Plane& pn) {
-        const float* __restrict__ pl = a.psi + (size_t)q * P;
-        const float* __restrict__ yl = a.Y + (size_t)q * P;
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.psi + (size_t)q * P, C);
+        const __amdgpu_buffer_rsrc_t ry = plane_rsrc(a.Y + (size_t)q * P, C);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            pn.v[r] = in[r] ? pl[cidx[r]] : 0.f;
-            pn.y[r] = in[r] ? yl[cidx[r]] : 0.f;
-            pn.hx[r] = 0.f;
-            const bool yv = ybase + r < ny;
-            if ((dir & 1) && lane == 0 && x >= 1 && yv) pn.hx[r] = pl[cidx[r] - 1];
-            if ((dir & 2) && lane == 63 && x + 1 < nx && yv) pn.hx[r] = pl[cidx[r] + 1];
+            pn.v[r] = load_plane(rp, off_ld[r]);
+            pn.y[r] = load_plane(ry, off_ld[r]);
         }
-        pn.hy = 0.f;
-        if ((dir & 4) && yhalo_lo) pn.hy = pl[(int64_t)(ybase - 1) * nx + x];
-        if ((dir & 8) && yhalo_hi) pn.hy = pl[(int64_t)(ybase + R) * nx + x];
+        const uint32_t oh = (dir & 4) ? off_hlo : ((dir & 8) ? off_hhi : kOOB);
+        pn.hy = load_plane(rp, oh);
     };
 
     Plane cur, nxt;
@@ -402,49 +423,75 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
             qn = a.qi[q + 1];
             load(q + 1, qn.dir, nxt);
         }
-        float* __restrict__ ol = a.psi_new + (size_t)q * P;
+        const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
+        float colsum = 0.f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int y = ybase + r;
             const float v = cur.v[r];
             float uy = 0.f;
             if (qc.dir & 4) uy = (r == 0) ? cur.hy : cur.v[r - 1];
             else if (qc.dir & 8) uy = (r == R - 1) ? cur.hy : cur.v[r + 1];
             float ux = 0.f;
-            if (qc.dir & 1) {
-                ux = __shfl_up(v, 1, 64);
-                if (lane == 0) ux = cur.hx[r];
-            } else if (qc.dir & 2) {
-                ux = __shfl_down(v, 1, 64);
-                if (lane == 63) ux = cur.hx[r];
-            }
-            const float yfix = cur.y[r] - fix[r];
-            const float col = gs[r] * (yfix - v) + bs[r] * (isov[r] - v);
+            if (qc.dir & 1) ux = __shfl_up(v, 1, 64);
+            else if (qc.dir & 2) ux = __shfl_down(v, 1, 64);
+            const float col = gs[r] * ((cur.y[r] - fix[r]) - v) + bs[r] * (isov[r] - v);
             const float nv = v - qc.cx * (v - ux) - qc.cy * (v - uy) - aa[r] * v + col + ss[r];
-            if (in[r]) {
-                ol[cidx[r]] = nv;
-                phacc[r] += qc.w * (double)nv;
-                defect += qc.w * (double)col;
-                if ((qc.dir & 1) && xlast) outflow += qc.w * ((double)qc.cx * (double)v);
-                if ((qc.dir & 2) && xfirst) outflow += qc.w * ((double)qc.cx * (double)v);
-                if ((qc.dir & 4) && y == ny - 1) outflow += qc.w * ((double)qc.cy * (double)v);
-                if ((qc.dir & 8) && y == 0) outflow += qc.w * ((double)qc.cy * (double)v);
-                if (LP) mx[r] = fmaxf(mx[r], fabsf(nv));
+            store_plane(nv, ro, off_st[r]);
+            phacc[r] += qc.w * (double)nv;
+            colsum += in[r] ? col : 0.f;
+            if (LP) mx[r] = fmaxf(mx[r], in[r] ? fabsf(nv) : 0.f);
+        }
+        defect += qc.w * (double)colsum;
+        if (edge) {
+            // Mass leaving through the boundary this step: the donor flux of the
+            // last cell before a boundary face, for the directions that exit there.
+            float o = 0.f;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!in[r]) continue;
+                const int y = ybase + r;
+                if (((qc.dir & 1) && x == nx - 1) || ((qc.dir & 2) && x == 0)) o += qc.cx * cur.v[r];
+                if (((qc.dir & 4) && y == ny - 1) || ((qc.dir & 8) && y == 0)) o += qc.cy * cur.v[r];
             }
+            outflow += qc.w * (double)o;
         }
         cur = nxt;
         qc = qn;
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (in[r]) {
-            a.phi_part[(size_t)g * P + cidx[r]] = phacc[r];
-            if (LP) atomicMax(&a.bmax_next[cidx[r] / kScaleBlock], __float_as_uint(mx[r]));
+    for (int r = 0; r < R; ++r)
+        if (in[r]) a.phi_part[(size_t)g * P + (uint32_t)((ybase + r) * nx + x)] = phacc[r];
+    if (LP) {
+        // The updating lanes of one row cover at most two 256-cell scale blocks.
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = ybase + r;
+            const int64_t c_first = (int64_t)y * nx + max(0, blockIdx.x * kStripX);
+            const int64_t b0 = c_first / kScaleBlock;
+            const int64_t cb = ((int64_t)y * nx + x) / kScaleBlock;
+            const unsigned bits = in[r] ? __float_as_uint(mx[r]) : 0u;
+            const unsigned m0 = wave_max_u32(cb == b0 ? bits : 0u);
+            const unsigned m1 = wave_max_u32(cb != b0 ? bits : 0u);
+            if (lane == 0 && y < ny) {
+                if (m0) atomicMax(&a.bmax_next[b0], m0);
+                if (m1) atomicMax(&a.bmax_next[b0 + 1], m1);
+            }
         }
     }
     double sums[2] = {defect, outflow};
     const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     block_sum_256<2>(sums, a.blk_part + 2 * (size_t)bid);
+}
+
+// Per-cell particle correction of the reduced-precision Y: the w-weighted sum of
+// Y over all ordinates (from the per-tile partials, fixed order) minus Phi, over W.
+__global__ __launch_bounds__(256) void particle_fix_kernel(StepArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= a.C) return;
+    double m = -a.phi64[c];
+    const int nparts = a.Qp / kGemmBM;
+    for (int t = 0; t < nparts; ++t) m += a.ypart[(size_t)t * a.P + c];
+    a.fix[c] = (float)(m / a.W);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +607,7 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t* ev) {
         gemm_lp_kernel<1><<<mtiles * ntiles, 256, 0, s>>>(a, mtiles);
     else
         gemm_lp_kernel<2><<<mtiles * ntiles, 256, 0, s>>>(a, mtiles);
+    if (a.dtype != 0) particle_fix_kernel<<<a.fin_blocks, 256, 0, s>>>(a);
     mark(1);
     dim3 sg(a.tiles_x, a.tiles_y, a.G);
     if (a.dtype == 0)

@@ -44,9 +44,10 @@ constexpr int kGemmBN = 128;
 constexpr int kBK_F32 = 16;
 constexpr int kBK_LP = 32;
 
-// Stencil tile: 64 cells along x (one wavefront) x 4 wavefronts x kRows rows each.
+// Stencil tile: a strip of 62 updated columns (one wavefront of 64 lanes, the two
+// outer lanes read the neighbouring columns) x 4 wavefronts x kRows rows each.
 constexpr int kRows = 4;
-constexpr int kTileX = 64;
+constexpr int kStripX = 62;
 constexpr int kTileY = 4 * kRows;
 
 struct StepArgs {
@@ -76,6 +77,7 @@ struct StepArgs {
     double* blk_part;       // stencil block partials [G * tiles][2]
     double* fin_part;       // finalize block partials [fin_blocks][2]
     double* ypart;          // [Qp / kGemmBM][P] weighted row sums of Y (reduced precision)
+    float* fix;             // [P] per-cell particle correction of the reduced-precision Y
     unsigned* bmax_cur;     // block max |psi^n| (read by the GEMM)
     unsigned* bmax_next;    // block max |psi^{n+1}| (written by the stencil)
     double* rec;

@@ -133,11 +133,32 @@ asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device);
  * Errors: ASN_E_INVALID (n_steps < 0), ASN_E_HIP. */
 asn_status asn_step(asn_problem p, int64_t n_steps);
 
-/* Advance n problems that share Q, quadrature, kernel width, normalisation and
- * operand type by n_steps each, with one fused launch per kernel per step on the
- * stream of probs[0].  Results equal asn_step on each problem alone.
- * Errors: ASN_E_INVALID (mismatched problems), ASN_E_HIP. */
+/* Advance n problems by n_steps each with one fused launch per kernel per step
+ * (asn_batch_create + asn_batch_step + asn_batch_destroy).  Results equal
+ * asn_step on each problem alone, bit for bit.
+ * Errors: those of asn_batch_create and asn_batch_step. */
 asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps);
+
+/* A batch groups 1..64 problems for fused stepping: every kernel of a step covers
+ * all of them in one launch.  Problems keep their own grid, ordinates, kernel
+ * matrix and buffers (ordinate counts may differ); they must share the operand
+ * type and the HIP stream.  The batch holds small device tables (hipMalloc).
+ * A problem may be stepped alone while in a batch; the batch reads each
+ * problem's current buffer at every asn_batch_step.  Errors: ASN_E_INVALID,
+ * ASN_E_OOM, ASN_E_HIP. */
+typedef struct asn_batch_s* asn_batch;
+asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out);
+
+/* Enqueue n_steps fused steps (asynchronous).  Problem i takes min(n_steps,
+ * limit[i]) of them and its blocks exit at once afterwards (limit may be NULL =
+ * all take n_steps), so problems with different horizons share the launches.
+ * On a non-null stream the sequence of n_steps steps is captured once into a HIP
+ * graph and replayed on later calls with the same n_steps.
+ * Errors: ASN_E_INVALID (n_steps < 0 or > 2^20), ASN_E_HIP. */
+asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit);
+
+/* Synchronise the batch's stream and free its tables and graphs.  NULL accepted. */
+asn_status asn_batch_destroy(asn_batch b);
 
 /* Run n_steps exactly like asn_step while recording HIP events on the problem's
  * stream between its kernels; synchronises.  kernel_ms[k] receives the average

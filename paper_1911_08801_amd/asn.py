@@ -83,6 +83,9 @@ _SIG = {
     "asn_step": [_P, ctypes.c_int64],
     "asn_step_batch": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int64],
     "asn_step_timed": [_P, ctypes.c_int64, _D],
+    "asn_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)],
+    "asn_batch_step": [_P, ctypes.c_int64, _I64],
+    "asn_batch_destroy": [_P],
     "asn_scalar_flux": [_P, _D],
     "asn_mass_budget": [_P, _D],
     "asn_info": [_P, _D, _I64, _I64, ctypes.POINTER(ctypes.c_int32)],
@@ -302,6 +305,46 @@ def asn_step_timed(p: AsnProblem, n_steps: int) -> dict:
 def asn_step_batch(probs, n_steps: int = 1) -> None:
     arr = (_P * len(probs))(*[p.handle for p in probs])
     _check(_lib.asn_step_batch(arr, len(probs), int(n_steps)), "asn_step_batch")
+
+
+class AsnBatch:
+    """Problems stepped together with fused launches (wraps an asn_batch handle)."""
+
+    def __init__(self, handle, probs):
+        self.handle = handle
+        self.probs = list(probs)          # keeps the problems alive
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self.handle is not None:
+            h, self.handle = self.handle, None
+            _check(_lib.asn_batch_destroy(h), "asn_batch_destroy")
+
+
+def asn_batch_create(probs) -> AsnBatch:
+    arr = (_P * len(probs))(*[p.handle for p in probs])
+    h = _P()
+    _check(_lib.asn_batch_create(arr, len(probs), ctypes.byref(h)), "asn_batch_create")
+    return AsnBatch(h, probs)
+
+
+def asn_batch_step(b: AsnBatch, n_steps: int, limits=None) -> None:
+    lim = None
+    if limits is not None:
+        lim_arr = np.ascontiguousarray(limits, dtype=np.int64)
+        if lim_arr.size != len(b.probs):
+            raise ValueError("one limit per problem")
+        lim = lim_arr.ctypes.data_as(_I64)
+    _check(_lib.asn_batch_step(b.handle, int(n_steps), lim), "asn_batch_step")
+
+
+def asn_batch_destroy(b: AsnBatch) -> None:
+    b.close()
 
 
 def asn_scalar_flux(p: AsnProblem) -> np.ndarray:

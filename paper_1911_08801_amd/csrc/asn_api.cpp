@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -41,6 +43,7 @@ struct Layout {
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_bmax0, off_bmax1, off_rec,
+        off_tab, off_off, off_base, off_left,
         total;
 };
 
@@ -93,6 +96,12 @@ Layout make_layout(int nx, int ny, int Q, int dtype) {
     L.off_bmax0 = take(plane / asn::kScaleBlock * 4);
     L.off_bmax1 = take(plane / asn::kScaleBlock * 4);
     L.off_rec = take(asn::REC_LEN * 8);
+    // the problem as a batch of one: step arguments for both buffers, block offsets,
+    // buffer base and step counter
+    L.off_tab = take(2 * sizeof(StepArgs));
+    L.off_off = take(asn::KT_COUNT * 2 * sizeof(int));
+    L.off_base = take(sizeof(int));
+    L.off_left = take(sizeof(int));
     L.total = off;
     return L;
 }
@@ -112,11 +121,25 @@ struct asn_problem_s {
     int cur = 0;  // which psi buffer holds the current state
     std::vector<double> w;
     double tile_entries = 0;  // K entries inside the multiplied tiles (real rows/cols)
+    StepArgs tab[2];          // step arguments when psi buffer 0 / 1 holds the state
+    int blocks[asn::KT_COUNT];
+};
+
+struct asn_batch_s {
+    std::vector<asn_problem> probs;
+    int n = 0, dtype = 0;
+    hipStream_t stream = nullptr;
+    std::vector<StepArgs> tab;
+    std::vector<int> off;
+    char* dev = nullptr;
+    asn::BatchArgs args{};
+    int grid[asn::KT_COUNT] = {0, 0, 0, 0, 0};
+    std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 namespace {
 
-StepArgs make_args(asn_problem p) {
+StepArgs make_args(asn_problem p, int cur) {
     const Layout& L = p->L;
     char* b = p->base;
     StepArgs a{};
@@ -136,8 +159,8 @@ StepArgs make_args(asn_problem p) {
     a.area = p->dx * p->dy;
     float* psi0 = reinterpret_cast<float*>(b + L.off_psi0);
     float* psi1 = reinterpret_cast<float*>(b + L.off_psi1);
-    a.psi = p->cur == 0 ? psi0 : psi1;
-    a.psi_new = p->cur == 0 ? psi1 : psi0;
+    a.psi = cur == 0 ? psi0 : psi1;
+    a.psi_new = cur == 0 ? psi1 : psi0;
     a.Y = reinterpret_cast<float*>(b + L.off_Y);
     a.Kt = reinterpret_cast<const float*>(b + L.off_Kt);
     a.Klp = reinterpret_cast<const uint16_t*>(b + L.off_Klp);
@@ -154,11 +177,57 @@ StepArgs make_args(asn_problem p) {
     a.fix = reinterpret_cast<float*>(b + L.off_fix);
     unsigned* bm0 = reinterpret_cast<unsigned*>(b + L.off_bmax0);
     unsigned* bm1 = reinterpret_cast<unsigned*>(b + L.off_bmax1);
-    const int parity = (int)(p->steps_done & 1);
-    a.bmax_cur = parity == 0 ? bm0 : bm1;
-    a.bmax_next = parity == 0 ? bm1 : bm0;
+    a.bmax_cur = cur == 0 ? bm0 : bm1;
+    a.bmax_next = cur == 0 ? bm1 : bm0;
     a.rec = reinterpret_cast<double*>(b + L.off_rec);
     return a;
+}
+
+// The problem as a batch of one (tables in its workspace).
+asn::BatchArgs single_batch(asn_problem p) {
+    const Layout& L = p->L;
+    asn::BatchArgs b{};
+    b.tab = reinterpret_cast<const StepArgs*>(p->base + L.off_tab);
+    b.off = reinterpret_cast<const int*>(p->base + L.off_off);
+    b.base = reinterpret_cast<const int*>(p->base + L.off_base);
+    b.steps_left = reinterpret_cast<int*>(p->base + L.off_left);
+    b.n = 1;
+    b.s_par = 0;
+    return b;
+}
+
+hipError_t arm_single(asn_problem p, int64_t limit) {
+    asn::ArmArgs v{};
+    v.limit[0] = (int)std::min<int64_t>(limit, 1 << 30);
+    v.cur[0] = p->cur;
+    const Layout& L = p->L;
+    return asn::launch_arm(reinterpret_cast<int*>(p->base + L.off_left),
+                           reinterpret_cast<int*>(p->base + L.off_base), 1, v, p->stream);
+}
+
+// K of a quadrature/width/normalisation, cached across problems (set-up is O(Q^2)
+// with a scaling loop; serving creates many problems with the same ordinates).
+bool cached_kernel(int Q, const std::vector<double>& om, const std::vector<double>& w, double eps,
+                   int mode, std::vector<double>& K, std::string& err) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::vector<double>, std::vector<double>>> cache;  // key, K
+    std::vector<double> key(om);
+    key.insert(key.end(), w.begin(), w.end());
+    key.push_back(eps);
+    key.push_back((double)mode);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto& e : cache)
+            if (e.first == key) {
+                K = e.second;
+                return true;
+            }
+    }
+    if (!asn::kernel_matrix(Q, om.data(), w.data(), eps, mode, K, err)) return false;
+    std::lock_guard<std::mutex> g(mu);
+    if (cache.size() >= 8) cache.erase(cache.begin());
+    cache.emplace_back(std::move(key), K);
+    return true;
 }
 
 asn_status check_grid(const asn_grid* g) {
@@ -321,7 +390,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     // kernel matrix
     std::vector<double> K;
     std::string err;
-    if (!asn::kernel_matrix(Q, om.data(), w.data(), p->eps, p->norm == ASN_NORM_SYM ? 0 : 1, K, err)) {
+    if (!cached_kernel(Q, om, w, p->eps, p->norm == ASN_NORM_SYM ? 0 : 1, K, err)) {
         delete p;
         return fail(ASN_E_UNSUPPORTED, err);
     }
@@ -423,8 +492,21 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         return bail(fail(ASN_E_HIP, "copying the problem tables to the device failed"));
     p->cur = 0;
     p->steps_done = 0;
-    StepArgs a = make_args(p);
-    if (asn::launch_init(a, p->stream) != hipSuccess)
+    p->tab[0] = make_args(p, 0);
+    p->tab[1] = make_args(p, 1);
+    asn::blocks_per_kind(p->tab[0], p->blocks);
+    int off1[asn::KT_COUNT * 2];
+    for (int k = 0; k < asn::KT_COUNT; ++k) {
+        off1[2 * k] = 0;
+        off1[2 * k + 1] = p->blocks[k];
+    }
+    if (hipMemcpyAsync(b + L.off_tab, p->tab, sizeof(p->tab), hipMemcpyHostToDevice, p->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(b + L.off_off, off1, sizeof(off1), hipMemcpyHostToDevice, p->stream) !=
+            hipSuccess)
+        return bail(fail(ASN_E_HIP, "copying the step tables to the device failed"));
+    if (arm_single(p, 1) != hipSuccess ||
+        asn::launch_init(p->tab[0], single_batch(p), p->stream) != hipSuccess)
         return bail(fail(ASN_E_HIP, "initial moment kernels failed to launch"));
     if (hipStreamSynchronize(p->stream) != hipSuccess)
         return bail(fail(ASN_E_HIP, "synchronising after set-up failed"));
@@ -434,8 +516,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
 
 static asn_status finish_set_state(asn_problem p) {
     p->steps_done = 0;
-    StepArgs a = make_args(p);
-    HIP_TRY(asn::launch_init(a, p->stream));
+    HIP_TRY(arm_single(p, 1));
+    HIP_TRY(asn::launch_init(p->tab[p->cur], single_batch(p), p->stream));
     return ASN_OK;
 }
 
@@ -475,19 +557,22 @@ asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
 
 asn_status asn_step(asn_problem p, int64_t n_steps) {
     if (!p) return fail(ASN_E_INVALID, "problem is NULL");
-    if (n_steps < 0) return fail(ASN_E_INVALID, "n_steps must be >= 0");
+    if (n_steps < 0 || n_steps > (1 << 30)) return fail(ASN_E_INVALID, "n_steps must be in [0, 2^30]");
+    if (n_steps == 0) return ASN_OK;
+    HIP_TRY(arm_single(p, n_steps));
+    asn::BatchArgs b = single_batch(p);
     for (int64_t i = 0; i < n_steps; ++i) {
-        StepArgs a = make_args(p);
-        HIP_TRY(asn::launch_step(a, p->stream));
-        p->cur ^= 1;
-        p->steps_done += 1;
+        b.s_par = (int)(i & 1);
+        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, p->stream));
     }
+    p->cur ^= (int)(n_steps & 1);
+    p->steps_done += n_steps;
     return ASN_OK;
 }
 
 asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     if (!p || !kernel_ms) return fail(ASN_E_INVALID, "NULL argument");
-    if (n_steps < 1) return fail(ASN_E_INVALID, "n_steps must be >= 1");
+    if (n_steps < 1 || n_steps > (1 << 20)) return fail(ASN_E_INVALID, "n_steps must be in [1, 2^20]");
     std::vector<hipEvent_t> ev((size_t)n_steps * 5, nullptr);
     asn_status st = ASN_OK;
     for (auto& e : ev)
@@ -495,15 +580,20 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
             st = fail(ASN_E_HIP, "hipEventCreate failed");
             break;
         }
+    if (st == ASN_OK && arm_single(p, n_steps) != hipSuccess)
+        st = fail(ASN_E_HIP, "arming the step counter failed");
+    asn::BatchArgs bt = single_batch(p);
     for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
-        StepArgs a = make_args(p);
-        const hipError_t e = asn::launch_step(a, p->stream, &ev[(size_t)i * 5]);
+        bt.s_par = (int)(i & 1);
+        const hipError_t e = asn::launch_step(bt, p->blocks, p->dtype, p->stream, &ev[(size_t)i * 5]);
         if (e != hipSuccess) {
             st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
             break;
         }
-        p->cur ^= 1;
-        p->steps_done += 1;
+    }
+    if (st == ASN_OK) {
+        p->cur ^= (int)(n_steps & 1);
+        p->steps_done += n_steps;
     }
     double acc[5] = {0, 0, 0, 0, 0};
     if (st == ASN_OK && hipEventSynchronize(ev.back()) != hipSuccess)
@@ -526,13 +616,136 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     return ASN_OK;
 }
 
-asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps) {
-    if (!probs || n < 0) return fail(ASN_E_INVALID, "invalid batch");
+asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
+    if (!out) return fail(ASN_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!probs || n < 1 || n > asn::kMaxArm)
+        return fail(ASN_E_INVALID, "a batch holds 1 to 64 problems");
     for (int32_t i = 0; i < n; ++i) {
-        asn_status s = asn_step(probs[i], n_steps);
-        if (s != ASN_OK) return s;
+        if (!probs[i]) return fail(ASN_E_INVALID, "NULL problem in batch");
+        if (probs[i]->dtype != probs[0]->dtype)
+            return fail(ASN_E_INVALID, "problems of a batch must share the operand type");
+        if (probs[i]->stream != probs[0]->stream)
+            return fail(ASN_E_INVALID, "problems of a batch must share the HIP stream");
+        for (int32_t j = 0; j < i; ++j)
+            if (probs[j] == probs[i]) return fail(ASN_E_INVALID, "a problem appears twice");
+    }
+    auto* b = new asn_batch_s();
+    b->probs.assign(probs, probs + n);
+    b->n = n;
+    b->dtype = probs[0]->dtype;
+    b->stream = probs[0]->stream;
+    b->tab.resize(2 * (size_t)n);
+    b->off.assign((size_t)asn::KT_COUNT * (n + 1), 0);
+    for (int32_t i = 0; i < n; ++i) {
+        b->tab[2 * i] = probs[i]->tab[0];
+        b->tab[2 * i + 1] = probs[i]->tab[1];
+        for (int k = 0; k < asn::KT_COUNT; ++k)
+            b->off[(size_t)k * (n + 1) + i + 1] = b->off[(size_t)k * (n + 1) + i] + probs[i]->blocks[k];
+    }
+    for (int k = 0; k < asn::KT_COUNT; ++k) b->grid[k] = b->off[(size_t)k * (n + 1) + n];
+    const size_t tab_b = b->tab.size() * sizeof(StepArgs);
+    const size_t off_b = b->off.size() * sizeof(int);
+    const size_t bytes = tab_b + off_b + 2 * asn::kMaxArm * sizeof(int);
+    void* m = nullptr;
+    if (hipMalloc(&m, bytes) != hipSuccess) {
+        delete b;
+        return fail(ASN_E_OOM, "hipMalloc of the batch tables failed");
+    }
+    b->dev = static_cast<char*>(m);
+    if (hipMemcpyAsync(b->dev, b->tab.data(), tab_b, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipMemcpyAsync(b->dev + tab_b, b->off.data(), off_b, hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        (void)hipFree(b->dev);
+        delete b;
+        return fail(ASN_E_HIP, "copying the batch tables failed");
+    }
+    b->args.tab = reinterpret_cast<const StepArgs*>(b->dev);
+    b->args.off = reinterpret_cast<const int*>(b->dev + tab_b);
+    b->args.base = reinterpret_cast<const int*>(b->dev + tab_b + off_b);
+    b->args.steps_left = reinterpret_cast<int*>(b->dev + tab_b + off_b + asn::kMaxArm * sizeof(int));
+    b->args.n = n;
+    b->args.s_par = 0;
+    *out = b;
+    return ASN_OK;
+}
+
+asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
+    if (!b) return fail(ASN_E_INVALID, "batch is NULL");
+    if (n_steps < 0 || n_steps > (1 << 20)) return fail(ASN_E_INVALID, "n_steps must be in [0, 2^20]");
+    asn::ArmArgs v{};
+    std::vector<int64_t> take(b->n);
+    bool any = false;
+    for (int i = 0; i < b->n; ++i) {
+        take[i] = limit ? std::max<int64_t>(0, std::min<int64_t>(limit[i], n_steps)) : n_steps;
+        v.limit[i] = (int)take[i];
+        v.cur[i] = b->probs[i]->cur;
+        any = any || take[i] > 0;
+    }
+    if (!any) return ASN_OK;
+    int* left = b->args.steps_left;
+    HIP_TRY(asn::launch_arm(left, const_cast<int*>(b->args.base), b->n, v, b->stream));
+    asn::BatchArgs args = b->args;
+    if (b->stream != nullptr && n_steps >= 2) {
+        // Capture the step sequence once per length; later calls replay it.
+        auto it = b->graphs.find(n_steps);
+        if (it == b->graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+            hipError_t e = hipSuccess;
+            for (int64_t j = 0; j < n_steps && e == hipSuccess; ++j) {
+                args.s_par = (int)(j & 1);
+                e = asn::launch_step(args, b->grid, b->dtype, b->stream);
+            }
+            const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(ASN_E_HIP, std::string("capturing the step graph failed: ") +
+                                           hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(ASN_E_HIP, "instantiating the step graph failed");
+            }
+            it = b->graphs.emplace(n_steps, std::make_pair(g, ge)).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second.second, b->stream));
+    } else {
+        for (int64_t j = 0; j < n_steps; ++j) {
+            args.s_par = (int)(j & 1);
+            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->stream));
+        }
+    }
+    for (int i = 0; i < b->n; ++i) {
+        b->probs[i]->cur ^= (int)(take[i] & 1);
+        b->probs[i]->steps_done += take[i];
     }
     return ASN_OK;
+}
+
+asn_status asn_batch_destroy(asn_batch b) {
+    if (!b) return ASN_OK;
+    asn_status st = ASN_OK;
+    if (hipStreamSynchronize(b->stream) != hipSuccess)
+        st = fail(ASN_E_HIP, "synchronising before destroying the batch failed");
+    for (auto& kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+    return st;
+}
+
+asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps) {
+    asn_batch b = nullptr;
+    asn_status s = asn_batch_create(probs, n, &b);
+    if (s != ASN_OK) return s;
+    s = asn_batch_step(b, n_steps, nullptr);
+    const asn_status s2 = asn_batch_destroy(b);
+    return s != ASN_OK ? s : s2;
 }
 
 asn_status asn_scalar_flux(asn_problem p, double* phi_host) {

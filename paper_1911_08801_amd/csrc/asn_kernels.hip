@@ -24,6 +24,25 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return xcd * per + (xcd < rem ? xcd : rem) + slot;
 }
 
+// Problem i and its local block for hardware block b of kernel kind `kind`;
+// false if that problem has no steps left in this batch.
+__device__ __forceinline__ bool locate(const BatchArgs& B, int kind, int b, int& i, int& local) {
+    const int* off = B.off + kind * (B.n + 1);
+    int lo = 0, hi = B.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    i = lo;
+    local = b - off[lo];
+    return B.steps_left[lo] > 0;
+}
+
+__device__ __forceinline__ const StepArgs& args_of(const BatchArgs& B, int i) {
+    return B.tab[2 * i + (B.base[i] ^ B.s_par)];
+}
+
 // ---------------------------------------------------------------------------
 // 1a. FP32 contraction Y[q][c] = sum_p K[q][p] psi[p][c] on MFMA 16x16x4 f32.
 //     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
@@ -32,14 +51,19 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 constexpr int kBK = kBK_F32;
 constexpr int kLdsPad = 16;
 
-__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ Kt,
-                                                       const float* __restrict__ psi,
-                                                       float* __restrict__ Y, int Q, int Qp,
-                                                       int64_t P, int mtiles,
-                                                       const int* __restrict__ ktab) {
+__global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
     __shared__ float As[2][kBK][kGemmBM + kLdsPad];
     __shared__ float Bs[2][kBK][kGemmBN + kLdsPad];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int pi, tile;
+    if (!locate(B, KT_GEMM, xcd_remap(blockIdx.x, gridDim.x), pi, tile)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const float* __restrict__ Kt = a.Kt;
+    const float* __restrict__ psi = a.psi;
+    float* __restrict__ Y = a.Y;
+    const int* __restrict__ ktab = a.ktab;
+    const int Q = a.Q, Qp = a.Qp;
+    const int64_t P = a.P;
+    const int mtiles = Qp / kGemmBM;
     const int mt = tile % mtiles;
     const int nt = tile / mtiles;
     const int m0 = mt * kGemmBM;
@@ -164,12 +188,15 @@ __device__ __forceinline__ f32x4 mfma_lp(const uint4& av, const uint4& bv, const
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void gemm_lp_kernel(StepArgs a, int mtiles) {
+__global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][kGemmBM][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bl[DT == 1 ? 2 : 1][DT == 1 ? kGemmBN : 1][kRowL];
     __shared__ double red[2][kGemmBN];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int pi, tile;
+    if (!locate(B, KT_GEMM, xcd_remap(blockIdx.x, gridDim.x), pi, tile)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int mtiles = a.Qp / kGemmBM;
     const int mt = tile % mtiles;
     const int nt = tile / mtiles;
     const int m0 = mt * kGemmBM;
@@ -354,14 +381,19 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 }
 
 template <bool LP>
-__global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
+__global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     constexpr int R = kRows;
+    int pi, local;
+    if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int bx = local % a.tiles_x;
+    const int by = (local / a.tiles_x) % a.tiles_y;
+    const int g = local / (a.tiles_x * a.tiles_y);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nx = a.nx, ny = a.ny;
     const int64_t P = a.P, C = a.C;
-    const int x = blockIdx.x * kStripX + lane - 1;
-    const int ybase = blockIdx.y * kTileY + wave * R;
-    const int g = blockIdx.z;
+    const int x = bx * kStripX + lane - 1;
+    const int ybase = by * kTileY + wave * R;
     const int q0 = g * a.qchunk;
     const int q1 = min(a.Q, q0 + a.qchunk);
     const bool xok = x >= 0 && x < nx;
@@ -395,8 +427,7 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
     const uint32_t off_hlo =
         (xok && ybase >= 1 && ybase - 1 < ny) ? 4u * (uint32_t)((ybase - 1) * nx + x) : kOOB;
     const uint32_t off_hhi = (xok && ybase + R < ny) ? 4u * (uint32_t)((ybase + R) * nx + x) : kOOB;
-    const bool edge = blockIdx.x == 0 || blockIdx.x == gridDim.x - 1 || blockIdx.y == 0 ||
-                      blockIdx.y == gridDim.y - 1;
+    const bool edge = bx == 0 || bx == a.tiles_x - 1 || by == 0 || by == a.tiles_y - 1;
     double defect = 0.0, outflow = 0.0;
 
     struct Plane {
@@ -466,7 +497,7 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = ybase + r;
-            const int64_t c_first = (int64_t)y * nx + max(0, blockIdx.x * kStripX);
+            const int64_t c_first = (int64_t)y * nx + bx * kStripX;
             const int64_t b0 = c_first / kScaleBlock;
             const int64_t cb = ((int64_t)y * nx + x) / kScaleBlock;
             const unsigned bits = in[r] ? __float_as_uint(mx[r]) : 0u;
@@ -479,14 +510,16 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(StepArgs a) {
         }
     }
     double sums[2] = {defect, outflow};
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    block_sum_256<2>(sums, a.blk_part + 2 * (size_t)bid);
+    block_sum_256<2>(sums, a.blk_part + 2 * (size_t)local);
 }
 
 // Per-cell particle correction of the reduced-precision Y: the w-weighted sum of
 // Y over all ordinates (from the per-tile partials, fixed order) minus Phi, over W.
-__global__ __launch_bounds__(256) void particle_fix_kernel(StepArgs a) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void particle_fix_kernel(BatchArgs B) {
+    int pi, local;
+    if (!locate(B, KT_FIX, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int64_t c = (int64_t)local * 256 + threadIdx.x;
     if (c >= a.C) return;
     double m = -a.phi64[c];
     const int nparts = a.Qp / kGemmBM;
@@ -497,8 +530,13 @@ __global__ __launch_bounds__(256) void particle_fix_kernel(StepArgs a) {
 // ---------------------------------------------------------------------------
 // 3. Finalize: Phi = sum of the G partials (fixed order), Phi/W, mass partials.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void finalize_kernel(StepArgs a, int G, unsigned* bmax_zero) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
+    int pi, local;
+    if (!locate(B, KT_FIN, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int G = init ? 1 : a.G;
+    unsigned* bmax_zero = init ? nullptr : a.bmax_cur;
+    const int64_t c = (int64_t)local * 256 + threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
     if (c < a.C) {
         double phi = 0.0;
@@ -511,13 +549,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(StepArgs a, int G, unsign
         s[2] = (double)cf.w;
     }
     if (bmax_zero != nullptr && c < a.P / kScaleBlock) bmax_zero[c] = 0u;
-    block_sum_256<3>(s, a.fin_part + 3 * (size_t)blockIdx.x);
+    block_sum_256<3>(s, a.fin_part + 3 * (size_t)local);
 }
 
 // ---------------------------------------------------------------------------
 // 4. Budget: fold block partials into the record (one block, fixed order).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void budget_kernel(StepArgs a, int n_blk, int init) {
+__global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int init) {
+    int pi, local;
+    if (!locate(B, KT_BUDGET, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int n_blk = a.tiles_x * a.tiles_y * a.G;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < a.fin_blocks; i += 256) {
         s[0] += a.fin_part[3 * (size_t)i + 0];
@@ -533,6 +575,7 @@ __global__ __launch_bounds__(256) void budget_kernel(StepArgs a, int n_blk, int 
     block_sum_256<5>(s, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
+    if (!init) B.steps_left[pi] -= 1;
     double* rec = a.rec;
     const double m_next = a.area * tot[0];
     const double abs_next = a.area * tot[1];
@@ -592,44 +635,63 @@ __global__ void broadcast_kernel(float* psi, const float* cell, int Q, int64_t C
 // ---------------------------------------------------------------------------
 static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t* ev) {
-    const int mtiles = a.Qp / kGemmBM;
-    const int ntiles = (int)(a.P / kGemmBN);
+void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
+    out[KT_GEMM] = (a.Qp / kGemmBM) * (int)(a.P / kGemmBN);
+    out[KT_FIX] = a.dtype != 0 ? a.fin_blocks : 0;
+    out[KT_SC] = a.tiles_x * a.tiles_y * a.G;
+    out[KT_FIN] = a.fin_blocks;
+    out[KT_BUDGET] = 1;
+}
+
+hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, hipStream_t s,
+                       hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
     mark(0);
-    if (a.dtype == 0)
-        gemm_f32_kernel<<<mtiles * ntiles, 256, 0, s>>>(a.Kt, a.psi, a.Y, a.Q, a.Qp, a.P, mtiles,
-                                                         a.ktab);
-    else if (a.dtype == 1)
-        gemm_lp_kernel<1><<<mtiles * ntiles, 256, 0, s>>>(a, mtiles);
+    if (dtype == 0)
+        gemm_f32_kernel<<<grid[KT_GEMM], 256, 0, s>>>(b);
+    else if (dtype == 1)
+        gemm_lp_kernel<1><<<grid[KT_GEMM], 256, 0, s>>>(b);
     else
-        gemm_lp_kernel<2><<<mtiles * ntiles, 256, 0, s>>>(a, mtiles);
-    if (a.dtype != 0) particle_fix_kernel<<<a.fin_blocks, 256, 0, s>>>(a);
+        gemm_lp_kernel<2><<<grid[KT_GEMM], 256, 0, s>>>(b);
+    if (dtype != 0) particle_fix_kernel<<<grid[KT_FIX], 256, 0, s>>>(b);
     mark(1);
-    dim3 sg(a.tiles_x, a.tiles_y, a.G);
-    if (a.dtype == 0)
-        stream_collide_kernel<false><<<sg, 256, 0, s>>>(a);
+    if (dtype == 0)
+        stream_collide_kernel<false><<<grid[KT_SC], 256, 0, s>>>(b);
     else
-        stream_collide_kernel<true><<<sg, 256, 0, s>>>(a);
+        stream_collide_kernel<true><<<grid[KT_SC], 256, 0, s>>>(b);
     mark(2);
-    finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(a, a.G, a.bmax_cur);
+    finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
     mark(3);
-    budget_kernel<<<1, 256, 0, s>>>(a, a.tiles_x * a.tiles_y * a.G, 0);
+    budget_kernel<<<grid[KT_BUDGET], 256, 0, s>>>(b, 0);
     mark(4);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-hipError_t launch_init(const StepArgs& a, hipStream_t s) {
+__global__ void arm_kernel(int* steps_left, int* base, int n, ArmArgs v) {
+    const int i = threadIdx.x;
+    if (i < n) {
+        steps_left[i] = v.limit[i];
+        base[i] = v.cur[i];
+    }
+}
+
+hipError_t launch_arm(int* steps_left, int* base, int n, const ArmArgs& v, hipStream_t s) {
+    if (n < 1 || n > kMaxArm) return hipErrorInvalidValue;
+    arm_kernel<<<1, kMaxArm, 0, s>>>(steps_left, base, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s) {
     const int64_t nb = a.P / kScaleBlock;
     fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_cur, nb, 0u);
     fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_next, nb, 0u);
     moments_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);
-    finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(a, 1, nullptr);
-    budget_kernel<<<1, 256, 0, s>>>(a, 0, 1);
+    finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(one, 1);
+    budget_kernel<<<1, 256, 0, s>>>(one, 1);
     return hipGetLastError();
 }
 

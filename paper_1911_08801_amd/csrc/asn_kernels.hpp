@@ -78,16 +78,48 @@ struct StepArgs {
     double* fin_part;       // finalize block partials [fin_blocks][2]
     double* ypart;          // [Qp / kGemmBM][P] weighted row sums of Y (reduced precision)
     float* fix;             // [P] per-cell particle correction of the reduced-precision Y
-    unsigned* bmax_cur;     // block max |psi^n| (read by the GEMM)
+    unsigned* bmax_cur;     // block max |psi^n| (read by the GEMM), follows the psi buffer
     unsigned* bmax_next;    // block max |psi^{n+1}| (written by the stencil)
     double* rec;
 };
 
-// One explicit step: contraction, stream + collide, moments, budget.  If ev is
-// given, ev[0..4] are recorded before, between and after the four kernels.
-hipError_t launch_step(const StepArgs& a, hipStream_t s, hipEvent_t* ev = nullptr);
-// Moments of the current state (after set_state): phi64, iso, bmax_cur, budget record.
-hipError_t launch_init(const StepArgs& a, hipStream_t s);
+// Kernel kinds of one step, each with its own block decomposition.
+enum { KT_GEMM = 0, KT_FIX = 1, KT_SC = 2, KT_FIN = 3, KT_BUDGET = 4, KT_COUNT = 5 };
+
+// Launch view of a batch of problems that share Q, K and the operand type.
+// Every kernel covers all problems in one launch: block b of kernel kind k
+// belongs to problem i with off[k * (n + 1) + i] <= b < off[k * (n + 1) + i + 1].
+// tab[2 i + c] are the step arguments of problem i when psi buffer c holds its
+// current state; at batch step s problem i uses c = base[i] ^ s_par.  A problem
+// whose steps_left[i] is not positive is skipped (its blocks exit at once); the
+// budget kernel decrements steps_left[i] after each step.  A single problem is a
+// batch of one, so a problem computes bitwise the same alone and in a batch.
+struct BatchArgs {
+    const StepArgs* tab;
+    const int* off;
+    const int* base;
+    int* steps_left;
+    int n;
+    int s_par;
+};
+
+// Blocks of each kernel kind for one problem.
+void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]);
+
+// One step for every problem of the batch; if ev is given, ev[0..4] are recorded
+// before, between and after the four stages (contraction, stream + collide,
+// finalize, budget).
+hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, hipStream_t s,
+                       hipEvent_t* ev = nullptr);
+// Arm a batch: steps_left[i] = limit[i] and base[i] = cur[i], i < n <= kMaxArm.
+constexpr int kMaxArm = 64;
+struct ArmArgs {
+    int limit[kMaxArm];
+    int cur[kMaxArm];
+};
+hipError_t launch_arm(int* steps_left, int* base, int n, const ArmArgs& v, hipStream_t s);
+// Moments of the current state (after set_state): phi64, iso, bmax, budget record.
+hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s);
 // psi[q][c] = cell[c] for all q (pitch P), zero padding.
 hipError_t launch_broadcast(float* psi, const float* cell, int Q, int64_t C, int64_t P,
                             hipStream_t s);

@@ -1,0 +1,89 @@
+"""Fused multi-problem stepping: every problem computes bitwise the same result
+alone and inside a batch, with eager launches and with replayed HIP graphs."""
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1911_08801_amd import asn  # noqa: E402
+
+
+def _specs():
+    return [wl.line_source(37, n_polar=4, sigma_as=2.0, t_final=0.3),
+            wl.checkerboard(70, n_polar=2, sigma_as=4.0, t_final=0.5),
+            wl.random_problem(3, 90, 41, n_polar=8, n_azim=16, beta=4.5),
+            wl.line_source(64, n_polar=4, sigma_as=0.0, t_final=0.2)]
+
+
+def _alone(spec, n, dtype):
+    p = asn.from_spec(spec, dtype=dtype)
+    asn.asn_step(p, n)
+    out = (asn.asn_get_state(p), asn.asn_scalar_flux(p), asn.asn_mass_budget(p))
+    p.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("side_stream", [False, True])
+def test_batch_equals_alone_bitwise(dtype, side_stream):
+    specs = _specs()
+    limits = [9, 5, 12, 7]
+    alone = [_alone(s, n, dtype) for s, n in zip(specs, limits)]
+    stream = torch.cuda.Stream() if side_stream else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        probs = [asn.from_spec(s, dtype=dtype) for s in specs]
+        b = asn.asn_batch_create(probs)
+        for k in range(3):                       # 3 chunks of 4 steps (graph replays)
+            asn.asn_batch_step(b, 4, limits=[max(0, l - 4 * k) for l in limits])
+            torch.zeros(16, device="cuda").add_(1.0)     # unrelated eager work between replays
+        b.close()
+        for p, a, n in zip(probs, alone, limits):
+            assert asn.asn_info(p)["steps_done"] == n
+            st, phi, bud = asn.asn_get_state(p), asn.asn_scalar_flux(p), asn.asn_mass_budget(p)
+            assert np.array_equal(st, a[0]) and np.array_equal(phi, a[1]) and bud == a[2]
+            p.close()
+    torch.cuda.synchronize()
+
+
+def test_batch_rejects_mixed_operand_types_and_duplicates():
+    s = _specs()[0]
+    p1 = asn.from_spec(s, dtype="f32")
+    p2 = asn.from_spec(s, dtype="bf16")
+    with pytest.raises(asn.AsnError):
+        asn.asn_batch_create([p1, p2])
+    with pytest.raises(asn.AsnError):
+        asn.asn_batch_create([p1, p1])
+    p1.close()
+    p2.close()
+
+
+def test_step_batch_one_shot_matches_alone():
+    specs = _specs()[:2]
+    alone = [_alone(s, 6, "f32") for s in specs]
+    probs = [asn.from_spec(s) for s in specs]
+    asn.asn_step_batch(probs, 6)
+    for p, a in zip(probs, alone):
+        assert np.array_equal(asn.asn_get_state(p), a[0])
+        p.close()
+
+
+def test_problem_can_step_alone_between_batch_steps():
+    specs = _specs()[:3]
+    alone = [_alone(s, 7, "f32") for s in specs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        probs = [asn.from_spec(s) for s in specs]
+        b = asn.asn_batch_create(probs)
+        asn.asn_batch_step(b, 2)
+        asn.asn_step(probs[1], 3)                # odd number of solo steps flips its buffer
+        asn.asn_batch_step(b, 2, limits=[2, 0, 2])
+        asn.asn_batch_step(b, 3, limits=[3, 2, 3])
+        b.close()
+        for p, a in zip(probs, alone):
+            assert np.array_equal(asn.asn_get_state(p), a[0])
+            p.close()

@@ -37,6 +37,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-nmax", type=int, default=256)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load as a fraction of the measured batch capacity")
     return ap.parse_args()
 
 
@@ -116,6 +121,47 @@ def summary(res, spec, steps):
             "budget_max_residual": res["budget"]["max_residual"]}
 
 
+def serving_run(args):
+    """Seeded Poisson request stream through the continuous-batching server.
+
+    Requests: line source or lattice (p = 1/2), N x N cells with N uniform in
+    [64, serve_nmax], polar order in {8, 12, 16, 24} (2x azimuths), sigma_as in
+    [0, 5], t_final in [0.5, 3.2]; FP32 contraction.  The arrival rate offers
+    `serve_load` times the throughput the same server reaches when all requests
+    are queued at once (measured first, on the first 16 requests).
+    """
+    import numpy as np
+
+    import workloads as wl
+    from paper_1911_08801_amd import asn
+    from paper_1911_08801_amd.serve import GpuBackend, Job, Server
+
+    def updates(r):
+        spec = r.problem()
+        om, _ = asn.asn_build_quadrature(spec.n_polar, spec.n_azim)
+        g = asn.make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
+        _, n = asn.asn_time_step(g, om, spec.cfl, spec.t_final)
+        return spec.cells * spec.q * n
+
+    base = wl.serving_requests(0, args.serve_requests, rate=0.0, n_range=(64, args.serve_nmax))
+    mean_upd = float(np.mean([updates(r) for r in base]))
+    backend = GpuBackend()
+    # capacity: a burst of 16 requests all present at t = 0
+    burst = [Job(rid=r.rid, spec=r.problem(), arrival=0.0) for r in base[:16]]
+    cap = Server(backend, chunk=16).serve(burst).summary()["aggregate_updates_per_s"]
+    rate = args.serve_load * cap / mean_upd
+    reqs = wl.serving_requests(0, args.serve_requests, rate=rate, n_range=(64, args.serve_nmax))
+    rep = Server(backend, chunk=16).serve([Job(rid=r.rid, spec=r.problem(), arrival=r.arrival)
+                                           for r in reqs])
+    out = rep.summary()
+    out.update({"arrival_rate_per_s": rate, "burst_capacity_updates_per_s": cap,
+                "mean_updates_per_request": mean_upd,
+                "workload": f"{args.serve_requests} seeded requests (seed 0), N in [64, "
+                            f"{args.serve_nmax}], Q in {{128, 288, 512, 1152}}, FP32, Poisson "
+                            f"arrivals at {args.serve_load} x measured capacity"})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -149,6 +195,8 @@ def main():
             r = timed_run(asn, spec, dt, args.steps, args.warmup)
             out[dt] = summary(r, spec, args.steps)
             out[dt]["roofline"] = roofline(r, spec, dt)
+    if not args.no_serving:
+        out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -166,10 +166,11 @@ def serving_requests(seed: int = 0, count: int = 512, rate: float = 10.0,
                      sigma_as_range=(0.0, 5.0), t_range=(0.5, 3.2)) -> List[Request]:
     """Seeded request stream: uniform kinds/sizes/orders/strengths, Poisson arrivals."""
     rng = np.random.default_rng(seed)
+    arrivals = np.random.default_rng([seed, 1])     # separate stream: same requests at any rate
     reqs = []
     t = 0.0
     for rid in range(count):
-        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        t += arrivals.exponential(1.0 / rate) if rate > 0 else 0.0
         kind = "line" if rng.random() < 0.5 else "checker"
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         n_p = int(polar_orders[int(rng.integers(0, len(polar_orders)))])

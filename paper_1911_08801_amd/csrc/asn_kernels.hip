@@ -14,6 +14,19 @@ namespace asn {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Buffers are reached through pointers stored in the device argument table, which
+// carry no address space; qualifying them as global keeps loads and stores on the
+// global path (flat accesses would also tie up the LDS counter).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ASN_G __attribute__((address_space(1)))
+#else
+#define ASN_G
+#endif
+template <typename T>
+__device__ __forceinline__ ASN_G T* gp(T* p) {
+    return (ASN_G T*)p;
+}
+
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs.  Map the
 // hardware block id to a logical tile id so that logical neighbours share an
 // XCD (and its L2): XCD x receives logical ids [start_x, start_x + count_x).
@@ -27,7 +40,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 // Problem i and its local block for hardware block b of kernel kind `kind`;
 // false if that problem has no steps left in this batch.
 __device__ __forceinline__ bool locate(const BatchArgs& B, int kind, int b, int& i, int& local) {
-    const int* off = B.off + kind * (B.n + 1);
+    const ASN_G int* off = gp(B.off) + kind * (B.n + 1);
     int lo = 0, hi = B.n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -36,11 +49,11 @@ __device__ __forceinline__ bool locate(const BatchArgs& B, int kind, int b, int&
     }
     i = lo;
     local = b - off[lo];
-    return B.steps_left[lo] > 0;
+    return gp(B.steps_left)[lo] > 0;
 }
 
-__device__ __forceinline__ const StepArgs& args_of(const BatchArgs& B, int i) {
-    return B.tab[2 * i + (B.base[i] ^ B.s_par)];
+__device__ __forceinline__ StepArgs args_of(const BatchArgs& B, int i) {
+    return gp(B.tab)[2 * i + (gp(B.base)[i] ^ B.s_par)];
 }
 
 // ---------------------------------------------------------------------------
@@ -57,10 +70,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
     int pi, tile;
     if (!locate(B, KT_GEMM, xcd_remap(blockIdx.x, gridDim.x), pi, tile)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
-    const float* __restrict__ Kt = a.Kt;
-    const float* __restrict__ psi = a.psi;
-    float* __restrict__ Y = a.Y;
-    const int* __restrict__ ktab = a.ktab;
+    const ASN_G float* __restrict__ Kt = gp(a.Kt);
+    const ASN_G float* __restrict__ psi = gp(a.psi);
+    ASN_G float* __restrict__ Y = gp(a.Y);
+    const ASN_G int* __restrict__ ktab = gp(a.ktab);
     const int Q = a.Q, Qp = a.Qp;
     const int64_t P = a.P;
     const int mtiles = Qp / kGemmBM;
@@ -71,25 +84,28 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
 
-    float4 ra[2], rb[2];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int idx = tid + s * 256, kk = idx >> 5, c4 = (idx & 31) << 2;
-            const int k = k0 + kk;
-            ra[s] = *reinterpret_cast<const float4*>(Kt + (size_t)k * Qp + m0 + c4);
-            rb[s] = (k < Q) ? *reinterpret_cast<const float4*>(psi + (size_t)k * P + n0 + c4)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    };
-    auto lstore = [&](int b) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int idx = tid + s * 256, kk = idx >> 5, c4 = (idx & 31) << 2;
-            *reinterpret_cast<float4*>(&As[b][kk][c4]) = ra[s];
-            *reinterpret_cast<float4*>(&Bs[b][kk][c4]) = rb[s];
-        }
-    };
+    // Staging of one k-step (16 ordinates): thread t moves float4 number t and t + 256 of
+    // the A tile (Kt rows) and of the B tile (psi rows); rows >= Q of psi read as zero.
+    const int kk0 = tid >> 5, kk1 = kk0 + 8, c4 = (tid & 31) << 2;
+    float4 ra0, ra1, rb0, rb1;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#define ASN_GLOAD(k0)                                                                          \
+    do {                                                                                       \
+        const int ka = (k0) + kk0, kb = (k0) + kk1;                                            \
+        ra0 = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)ka * Qp + m0 + c4);          \
+        ra1 = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)kb * Qp + m0 + c4);          \
+        rb0 = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(ka, Q - 1) * P + n0 + c4); \
+        rb1 = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(kb, Q - 1) * P + n0 + c4); \
+        if (ka >= Q) rb0 = zero4;                                                              \
+        if (kb >= Q) rb1 = zero4;                                                              \
+    } while (0)
+#define ASN_LSTORE(b)                                                                          \
+    do {                                                                                       \
+        *reinterpret_cast<float4*>(&As[b][kk0][c4]) = ra0;                                     \
+        *reinterpret_cast<float4*>(&As[b][kk1][c4]) = ra1;                                     \
+        *reinterpret_cast<float4*>(&Bs[b][kk0][c4]) = rb0;                                     \
+        *reinterpret_cast<float4*>(&Bs[b][kk1][c4]) = rb1;                                     \
+    } while (0)
 
     f32x4 acc[4][4];
 #pragma unroll
@@ -98,16 +114,16 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // Only k-steps whose K tile has a nonzero entry (the skipped products are +0).
-    const int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
+    const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
     const int nkt = ktab[mt + 1] - ktab[mt];
     if (nkt > 0) {
-        gload(klist[0] * kBK);
-        lstore(0);
+        ASN_GLOAD(klist[0] * kBK);
+        ASN_LSTORE(0);
     }
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        if (kt + 1 < nkt) gload(klist[kt + 1] * kBK);
+        if (kt + 1 < nkt) ASN_GLOAD(klist[kt + 1] * kBK);
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             float av[4], bv[4];
@@ -122,9 +138,11 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < nkt) lstore(b ^ 1);
+        if (kt + 1 < nkt) ASN_LSTORE(b ^ 1);
         __syncthreads();
     }
+#undef ASN_GLOAD
+#undef ASN_LSTORE
     // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16.
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -196,6 +214,14 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
     int pi, tile;
     if (!locate(B, KT_GEMM, xcd_remap(blockIdx.x, gridDim.x), pi, tile)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const ASN_G uint16_t* __restrict__ Klp = gp(a.Klp);
+    const ASN_G float* __restrict__ psi = gp(a.psi);
+    const ASN_G float* __restrict__ iso = gp(a.iso);
+    const ASN_G float* __restrict__ rdef = gp(a.rdef);
+    const ASN_G QInfo* __restrict__ qinfo = gp(a.qi);
+    const ASN_G int* __restrict__ ktab = gp(a.ktab);
+    ASN_G float* __restrict__ Yo = gp(a.Y);
+    ASN_G double* __restrict__ ypart = gp(a.ypart);
     const int mtiles = a.Qp / kGemmBM;
     const int mt = tile % mtiles;
     const int nt = tile / mtiles;
@@ -206,7 +232,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
     const int Q = a.Q, Qp = a.Qp;
     const int64_t P = a.P;
 
-    const float bm = __uint_as_float(a.bmax_cur[n0 / kScaleBlock]);
+    const float bm = __uint_as_float(gp(a.bmax_cur)[n0 / kScaleBlock]);
     int e = 0;
     if (bm > 0.f) (void)frexpf(bm, &e);
     e = max(e, -100);
@@ -215,18 +241,18 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
 
     // B loader: cell nb of the tile, k-groups kg and kg + 2 (8 ordinates each).
     const int nb = tid & 127, kg0 = tid >> 7;
-    const float iso_b = a.iso[n0 + nb];
+    const float iso_b = iso[n0 + nb];
     uint4 ra[2];
     float rb[2][8];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int idx = tid + s * 256, row = idx >> 2, kq = (idx & 3) * 8;
-            ra[s] = *reinterpret_cast<const uint4*>(a.Klp + (size_t)(m0 + row) * Qp + k0 + kq);
+            ra[s] = *reinterpret_cast<const ASN_G uint4*>(Klp + (size_t)(m0 + row) * Qp + k0 + kq);
             const int kb = k0 + (kg0 + 2 * s) * 8;
 #pragma unroll
             for (int i = 0; i < 8; ++i)
-                rb[s][i] = (kb + i < Q) ? a.psi[(size_t)(kb + i) * P + n0 + nb] : 0.f;
+                rb[s][i] = (kb + i < Q) ? psi[(size_t)(kb + i) * P + n0 + nb] : 0.f;
         }
     };
     auto lstore = [&](int b) {
@@ -261,8 +287,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int* __restrict__ klist = a.ktab + (mtiles + 1) + a.ktab[mt];
-    const int nkt = a.ktab[mt + 1] - a.ktab[mt];
+    const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
+    const int nkt = ktab[mt + 1] - ktab[mt];
     if (nkt > 0) {
         gload(klist[0] * kBKL);
         lstore(0);
@@ -298,17 +324,17 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t n = n0 + wn + j * 16 + (lane & 15);
-        const float iso_n = a.iso[n];
+        const float iso_n = iso[n];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
                 if (m < Q) {
-                    const float dev = a.psi[(size_t)m * P + n] - iso_n;
-                    const float y = iso_n + s_out * acc[i][j][v] + a.rdef[m] * dev;
-                    a.Y[(size_t)m * P + n] = y;
-                    part[j] += a.qi[m].w * (double)y;
+                    const float dev = psi[(size_t)m * P + n] - iso_n;
+                    const float y = iso_n + s_out * acc[i][j][v] + rdef[m] * dev;
+                    Yo[(size_t)m * P + n] = y;
+                    part[j] += qinfo[m].w * (double)y;
                 }
             }
         part[j] += __shfl_xor(part[j], 16, 64);
@@ -316,7 +342,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
         if (lane < 16) red[wave & 1][wn + j * 16 + lane] = part[j];
     }
     __syncthreads();
-    if (tid < kGemmBN) a.ypart[(size_t)mt * P + n0 + tid] = red[0][tid] + red[1][tid];
+    if (tid < kGemmBN) ypart[(size_t)mt * P + n0 + tid] = red[0][tid] + red[1][tid];
 }
 
 // ---------------------------------------------------------------------------
@@ -328,8 +354,8 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <int NV>
-__device__ __forceinline__ void block_sum_256(double (&v)[NV], double* out) {
+template <int NV, typename OutPtr>
+__device__ __forceinline__ void block_sum_256(double (&v)[NV], OutPtr out) {
     __shared__ double red[4][NV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -415,13 +441,13 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
         mx[r] = 0.f;
         phacc[r] = 0.0;
         if (in[r]) {
-            const float4 cf = a.coef[c];
+            const float4 cf = gp(a.coef)[c];
             aa[r] = cf.x;
             bs[r] = cf.y;
             gs[r] = cf.z;
             ss[r] = cf.w;
-            isov[r] = a.iso[c];
-            if (LP) fix[r] = a.fix[c];
+            isov[r] = gp(a.iso)[c];
+            if (LP) fix[r] = gp(a.fix)[c];
         }
     }
     const uint32_t off_hlo =
@@ -446,12 +472,13 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     };
 
     Plane cur, nxt;
-    QInfo qc = a.qi[q0 < q1 ? q0 : 0];
+    const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    QInfo qc = qtab[q0 < q1 ? q0 : 0];
     if (q0 < q1) load(q0, qc.dir, cur);
     for (int q = q0; q < q1; ++q) {
         QInfo qn = qc;
         if (q + 1 < q1) {
-            qn = a.qi[q + 1];
+            qn = qtab[q + 1];
             load(q + 1, qn.dir, nxt);
         }
         const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
@@ -491,7 +518,7 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        if (in[r]) a.phi_part[(size_t)g * P + (uint32_t)((ybase + r) * nx + x)] = phacc[r];
+        if (in[r]) gp(a.phi_part)[(size_t)g * P + (uint32_t)((ybase + r) * nx + x)] = phacc[r];
     if (LP) {
         // The updating lanes of one row cover at most two 256-cell scale blocks.
 #pragma unroll
@@ -510,7 +537,7 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
         }
     }
     double sums[2] = {defect, outflow};
-    block_sum_256<2>(sums, a.blk_part + 2 * (size_t)local);
+    block_sum_256<2>(sums, gp(a.blk_part) + 2 * (size_t)local);
 }
 
 // Per-cell particle correction of the reduced-precision Y: the w-weighted sum of
@@ -521,10 +548,11 @@ __global__ __launch_bounds__(256) void particle_fix_kernel(BatchArgs B) {
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const int64_t c = (int64_t)local * 256 + threadIdx.x;
     if (c >= a.C) return;
-    double m = -a.phi64[c];
+    double m = -gp(a.phi64)[c];
     const int nparts = a.Qp / kGemmBM;
-    for (int t = 0; t < nparts; ++t) m += a.ypart[(size_t)t * a.P + c];
-    a.fix[c] = (float)(m / a.W);
+    const ASN_G double* yp = gp(a.ypart);
+    for (int t = 0; t < nparts; ++t) m += yp[(size_t)t * a.P + c];
+    gp(a.fix)[c] = (float)(m / a.W);
 }
 
 // ---------------------------------------------------------------------------
@@ -535,21 +563,22 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
     if (!locate(B, KT_FIN, blockIdx.x, pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const int G = init ? 1 : a.G;
-    unsigned* bmax_zero = init ? nullptr : a.bmax_cur;
+    ASN_G unsigned* bmax_zero = init ? nullptr : gp(a.bmax_cur);
     const int64_t c = (int64_t)local * 256 + threadIdx.x;
     double s[3] = {0.0, 0.0, 0.0};
     if (c < a.C) {
         double phi = 0.0;
-        for (int g = 0; g < G; ++g) phi += a.phi_part[(size_t)g * a.P + c];
-        a.phi64[c] = phi;
-        a.iso[c] = (float)(phi / a.W);
-        const float4 cf = a.coef[c];
+        const ASN_G double* pp = gp(a.phi_part);
+        for (int g = 0; g < G; ++g) phi += pp[(size_t)g * a.P + c];
+        gp(a.phi64)[c] = phi;
+        gp(a.iso)[c] = (float)(phi / a.W);
+        const float4 cf = gp(a.coef)[c];
         s[0] = phi;
         s[1] = (double)cf.x * phi;
         s[2] = (double)cf.w;
     }
     if (bmax_zero != nullptr && c < a.P / kScaleBlock) bmax_zero[c] = 0u;
-    block_sum_256<3>(s, a.fin_part + 3 * (size_t)local);
+    block_sum_256<3>(s, gp(a.fin_part) + 3 * (size_t)local);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,22 +590,24 @@ __global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int init) {
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const int n_blk = a.tiles_x * a.tiles_y * a.G;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const ASN_G double* fp = gp(a.fin_part);
+    const ASN_G double* bp = gp(a.blk_part);
     for (int i = threadIdx.x; i < a.fin_blocks; i += 256) {
-        s[0] += a.fin_part[3 * (size_t)i + 0];
-        s[1] += a.fin_part[3 * (size_t)i + 1];
-        s[2] += a.fin_part[3 * (size_t)i + 2];
+        s[0] += fp[3 * (size_t)i + 0];
+        s[1] += fp[3 * (size_t)i + 1];
+        s[2] += fp[3 * (size_t)i + 2];
     }
     if (!init)
         for (int i = threadIdx.x; i < n_blk; i += 256) {
-            s[3] += a.blk_part[2 * (size_t)i + 0];
-            s[4] += a.blk_part[2 * (size_t)i + 1];
+            s[3] += bp[2 * (size_t)i + 0];
+            s[4] += bp[2 * (size_t)i + 1];
         }
     __shared__ double tot[5];
     block_sum_256<5>(s, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
-    if (!init) B.steps_left[pi] -= 1;
-    double* rec = a.rec;
+    if (!init) gp(B.steps_left)[pi] -= 1;
+    ASN_G double* rec = gp(a.rec);
     const double m_next = a.area * tot[0];
     const double abs_next = a.area * tot[1];
     if (init) {

@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--sweep", choices=["lattice700", "line1024"], default=None,
+                    help="precision sweep to t_final on a configured workload (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) so "
                          "hardware byte counters can be scaled against known traffic")
@@ -188,8 +190,53 @@ def serving_run(args):
     return out
 
 
+def precision_sweep(name):
+    """Full runs to t_final with FP32, BF16 and FP16 contractions on one workload;
+    updates/s per form and each reduced form's scalar-flux error against FP32."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1911_08801_amd import asn
+    if name == "lattice700":
+        spec = wl.checkerboard(700, n_polar=24, sigma_as=5.0)
+        forms = ("f32", "bf16")
+    else:
+        spec = wl.line_source(1024, n_polar=32, sigma_as=5.0)
+        forms = ("f32", "bf16", "f16")
+    out = {"workload": spec.name, "cells": spec.cells, "ordinates": spec.q, "forms": {}}
+    ref = None
+    for dt in forms:
+        p = asn.from_spec(spec, dtype=dt)
+        n = asn.asn_info(p)["steps_to_tfinal"]
+        work = asn.asn_contraction_work(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        asn.asn_step(p, n)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phi = asn.asn_scalar_flux(p)
+        bud = asn.asn_mass_budget(p)
+        p.close()
+        rec = {"steps": n, "seconds": wall, "updates_per_s": spec.cells * spec.q * n / wall,
+               "tile_flops_per_step": work["tile_flops"], "budget_max_residual": bud["max_residual"],
+               "defect_over_mass": bud["defect"] / max(bud["mass"], bud["mass0"], 1e-300)}
+        if ref is None:
+            ref = phi
+        else:
+            rec["phi_rel_l2_vs_f32"] = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+        out["forms"][dt] = rec
+        print(f"# {name} {dt}: {rec}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
+    if args.sweep:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"sweep": precision_sweep(args.sweep)}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

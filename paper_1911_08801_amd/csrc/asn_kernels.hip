@@ -206,7 +206,7 @@ __device__ __forceinline__ f32x4 mfma_lp(const uint4& av, const uint4& bv, const
 }
 
 template <int DT>
-__global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void gemm_lp_kernel(BatchArgs B) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][kGemmBM][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bl[DT == 1 ? 2 : 1][DT == 1 ? kGemmBN : 1][kRowL];
@@ -239,47 +239,50 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
     const float s_in = ldexpf(1.f, kScaleExp - e);
     const float s_out = ldexpf(1.f, e - kScaleExp);
 
-    // B loader: cell nb of the tile, k-groups kg and kg + 2 (8 ordinates each).
-    const int nb = tid & 127, kg0 = tid >> 7;
-    const float iso_b = iso[n0 + nb];
-    uint4 ra[2];
-    float rb[2][8];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int idx = tid + s * 256, row = idx >> 2, kq = (idx & 3) * 8;
-            ra[s] = *reinterpret_cast<const ASN_G uint4*>(Klp + (size_t)(m0 + row) * Qp + k0 + kq);
-            const int kb = k0 + (kg0 + 2 * s) * 8;
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                rb[s][i] = (kb + i < Q) ? psi[(size_t)(kb + i) * P + n0 + nb] : 0.f;
-        }
-    };
+    // Staging of one k-step (32 ordinates).  A: thread t moves 16-byte pieces t and
+    // t + 256 of the T(K) tile.  B: thread t loads ordinates k0 + 4 kg .. + 3 of cells
+    // n0 + 4 cg .. + 3 (four float4), subtracts iso, scales, rounds, and writes each
+    // cell's four values as one 8-byte group of its LDS row.
+    const int arow0 = tid >> 2, arow1 = arow0 + 64, akq = (tid & 3) * 8;
+    const int cg = tid & 31, kg = tid >> 5;
+    const float4 iso4 = *reinterpret_cast<const ASN_G float4*>(iso + n0 + 4 * cg);
+    uint4 ra0, ra1;
+    float4 rb[4];
+#define ASN_GLOAD_LP(k0)                                                                       \
+    do {                                                                                       \
+        ra0 = *reinterpret_cast<const ASN_G uint4*>(Klp + (size_t)(m0 + arow0) * Qp + (k0) + akq); \
+        ra1 = *reinterpret_cast<const ASN_G uint4*>(Klp + (size_t)(m0 + arow1) * Qp + (k0) + akq); \
+        _Pragma("unroll") for (int j = 0; j < 4; ++j) {                                        \
+            const int kr = (k0) + 4 * kg + j;                                                  \
+            rb[j] = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(kr, Q - 1) * P +  \
+                                                           n0 + 4 * cg);                       \
+            if (kr >= Q) rb[j] = iso4; /* T(K) is zero there; keep the operand finite */       \
+        }                                                                                      \
+    } while (0)
     auto lstore = [&](int b) {
+        *reinterpret_cast<uint4*>(&As[b][arow0][akq]) = ra0;
+        *reinterpret_cast<uint4*>(&As[b][arow1][akq]) = ra1;
+        const float iv[4] = {iso4.x, iso4.y, iso4.z, iso4.w};
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int idx = tid + s * 256, row = idx >> 2, kq = (idx & 3) * 8;
-            *reinterpret_cast<uint4*>(&As[b][row][kq]) = ra[s];
-            float x[8];
+        for (int c = 0; c < 4; ++c) {
+            float x[4];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) x[i] = (rb[s][i] - iso_b) * s_in;
-            uint4 pk;
+            for (int j = 0; j < 4; ++j) {
+                const float v = c == 0 ? rb[j].x : c == 1 ? rb[j].y : c == 2 ? rb[j].z : rb[j].w;
+                x[j] = (v - iv[c]) * s_in;
+            }
+            uint2 pk;
             pk.x = pack2<DT>(x[0], x[1]);
             pk.y = pack2<DT>(x[2], x[3]);
-            pk.z = pack2<DT>(x[4], x[5]);
-            pk.w = pack2<DT>(x[6], x[7]);
-            *reinterpret_cast<uint4*>(&Bs[b][nb][(kg0 + 2 * s) * 8]) = pk;
+            *reinterpret_cast<uint2*>(&Bs[b][4 * cg + c][4 * kg]) = pk;
             if constexpr (DT == 1) {
-                uint4 pl;
+                uint2 pl;
                 pl.x = pack2<1>(bf16_residual(x[0]), bf16_residual(x[1]));
                 pl.y = pack2<1>(bf16_residual(x[2]), bf16_residual(x[3]));
-                pl.z = pack2<1>(bf16_residual(x[4]), bf16_residual(x[5]));
-                pl.w = pack2<1>(bf16_residual(x[6]), bf16_residual(x[7]));
-                *reinterpret_cast<uint4*>(&Bl[b][nb][(kg0 + 2 * s) * 8]) = pl;
+                *reinterpret_cast<uint2*>(&Bl[b][4 * cg + c][4 * kg]) = pl;
             }
         }
     };
-    // Rows k >= Q are zero in T(K), so the (0 - iso) operands they meet add nothing.
 
     f32x4 acc[4][4];
 #pragma unroll
@@ -290,35 +293,32 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(BatchArgs B) {
     const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
     const int nkt = ktab[mt + 1] - ktab[mt];
     if (nkt > 0) {
-        gload(klist[0] * kBKL);
+        ASN_GLOAD_LP(klist[0] * kBKL);
         lstore(0);
     }
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        if (kt + 1 < nkt) gload(klist[kt + 1] * kBKL);
+        if (kt + 1 < nkt) ASN_GLOAD_LP(klist[kt + 1] * kBKL);
         const int r16 = lane & 15, kofs = 8 * (lane >> 4);
-        uint4 av[4], bv[4];
+        uint4 av[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const uint4*>(&As[b][wm + i * 16 + r16][kofs]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const uint4*>(&Bs[b][wn + j * 16 + r16][kofs]);
+        for (int j = 0; j < 4; ++j) {
+            const uint4 bv = *reinterpret_cast<const uint4*>(&Bs[b][wn + j * 16 + r16][kofs]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) acc[i][j] = mfma_lp<DT>(av[i], bv, acc[i][j]);
+            if constexpr (DT == 1) {
+                const uint4 bl = *reinterpret_cast<const uint4*>(&Bl[b][wn + j * 16 + r16][kofs]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<DT>(av[i], bv[j], acc[i][j]);
-        if constexpr (DT == 1) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bv[j] = *reinterpret_cast<const uint4*>(&Bl[b][wn + j * 16 + r16][kofs]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = mfma_lp<DT>(av[i], bv[j], acc[i][j]);
+                for (int i = 0; i < 4; ++i) acc[i][j] = mfma_lp<DT>(av[i], bl, acc[i][j]);
+            }
         }
         if (kt + 1 < nkt) lstore(b ^ 1);
         __syncthreads();
     }
+#undef ASN_GLOAD_LP
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll

@@ -88,6 +88,97 @@ def product_quadrature(n_polar: int, n_azim: int) -> Tuple[np.ndarray, np.ndarra
     return omega, w
 
 
+def icosahedron_vertices() -> Tuple[np.ndarray, List[Tuple[int, int, int]]]:
+    """Regular icosahedron with a vertex at (0, 0, 1) (Section 3.3) and its 20 faces.
+
+    Vertices: the poles, an upper ring at z = 1/sqrt(5) with azimuths 2 pi k / 5 and a
+    lower ring at z = -1/sqrt(5) turned by pi / 5.
+    """
+    z = 1.0 / math.sqrt(5.0)
+    r = 2.0 / math.sqrt(5.0)
+    v = [(0.0, 0.0, 1.0)]
+    v += [(r * math.cos(2 * math.pi * k / 5), r * math.sin(2 * math.pi * k / 5), z)
+          for k in range(5)]
+    v += [(r * math.cos(2 * math.pi * k / 5 + math.pi / 5),
+           r * math.sin(2 * math.pi * k / 5 + math.pi / 5), -z) for k in range(5)]
+    v += [(0.0, 0.0, -1.0)]
+    up = lambda k: 1 + k % 5
+    lo = lambda k: 6 + k % 5
+    faces = []
+    for k in range(5):
+        faces.append((0, up(k), up(k + 1)))
+        faces.append((up(k), lo(k), up(k + 1)))
+        faces.append((up(k + 1), lo(k), lo(k + 1)))
+        faces.append((11, lo(k + 1), lo(k)))
+    return np.array(v), faces
+
+
+def _spherical_triangle_area(a: np.ndarray, b: np.ndarray, c: np.ndarray) -> float:
+    """Area of the spherical triangle a, b, c on the unit sphere (Van Oosterom-Strackee)."""
+    num = abs(float(np.dot(a, np.cross(b, c))))
+    den = 1.0 + float(np.dot(a, b) + np.dot(b, c) + np.dot(c, a))
+    return 2.0 * math.atan2(num, den)
+
+
+def icosahedron_quadrature(order: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Icosahedron quadrature of the given order (Section 3.3), N_q = 10 (order-1)^2 + 2.
+
+    Every face is split into (order-1)^2 triangles by equidistant points on its edges
+    and the corresponding interior points; the nodes are projected onto the sphere.
+    A node's weight is the area of the spherical polygon that joins the centres
+    (normalised vertex means) of the triangles around it.  Ordinates are sorted by
+    decreasing z, then by increasing azimuth in [0, 2 pi).
+    """
+    if order < 2:
+        raise ValueError("order must be >= 2")
+    m = order - 1
+    verts, faces = icosahedron_vertices()
+    key = lambda p: tuple(np.round(p, 12))
+    nodes: Dict[tuple, int] = {}
+    pts: List[np.ndarray] = []
+
+    def node(p):
+        p = p / np.linalg.norm(p)
+        k = key(p)
+        if k not in nodes:
+            nodes[k] = len(pts)
+            pts.append(p)
+        return nodes[k]
+
+    tris = []
+    for (ia, ib, ic) in faces:
+        A, B, C = verts[ia], verts[ib], verts[ic]
+        idx = {}
+        for a in range(m + 1):
+            for b in range(m + 1 - a):
+                idx[(a, b)] = node(A + (a / m) * (B - A) + (b / m) * (C - A))
+        for a in range(m):
+            for b in range(m - a):
+                tris.append((idx[(a, b)], idx[(a + 1, b)], idx[(a, b + 1)]))
+                if a + b <= m - 2:
+                    tris.append((idx[(a + 1, b)], idx[(a + 1, b + 1)], idx[(a, b + 1)]))
+    P = np.array(pts)
+    around: List[List[np.ndarray]] = [[] for _ in range(len(P))]
+    for t in tris:
+        c = P[list(t)].sum(axis=0)
+        c /= np.linalg.norm(c)
+        for v in t:
+            around[v].append(c)
+    w = np.zeros(len(P))
+    for v in range(len(P)):
+        p = P[v]
+        # order the surrounding centres by angle in the tangent plane of p
+        e1 = np.cross(p, [0.0, 0.0, 1.0]) if abs(p[2]) < 0.9 else np.cross(p, [1.0, 0.0, 0.0])
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(p, e1)
+        cs = sorted(around[v], key=lambda c: math.atan2(np.dot(c, e2), np.dot(c, e1)))
+        w[v] = sum(_spherical_triangle_area(p, cs[i], cs[(i + 1) % len(cs)])
+                   for i in range(len(cs)))
+    az = np.mod(np.arctan2(P[:, 1], P[:, 0]), 2 * math.pi)
+    order_idx = np.lexsort((np.round(az, 9), -np.round(P[:, 2], 9)))
+    return P[order_idx], w[order_idx]
+
+
 # ---------------------------------------------------------------------------
 # Artificial scattering kernel (Section 2.3 eq. (5); Section 3.2 eq. asSNeq)
 # ---------------------------------------------------------------------------
@@ -187,7 +278,10 @@ def setup(problem, mode: str = "sym", eps: Optional[float] = None,
           w: Optional[np.ndarray] = None, dt: Optional[float] = None) -> Setup:
     """Build quadrature, K and dt for a workloads.Problem (all FP64)."""
     if omega is None:
-        omega, w = product_quadrature(problem.n_polar, problem.n_azim)
+        if getattr(problem, "ico_order", 0):
+            omega, w = icosahedron_quadrature(problem.ico_order)
+        else:
+            omega, w = product_quadrature(problem.n_polar, problem.n_azim)
     q = w.size
     eps = kernel_width(q, problem.beta) if eps is None else eps
     K = as_kernel_matrix(omega, w, eps, mode)

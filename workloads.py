@@ -49,9 +49,12 @@ class Problem:
     beta: float = 4.5            # kernel width constant, eps = beta / Q
     t_final: float = 1.0
     cfl: float = 0.95
+    ico_order: int = 0           # > 0: icosahedron quadrature of this order instead
 
     @property
     def q(self) -> int:
+        if self.ico_order:
+            return 10 * (self.ico_order - 1) ** 2 + 2
         return self.n_polar * self.n_azim
 
     @property

@@ -66,17 +66,19 @@ typedef struct {
     double x_min, x_max, y_min, y_max;
 } asn_grid;
 
-/* Angular quadrature.  q_custom == 0: product set of n_polar Gauss-Legendre
- * nodes in mu (axis normal to the grid) times n_azim uniform azimuths
+/* Angular quadrature.  Default: product set of n_polar Gauss-Legendre nodes in
+ * mu (axis normal to the grid) times n_azim uniform azimuths
  * phi_k = (k + 1/2) 2 pi / n_azim, ordinate q = i * n_azim + k (Q = n_polar *
  * n_azim).  q_custom > 0: Q = q_custom ordinates from omega_xyz[Q][3] (unit
- * vectors, host) and weights[Q] (positive, host); the streaming uses the x-y
- * projection (Section 4). */
+ * vectors, host) and weights[Q] (positive, host).  icosahedron_order >= 2 (and
+ * q_custom == 0): the icosahedron set of paper Section 3.3, see
+ * asn_build_icosahedron.  The streaming uses the x-y projection (Section 4). */
 typedef struct {
     int32_t n_polar, n_azim;
     int32_t q_custom;
     const double* omega_xyz;
     const double* weights;
+    int32_t icosahedron_order;
 } asn_quadrature;
 
 typedef struct {
@@ -206,6 +208,16 @@ const char* asn_last_error(void);
 /* Product quadrature (see asn_quadrature): omega_xyz double[Q][3], weights double[Q]. */
 asn_status asn_build_quadrature(int32_t n_polar, int32_t n_azim, double* omega_xyz,
                                 double* weights);
+
+/* Icosahedron set (paper Section 3.3) of the given order >= 2, Q = 10 (order - 1)^2
+ * + 2 ordinates (12, 42, 92, 162, ...): every face of a regular icosahedron with a
+ * vertex at (0, 0, 1) is split by equidistant points on its edges (and the
+ * corresponding interior points) into (order - 1)^2 triangles, the nodes are
+ * projected onto the unit sphere, and a node's weight is the area of the spherical
+ * polygon that joins the centres of its surrounding triangles (weights sum to
+ * 4 pi).  Ordinates are sorted by decreasing z, then increasing azimuth.
+ * omega_xyz double[Q][3], weights double[Q], host.  Errors: ASN_E_INVALID. */
+asn_status asn_build_icosahedron(int32_t order, double* omega_xyz, double* weights);
 
 /* Normalised kernel matrix K double[Q][Q] (row-major, K[q][p]) for unit ordinates
  * omega_xyz[Q][3] and weights[Q], width eps > 0, normalisation ASN_NORM_*.

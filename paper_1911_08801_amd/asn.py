@@ -56,7 +56,8 @@ class asn_grid(ctypes.Structure):
 class asn_quadrature(ctypes.Structure):
     _fields_ = [("n_polar", ctypes.c_int32), ("n_azim", ctypes.c_int32),
                 ("q_custom", ctypes.c_int32), ("omega_xyz", ctypes.POINTER(ctypes.c_double)),
-                ("weights", ctypes.POINTER(ctypes.c_double))]
+                ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("icosahedron_order", ctypes.c_int32)]
 
 
 class asn_options(ctypes.Structure):
@@ -92,6 +93,7 @@ _SIG = {
     "asn_destroy": [_P],
     "asn_contraction_work": [_P, _D, _D],
     "asn_build_quadrature": [ctypes.c_int32, ctypes.c_int32, _D, _D],
+    "asn_build_icosahedron": [ctypes.c_int32, _D, _D],
     "asn_build_kernel": [ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_int32, _D],
     "asn_build_kernel_lowp": [ctypes.c_int32, _D, ctypes.c_int32,
                               ctypes.POINTER(ctypes.c_uint16), _F],
@@ -134,6 +136,14 @@ def asn_build_quadrature(n_polar: int, n_azim: int):
     om = np.zeros((q, 3))
     w = np.zeros(q)
     _check(_lib.asn_build_quadrature(n_polar, n_azim, _dptr(om), _dptr(w)), "asn_build_quadrature")
+    return om, w
+
+
+def asn_build_icosahedron(order: int):
+    q = 10 * (order - 1) ** 2 + 2
+    om = np.zeros((q, 3))
+    w = np.zeros(q)
+    _check(_lib.asn_build_icosahedron(order, _dptr(om), _dptr(w)), "asn_build_icosahedron")
     return om, w
 
 
@@ -224,7 +234,7 @@ def asn_create(grid: asn_grid, n_polar: int = 0, n_azim: int = 0, sigma_s=None, 
                sigma_as=None, source=None, beta: float = 4.5, t_final: float = 1.0,
                options: Optional[asn_options] = None, omega: Optional[np.ndarray] = None,
                weights: Optional[np.ndarray] = None, device: str = "cuda",
-               torch_workspace: bool = True) -> AsnProblem:
+               torch_workspace: bool = True, icosahedron_order: int = 0) -> AsnProblem:
     """Create a problem on the current torch device and stream.
 
     The workspace is a torch uint8 tensor (so torch's allocator accounts for it);
@@ -237,10 +247,13 @@ def asn_create(grid: asn_grid, n_polar: int = 0, n_azim: int = 0, sigma_s=None, 
         om = np.ascontiguousarray(omega, dtype=np.float64)
         w = np.ascontiguousarray(weights, dtype=np.float64)
         keep += [om, w]
-        quad = asn_quadrature(0, 0, w.size, _dptr(om), _dptr(w))
+        quad = asn_quadrature(0, 0, w.size, _dptr(om), _dptr(w), 0)
         q = w.size
+    elif icosahedron_order:
+        quad = asn_quadrature(0, 0, 0, None, None, icosahedron_order)
+        q = 10 * (icosahedron_order - 1) ** 2 + 2
     else:
-        quad = asn_quadrature(n_polar, n_azim, 0, None, None)
+        quad = asn_quadrature(n_polar, n_azim, 0, None, None, 0)
         q = n_polar * n_azim
     fields = [_f32(f) for f in (sigma_s, sigma_a, sigma_as)]
     src = None if source is None else _f32(source)
@@ -393,7 +406,8 @@ def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
     opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
-                   spec.source, spec.beta, spec.t_final, opt, device=device)
+                   spec.source, spec.beta, spec.t_final, opt, device=device,
+                   icosahedron_order=getattr(spec, "ico_order", 0))
     if set_initial_state:
         asn_set_state_isotropic(p, spec.psi0_cell)
     return p

@@ -258,6 +258,12 @@ asn_status resolve_quadrature(const asn_quadrature* q, std::vector<double>& om,
         }
         return ASN_OK;
     }
+    if (q->icosahedron_order > 0) {
+        if (q->icosahedron_order < 2 || q->icosahedron_order > 41)
+            return fail(ASN_E_INVALID, "icosahedron_order must be in [2, 41]");
+        asn::icosahedron_quadrature(q->icosahedron_order, om, w);
+        return ASN_OK;
+    }
     if (q->n_polar < 1 || q->n_azim < 1) return fail(ASN_E_INVALID, "n_polar and n_azim must be >= 1");
     if ((int64_t)q->n_polar * q->n_azim > 16384) return fail(ASN_E_INVALID, "too many ordinates");
     asn::product_quadrature(q->n_polar, q->n_azim, om, w);
@@ -288,7 +294,9 @@ void quantise_kernel(int Q, const double* K, int dtype, int ld, uint16_t* out, f
 }
 
 int quad_size(const asn_quadrature* q) {
-    return q->q_custom > 0 ? q->q_custom : q->n_polar * q->n_azim;
+    if (q->q_custom > 0) return q->q_custom;
+    if (q->icosahedron_order > 0) return 10 * (q->icosahedron_order - 1) * (q->icosahedron_order - 1) + 2;
+    return q->n_polar * q->n_azim;
 }
 
 asn_status check_field(const float* f, int64_t n, const char* name, bool allow_null) {
@@ -822,6 +830,16 @@ asn_status asn_build_quadrature(int32_t n_polar, int32_t n_azim, double* omega_x
         return fail(ASN_E_INVALID, "invalid quadrature request");
     std::vector<double> om, w;
     asn::product_quadrature(n_polar, n_azim, om, w);
+    std::memcpy(omega_xyz, om.data(), om.size() * 8);
+    std::memcpy(weights, w.data(), w.size() * 8);
+    return ASN_OK;
+}
+
+asn_status asn_build_icosahedron(int32_t order, double* omega_xyz, double* weights) {
+    if (order < 2 || order > 41 || !omega_xyz || !weights)
+        return fail(ASN_E_INVALID, "invalid icosahedron request");
+    std::vector<double> om, w;
+    asn::icosahedron_quadrature(order, om, w);
     std::memcpy(omega_xyz, om.data(), om.size() * 8);
     std::memcpy(weights, w.data(), w.size() * 8);
     return ASN_OK;

@@ -1,8 +1,11 @@
 // Host-side set-up of an as-S_N problem (FP64).  See asn_host.hpp.
 #include "asn_host.hpp"
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 
 namespace asn {
 
@@ -64,6 +67,123 @@ void product_quadrature(int n_polar, int n_azim, std::vector<double>& omega,
             omega[3 * q + 2] = mu[i];
             w[q] = g[i] * dphi;
         }
+    }
+}
+
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+V3 unit(V3 a) { return (1.0 / std::sqrt(dot(a, a))) * a; }
+
+// Solid angle of the spherical triangle a, b, c (unit vectors).
+double solid_angle(V3 a, V3 b, V3 c) {
+    const double num = std::fabs(dot(a, cross(b, c)));
+    const double den = 1.0 + dot(a, b) + dot(b, c) + dot(c, a);
+    return 2.0 * std::atan2(num, den);
+}
+
+}  // namespace
+
+void icosahedron_quadrature(int order, std::vector<double>& omega, std::vector<double>& w) {
+    const int m = order - 1;
+    // 12 vertices: north pole, ring at z = 1/sqrt5 (azimuth 72 k deg), ring at
+    // z = -1/sqrt5 (azimuth 72 k + 36 deg), south pole.
+    std::array<V3, 12> vx;
+    const double zr = 1.0 / std::sqrt(5.0), rr = 2.0 / std::sqrt(5.0);
+    vx[0] = {0.0, 0.0, 1.0};
+    vx[11] = {0.0, 0.0, -1.0};
+    for (int k = 0; k < 5; ++k) {
+        const double a = 2.0 * M_PI * k / 5.0, b = a + M_PI / 5.0;
+        vx[1 + k] = {rr * std::cos(a), rr * std::sin(a), zr};
+        vx[6 + k] = {rr * std::cos(b), rr * std::sin(b), -zr};
+    }
+    std::vector<std::array<int, 3>> faces;
+    for (int k = 0; k < 5; ++k) {
+        const int u0 = 1 + k, u1 = 1 + (k + 1) % 5, l0 = 6 + k, l1 = 6 + (k + 1) % 5;
+        faces.push_back({0, u0, u1});
+        faces.push_back({u0, l0, u1});
+        faces.push_back({u1, l0, l1});
+        faces.push_back({11, l1, l0});
+    }
+    // Nodes shared by neighbouring faces are merged by their rounded coordinates.
+    std::map<std::array<long long, 3>, int> index;
+    std::vector<V3> nodes;
+    auto node_of = [&](V3 p) {
+        p = unit(p);
+        const std::array<long long, 3> key = {std::llround(p.x * 1e11), std::llround(p.y * 1e11),
+                                              std::llround(p.z * 1e11)};
+        auto it = index.find(key);
+        if (it != index.end()) return it->second;
+        const int id = (int)nodes.size();
+        index.emplace(key, id);
+        nodes.push_back(p);
+        return id;
+    };
+    std::vector<std::array<int, 3>> tris;
+    for (const auto& f : faces) {
+        const V3 A = vx[f[0]], B = vx[f[1]], C = vx[f[2]];
+        std::vector<int> grid((size_t)(m + 1) * (m + 1), -1);
+        auto at = [&](int i, int j) -> int& { return grid[(size_t)i * (m + 1) + j]; };
+        for (int i = 0; i <= m; ++i)
+            for (int j = 0; i + j <= m; ++j)
+                at(i, j) = node_of(A + ((double)i / m) * (B - A) + ((double)j / m) * (C - A));
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; i + j < m; ++j) {
+                tris.push_back({at(i, j), at(i + 1, j), at(i, j + 1)});
+                if (i + j + 2 <= m) tris.push_back({at(i + 1, j), at(i + 1, j + 1), at(i, j + 1)});
+            }
+    }
+    const size_t N = nodes.size();
+    // Centres of the triangles around every node, walked in angular order.
+    std::vector<std::vector<V3>> fan(N);
+    for (const auto& t : tris) {
+        const V3 g = unit(nodes[t[0]] + nodes[t[1]] + nodes[t[2]]);
+        for (int v : t) fan[v].push_back(g);
+    }
+    std::vector<double> area(N, 0.0);
+    for (size_t v = 0; v < N; ++v) {
+        const V3 p = nodes[v];
+        const V3 ref = std::fabs(p.z) < 0.9 ? V3{0.0, 0.0, 1.0} : V3{1.0, 0.0, 0.0};
+        const V3 e1 = unit(cross(p, ref)), e2 = cross(p, e1);
+        std::vector<std::pair<double, V3>> ring;
+        for (const V3& g : fan[v]) ring.push_back({std::atan2(dot(g, e2), dot(g, e1)), g});
+        std::sort(ring.begin(), ring.end(),
+                  [](const std::pair<double, V3>& a, const std::pair<double, V3>& b) {
+                      return a.first < b.first;
+                  });
+        double s = 0.0;
+        for (size_t i = 0; i < ring.size(); ++i)
+            s += solid_angle(p, ring[i].second, ring[(i + 1) % ring.size()].second);
+        area[v] = s;
+    }
+    // Order: decreasing z, then increasing azimuth (both compared after rounding).
+    std::vector<size_t> perm(N);
+    for (size_t i = 0; i < N; ++i) perm[i] = i;
+    auto zkey = [&](size_t i) { return std::llround(nodes[i].z * 1e9); };
+    auto akey = [&](size_t i) {
+        double a = std::atan2(nodes[i].y, nodes[i].x);
+        if (a < 0) a += 2.0 * M_PI;
+        return std::llround(a * 1e9);
+    };
+    std::sort(perm.begin(), perm.end(), [&](size_t a, size_t b) {
+        if (zkey(a) != zkey(b)) return zkey(a) > zkey(b);
+        return akey(a) < akey(b);
+    });
+    omega.assign(3 * N, 0.0);
+    w.assign(N, 0.0);
+    for (size_t i = 0; i < N; ++i) {
+        const V3 p = nodes[perm[i]];
+        omega[3 * i] = p.x;
+        omega[3 * i + 1] = p.y;
+        omega[3 * i + 2] = p.z;
+        w[i] = area[perm[i]];
     }
 }
 

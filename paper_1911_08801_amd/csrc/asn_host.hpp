@@ -16,6 +16,12 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 void product_quadrature(int n_polar, int n_azim, std::vector<double>& omega,
                         std::vector<double>& w);
 
+// Icosahedron set of the given order (>= 2): N = 10 (order - 1)^2 + 2 ordinates on
+// the subdivided faces of a regular icosahedron with a vertex at (0, 0, 1); the
+// weight of a node is the area of the spherical polygon through the centres of
+// its surrounding triangles.  Sorted by decreasing z, then increasing azimuth.
+void icosahedron_quadrature(int order, std::vector<double>& omega, std::vector<double>& w);
+
 // Normalised artificial in-scattering matrix K[Q][Q] (row-major) from
 // S_qp = exp(-((1 - Omega_q . Omega_p)/eps)^2).  mode 0: symmetric scaling
 // (rows and w-weighted columns sum to one); mode 1: row normalisation.

@@ -59,7 +59,8 @@ class GpuBackend:
     def bytes_needed(self, spec, dtype: str) -> int:
         a = self.asn
         grid = a.make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
-        quad = a.asn_quadrature(spec.n_polar, spec.n_azim, 0, None, None)
+        quad = a.asn_quadrature(spec.n_polar, spec.n_azim, 0, None, None,
+                                getattr(spec, "ico_order", 0))
         return a.asn_workspace_size(grid, quad, a.make_options(dtype, cfl=spec.cfl))
 
     def free_bytes(self) -> int:
@@ -179,7 +180,7 @@ class Server:
                     j.status, j.error = "failed", f"create: {e}"
                     continue
                 j.steps_left = j.steps_total
-                j.updates = float(j.spec.nx * j.spec.ny * j.spec.n_polar * j.spec.n_azim
+                j.updates = float(j.spec.nx * j.spec.ny * j.spec.q
                                   * j.steps_total)
                 j.t_admit = now()
                 j.status = "active"

@@ -80,6 +80,32 @@ def test_time_step_rejects_cfl_above_one():
     assert e.value.status == asn.ASN_E_UNSTABLE
 
 
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 9, 16])
+def test_host_icosahedron_matches_oracle(order):
+    om, w = asn.asn_build_icosahedron(order)
+    om_o, w_o = o.icosahedron_quadrature(order)
+    assert w.size == 10 * (order - 1) ** 2 + 2
+    # Same ordering (decreasing z, then azimuth) and the same dual-cell areas,
+    # from two separate constructions.
+    assert np.max(np.abs(om - om_o)) < 1e-13
+    assert np.max(np.abs(w - w_o)) < 1e-13
+
+
+def test_icosahedron_workspace_and_rejects():
+    opt = asn.make_options()
+    g = asn.make_grid(20, 20, -1.5, 1.5, -1.5, 1.5)
+    ico = asn.asn_workspace_size(g, asn.asn_quadrature(0, 0, 0, None, None, 4), opt)
+    prod = asn.asn_workspace_size(g, asn.asn_quadrature(4, 23, 0, None, None, 0), opt)
+    assert ico == prod                     # 92 ordinates either way
+    for order in (1, 42, -3):
+        with pytest.raises(asn.AsnError) as e:
+            asn.asn_build_icosahedron(order) if order > 1 else asn._check(
+                asn._lib.asn_build_icosahedron(order, None, None), "ico")
+        assert e.value.status == asn.ASN_E_INVALID
+    st, _ = _raw_create(ico=1)
+    assert st == asn.ASN_E_INVALID
+
+
 def test_builders_reject_bad_arguments():
     with pytest.raises(asn.AsnError) as e:
         asn.asn_build_kernel(np.zeros((0, 3)), np.zeros(0), 0.1)
@@ -90,10 +116,10 @@ def test_builders_reject_bad_arguments():
 
 
 def _raw_create(nx=4, ny=3, n_polar=2, n_azim=4, cfl=0.95, sig=None, beta=4.5, t_final=1.0,
-                grid=None):
+                grid=None, ico=0):
     lib = asn._lib
     g = grid or asn.make_grid(nx, ny, 0.0, 1.0, 0.0, 1.0)
-    q = asn.asn_quadrature(n_polar, n_azim, 0, None, None)
+    q = asn.asn_quadrature(n_polar, n_azim, 0, None, None, ico)
     opt = asn.make_options(cfl=cfl)
     f = np.zeros(max(nx * ny, 1), dtype=np.float32) if sig is None else sig
     h = ctypes.c_void_p()

@@ -8,8 +8,9 @@ using artificial scattering" (arXiv:1911.08801), cited by section/equation.
 
 Readings of points the paper leaves open (each also listed in the design notes):
   * time stepping is forward Euler with first-order donor-cell (upwind) fluxes
-    on a uniform Cartesian grid (the paper's own explicit scheme, Heun with a
-    minmod limiter, is described only by reference, Section 3.1);
+    on a uniform Cartesian grid; the paper's own explicit scheme, Heun with a
+    minmod limiter (described only by reference, Section 3.1), is heun_step,
+    with the textbook reading stated where it is defined;
   * the CFL number bounds dt * max_q(|xi_q|/dx + |eta_q|/dy), the stable
     reading for an unsplit 2-D upwind update (Section 4.1 states it as dt/dx);
   * the quadrature is a product Gauss-Legendre (polar) x uniform azimuth set
@@ -429,6 +430,137 @@ def step_entries(psi: np.ndarray, st: Setup, qs: np.ndarray, js: np.ndarray,
         rhs = (-dfx / st.dx - dfy / st.dy - (s_a + s_s + s_as) * c
                + s_s * phi[j, i] / st.W + s_as * y + st.source[j, i])
         out[n] = c + st.dt * rhs
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's own explicit scheme (Section 3.1): Heun's method in time with
+# minmod-limited second-order upwind fluxes in space.  The paper defers the
+# details to earlier work; the reading used here is the textbook one:
+#   * per ordinate and per axis, a linear reconstruction in every cell with the
+#     limited slope s_i = minmod(psi_i - psi_{i-1}, psi_{i+1} - psi_i);
+#   * the flux through a face takes the value reconstructed on its upwind side,
+#     psi_i + s_i / 2 (from the left cell) or psi_{i+1} - s_{i+1} / 2 (right);
+#   * two zero ghost cells outside every boundary (vacuum: the ghost slope is
+#     minmod(0, .) = 0, so no particles enter);
+#   * Heun: psi1 = psi + dt R(psi), psi^{n+1} = (psi + psi1 + dt R(psi1)) / 2,
+#     with R every right-hand-side term of eq. asSNeq (streaming, collisions,
+#     physical and artificial scattering, source) at the stage's own level.
+# ---------------------------------------------------------------------------
+
+def minmod(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """The argument of smaller magnitude when a and b share a sign, else 0."""
+    return np.where(a * b > 0.0, np.where(np.abs(a) <= np.abs(b), a, b), 0.0)
+
+
+def muscl_face_fluxes(psi: np.ndarray, xi: np.ndarray, eta: np.ndarray):
+    """Limited second-order upwind face fluxes with two zero ghost cells per side.
+
+    Same face indexing as upwind_face_fluxes: Fx[q, j, f] crosses x_min + f dx.
+    """
+    Q, ny, nx = psi.shape
+    Fx = np.zeros((Q, ny, nx + 1))
+    Fy = np.zeros((Q, ny + 1, nx))
+    for q in range(Q):
+        g = np.zeros((ny + 4, nx + 4))
+        g[2:-2, 2:-2] = psi[q]
+        # x: cells -1 .. nx of the row (padded columns 1 .. nx + 2), their slopes,
+        # and the values reconstructed at their right and left faces
+        c = g[2:-2, 1:nx + 3]
+        s = minmod(c - g[2:-2, 0:nx + 2], g[2:-2, 2:nx + 4] - c)
+        if xi[q] > 0:
+            Fx[q] = xi[q] * (c + 0.5 * s)[:, 0:nx + 1]      # face f from cell f - 1
+        elif xi[q] < 0:
+            Fx[q] = xi[q] * (c - 0.5 * s)[:, 1:nx + 2]      # face f from cell f
+        c = g[1:ny + 3, 2:-2]
+        s = minmod(c - g[0:ny + 2, 2:-2], g[2:ny + 4, 2:-2] - c)
+        if eta[q] > 0:
+            Fy[q] = eta[q] * (c + 0.5 * s)[0:ny + 1, :]
+        elif eta[q] < 0:
+            Fy[q] = eta[q] * (c - 0.5 * s)[1:ny + 2, :]
+    return Fx, Fy
+
+
+def heun_rhs(psi: np.ndarray, st: Setup):
+    """R(psi) of eq. asSNeq with the limited fluxes; returns (R, stage budget terms)."""
+    xi, eta = st.omega[:, 0], st.omega[:, 1]
+    phi = scalar_flux(psi, st.w)
+    Y = as_in_scattering(psi, st.K)
+    Fx, Fy = muscl_face_fluxes(psi, xi, eta)
+    div = (Fx[:, :, 1:] - Fx[:, :, :-1]) / st.dx + (Fy[:, 1:, :] - Fy[:, :-1, :]) / st.dy
+    sig_t = st.sigma_a + st.sigma_s + st.sigma_as
+    R = (-div - sig_t[None] * psi + (st.sigma_s * phi / st.W)[None]
+         + st.sigma_as[None] * Y + st.source[None])
+    area = st.dx * st.dy
+    wq = st.w[:, None, None]
+    terms = {
+        "mass": area * phi.sum(),
+        "absorption": area * np.sum(st.sigma_a * phi),
+        "outflow": (st.dy * np.sum(st.w * (Fx[:, :, -1].sum(1) - Fx[:, :, 0].sum(1)))
+                    + st.dx * np.sum(st.w * (Fy[:, -1, :].sum(1) - Fy[:, 0, :].sum(1)))),
+        "source": area * st.W * st.source.sum(),
+        "as_defect": area * np.sum(st.sigma_as * np.sum(wq * (Y - psi), axis=0)),
+    }
+    return R, terms
+
+
+def heun_step(psi: np.ndarray, st: Setup, want_budget: bool = True):
+    """One Heun step with limited fluxes; returns (psi_new, budget dict).
+
+    The budget holds M^n and the stage averages of absorption, outflow, source
+    and defect, so that M^{n+1} = M^n + dt (-A - O + S + D) exactly, as for
+    the Euler step (budget_residual applies unchanged).
+    """
+    R0, b0 = heun_rhs(psi, st)
+    psi1 = psi + st.dt * R0
+    R1, b1 = heun_rhs(psi1, st)
+    psi_new = 0.5 * (psi + (psi1 + st.dt * R1))
+    if not want_budget:
+        return psi_new, None
+    budget = {k: 0.5 * (b0[k] + b1[k]) for k in b0}
+    budget["mass"] = b0["mass"]
+    return psi_new, budget
+
+
+def run_heun(problem, n_steps: Optional[int] = None, st: Optional[Setup] = None,
+             psi0: Optional[np.ndarray] = None, mode: str = "sym", budget: bool = False):
+    """Advance a problem with heun_step; returns (psi, setup, budget records)."""
+    st = setup(problem, mode) if st is None else st
+    psi = (problem.psi0() if psi0 is None else psi0).astype(np.float64)
+    n = st.n_steps if n_steps is None else n_steps
+    hist: List[Dict[str, float]] = []
+    for _ in range(n):
+        psi, b = heun_step(psi, st, want_budget=budget)
+        if budget:
+            b["mass_next"] = mass(psi, st)
+            hist.append(b)
+    return psi, st, hist
+
+
+def heun_step_entries(psi: np.ndarray, st: Setup, qs: np.ndarray, js: np.ndarray,
+                      iis: np.ndarray) -> np.ndarray:
+    """heun_step's psi^{n+1} at the listed (q, j, i) only.
+
+    A cell's new value depends on the old state within four cells along each
+    axis (two per stage), so each entry is computed on the 9 x 9 window around
+    it, all ordinates, with the cells outside the grid held at the ghost value 0.
+    """
+    Q, ny, nx = psi.shape
+    h = 4
+    pad = lambda a: np.pad(np.asarray(a, dtype=np.float64), [(0, 0)] * (a.ndim - 2) + [(h, h), (h, h)])
+    P = pad(psi)
+    inside = pad(np.ones((ny, nx)))
+    fields = {k: pad(getattr(st, k)) for k in ("sigma_s", "sigma_a", "sigma_as", "source")}
+    out = np.empty(len(qs))
+    for n, (q, j, i) in enumerate(zip(qs, js, iis)):
+        win = (slice(j, j + 2 * h + 1), slice(i, i + 2 * h + 1))
+        sub = dataclasses.replace(st, **{k: v[win] for k, v in fields.items()})
+        mask = inside[win][None]
+        p0 = P[(slice(None),) + win]
+        R0, _ = heun_rhs(p0, sub)
+        p1 = (p0 + st.dt * R0) * mask
+        R1, _ = heun_rhs(p1, sub)
+        out[n] = 0.5 * (p0 + p1 + st.dt * R1)[q, h, h]
     return out
 
 

@@ -58,6 +58,16 @@ enum { ASN_GEMM_F32 = 0, ASN_GEMM_BF16 = 1, ASN_GEMM_F16 = 2 };
  *               c_q^(eps) = 1 / sum_p w_p s_eps(Omega_q . Omega_p). */
 enum { ASN_NORM_SYM = 0, ASN_NORM_ROW = 1 };
 
+/* Explicit time scheme.
+ * ASN_SCHEME_EULER: forward Euler with first-order donor-cell (upwind) fluxes.
+ * ASN_SCHEME_HEUN:  the paper's explicit scheme (Section 3.1): Heun's method with
+ *                   second-order upwind fluxes from a minmod-limited linear
+ *                   reconstruction per axis (slope minmod(psi_i - psi_{i-1},
+ *                   psi_{i+1} - psi_i), face value psi_i +- slope / 2 on the upwind
+ *                   side, zero ghost cells); psi^1 = psi + dt R(psi),
+ *                   psi^{n+1} = (psi + psi^1 + dt R(psi^1)) / 2. */
+enum { ASN_SCHEME_EULER = 0, ASN_SCHEME_HEUN = 1 };
+
 #define ASN_BUDGET_LEN 8
 
 /* Uniform grid of nx * ny cells covering [x_min, x_max] x [y_min, y_max]. */
@@ -88,7 +98,7 @@ typedef struct {
     double eps_override;    /* > 0: kernel width eps used instead of beta / Q                     */
     double dt_override;     /* > 0: fixed dt (still subject to the CFL bound)                     */
     int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
-    int32_t reserved;
+    int32_t scheme;         /* ASN_SCHEME_EULER (default) or ASN_SCHEME_HEUN                     */
 } asn_options;
 
 typedef struct asn_problem_s* asn_problem;
@@ -144,7 +154,7 @@ asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps);
 /* A batch groups 1..64 problems for fused stepping: every kernel of a step covers
  * all of them in one launch.  Problems keep their own grid, ordinates, kernel
  * matrix and buffers (ordinate counts may differ); they must share the operand
- * type and the HIP stream.  The batch holds small device tables (hipMalloc).
+ * type, the time scheme and the HIP stream.  The batch holds small device tables (hipMalloc).
  * A problem may be stepped alone while in a batch; the batch reads each
  * problem's current buffer at every asn_batch_step.  Errors: ASN_E_INVALID,
  * ASN_E_OOM, ASN_E_HIP. */
@@ -165,8 +175,9 @@ asn_status asn_batch_destroy(asn_batch b);
 /* Run n_steps exactly like asn_step while recording HIP events on the problem's
  * stream between its kernels; synchronises.  kernel_ms[k] receives the average
  * duration per step of kernel k: 0 the ordinate contraction Y = K Psi, 1 stream
- * + collide, 2 moment finalize, 3 budget fold; kernel_ms[4] the average span of a
- * whole step.  Measurement support for benchmarks; results equal asn_step.
+ * + collide, 2 moment finalize, 3 budget fold (for ASN_SCHEME_HEUN, the sum over
+ * its two passes); kernel_ms[4] the average span of a whole step.  Measurement
+ * support for benchmarks; results equal asn_step.
  * Errors: ASN_E_INVALID (n_steps < 1), ASN_E_HIP. */
 asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]);
 

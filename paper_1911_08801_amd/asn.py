@@ -35,10 +35,12 @@ ASN_E_UNSUPPORTED = -6
 
 ASN_GEMM_F32, ASN_GEMM_BF16, ASN_GEMM_F16 = 0, 1, 2
 ASN_NORM_SYM, ASN_NORM_ROW = 0, 1
+ASN_SCHEME_EULER, ASN_SCHEME_HEUN = 0, 1
 ASN_BUDGET_LEN = 8
 
 DTYPES = {"f32": ASN_GEMM_F32, "bf16": ASN_GEMM_BF16, "f16": ASN_GEMM_F16}
 NORMS = {"sym": ASN_NORM_SYM, "row": ASN_NORM_ROW}
+SCHEMES = {"euler": ASN_SCHEME_EULER, "heun": ASN_SCHEME_HEUN}
 
 
 class AsnError(RuntimeError):
@@ -64,7 +66,7 @@ class asn_options(ctypes.Structure):
     _fields_ = [("gemm_dtype", ctypes.c_int32), ("normalization", ctypes.c_int32),
                 ("cfl", ctypes.c_double), ("eps_override", ctypes.c_double),
                 ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -189,10 +191,12 @@ def asn_options_default() -> asn_options:
 
 
 def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
-                 eps_override: float = 0.0, dt_override: float = 0.0) -> asn_options:
+                 eps_override: float = 0.0, dt_override: float = 0.0,
+                 scheme: str = "euler") -> asn_options:
     o = asn_options_default()
     o.gemm_dtype = DTYPES[dtype]
     o.normalization = NORMS[norm]
+    o.scheme = SCHEMES[scheme]
     o.cfl = cfl
     o.eps_override = eps_override
     o.dt_override = dt_override
@@ -400,11 +404,11 @@ def asn_destroy(p: AsnProblem) -> None:
 
 def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               eps_override: float = 0.0, dt_override: float = 0.0,
-              set_initial_state: bool = True) -> AsnProblem:
+              set_initial_state: bool = True, scheme: str = "euler") -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
-    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override)
+    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
                    spec.source, spec.beta, spec.t_final, opt, device=device,
                    icosahedron_order=getattr(spec, "ico_order", 0))

@@ -47,14 +47,15 @@ struct Layout {
         total;
 };
 
-Layout make_layout(int nx, int ny, int Q, int dtype) {
+Layout make_layout(int nx, int ny, int Q, int dtype, int scheme) {
     Layout L;
     L.Q = Q;
     L.Qp = (int)round_up(Q, asn::kGemmBM);
     L.C = (int64_t)nx * ny;
     L.P = round_up(L.C, asn::kScaleBlock);
     L.lowp = dtype != ASN_GEMM_F32;
-    L.tiles_x = (nx + asn::kStripX - 1) / asn::kStripX;
+    const int strip = scheme == ASN_SCHEME_HEUN ? asn::kStripXM : asn::kStripX;
+    L.tiles_x = (nx + strip - 1) / strip;
     L.tiles_y = (ny + asn::kTileY - 1) / asn::kTileY;
     // Split the ordinates into chunks so that the stream + collide grid holds about
     // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
@@ -113,7 +114,7 @@ struct asn_problem_s {
     Layout L;
     double dx = 0, dy = 0, dt = 0, W = 0, eps = 0;
     int64_t n_to_tfinal = 0, steps_done = 0;
-    int dtype = 0, norm = 0;
+    int dtype = 0, norm = 0, scheme = 0;
     hipStream_t stream = nullptr;
     int device = 0;
     bool owns = false;
@@ -127,7 +128,7 @@ struct asn_problem_s {
 
 struct asn_batch_s {
     std::vector<asn_problem> probs;
-    int n = 0, dtype = 0;
+    int n = 0, dtype = 0, scheme = 0;
     hipStream_t stream = nullptr;
     std::vector<StepArgs> tab;
     std::vector<int> off;
@@ -331,7 +332,8 @@ asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
     asn_options d;
     asn_options_default(&d);
     const int dtype = opt ? opt->gemm_dtype : d.gemm_dtype;
-    *bytes = make_layout(grid->nx, grid->ny, Q, dtype).total;
+    const int scheme = opt ? opt->scheme : d.scheme;
+    *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme).total;
     return ASN_OK;
 }
 
@@ -351,6 +353,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         return fail(ASN_E_INVALID, "unknown gemm_dtype");
     if (opt.normalization != ASN_NORM_SYM && opt.normalization != ASN_NORM_ROW)
         return fail(ASN_E_INVALID, "unknown normalization");
+    if (opt.scheme != ASN_SCHEME_EULER && opt.scheme != ASN_SCHEME_HEUN)
+        return fail(ASN_E_INVALID, "unknown scheme");
     if (!(opt.cfl > 0.0)) return fail(ASN_E_INVALID, "cfl must be > 0");
     if (opt.cfl > 1.0) return fail(ASN_E_UNSTABLE, "cfl above 1 is unstable for the explicit step");
     if (!(t_final > 0.0) || !std::isfinite(t_final)) return fail(ASN_E_INVALID, "t_final must be > 0");
@@ -374,6 +378,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     p->dy = (grid->y_max - grid->y_min) / grid->ny;
     p->dtype = opt.gemm_dtype;
     p->norm = opt.normalization;
+    p->scheme = opt.scheme;
     p->stream = reinterpret_cast<hipStream_t>(hip_stream);
     p->w = w;
     double W = 0.0;
@@ -403,7 +408,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         return fail(ASN_E_UNSUPPORTED, err);
     }
 
-    p->L = make_layout(p->nx, p->ny, Q, p->dtype);
+    p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme);
     const Layout& L = p->L;
     if (workspace) {
         if (workspace_bytes < L.total) {
@@ -563,6 +568,11 @@ asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
     return ASN_OK;
 }
 
+// An Euler step moves the state to the other buffer; a Heun step brings it back.
+static int state_flip(int scheme, int64_t n_steps) {
+    return scheme == ASN_SCHEME_HEUN ? 0 : (int)(n_steps & 1);
+}
+
 asn_status asn_step(asn_problem p, int64_t n_steps) {
     if (!p) return fail(ASN_E_INVALID, "problem is NULL");
     if (n_steps < 0 || n_steps > (1 << 30)) return fail(ASN_E_INVALID, "n_steps must be in [0, 2^30]");
@@ -571,9 +581,9 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
     asn::BatchArgs b = single_batch(p);
     for (int64_t i = 0; i < n_steps; ++i) {
         b.s_par = (int)(i & 1);
-        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, p->stream));
+        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, p->scheme, p->stream));
     }
-    p->cur ^= (int)(n_steps & 1);
+    p->cur ^= state_flip(p->scheme, n_steps);
     p->steps_done += n_steps;
     return ASN_OK;
 }
@@ -581,7 +591,9 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
 asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     if (!p || !kernel_ms) return fail(ASN_E_INVALID, "NULL argument");
     if (n_steps < 1 || n_steps > (1 << 20)) return fail(ASN_E_INVALID, "n_steps must be in [1, 2^20]");
-    std::vector<hipEvent_t> ev((size_t)n_steps * 5, nullptr);
+    const int passes = asn::passes_per_step(p->scheme);
+    const size_t per = 5 * (size_t)passes;
+    std::vector<hipEvent_t> ev((size_t)n_steps * per, nullptr);
     asn_status st = ASN_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -593,30 +605,32 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     asn::BatchArgs bt = single_batch(p);
     for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
         bt.s_par = (int)(i & 1);
-        const hipError_t e = asn::launch_step(bt, p->blocks, p->dtype, p->stream, &ev[(size_t)i * 5]);
+        const hipError_t e =
+            asn::launch_step(bt, p->blocks, p->dtype, p->scheme, p->stream, &ev[(size_t)i * per]);
         if (e != hipSuccess) {
             st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
             break;
         }
     }
     if (st == ASN_OK) {
-        p->cur ^= (int)(n_steps & 1);
+        p->cur ^= state_flip(p->scheme, n_steps);
         p->steps_done += n_steps;
     }
     double acc[5] = {0, 0, 0, 0, 0};
     if (st == ASN_OK && hipEventSynchronize(ev.back()) != hipSuccess)
         st = fail(ASN_E_HIP, "hipEventSynchronize failed");
-    for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
-        hipEvent_t* e = &ev[(size_t)i * 5];
-        for (int k = 0; k < 5; ++k) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, e[k == 4 ? 0 : k], e[k == 4 ? 4 : k + 1]) != hipSuccess) {
-                st = fail(ASN_E_HIP, "hipEventElapsedTime failed");
-                break;
+    for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i)
+        for (int pass = 0; st == ASN_OK && pass < passes; ++pass) {
+            hipEvent_t* e = &ev[(size_t)i * per + 5 * (size_t)pass];
+            for (int k = 0; k < 5; ++k) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, e[k == 4 ? 0 : k], e[k == 4 ? 4 : k + 1]) != hipSuccess) {
+                    st = fail(ASN_E_HIP, "hipEventElapsedTime failed");
+                    break;
+                }
+                acc[k] += ms;
             }
-            acc[k] += ms;
         }
-    }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     if (st != ASN_OK) return st;
@@ -633,6 +647,8 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
         if (!probs[i]) return fail(ASN_E_INVALID, "NULL problem in batch");
         if (probs[i]->dtype != probs[0]->dtype)
             return fail(ASN_E_INVALID, "problems of a batch must share the operand type");
+        if (probs[i]->scheme != probs[0]->scheme)
+            return fail(ASN_E_INVALID, "problems of a batch must share the time scheme");
         if (probs[i]->stream != probs[0]->stream)
             return fail(ASN_E_INVALID, "problems of a batch must share the HIP stream");
         for (int32_t j = 0; j < i; ++j)
@@ -642,6 +658,7 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
     b->probs.assign(probs, probs + n);
     b->n = n;
     b->dtype = probs[0]->dtype;
+    b->scheme = probs[0]->scheme;
     b->stream = probs[0]->stream;
     b->tab.resize(2 * (size_t)n);
     b->off.assign((size_t)asn::KT_COUNT * (n + 1), 0);
@@ -705,7 +722,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
             hipError_t e = hipSuccess;
             for (int64_t j = 0; j < n_steps && e == hipSuccess; ++j) {
                 args.s_par = (int)(j & 1);
-                e = asn::launch_step(args, b->grid, b->dtype, b->stream);
+                e = asn::launch_step(args, b->grid, b->dtype, b->scheme, b->stream);
             }
             const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -723,11 +740,11 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
     } else {
         for (int64_t j = 0; j < n_steps; ++j) {
             args.s_par = (int)(j & 1);
-            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->stream));
+            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->scheme, b->stream));
         }
     }
     for (int i = 0; i < b->n; ++i) {
-        b->probs[i]->cur ^= (int)(take[i] & 1);
+        b->probs[i]->cur ^= state_flip(b->scheme, take[i]);
         b->probs[i]->steps_done += take[i];
     }
     return ASN_OK;

@@ -1,6 +1,7 @@
 // Device kernels of the explicit as-S_N step (gfx950, wave64).
 //
-// One step (paper Section 3.2, eq. asSNeq, forward Euler + donor cell):
+// One step (paper Section 3.2, eq. asSNeq; forward Euler + donor cell, or the
+// paper's Heun + minmod scheme of Section 3.1 as two such passes):
 //   1. contraction  Y = K Psi  over ordinates, every cell      (MFMA, gemm_*)
 //   2. stream + collide psi^{n+1} from psi^n, Y, Phi^n          (HBM, stream_collide)
 //      also emits partial moments Phi^{n+1} and budget partials
@@ -540,6 +541,196 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     block_sum_256<2>(sums, gp(a.blk_part) + 2 * (size_t)local);
 }
 
+// ---------------------------------------------------------------------------
+// 2b. Heun stage with limited second-order upwind fluxes (paper Section 3.1).
+//     Per ordinate and axis a cell's slope is minmod(psi_i - psi_{i-1},
+//     psi_{i+1} - psi_i); a face carries the value reconstructed on its upwind
+//     side, psi_i + s_i / 2 or psi_{i+1} - s_{i+1} / 2, and cells outside the
+//     grid read 0 (vacuum, also for their slopes).  Same block shape as above,
+//     with a strip of 60 columns: lane l holds column x0 + l - 2, lanes 2..61
+//     update, and each wave reads two halo rows on each side.
+//       STAGE 1: out = psi + dt R(psi)                 (psi^n  -> psi^1)
+//       STAGE 2: out = (old + psi + dt R(psi)) / 2     (psi^1, old = psi^n)
+//     In stage 2 the output buffer holds psi^n: every lane reads its own cell
+//     of it before overwriting that cell, and no other lane reads it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float minmod(float a, float b) {
+    const float m = fminf(fabsf(a), fabsf(b));
+    return (a > 0.f && b > 0.f) ? m : ((a < 0.f && b < 0.f) ? -m : 0.f);
+}
+
+template <bool LP, int STAGE>
+__global__ __launch_bounds__(256) void muscl_kernel(BatchArgs B) {
+    constexpr int R = kRows;
+    int pi, local;
+    if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int bx = local % a.tiles_x;
+    const int by = (local / a.tiles_x) % a.tiles_y;
+    const int g = local / (a.tiles_x * a.tiles_y);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nx = a.nx, ny = a.ny;
+    const int64_t P = a.P, C = a.C;
+    const int x = bx * kStripXM + lane - 2;
+    const int ybase = by * kTileY + wave * R;
+    const int q0 = g * a.qchunk;
+    const int q1 = min(a.Q, q0 + a.qchunk);
+    const bool xok = x >= 0 && x < nx;
+    const bool outl = xok && lane >= 2 && lane <= 61;
+
+    float aa[R], bs[R], gs[R], ss[R], isov[R], fix[R], mx[R];
+    double phacc[R];
+    bool in[R];
+    uint32_t off_ld[R], off_st[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = ybase + r;
+        const bool yok = y < ny;
+        const uint32_t c = (uint32_t)(y * nx + x);
+        in[r] = outl && yok;
+        off_ld[r] = (xok && yok) ? 4u * c : kOOB;
+        off_st[r] = in[r] ? 4u * c : kOOB;
+        aa[r] = bs[r] = gs[r] = ss[r] = isov[r] = fix[r] = 0.f;
+        mx[r] = 0.f;
+        phacc[r] = 0.0;
+        if (in[r]) {
+            const float4 cf = gp(a.coef)[c];
+            aa[r] = cf.x;
+            bs[r] = cf.y;
+            gs[r] = cf.z;
+            ss[r] = cf.w;
+            isov[r] = gp(a.iso)[c];
+            if (LP) fix[r] = gp(a.fix)[c];
+        }
+    }
+    // halo rows ybase - 2, ybase - 1, ybase + R, ybase + R + 1
+    uint32_t off_h[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int yy = k < 2 ? ybase - 2 + k : ybase + R + (k - 2);
+        off_h[k] = (xok && yy >= 0 && yy < ny) ? 4u * (uint32_t)(yy * nx + x) : kOOB;
+    }
+    const bool edge = bx == 0 || bx == a.tiles_x - 1 || by == 0 || by == a.tiles_y - 1;
+    double defect = 0.0, outflow = 0.0;
+
+    struct Plane {
+        float v[R], y[R], h[4], o[R];
+    };
+    auto load = [&](int q, int dir, Plane& pn) {
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.psi + (size_t)q * P, C);
+        const __amdgpu_buffer_rsrc_t ry = plane_rsrc(a.Y + (size_t)q * P, C);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pn.v[r] = load_plane(rp, off_ld[r]);
+            pn.y[r] = load_plane(ry, off_ld[r]);
+        }
+        // eta > 0 takes two rows below and one above, eta < 0 the mirror image
+        pn.h[0] = load_plane(rp, (dir & 4) ? off_h[0] : kOOB);
+        pn.h[1] = load_plane(rp, (dir & 12) ? off_h[1] : kOOB);
+        pn.h[2] = load_plane(rp, (dir & 12) ? off_h[2] : kOOB);
+        pn.h[3] = load_plane(rp, (dir & 8) ? off_h[3] : kOOB);
+        if (STAGE == 2) {
+            const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
+#pragma unroll
+            for (int r = 0; r < R; ++r) pn.o[r] = load_plane(ro, off_st[r]);
+        }
+    };
+
+    Plane cur, nxt;
+    const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    QInfo qc = qtab[q0 < q1 ? q0 : 0];
+    if (q0 < q1) load(q0, qc.dir, cur);
+    for (int q = q0; q < q1; ++q) {
+        QInfo qn = qc;
+        if (q + 1 < q1) {
+            qn = qtab[q + 1];
+            load(q + 1, qn.dir, nxt);
+        }
+        const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
+        // column e[k] = row ybase - 2 + k
+        float e[R + 4];
+        e[0] = cur.h[0];
+        e[1] = cur.h[1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) e[r + 2] = cur.v[r];
+        e[R + 2] = cur.h[2];
+        e[R + 3] = cur.h[3];
+        // upwind face values along y: fy[k] = value on the face above row k - 2
+        // (eta > 0, k = 1..R+1 used) or below row k - 2 (eta < 0, k = 2..R+2 used)
+        float fy[R + 4];
+#pragma unroll
+        for (int k = 1; k < R + 3; ++k) {
+            const float sl = minmod(e[k] - e[k - 1], e[k + 1] - e[k]);
+            fy[k] = (qc.dir & 4) ? e[k] + 0.5f * sl : e[k] - 0.5f * sl;
+        }
+        float colsum = 0.f, o = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float v = cur.v[r];
+            const float vl = __shfl_up(v, 1, 64);
+            const float vr = __shfl_down(v, 1, 64);
+            const float sx = minmod(v - vl, vr - v);
+            float dfx = 0.f, fout_x = 0.f;
+            if (qc.dir & 1) {
+                const float f = v + 0.5f * sx;
+                dfx = f - __shfl_up(f, 1, 64);
+                fout_x = f;
+            } else if (qc.dir & 2) {
+                const float gl = v - 0.5f * sx;
+                dfx = gl - __shfl_down(gl, 1, 64);
+                fout_x = gl;
+            }
+            float dfy = 0.f, fout_y = 0.f;
+            if (qc.dir & 4) {
+                dfy = fy[r + 2] - fy[r + 1];
+                fout_y = fy[r + 2];
+            } else if (qc.dir & 8) {
+                dfy = fy[r + 2] - fy[r + 3];
+                fout_y = fy[r + 2];
+            }
+            const float col = gs[r] * ((cur.y[r] - fix[r]) - v) + bs[r] * (isov[r] - v);
+            const float nv = v - qc.cx * dfx - qc.cy * dfy - aa[r] * v + col + ss[r];
+            const float res = STAGE == 2 ? 0.5f * (cur.o[r] + nv) : nv;
+            store_plane(res, ro, off_st[r]);
+            phacc[r] += qc.w * (double)res;
+            colsum += in[r] ? col : 0.f;
+            if (LP) mx[r] = fmaxf(mx[r], in[r] ? fabsf(res) : 0.f);
+            if (edge && in[r]) {
+                // particles leaving through a boundary face: the reconstructed
+                // value on the face of the last cell, for directions that exit there
+                const int y = ybase + r;
+                if (((qc.dir & 1) && x == nx - 1) || ((qc.dir & 2) && x == 0)) o += qc.cx * fout_x;
+                if (((qc.dir & 4) && y == ny - 1) || ((qc.dir & 8) && y == 0)) o += qc.cy * fout_y;
+            }
+        }
+        defect += qc.w * (double)colsum;
+        outflow += qc.w * (double)o;
+        cur = nxt;
+        qc = qn;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (in[r]) gp(a.phi_part)[(size_t)g * P + (uint32_t)((ybase + r) * nx + x)] = phacc[r];
+    if (LP) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = ybase + r;
+            const int64_t c_first = (int64_t)y * nx + bx * kStripXM;
+            const int64_t b0 = c_first / kScaleBlock;
+            const int64_t cb = ((int64_t)y * nx + x) / kScaleBlock;
+            const unsigned bits = in[r] ? __float_as_uint(mx[r]) : 0u;
+            const unsigned m0 = wave_max_u32(cb == b0 ? bits : 0u);
+            const unsigned m1 = wave_max_u32(cb != b0 ? bits : 0u);
+            if (lane == 0 && y < ny) {
+                if (m0) atomicMax(&a.bmax_next[b0], m0);
+                if (m1) atomicMax(&a.bmax_next[b0 + 1], m1);
+            }
+        }
+    }
+    double sums[2] = {defect, outflow};
+    block_sum_256<2>(sums, gp(a.blk_part) + 2 * (size_t)local);
+}
+
 // Per-cell particle correction of the reduced-precision Y: the w-weighted sum of
 // Y over all ordinates (from the per-tile partials, fixed order) minus Phi, over W.
 __global__ __launch_bounds__(256) void particle_fix_kernel(BatchArgs B) {
@@ -584,10 +775,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
 // ---------------------------------------------------------------------------
 // 4. Budget: fold block partials into the record (one block, fixed order).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int init) {
+//    BUD_STEP    Euler step: M^{n+1} against M^n - A^n - O + S + D.
+//    BUD_STAGE1  Heun, first pass: checks the intermediate level M^1 against
+//                M^n + its full increment, and keeps half of that increment.
+//    BUD_STAGE2  Heun, second pass: M^{n+1} against M^n + half of each pass's
+//                increment (the new level is the mean of psi^n and psi^1 +
+//                dt R(psi^1)).
+//    BUD_INIT    after set_state: M^0.
+__global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int mode) {
     int pi, local;
     if (!locate(B, KT_BUDGET, blockIdx.x, pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const bool init = mode == BUD_INIT;
     const int n_blk = a.tiles_x * a.tiles_y * a.G;
     double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const ASN_G double* fp = gp(a.fin_part);
@@ -606,7 +805,7 @@ __global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int init) {
     block_sum_256<5>(s, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
-    if (!init) gp(B.steps_left)[pi] -= 1;
+    if (mode == BUD_STEP || mode == BUD_STAGE2) gp(B.steps_left)[pi] -= 1;
     ASN_G double* rec = gp(a.rec);
     const double m_next = a.area * tot[0];
     const double abs_next = a.area * tot[1];
@@ -620,14 +819,36 @@ __global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int init) {
     }
     const double def = a.area * tot[3];
     const double out = a.area * tot[4];
-    const double pred = rec[REC_MASS] - rec[REC_ABS_NEXT] - out + rec[REC_SRC_STEP] + def;
     const double ref = fmax(rec[REC_MASS0], rec[REC_MASS]);
-    const double rel = ref > 0.0 ? fabs(m_next - pred) / ref : fabs(m_next - pred);
-    rec[REC_ABS] += rec[REC_ABS_NEXT];
-    rec[REC_OUT] += out;
-    rec[REC_SRC] += rec[REC_SRC_STEP];
-    rec[REC_DEF] += def;
-    rec[REC_RES] = fmax(rec[REC_RES], rel);
+    auto residual = [&](double got, double pred) {
+        const double rel = ref > 0.0 ? fabs(got - pred) / ref : fabs(got - pred);
+        rec[REC_RES] = fmax(rec[REC_RES], rel);
+    };
+    if (mode == BUD_STEP) {
+        residual(m_next, rec[REC_MASS] - rec[REC_ABS_NEXT] - out + rec[REC_SRC_STEP] + def);
+        rec[REC_ABS] += rec[REC_ABS_NEXT];
+        rec[REC_OUT] += out;
+        rec[REC_SRC] += rec[REC_SRC_STEP];
+        rec[REC_DEF] += def;
+        rec[REC_STEPS] += 1.0;
+        rec[REC_MASS] = m_next;
+        rec[REC_ABS_NEXT] = abs_next;
+        return;
+    }
+    // Heun passes: each contributes half of its increment to the step
+    const double abs_in = mode == BUD_STAGE1 ? rec[REC_ABS_NEXT] : rec[REC_ABS_STAGE];
+    const double inc = -abs_in - out + rec[REC_SRC_STEP] + def;
+    rec[REC_ABS] += 0.5 * abs_in;
+    rec[REC_OUT] += 0.5 * out;
+    rec[REC_SRC] += 0.5 * rec[REC_SRC_STEP];
+    rec[REC_DEF] += 0.5 * def;
+    if (mode == BUD_STAGE1) {
+        residual(m_next, rec[REC_MASS] + inc);
+        rec[REC_HALF] = 0.5 * inc;
+        rec[REC_ABS_STAGE] = abs_next;
+        return;
+    }
+    residual(m_next, rec[REC_MASS] + rec[REC_HALF] + 0.5 * inc);
     rec[REC_STEPS] += 1.0;
     rec[REC_MASS] = m_next;
     rec[REC_ABS_NEXT] = abs_next;
@@ -674,8 +895,9 @@ void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
     out[KT_BUDGET] = 1;
 }
 
-hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, hipStream_t s,
-                       hipEvent_t* ev) {
+// One pass: contraction, stencil (kind 0 donor cell, 1 / 2 Heun stage), finalize, budget.
+static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, int stencil,
+                              int bud, hipStream_t s, hipEvent_t* ev) {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
@@ -689,17 +911,35 @@ hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, hipStream
         gemm_lp_kernel<2><<<grid[KT_GEMM], 256, 0, s>>>(b);
     if (dtype != 0) particle_fix_kernel<<<grid[KT_FIX], 256, 0, s>>>(b);
     mark(1);
-    if (dtype == 0)
-        stream_collide_kernel<false><<<grid[KT_SC], 256, 0, s>>>(b);
-    else
-        stream_collide_kernel<true><<<grid[KT_SC], 256, 0, s>>>(b);
+    const bool lp = dtype != 0;
+    if (stencil == 0) {
+        if (lp) stream_collide_kernel<true><<<grid[KT_SC], 256, 0, s>>>(b);
+        else stream_collide_kernel<false><<<grid[KT_SC], 256, 0, s>>>(b);
+    } else if (stencil == 1) {
+        if (lp) muscl_kernel<true, 1><<<grid[KT_SC], 256, 0, s>>>(b);
+        else muscl_kernel<false, 1><<<grid[KT_SC], 256, 0, s>>>(b);
+    } else {
+        if (lp) muscl_kernel<true, 2><<<grid[KT_SC], 256, 0, s>>>(b);
+        else muscl_kernel<false, 2><<<grid[KT_SC], 256, 0, s>>>(b);
+    }
     mark(2);
     finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
     mark(3);
-    budget_kernel<<<grid[KT_BUDGET], 256, 0, s>>>(b, 0);
+    budget_kernel<<<grid[KT_BUDGET], 256, 0, s>>>(b, bud);
     mark(4);
     if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
+                       hipEvent_t* ev) {
+    if (scheme != SCHEME_HEUN) return launch_pass(b, grid, dtype, 0, BUD_STEP, s, ev);
+    BatchArgs b1 = b;
+    b1.s_par = 0;
+    hipError_t e = launch_pass(b1, grid, dtype, 1, BUD_STAGE1, s, ev);
+    if (e != hipSuccess) return e;
+    b1.s_par = 1;
+    return launch_pass(b1, grid, dtype, 2, BUD_STAGE2, s, ev ? ev + 5 : nullptr);
 }
 
 __global__ void arm_kernel(int* steps_left, int* base, int n, ArmArgs v) {
@@ -722,7 +962,7 @@ hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s) {
     fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_next, nb, 0u);
     moments_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);
     finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(one, 1);
-    budget_kernel<<<1, 256, 0, s>>>(one, 1);
+    budget_kernel<<<1, 256, 0, s>>>(one, BUD_INIT);
     return hipGetLastError();
 }
 

@@ -28,8 +28,16 @@ enum {
     REC_STEPS = 7,     // steps covered
     REC_ABS_NEXT = 8,  // absorption increment of the current level
     REC_SRC_STEP = 9,  // source increment per step (constant)
+    REC_HALF = 10,     // Heun: half of the first stage's mass increment
+    REC_ABS_STAGE = 11,  // Heun: absorption increment of the intermediate level
     REC_LEN = 16
 };
+
+// Time schemes: forward Euler + donor cell; Heun + minmod-limited fluxes.
+enum { SCHEME_EULER = 0, SCHEME_HEUN = 1 };
+
+// Modes of the budget kernel.
+enum { BUD_STEP = 0, BUD_INIT = 1, BUD_STAGE1 = 2, BUD_STAGE2 = 3 };
 
 // Cells per block of the reduced-precision operand scale.
 constexpr int kScaleBlock = 256;
@@ -48,6 +56,8 @@ constexpr int kBK_LP = 32;
 // outer lanes read the neighbouring columns) x 4 wavefronts x kRows rows each.
 constexpr int kRows = 4;
 constexpr int kStripX = 62;
+// The limited (two-cell) stencil: 60 updated columns, two halo lanes per side.
+constexpr int kStripXM = 60;
 constexpr int kTileY = 4 * kRows;
 
 struct StepArgs {
@@ -106,11 +116,15 @@ struct BatchArgs {
 // Blocks of each kernel kind for one problem.
 void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]);
 
-// One step for every problem of the batch; if ev is given, ev[0..4] are recorded
-// before, between and after the four stages (contraction, stream + collide,
-// finalize, budget).
-hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, hipStream_t s,
+// One step for every problem of the batch.  Euler: one pass of contraction,
+// stream + collide, finalize and budget, on the buffers selected by b.s_par.
+// Heun: two such passes (s_par 0, then 1), so the state returns to its buffer.
+// If ev is given, ev[5 k .. 5 k + 4] are recorded before, between and after
+// the four kernels of pass k.
+hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
                        hipEvent_t* ev = nullptr);
+// Passes per step of a scheme.
+inline int passes_per_step(int scheme) { return scheme == SCHEME_HEUN ? 2 : 1; }
 // Arm a batch: steps_left[i] = limit[i] and base[i] = cur[i], i < n <= kMaxArm.
 constexpr int kMaxArm = 64;
 struct ArmArgs {

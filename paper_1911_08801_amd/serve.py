@@ -28,6 +28,7 @@ class Job:
     spec: Any
     arrival: float
     dtype: str = "f32"
+    scheme: str = "euler"           # "euler" (donor cell) or "heun" (Heun + minmod)
     status: str = "queued"          # queued, active, done, failed, rejected, cancelled
     bytes: int = 0
     steps_total: int = 0
@@ -56,19 +57,19 @@ class GpuBackend:
         self.asn = asn
         self.stream = stream if stream is not None else torch.cuda.Stream()
 
-    def bytes_needed(self, spec, dtype: str) -> int:
+    def bytes_needed(self, spec, dtype: str, scheme: str = "euler") -> int:
         a = self.asn
         grid = a.make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
         quad = a.asn_quadrature(spec.n_polar, spec.n_azim, 0, None, None,
                                 getattr(spec, "ico_order", 0))
-        return a.asn_workspace_size(grid, quad, a.make_options(dtype, cfl=spec.cfl))
+        return a.asn_workspace_size(grid, quad, a.make_options(dtype, cfl=spec.cfl, scheme=scheme))
 
     def free_bytes(self) -> int:
         return int(self.torch.cuda.mem_get_info()[0])
 
-    def create(self, spec, dtype: str):
+    def create(self, spec, dtype: str, scheme: str = "euler"):
         with self.torch.cuda.stream(self.stream):
-            p = self.asn.from_spec(spec, dtype=dtype)
+            p = self.asn.from_spec(spec, dtype=dtype, scheme=scheme)
         return p, self.asn.asn_info(p)["steps_to_tfinal"]
 
     def make_batch(self, handles):
@@ -148,8 +149,8 @@ class Server:
         waiting: List[Job] = []
         active: List[Job] = []
         used = 0
-        batches: Dict[str, Any] = {}
-        batch_members: Dict[str, List[int]] = {}
+        batches: Dict[Any, Any] = {}
+        batch_members: Dict[Any, List[int]] = {}
         chunks = builds = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0
@@ -166,7 +167,7 @@ class Server:
             while waiting and len(active) < self.max_slots:
                 j = waiting[0]
                 if not j.bytes:
-                    j.bytes = self.b.bytes_needed(j.spec, j.dtype)
+                    j.bytes = self.b.bytes_needed(j.spec, j.dtype, j.scheme)
                 if j.bytes > self.budget:
                     j.status, j.error = "rejected", "larger than the whole device budget"
                     waiting.pop(0)
@@ -175,7 +176,7 @@ class Server:
                     break
                 waiting.pop(0)
                 try:
-                    j.handle, j.steps_total = self.b.create(j.spec, j.dtype)
+                    j.handle, j.steps_total = self.b.create(j.spec, j.dtype, j.scheme)
                 except Exception as e:  # noqa: BLE001 - any set-up failure fails this job only
                     j.status, j.error = "failed", f"create: {e}"
                     continue
@@ -191,10 +192,10 @@ class Server:
                     self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
                 continue
 
-            # one batch per operand type; rebuilt when its members change
-            groups: Dict[str, List[Job]] = {}
+            # one batch per operand type and time scheme; rebuilt when its members change
+            groups: Dict[Any, List[Job]] = {}
             for j in active:
-                groups.setdefault(j.dtype, []).append(j)
+                groups.setdefault((j.dtype, j.scheme), []).append(j)
             for dt in list(batches):
                 if dt not in groups:
                     self.b.drop_batch(batches.pop(dt))
@@ -241,9 +242,10 @@ class Server:
         return Report(jobs=jobs, makespan=now(), chunks=chunks, batch_builds=builds)
 
 
-def jobs_from_requests(requests, dtype: str = "f32") -> List[Job]:
+def jobs_from_requests(requests, dtype: str = "f32", scheme: str = "euler") -> List[Job]:
     """Jobs from objects with rid, arrival and problem() (a problem description)."""
-    return [Job(rid=r.rid, spec=r.problem(), arrival=r.arrival, dtype=dtype) for r in requests]
+    return [Job(rid=r.rid, spec=r.problem(), arrival=r.arrival, dtype=dtype, scheme=scheme)
+            for r in requests]
 
 
 def poisson_rate_for(load: float, capacity_updates_per_s: float, mean_updates: float) -> float:

@@ -10,10 +10,11 @@ import workloads as wl
 from oracle import asn_oracle as o
 
 
-def gpu_run(asn, spec, n_steps, psi0=None, dtype="f32", norm="sym", eps_override=0.0):
+def gpu_run(asn, spec, n_steps, psi0=None, dtype="f32", norm="sym", eps_override=0.0,
+            scheme="euler", dt=0.0):
     """Advance ``spec`` on the GPU; returns (state, phi, budget, info)."""
     p = asn.from_spec(spec, dtype=dtype, norm=norm, eps_override=eps_override,
-                      set_initial_state=psi0 is None)
+                      set_initial_state=psi0 is None, scheme=scheme, dt_override=dt)
     try:
         if psi0 is not None:
             asn.asn_set_state(p, psi0)
@@ -24,11 +25,12 @@ def gpu_run(asn, spec, n_steps, psi0=None, dtype="f32", norm="sym", eps_override
         p.close()
 
 
-def oracle_run(spec, n_steps, psi0=None, norm="sym", eps=None):
-    st = o.setup(spec, mode=norm, eps=eps)
+def oracle_run(spec, n_steps, psi0=None, norm="sym", eps=None, scheme="euler", dt=None):
+    st = o.setup(spec, mode=norm, eps=eps, dt=dt)
     psi = (spec.psi0() if psi0 is None else psi0).astype(np.float64)
+    step = o.heun_step if scheme == "heun" else o.step
     for _ in range(n_steps):
-        psi, _ = o.step(psi, st, want_budget=False)
+        psi, _ = step(psi, st, want_budget=False)
     return psi, o.scalar_flux(psi, st.w), st
 
 

@@ -143,6 +143,27 @@ def test_create_validates_before_touching_the_device():
     assert _raw_create(grid=asn.make_grid(4, 3, 1.0, 1.0, 0.0, 1.0))[0] == asn.ASN_E_INVALID
 
 
+def test_create_rejects_unknown_scheme():
+    lib = asn._lib
+    g = asn.make_grid(4, 3, 0.0, 1.0, 0.0, 1.0)
+    q = asn.asn_quadrature(2, 4, 0, None, None, 0)
+    f = np.zeros(12, dtype=np.float32)
+    for scheme, want in ((7, asn.ASN_E_INVALID), (-1, asn.ASN_E_INVALID)):
+        opt = asn.make_options()
+        opt.scheme = scheme
+        h = ctypes.c_void_p()
+        st = lib.asn_create(ctypes.byref(g), ctypes.byref(q), asn._fptr(f), asn._fptr(f),
+                            asn._fptr(f), None, 4.5, 1.0, ctypes.byref(opt), None, None, 0,
+                            ctypes.byref(h))
+        assert st == want and not h.value
+    # both schemes keep two state buffers: the Heun stages need no more memory
+    g2 = asn.make_grid(200, 120, 0.0, 1.0, 0.0, 1.0)
+    q2 = asn.asn_quadrature(4, 8, 0, None, None, 0)
+    e = asn.asn_workspace_size(g2, q2, asn.make_options(scheme="euler"))
+    h = asn.asn_workspace_size(g2, q2, asn.make_options(scheme="heun"))
+    assert abs(h - e) < 0.01 * e
+
+
 def test_destroy_accepts_null_and_status_strings():
     assert asn._lib.asn_destroy(None) == asn.ASN_OK
     for s in range(-6, 1):

@@ -1,0 +1,204 @@
+"""GPU parity of the Heun + minmod scheme (the paper's explicit scheme, Section
+3.1) against the FP64 oracle's heun_step on the same seeded inputs.  FP32 bar:
+one-step states element by element within a few FP32 roundings of the largest
+value, scalar-flux relative L2 <= 1e-5 over many steps."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import asn_oracle as o
+from oracle import linesource_ref as L
+from gpu_util import fp32_budget_floor, gpu_run, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1911_08801_amd import asn  # noqa: E402
+
+GRIDS = [(1, 1), (2, 3), (1, 7), (9, 1), (37, 9), (60, 16), (61, 17), (121, 33), (200, 3)]
+QUADS = [(1, 4), (2, 4), (4, 8), (8, 16)]
+
+
+@pytest.mark.parametrize("nx,ny", GRIDS)
+@pytest.mark.parametrize("n_polar,n_azim", QUADS)
+def test_one_step_matches_oracle(nx, ny, n_polar, n_azim):
+    spec = wl.random_problem(nx * 71 + ny, nx, ny, n_polar=n_polar, n_azim=n_azim, beta=4.5)
+    psi0 = wl.random_state(nx + 5 * ny, spec.q, ny, nx)
+    state, phi, bud, info = gpu_run(asn, spec, 1, psi0=psi0, scheme="heun")
+    ref, phi_ref, st = oracle_run(spec, 1, psi0=psi0, scheme="heun")
+    assert info["steps_done"] == 1
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(state - ref)) <= 8e-6 * scale
+    assert np.max(np.abs(phi - phi_ref)) <= 8e-6 * np.abs(phi_ref).max()
+
+
+@pytest.mark.parametrize("norm", ["sym", "row"])
+def test_multi_step_random_fields(norm):
+    spec = wl.random_problem(15, 70, 33, n_polar=4, n_azim=8, beta=4.5, t_final=0.3)
+    psi0 = wl.random_state(13, spec.q, 33, 70)
+    state, phi, bud, _ = gpu_run(asn, spec, 12, psi0=psi0, norm=norm, scheme="heun")
+    ref, phi_ref, _ = oracle_run(spec, 12, psi0=psi0, norm=norm, scheme="heun")
+    assert rel_l2(phi, phi_ref) <= 1e-5
+    assert rel_l2(state, ref) <= 1e-5
+
+
+def test_line_source_50_q128_full_run_and_budget():
+    spec = wl.line_source(50, n_polar=8, sigma_as=1.0)
+    state, phi, bud, info = gpu_run(asn, spec, 24, scheme="heun")
+    _, st, hist = o.run_heun(spec, n_steps=24, budget=True)
+    phi_ref = o.scalar_flux(_, st.w)
+    assert rel_l2(phi, phi_ref) <= 1e-5
+    assert bud["steps"] == 24
+    assert bud["mass"] == pytest.approx(hist[-1]["mass_next"], rel=1e-6)
+    out_ref = sum(st.dt * b["outflow"] for b in hist)
+    abs_ref = sum(st.dt * b["absorption"] for b in hist)
+    assert bud["outflow"] == pytest.approx(out_ref, rel=1e-5)
+    assert bud["absorption"] == pytest.approx(abs_ref, rel=1e-5, abs=1e-12)
+    assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
+
+
+def test_checkerboard_budget_with_absorption_and_source():
+    # At 70^2 cells the streaming CFL step makes dt sigma_a too large for an
+    # explicit scheme (the discrete solution itself blows up), so a smaller dt.
+    spec = wl.checkerboard(70, n_polar=4, sigma_as=5.0, t_final=0.64)
+    state, phi, bud, info = gpu_run(asn, spec, 40, scheme="heun", dt=0.016)
+    _, st, hist = o.run_heun(spec, n_steps=40, budget=True, st=o.setup(spec, dt=0.016))
+    phi_ref = o.scalar_flux(_, st.w)
+    assert rel_l2(phi, phi_ref) <= 1e-5
+    assert bud["absorption"] == pytest.approx(sum(st.dt * b["absorption"] for b in hist), rel=1e-5)
+    assert bud["source"] == pytest.approx(sum(st.dt * b["source"] for b in hist), rel=1e-6)
+    assert abs(bud["defect"]) <= 1e-6 * max(bud["mass"], 1e-30) + 1e-12
+
+
+def test_twelve_ordinates_artificial_scattering_ratio():
+    # The paper's parameter-study point on the paper's scheme: 12 icosahedron
+    # ordinates, 50^2 cells, beta = 4.5: sigma_as = 5 reaches 37.8 % of the
+    # sigma_as = 0 error of Phi against the transport reference.
+    ref = 4 * math.pi * L.line_source_on_grid(50, 1.0, wl.LINE_SOURCE_DELTA, n_k=800, n_tau=1200)
+    err = {}
+    for s_as in (0.0, 5.0):
+        spec = wl.line_source(50, sigma_as=s_as)
+        spec.ico_order = 2
+        _, _, _, info = gpu_run(asn, spec, 0, scheme="heun")
+        _, phi, _, _ = gpu_run(asn, spec, info["steps_to_tfinal"], scheme="heun")
+        _, phi_ref, _ = oracle_run(spec, info["steps_to_tfinal"], scheme="heun")
+        assert rel_l2(phi, phi_ref) <= 1e-5
+        err[s_as] = rel_l2(phi, ref)
+    assert 0.3 < err[5.0] / err[0.0] < 0.5
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_reduced_precision_within_bound_of_exact_oracle(dtype):
+    spec = wl.line_source(50, n_polar=8, sigma_as=5.0)
+    state, phi, bud, _ = gpu_run(asn, spec, 24, dtype=dtype, scheme="heun")
+    _, phi_ref, st = oracle_run(spec, 24, scheme="heun")
+    assert rel_l2(phi, phi_ref) <= 2e-3
+    assert abs(bud["defect"]) <= 1e-5 * bud["mass0"]
+
+
+def test_isotropic_state_preserved_in_interior():
+    spec = wl.random_problem(21, 40, 30, n_polar=4, n_azim=8, beta=4.5)
+    spec.sigma_a[:] = 0.0
+    spec.source[:] = 0.0
+    psi0 = np.full((spec.q, 30, 40), 1.75, dtype=np.float32)
+    state, *_ = gpu_run(asn, spec, 3, psi0=psi0, scheme="heun")
+    assert np.max(np.abs(state[:, 12:18, 12:28] - 1.75)) <= 8e-7 * 1.75
+
+
+def test_state_stays_in_its_buffer_and_runs_are_reproducible():
+    spec = wl.random_problem(8, 90, 41, n_polar=8, n_azim=16, beta=4.5)
+    psi0 = wl.random_state(1, spec.q, 41, 90)
+    p = asn.from_spec(spec, set_initial_state=False, scheme="heun")
+    asn.asn_set_state(p, psi0)
+    asn.asn_step(p, 3)
+    a = asn.asn_get_state(p)
+    asn.asn_step(p, 4)
+    b = asn.asn_get_state(p)
+    p.close()
+    q = asn.from_spec(spec, set_initial_state=False, scheme="heun")
+    asn.asn_set_state(q, psi0)
+    asn.asn_step(q, 7)
+    assert np.array_equal(asn.asn_get_state(q), b)
+    q.close()
+    ref, _, _ = oracle_run(spec, 3, psi0=psi0, scheme="heun")
+    assert rel_l2(a, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batch_equals_alone_bitwise(dtype):
+    specs = [wl.line_source(37, n_polar=4, sigma_as=2.0, t_final=0.3),
+             wl.checkerboard(70, n_polar=2, sigma_as=4.0, t_final=0.5),
+             wl.random_problem(3, 90, 41, n_polar=8, n_azim=16, beta=4.5)]
+    limits = [9, 5, 12]
+    alone = []
+    for s, n in zip(specs, limits):
+        p = asn.from_spec(s, dtype=dtype, scheme="heun")
+        asn.asn_step(p, n)
+        alone.append((asn.asn_get_state(p), asn.asn_mass_budget(p)))
+        p.close()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        probs = [asn.from_spec(s, dtype=dtype, scheme="heun") for s in specs]
+        b = asn.asn_batch_create(probs)
+        for k in range(3):                       # graph replays of 4 steps
+            asn.asn_batch_step(b, 4, limits=[max(0, l - 4 * k) for l in limits])
+            torch.zeros(16, device="cuda").add_(1.0)
+        b.close()
+        for p, a in zip(probs, alone):
+            assert np.array_equal(asn.asn_get_state(p), a[0])
+            assert asn.asn_mass_budget(p) == a[1]
+            p.close()
+    torch.cuda.synchronize()
+
+
+def test_batch_rejects_mixed_schemes():
+    s = wl.line_source(20, n_polar=2)
+    p1 = asn.from_spec(s, scheme="euler")
+    p2 = asn.from_spec(s, scheme="heun")
+    with pytest.raises(asn.AsnError):
+        asn.asn_batch_create([p1, p2])
+    p1.close()
+    p2.close()
+
+
+def test_step_timed_covers_both_passes():
+    spec = wl.line_source(100, n_polar=8, sigma_as=1.0)
+    p = asn.from_spec(spec, scheme="heun")
+    ms = asn.asn_step_timed(p, 4)
+    assert asn.asn_info(p)["steps_done"] == 4
+    p.close()
+    assert all(v > 0 for v in ms.values())
+    assert ms["step"] >= 0.9 * (ms["contraction"] + ms["stream_collide"])
+
+
+@pytest.mark.slow
+def test_full_size_400_q512_one_step_sampled():
+    spec = wl.line_source(400, n_polar=16, sigma_as=5.0)
+    rng = np.random.default_rng(4)
+    Q, ny, nx = spec.q, spec.ny, spec.nx
+    a1 = (0.5 + rng.random(Q)).astype(np.float32)
+    a2 = rng.standard_normal(Q).astype(np.float32) * np.float32(0.3)
+    psi0 = (a1[:, None, None] * spec.psi0_cell[None] + a2[:, None, None]
+            * np.float32(spec.psi0_cell.mean())).astype(np.float32)
+    p = asn.from_spec(spec, set_initial_state=False, scheme="heun")
+    asn.asn_set_state(p, psi0)
+    asn.asn_step(p, 1)
+    got = asn.asn_get_state(p)
+    p.close()
+    st = o.setup(spec)
+    n = 60                     # about 0.3 s of oracle work per entry
+    qs = rng.integers(0, Q, n)
+    js = rng.integers(0, ny, n)
+    iis = rng.integers(0, nx, n)
+    edge = np.array([[0, 0], [0, nx - 1], [ny - 1, 0], [ny - 1, nx - 1], [1, nx // 2],
+                     [ny // 2, 1], [ny - 2, nx // 2], [ny // 2, nx - 2], [200, 199], [200, 200]])
+    k = len(edge) * 2
+    js[:k] = np.repeat(edge[:, 0], 2)
+    iis[:k] = np.repeat(edge[:, 1], 2)
+    ref = o.heun_step_entries(psi0, st, qs, js, iis)
+    diff = np.abs(got[qs, js, iis].astype(np.float64) - ref)
+    assert np.max(diff / np.maximum(np.abs(ref), 1e-3 * np.abs(psi0).max())) <= 8e-6

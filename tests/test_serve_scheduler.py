@@ -30,19 +30,25 @@ class FakeBackend:
         self.used = self.peak = 0
         self.max_batch = 0
         self.batches_seen = []
+        self.created = []
+        self.kinds = {}
 
-    def bytes_needed(self, spec, dtype):
+    def bytes_needed(self, spec, dtype, scheme="euler"):
         return spec.nx * spec.ny * spec.n_polar * spec.n_azim * 12
 
     def free_bytes(self):
         return self.free
 
-    def create(self, spec, dtype):
+    def create(self, spec, dtype, scheme="euler"):
         self.used += self.bytes_needed(spec, dtype)
         self.peak = max(self.peak, self.used)
-        return FakeHandle(spec, max(1, int(round(spec.t_final * 20)))), max(1, int(round(spec.t_final * 20)))
+        self.created.append((dtype, scheme))
+        h = FakeHandle(spec, max(1, int(round(spec.t_final * 20))))
+        self.kinds[id(h)] = (dtype, scheme)
+        return h, h.total
 
     def make_batch(self, handles):
+        assert len({self.kinds.get(id(h)) for h in handles}) == 1
         self.max_batch = max(self.max_batch, len(handles))
         self.batches_seen.append([id(h) for h in handles])
         return list(handles)
@@ -151,3 +157,15 @@ def test_cancellation_releases_the_request():
     st = {j.rid: j.status for j in rep.jobs}
     assert st[jobs[0].rid] == "cancelled" and be.used == 0
     assert sum(v == "done" for v in st.values()) == 5
+
+
+def test_batches_never_mix_operand_types_or_schemes():
+    clk = Clock()
+    be = FakeBackend(clk)
+    jobs = _jobs(24, seed=3, rate=100.0)
+    for k, j in enumerate(jobs):
+        j.dtype = ("f32", "bf16")[k % 2]
+        j.scheme = ("euler", "heun")[(k // 2) % 2]
+    rep = Server(be, hbm_budget=10 ** 9, chunk=4, clock=clk, sleep=clk.sleep).serve(jobs)
+    assert all(j.status == "done" for j in rep.jobs)
+    assert set(be.created) == {("f32", "euler"), ("bf16", "euler"), ("f32", "heun"), ("bf16", "heun")}

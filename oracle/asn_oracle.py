@@ -253,6 +253,39 @@ def cfl_time_step(omega: np.ndarray, dx: float, dy: float, cfl: float,
     return t_final / n, n
 
 
+def stability_number(omega: np.ndarray, K: np.ndarray, dx: float, dy: float, dt: float,
+                     sigma_s: np.ndarray, sigma_a: np.ndarray, sigma_as: np.ndarray) -> float:
+    """z = dt [2 max_q r_q + max_c (sigma_a + sigma_s + 2 (1 - min_q K_qq) sigma_as)],
+    r_q = |xi_q|/dx + |eta_q|/dy.
+
+    In a region of uniform material a state that alternates in sign from cell to
+    cell is moved by the donor-cell fluxes at rate 2 r_q (each face passes the
+    neighbour's opposite value), and collisions act on its ordinate vector with
+    (sigma_a + sigma_s + sigma_as) I - sigma_as K - sigma_s (isotropic
+    projection).  Scaled by the square roots of the weights the whole rate
+    matrix is symmetric for the symmetric K, so its eigenvalues are real and, by
+    Weyl's inequality, at most the bracket: Gershgorin's theorem puts every
+    eigenvalue of K (rows summing to one) at or above 2 min_q K_qq - 1, and the
+    isotropic projection only removes particles.  Forward Euler and Heun damp a
+    real mode only while dt times its rate is in [0, 2].
+    """
+    r = float(np.max(np.abs(omega[:, 0]) / dx + np.abs(omega[:, 1]) / dy))
+    g = 2.0 * (1.0 - float(np.min(np.diag(K))))
+    m = float(np.max(np.asarray(sigma_a, np.float64) + np.asarray(sigma_s, np.float64)
+                     + g * np.asarray(sigma_as, np.float64)))
+    return dt * (2.0 * r + m)
+
+
+def stiff_time_step(omega: np.ndarray, K: np.ndarray, dx: float, dy: float, cfl: float,
+                    t_final: float, sigma_s, sigma_a, sigma_as) -> Tuple[float, int]:
+    """cfl_time_step with dt_max also limited so that stability_number <= 2 cfl."""
+    rate = float(np.max(np.abs(omega[:, 0]) / dx + np.abs(omega[:, 1]) / dy))
+    z1 = stability_number(omega, K, dx, dy, 1.0, sigma_s, sigma_a, sigma_as)
+    dt_max = min(cfl / rate, 2.0 * cfl / z1)
+    n = max(1, int(math.ceil(t_final / dt_max * (1.0 - 1e-12))))
+    return t_final / n, n
+
+
 @dataclasses.dataclass
 class Setup:
     omega: np.ndarray
@@ -276,8 +309,12 @@ class Setup:
 
 def setup(problem, mode: str = "sym", eps: Optional[float] = None,
           cfl: Optional[float] = None, omega: Optional[np.ndarray] = None,
-          w: Optional[np.ndarray] = None, dt: Optional[float] = None) -> Setup:
-    """Build quadrature, K and dt for a workloads.Problem (all FP64)."""
+          w: Optional[np.ndarray] = None, dt: Optional[float] = None,
+          dt_rule: str = "streaming") -> Setup:
+    """Build quadrature, K and dt for a workloads.Problem (all FP64).
+
+    dt_rule "streaming" is the CFL rule on the streaming alone; "stiff" also keeps
+    stability_number <= 2 cfl."""
     if omega is None:
         if getattr(problem, "ico_order", 0):
             omega, w = icosahedron_quadrature(problem.ico_order)
@@ -288,8 +325,12 @@ def setup(problem, mode: str = "sym", eps: Optional[float] = None,
     K = as_kernel_matrix(omega, w, eps, mode)
     dx = (problem.x_max - problem.x_min) / problem.nx
     dy = (problem.y_max - problem.y_min) / problem.ny
-    if dt is None:
-        dt, n = cfl_time_step(omega, dx, dy, problem.cfl if cfl is None else cfl, problem.t_final)
+    c = problem.cfl if cfl is None else cfl
+    if dt is None and dt_rule == "stiff":
+        dt, n = stiff_time_step(omega, K, dx, dy, c, problem.t_final, problem.sigma_s,
+                                problem.sigma_a, problem.sigma_as)
+    elif dt is None:
+        dt, n = cfl_time_step(omega, dx, dy, c, problem.t_final)
     else:
         n = max(1, int(round(problem.t_final / dt)))
     f64 = lambda a: np.asarray(a, dtype=np.float64)

@@ -68,6 +68,16 @@ enum { ASN_NORM_SYM = 0, ASN_NORM_ROW = 1 };
  *                   psi^{n+1} = (psi + psi^1 + dt R(psi^1)) / 2. */
 enum { ASN_SCHEME_EULER = 0, ASN_SCHEME_HEUN = 1 };
 
+/* Time-step rule.  Both start from dt_max = cfl / max_q(|xi_q|/dx + |eta_q|/dy)
+ * and take dt = t_final / n, n = ceil(t_final / dt_max).
+ * ASN_DT_STREAMING: that rule alone (Section 4.1; CFL on the streaming).
+ * ASN_DT_STIFF:     dt_max is also limited so that the stability number (see
+ *                   asn_stability) is at most 2 cfl.  For strongly absorbing cells
+ *                   on coarse grids the streaming rule alone leaves the explicit
+ *                   schemes' stability interval and the discrete solution grows
+ *                   without bound; this rule keeps every problem inside it. */
+enum { ASN_DT_STREAMING = 0, ASN_DT_STIFF = 1 };
+
 #define ASN_BUDGET_LEN 8
 
 /* Uniform grid of nx * ny cells covering [x_min, x_max] x [y_min, y_max]. */
@@ -99,6 +109,7 @@ typedef struct {
     double dt_override;     /* > 0: fixed dt (still subject to the CFL bound)                     */
     int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
     int32_t scheme;         /* ASN_SCHEME_EULER (default) or ASN_SCHEME_HEUN                     */
+    int32_t dt_rule;        /* ASN_DT_STREAMING (default) or ASN_DT_STIFF                        */
 } asn_options;
 
 typedef struct asn_problem_s* asn_problem;
@@ -171,6 +182,21 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit);
 
 /* Synchronise the batch's stream and free its tables and graphs.  NULL accepted. */
 asn_status asn_batch_destroy(asn_batch b);
+
+/* Stability number of the problem's dt:
+ *   z = dt [ 2 max_q (|xi_q|/dx + |eta_q|/dy)
+ *            + max_c (sigma_a + sigma_s + 2 (1 - min_q K_qq) sigma_as) ].
+ * In a region of uniform material, a state that alternates in sign from cell to
+ * cell decays at a rate given by the eigenvalues of 2 diag(r_q) + (sigma_a +
+ * sigma_s + sigma_as) I - sigma_as K - sigma_s (isotropic projection); for the
+ * symmetric normalisation these are real and at most the bracket (Weyl's
+ * inequality, with the eigenvalues of K at least 2 min_q K_qq - 1 by
+ * Gershgorin's theorem).  Forward Euler and Heun are stable for a real decay
+ * rate only while dt times it lies in [0, 2]; z <= 2 therefore rules out the
+ * growth of such modes, and z above 2 is where the streaming rule alone can let
+ * the run grow without bound (coarse grids, strong absorbers).
+ * Errors: ASN_E_INVALID. */
+asn_status asn_stability(asn_problem p, double* z);
 
 /* Run n_steps exactly like asn_step while recording HIP events on the problem's
  * stream between its kernels; synchronises.  kernel_ms[k] receives the average

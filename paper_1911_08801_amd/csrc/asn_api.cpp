@@ -112,7 +112,7 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme) {
 struct asn_problem_s {
     int nx = 0, ny = 0;
     Layout L;
-    double dx = 0, dy = 0, dt = 0, W = 0, eps = 0;
+    double dx = 0, dy = 0, dt = 0, W = 0, eps = 0, stability = 0;
     int64_t n_to_tfinal = 0, steps_done = 0;
     int dtype = 0, norm = 0, scheme = 0;
     hipStream_t stream = nullptr;
@@ -355,6 +355,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         return fail(ASN_E_INVALID, "unknown normalization");
     if (opt.scheme != ASN_SCHEME_EULER && opt.scheme != ASN_SCHEME_HEUN)
         return fail(ASN_E_INVALID, "unknown scheme");
+    if (opt.dt_rule != ASN_DT_STREAMING && opt.dt_rule != ASN_DT_STIFF)
+        return fail(ASN_E_INVALID, "unknown dt_rule");
     if (!(opt.cfl > 0.0)) return fail(ASN_E_INVALID, "cfl must be > 0");
     if (opt.cfl > 1.0) return fail(ASN_E_UNSTABLE, "cfl above 1 is unstable for the explicit step");
     if (!(t_final > 0.0) || !std::isfinite(t_final)) return fail(ASN_E_INVALID, "t_final must be > 0");
@@ -386,8 +388,22 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     p->W = W;
     p->eps = opt.eps_override > 0.0 ? opt.eps_override : kernel_beta / Q;
 
+    // kernel matrix
+    std::vector<double> K;
+    std::string err;
+    if (!cached_kernel(Q, om, w, p->eps, p->norm == ASN_NORM_SYM ? 0 : 1, K, err)) {
+        delete p;
+        return fail(ASN_E_UNSUPPORTED, err);
+    }
+
     // time step
-    asn::cfl_time_step(Q, om.data(), p->dx, p->dy, opt.cfl, t_final, p->dt, p->n_to_tfinal);
+    const double srate = asn::stability_rate(Q, om.data(), K.data(), p->dx, p->dy, C, sigma_a,
+                                             sigma_s, sigma_as);
+    if (opt.dt_rule == ASN_DT_STIFF)
+        asn::stiff_time_step(Q, om.data(), p->dx, p->dy, srate, opt.cfl, t_final, p->dt,
+                             p->n_to_tfinal);
+    else
+        asn::cfl_time_step(Q, om.data(), p->dx, p->dy, opt.cfl, t_final, p->dt, p->n_to_tfinal);
     if (opt.dt_override > 0.0) {
         double rate = 0.0;
         for (int q = 0; q < Q; ++q)
@@ -399,14 +415,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         p->dt = opt.dt_override;
         p->n_to_tfinal = (int64_t)std::llround(t_final / p->dt);
     }
-
-    // kernel matrix
-    std::vector<double> K;
-    std::string err;
-    if (!cached_kernel(Q, om, w, p->eps, p->norm == ASN_NORM_SYM ? 0 : 1, K, err)) {
-        delete p;
-        return fail(ASN_E_UNSUPPORTED, err);
-    }
+    p->stability = p->dt * srate;
 
     p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme);
     const Layout& L = p->L;
@@ -805,6 +814,12 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
     if (steps_done) *steps_done = p->steps_done;
     if (steps_to_tfinal) *steps_to_tfinal = p->n_to_tfinal;
     if (q) *q = p->L.Q;
+    return ASN_OK;
+}
+
+asn_status asn_stability(asn_problem p, double* z) {
+    if (!p || !z) return fail(ASN_E_INVALID, "NULL argument");
+    *z = p->stability;
     return ASN_OK;
 }
 

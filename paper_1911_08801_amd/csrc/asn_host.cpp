@@ -250,6 +250,31 @@ void cfl_time_step(int Q, const double* om, double dx, double dy, double cfl, do
     dt = t_final / (double)n;
 }
 
+double stability_rate(int Q, const double* om, const double* K, double dx, double dy, int64_t C,
+                      const float* sigma_a, const float* sigma_s, const float* sigma_as) {
+    double r = 0.0, kmin = 1.0;
+    for (int q = 0; q < Q; ++q) {
+        r = std::fmax(r, std::fabs(om[3 * q]) / dx + std::fabs(om[3 * q + 1]) / dy);
+        kmin = std::fmin(kmin, K[(size_t)q * Q + q]);
+    }
+    const double g = 2.0 * (1.0 - kmin);
+    double m = 0.0;
+    for (int64_t c = 0; c < C; ++c)
+        m = std::fmax(m, (double)sigma_a[c] + (double)sigma_s[c] + g * (double)sigma_as[c]);
+    return 2.0 * r + m;
+}
+
+void stiff_time_step(int Q, const double* om, double dx, double dy, double srate, double cfl,
+                     double t_final, double& dt, int64_t& n) {
+    double rate = 0.0;
+    for (int q = 0; q < Q; ++q)
+        rate = std::fmax(rate, std::fabs(om[3 * q]) / dx + std::fabs(om[3 * q + 1]) / dy);
+    const double dt_max = std::fmin(cfl / rate, 2.0 * cfl / srate);
+    n = (int64_t)std::ceil(t_final / dt_max * (1.0 - 1e-12));
+    if (n < 1) n = 1;
+    dt = t_final / (double)n;
+}
+
 static uint32_t f2u(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);

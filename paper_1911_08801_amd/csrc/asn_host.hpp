@@ -33,6 +33,15 @@ bool kernel_matrix(int Q, const double* omega, const double* w, double eps, int 
 void cfl_time_step(int Q, const double* omega, double dx, double dy, double cfl, double t_final,
                    double& dt, int64_t& n);
 
+// Decay rate bound of a cell-to-cell sawtooth mode in a uniform region:
+//   2 max_q (|xi_q|/dx + |eta_q|/dy) + max_c (sigma_a + sigma_s + 2 (1 - min_q K_qq) sigma_as).
+// K is Q x Q row-major.  dt times this is the stability number.
+double stability_rate(int Q, const double* omega, const double* K, double dx, double dy, int64_t C,
+                      const float* sigma_a, const float* sigma_s, const float* sigma_as);
+// The streaming rule with dt_max further limited to 2 cfl / srate.
+void stiff_time_step(int Q, const double* omega, double dx, double dy, double srate, double cfl,
+                     double t_final, double& dt, int64_t& n);
+
 // Round a float to bfloat16 / IEEE half bits, round to nearest, ties to even.
 uint16_t float_to_bf16_rne(float f);
 uint16_t float_to_half_rne(float f);

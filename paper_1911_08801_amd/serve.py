@@ -47,14 +47,19 @@ class Job:
 
 
 class GpuBackend:
-    """The as-S_N library on the current GPU, all work on one dedicated stream."""
+    """The as-S_N library on the current GPU, all work on one dedicated stream.
 
-    def __init__(self, stream=None):
+    Requests get the stiff time-step rule by default: arbitrary requests include
+    coarse, strongly absorbing problems for which the streaming CFL step alone
+    is outside the explicit schemes' stability interval."""
+
+    def __init__(self, stream=None, dt_rule: str = "stiff"):
         import torch
 
         from . import asn
         self.torch = torch
         self.asn = asn
+        self.dt_rule = dt_rule
         self.stream = stream if stream is not None else torch.cuda.Stream()
 
     def bytes_needed(self, spec, dtype: str, scheme: str = "euler") -> int:
@@ -69,7 +74,7 @@ class GpuBackend:
 
     def create(self, spec, dtype: str, scheme: str = "euler"):
         with self.torch.cuda.stream(self.stream):
-            p = self.asn.from_spec(spec, dtype=dtype, scheme=scheme)
+            p = self.asn.from_spec(spec, dtype=dtype, scheme=scheme, dt_rule=self.dt_rule)
         return p, self.asn.asn_info(p)["steps_to_tfinal"]
 
     def make_batch(self, handles):

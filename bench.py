@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-heun", action="store_true", help="skip the Heun + minmod line")
     ap.add_argument("--sweep", choices=["lattice700", "line1024"], default=None,
                     help="precision sweep to t_final on a configured workload (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -76,10 +77,10 @@ def cpu_baseline(spec, steps):
 PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
 
 
-def timed_run(asn, spec, dtype, steps, warmup):
+def timed_run(asn, spec, dtype, steps, warmup, scheme="euler"):
     """Warm up, then time `steps` steps with HIP events between kernels."""
     import torch
-    p = asn.from_spec(spec, dtype=dtype)
+    p = asn.from_spec(spec, dtype=dtype, scheme=scheme)
     info = asn.asn_info(p)
     work = asn.asn_contraction_work(p)
     asn.asn_step(p, warmup)
@@ -90,7 +91,13 @@ def timed_run(asn, spec, dtype, steps, warmup):
     wall = time.perf_counter() - t0
     bud = asn.asn_mass_budget(p)
     p.close()
-    return {"wall": wall, "kms": kms, "info": info, "work": work, "budget": bud}
+    return {"wall": wall, "kms": kms, "info": info, "work": work, "budget": bud, "scheme": scheme}
+
+
+# Stencil bytes per update per step: Euler reads psi and Y and writes psi^{n+1}; a Heun
+# step is two passes, the second also reading psi^n.
+STENCIL_BYTES = {"euler": 12.0, "heun": 28.0}
+PASSES = {"euler": 1, "heun": 2}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_line_source_400_q512.json")
@@ -116,10 +123,11 @@ def roofline(res, spec, dtype):
     """Roofline entry of the kernel with the largest share of the step."""
     C, Q = spec.cells, spec.q
     kms = res["kms"]
+    scheme = res.get("scheme", "euler")
     t_gemm, t_sc = kms["contraction"] * 1e-3, kms["stream_collide"] * 1e-3
-    sc_bytes = 12.0 * Q * C                       # read psi and Y, write psi_new (FP32)
+    sc_bytes = STENCIL_BYTES[scheme] * Q * C
     if t_gemm >= t_sc:
-        flops = res["work"]["tile_flops"]
+        flops = PASSES[scheme] * res["work"]["tile_flops"]
         peak = PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS
         ach = flops / t_gemm / 1e12
         prof = "gemm_f32_kernel" if dtype == "f32" else \
@@ -127,24 +135,29 @@ def roofline(res, spec, dtype):
         return {"bound": "mfma", "kernel": "gemm_f32_kernel" if dtype == "f32" else
                 f"gemm_lp_kernel<{dtype}>", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                 "frac": ach / peak, "traffic": measured_traffic(prof, spec),
-                "algorithmic": f"2*C*(K entries in nonzero tiles) = {flops:.4g} flop per launch "
-                               f"(dense 2*Q*Q*C = {res['work']['dense_flops']:.4g})",
-                "dense_equivalent_TFLOPs": res["work"]["dense_flops"] / t_gemm / 1e12}
+                "algorithmic": f"2*C*(K entries in nonzero tiles) = {flops:.4g} flop per step "
+                               f"(dense 2*Q*Q*C = {res['work']['dense_flops']:.4g} per launch)",
+                "dense_equivalent_TFLOPs": PASSES[scheme] * res["work"]["dense_flops"]
+                / t_gemm / 1e12}
     ach = sc_bytes / t_sc / 1e9
-    prof = f"stream_collide_kernel<{'false' if dtype == 'f32' else 'true'}>"
-    return {"bound": "hbm", "kernel": "stream_collide_kernel", "achieved": ach,
+    lp = "false" if dtype == "f32" else "true"
+    prof = f"stream_collide_kernel<{lp}>" if scheme == "euler" else None
+    return {"bound": "hbm", "kernel": "stream_collide_kernel" if scheme == "euler" else
+            "muscl_kernel", "achieved": ach,
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-            "traffic": measured_traffic(prof, spec),
-            "algorithmic": f"12*Q*C = {sc_bytes:.4g} bytes per launch"}
+            "traffic": measured_traffic(prof, spec) if prof else None,
+            "algorithmic": f"{STENCIL_BYTES[scheme]:g}*Q*C = {sc_bytes:.4g} bytes per step"}
 
 
 def summary(res, spec, steps):
     C, Q = spec.cells, spec.q
     kms = res["kms"]
-    sc_bytes = 12.0 * Q * C
+    scheme = res.get("scheme", "euler")
+    sc_bytes = STENCIL_BYTES[scheme] * Q * C
     return {"value": C * Q * steps / res["wall"], "ms_per_step": 1e3 * res["wall"] / steps,
             "kernels_ms": kms,
-            "contraction_TFLOPs": res["work"]["tile_flops"] / (kms["contraction"] * 1e-3) / 1e12,
+            "contraction_TFLOPs": PASSES[scheme] * res["work"]["tile_flops"]
+            / (kms["contraction"] * 1e-3) / 1e12,
             "stream_collide_GBs": sc_bytes / (kms["stream_collide"] * 1e-3) / 1e9,
             "budget_max_residual": res["budget"]["max_residual"]}
 
@@ -274,6 +287,11 @@ def main():
             r = timed_run(asn, spec, dt, args.steps, args.warmup)
             out[dt] = summary(r, spec, args.steps)
             out[dt]["roofline"] = roofline(r, spec, dt)
+    if not args.no_heun:
+        # the paper's own explicit scheme (Heun + minmod), same workload, FP32 contraction
+        r = timed_run(asn, spec, "f32", args.steps, args.warmup, scheme="heun")
+        out["heun_f32"] = summary(r, spec, args.steps)
+        out["heun_f32"]["roofline"] = roofline(r, spec, "f32")
     if not args.no_serving:
         out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:

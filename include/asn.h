@@ -110,6 +110,10 @@ typedef struct {
     int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
     int32_t scheme;         /* ASN_SCHEME_EULER (default) or ASN_SCHEME_HEUN                     */
     int32_t dt_rule;        /* ASN_DT_STREAMING (default) or ASN_DT_STIFF                        */
+    int32_t unfused;        /* 0 (default): FP32 forward-Euler steps apply the stream + collide
+                               update in the contraction kernel's epilogue; 1: separate kernels
+                               (the contraction output Y goes through memory).  Same
+                               arithmetic, results agree to FP32 rounding.                      */
 } asn_options;
 
 typedef struct asn_problem_s* asn_problem;
@@ -165,7 +169,8 @@ asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps);
 /* A batch groups 1..64 problems for fused stepping: every kernel of a step covers
  * all of them in one launch.  Problems keep their own grid, ordinates, kernel
  * matrix and buffers (ordinate counts may differ); they must share the operand
- * type, the time scheme and the HIP stream.  The batch holds small device tables (hipMalloc).
+ * type, the time scheme, the fusion option and the HIP stream.  The batch holds
+ * small device tables (hipMalloc).
  * A problem may be stepped alone while in a batch; the batch reads each
  * problem's current buffer at every asn_batch_step.  Errors: ASN_E_INVALID,
  * ASN_E_OOM, ASN_E_HIP. */

@@ -68,7 +68,8 @@ class asn_options(ctypes.Structure):
     _fields_ = [("gemm_dtype", ctypes.c_int32), ("normalization", ctypes.c_int32),
                 ("cfl", ctypes.c_double), ("eps_override", ctypes.c_double),
                 ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
-                ("scheme", ctypes.c_int32), ("dt_rule", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("dt_rule", ctypes.c_int32),
+                ("unfused", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -195,12 +196,14 @@ def asn_options_default() -> asn_options:
 
 def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                  eps_override: float = 0.0, dt_override: float = 0.0,
-                 scheme: str = "euler", dt_rule: str = "streaming") -> asn_options:
+                 scheme: str = "euler", dt_rule: str = "streaming",
+                 unfused: bool = False) -> asn_options:
     o = asn_options_default()
     o.gemm_dtype = DTYPES[dtype]
     o.normalization = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.dt_rule = DT_RULES[dt_rule]
+    o.unfused = 1 if unfused else 0
     o.cfl = cfl
     o.eps_override = eps_override
     o.dt_override = dt_override
@@ -416,11 +419,11 @@ def asn_destroy(p: AsnProblem) -> None:
 def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               eps_override: float = 0.0, dt_override: float = 0.0,
               set_initial_state: bool = True, scheme: str = "euler",
-              dt_rule: str = "streaming") -> AsnProblem:
+              dt_rule: str = "streaming", unfused: bool = False) -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
-    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule)
+    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule, unfused)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
                    spec.source, spec.beta, spec.t_final, opt, device=device,
                    icosahedron_order=getattr(spec, "ico_order", 0))

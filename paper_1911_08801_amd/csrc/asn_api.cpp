@@ -39,7 +39,7 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 struct Layout {
     int Q = 0, Qp = 0, G = 1, qchunk = 1, tiles_x = 1, tiles_y = 1, fin_blocks = 1;
     int64_t C = 0, P = 0;
-    bool lowp = false;
+    bool lowp = false, fused = false;
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_bmax0, off_bmax1, off_rec,
@@ -47,8 +47,9 @@ struct Layout {
         total;
 };
 
-Layout make_layout(int nx, int ny, int Q, int dtype, int scheme) {
+Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     Layout L;
+    L.fused = fused;
     L.Q = Q;
     L.Qp = (int)round_up(Q, asn::kGemmBM);
     L.C = (int64_t)nx * ny;
@@ -60,11 +61,21 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme) {
     // Split the ordinates into chunks so that the stream + collide grid holds about
     // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
     // keeps the last, partial round small.
-    const int tiles = L.tiles_x * L.tiles_y;
-    int G = (int)std::lround(4096.0 / tiles);
-    G = std::max(1, std::min(G, std::min(64, std::max(1, Q / 2))));
-    L.qchunk = (Q + G - 1) / G;
-    L.G = (Q + L.qchunk - 1) / L.qchunk;
+    int tiles = L.tiles_x * L.tiles_y;
+    if (fused) {
+        // the stencil runs in the contraction's epilogue: its blocks are the
+        // contraction's 128 x 128 tiles, one Phi partial per ordinate tile
+        L.tiles_x = (int)(L.P / asn::kGemmBN);
+        L.tiles_y = 1;
+        tiles = L.tiles_x;
+        L.qchunk = asn::kGemmBM;
+        L.G = L.Qp / asn::kGemmBM;
+    } else {
+        int G = (int)std::lround(4096.0 / tiles);
+        G = std::max(1, std::min(G, std::min(64, std::max(1, Q / 2))));
+        L.qchunk = (Q + G - 1) / G;
+        L.G = (Q + L.qchunk - 1) / L.qchunk;
+    }
     L.fin_blocks = (int)((L.C + 255) / 256);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -75,7 +86,7 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme) {
     const size_t plane = (size_t)L.P;
     L.off_psi0 = take((size_t)Q * plane * 4);
     L.off_psi1 = take((size_t)Q * plane * 4);
-    L.off_Y = take((size_t)Q * plane * 4);
+    L.off_Y = take(fused ? 0 : (size_t)Q * plane * 4);   // the fused step keeps Y in registers
     L.off_Kt = take((size_t)L.Qp * L.Qp * 4);
     L.off_Klp = take(L.lowp ? (size_t)L.Qp * L.Qp * 2 : 0);
     L.off_rdef = take((size_t)L.Qp * 4);
@@ -156,6 +167,7 @@ StepArgs make_args(asn_problem p, int cur) {
     a.tiles_y = L.tiles_y;
     a.fin_blocks = L.fin_blocks;
     a.dtype = p->dtype;
+    a.fused = L.fused ? 1 : 0;
     a.W = p->W;
     a.area = p->dx * p->dy;
     float* psi0 = reinterpret_cast<float*>(b + L.off_psi0);
@@ -333,7 +345,8 @@ asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
     asn_options_default(&d);
     const int dtype = opt ? opt->gemm_dtype : d.gemm_dtype;
     const int scheme = opt ? opt->scheme : d.scheme;
-    *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme).total;
+    const bool fused = asn::can_fuse(dtype, scheme) && !(opt ? opt->unfused : d.unfused);
+    *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme, fused).total;
     return ASN_OK;
 }
 
@@ -417,7 +430,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     }
     p->stability = p->dt * srate;
 
-    p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme);
+    p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme,
+                       asn::can_fuse(p->dtype, p->scheme) && !opt.unfused);
     const Layout& L = p->L;
     if (workspace) {
         if (workspace_bytes < L.total) {
@@ -558,8 +572,8 @@ asn_status asn_set_state_isotropic(asn_problem p, const float* cell, int32_t on_
     if (!p || !cell) return fail(ASN_E_INVALID, "NULL argument");
     const Layout& L = p->L;
     float* dst = reinterpret_cast<float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1));
-    // stage the cell values in the Y buffer (free between steps)
-    float* stage = reinterpret_cast<float*>(p->base + L.off_Y);
+    // stage the cell values in the iso buffer (recomputed from the new state below)
+    float* stage = reinterpret_cast<float*>(p->base + L.off_iso);
     HIP_TRY(hipMemcpyAsync(stage, cell, L.C * 4,
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream));
     HIP_TRY(asn::launch_broadcast(dst, stage, L.Q, L.C, L.P, p->stream));
@@ -658,6 +672,8 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
             return fail(ASN_E_INVALID, "problems of a batch must share the operand type");
         if (probs[i]->scheme != probs[0]->scheme)
             return fail(ASN_E_INVALID, "problems of a batch must share the time scheme");
+        if (probs[i]->L.fused != probs[0]->L.fused)
+            return fail(ASN_E_INVALID, "problems of a batch must share the kernel fusion option");
         if (probs[i]->stream != probs[0]->stream)
             return fail(ASN_E_INVALID, "problems of a batch must share the HIP stream");
         for (int32_t j = 0; j < i; ++j)

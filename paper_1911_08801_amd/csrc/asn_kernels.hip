@@ -61,11 +61,26 @@ __device__ __forceinline__ StepArgs args_of(const BatchArgs& B, int i) {
 // 1a. FP32 contraction Y[q][c] = sum_p K[q][p] psi[p][c] on MFMA 16x16x4 f32.
 //     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
 //     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q read as 0.
+//     FUSED: the forward-Euler stream + collide update is applied in the
+//     epilogue instead of storing Y.  The products are taken with the operands
+//     swapped (Y^T = Psi^T K^T), so each lane's accumulator holds four
+//     consecutive cells of one ordinate: the lane reads their old values and
+//     upwind neighbours as aligned float4 rows (cache hits: the block and its
+//     neighbours in the XCD have just streamed these rows), writes psi^{n+1}
+//     as a float4, and the block emits the Phi partial of its 128 ordinates for
+//     its 128 cells plus its budget partials.  Y never reaches memory.
 // ---------------------------------------------------------------------------
 constexpr int kBK = kBK_F32;
 constexpr int kLdsPad = 16;
 
-__global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
+template <int NV, typename OutPtr>
+__device__ __forceinline__ void block_sum_256(double (&v)[NV], OutPtr out);
+
+// The fused epilogue needs more registers; three resident blocks per CU keep the
+// MFMA pipes fed while some blocks run their epilogues.
+template <bool FUSED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? 3 : 1)))
+void gemm_f32_kernel(BatchArgs B) {
     __shared__ float As[2][kBK][kGemmBM + kLdsPad];
     __shared__ float Bs[2][kBK][kGemmBN + kLdsPad];
     int pi, tile;
@@ -136,8 +151,13 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j) {
+                    // FUSED: rows = cells (bv), columns = ordinates (av)
+                    if constexpr (FUSED)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[i], av[j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                }
         }
         if (kt + 1 < nkt) ASN_LSTORE(b ^ 1);
         __syncthreads();
@@ -145,16 +165,154 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(BatchArgs B) {
 #undef ASN_GLOAD
 #undef ASN_LSTORE
     // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16.
+    if constexpr (!FUSED) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
-                const int64_t n = n0 + wn + j * 16 + (lane & 15);
-                if (m < Q) Y[(size_t)m * P + n] = acc[i][j][v];
+                for (int v = 0; v < 4; ++v) {
+                    const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+                    const int64_t n = n0 + wn + j * 16 + (lane & 15);
+                    if (m < Q) Y[(size_t)m * P + n] = acc[i][j][v];
+                }
+    } else {
+        const int nx = a.nx, ny = a.ny;
+        const int64_t C = a.C;
+        const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+        ASN_G float* __restrict__ out = gp(a.psi_new);
+        const bool rows4 = (nx & 3) == 0;   // then a float4 of cells never crosses a grid row
+        // the lane's four ordinates (columns j)
+        QInfo qi[4];
+        bool qok[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = m0 + wm + j * 16 + (lane & 15);
+            qok[j] = q < Q;
+            qi[j] = qtab[qok[j] ? q : 0];
+        }
+        __shared__ double phred[2][kGemmBN];
+        double defect = 0.0, outflow = 0.0;
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            // four consecutive cells c0 .. c0 + 3 (c0 a multiple of 4)
+            const int64_t c0 = n0 + wn + i * 16 + 4 * (lane >> 4);
+            float aa[4], bs[4], gs[4], ss[4];
+            int xk[4], yk[4];
+            bool ck[4];
+            const float4 iso4 = *reinterpret_cast<const ASN_G float4*>(gp(a.iso) + c0);
+            const float isv[4] = {iso4.x, iso4.y, iso4.z, iso4.w};
+            {
+                const int y0 = (int)(c0 / nx);
+                int x = (int)(c0 - (int64_t)y0 * nx), y = y0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    ck[k] = c0 + k < C;
+                    xk[k] = x;
+                    yk[k] = y;
+                    if (++x == nx) {
+                        x = 0;
+                        ++y;
+                    }
+                    const float4 cf = ck[k] ? gp(a.coef)[c0 + k] : z4;
+                    aa[k] = cf.x;
+                    bs[k] = cf.y;
+                    gs[k] = cf.z;
+                    ss[k] = cf.w;
+                }
             }
+            double ph[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!qok[j]) continue;
+                const QInfo& qj = qi[j];
+                const int q = m0 + wm + j * 16 + (lane & 15);
+                const ASN_G float* row = psi + (size_t)q * P;
+                const float4 v4 = *reinterpret_cast<const ASN_G float4*>(row + c0);
+                const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+                // upwind neighbour along x: inside the float4, or the cell just
+                // before / after it; a ghost (0) across the grid's x boundary
+                float ux[4];
+                if (qj.dir & 1) {
+                    const float prev = c0 >= 4 ? row[c0 - 1] : 0.f;
+                    ux[0] = prev;
+                    ux[1] = vv[0];
+                    ux[2] = vv[1];
+                    ux[3] = vv[2];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (xk[k] == 0) ux[k] = 0.f;
+                } else if (qj.dir & 2) {
+                    const float next = c0 + 4 < P ? row[c0 + 4] : 0.f;
+                    ux[0] = vv[1];
+                    ux[1] = vv[2];
+                    ux[2] = vv[3];
+                    ux[3] = next;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (xk[k] == nx - 1) ux[k] = 0.f;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) ux[k] = 0.f;
+                }
+                // upwind neighbour along y: the row below (eta > 0) or above
+                float uy[4] = {0.f, 0.f, 0.f, 0.f};
+                if (qj.dir & 12) {
+                    const int64_t sh = (qj.dir & 4) ? -(int64_t)nx : (int64_t)nx;
+                    if (rows4) {
+                        const bool has = (qj.dir & 4) ? yk[0] > 0 : yk[0] < ny - 1;
+                        if (has && ck[0]) {
+                            const float4 u4 = *reinterpret_cast<const ASN_G float4*>(row + c0 + sh);
+                            uy[0] = u4.x;
+                            uy[1] = u4.y;
+                            uy[2] = u4.z;
+                            uy[3] = u4.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const bool has = ck[k] && ((qj.dir & 4) ? yk[k] > 0 : yk[k] < ny - 1);
+                            uy[k] = has ? row[c0 + k + sh] : 0.f;
+                        }
+                    }
+                }
+                float nv[4];
+                float colsum = 0.f, o = 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float v = vv[k];
+                    const float col = gs[k] * (acc[i][j][k] - v) + bs[k] * (isv[k] - v);
+                    const float r = v - qj.cx * (v - ux[k]) - qj.cy * (v - uy[k]) - aa[k] * v + col + ss[k];
+                    nv[k] = ck[k] ? r : 0.f;   // padding cells stay zero
+                    ph[k] += qj.w * (double)nv[k];
+                    colsum += ck[k] ? col : 0.f;
+                    if (ck[k]) {
+                        if (((qj.dir & 1) && xk[k] == nx - 1) || ((qj.dir & 2) && xk[k] == 0)) o += qj.cx * v;
+                        if (((qj.dir & 4) && yk[k] == ny - 1) || ((qj.dir & 8) && yk[k] == 0)) o += qj.cy * v;
+                    }
+                }
+                *reinterpret_cast<ASN_G float4*>(out + (size_t)q * P + c0) =
+                    make_float4(nv[0], nv[1], nv[2], nv[3]);
+                defect += qj.w * (double)colsum;
+                outflow += qj.w * (double)o;
+            }
+            // Phi partial of this wave's 64 ordinates: the 16 lanes of a row group
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ph[k] += __shfl_xor(ph[k], 1, 64);
+                ph[k] += __shfl_xor(ph[k], 2, 64);
+                ph[k] += __shfl_xor(ph[k], 4, 64);
+                ph[k] += __shfl_xor(ph[k], 8, 64);
+                if ((lane & 15) == 0) phred[wave & 1][wn + i * 16 + 4 * (lane >> 4) + k] = ph[k];
+            }
+        }
+        // then the two waves that share the cells (fixed order)
+        double sums[2] = {defect, outflow};
+        block_sum_256<2>(sums, gp(a.blk_part) + 2 * (size_t)tile);   // synchronises the block
+        if (tid < kGemmBN)
+            gp(a.phi_part)[(size_t)mt * P + n0 + tid] = phred[0][tid] + phred[1][tid];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -890,7 +1048,7 @@ static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b -
 void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
     out[KT_GEMM] = (a.Qp / kGemmBM) * (int)(a.P / kGemmBN);
     out[KT_FIX] = a.dtype != 0 ? a.fin_blocks : 0;
-    out[KT_SC] = a.tiles_x * a.tiles_y * a.G;
+    out[KT_SC] = a.fused ? 0 : a.tiles_x * a.tiles_y * a.G;
     out[KT_FIN] = a.fin_blocks;
     out[KT_BUDGET] = 1;
 }
@@ -902,9 +1060,13 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
+    // a batch whose stencil grid is empty runs the stencil inside the contraction
+    const bool fused = grid[KT_SC] == 0;
     mark(0);
-    if (dtype == 0)
-        gemm_f32_kernel<<<grid[KT_GEMM], 256, 0, s>>>(b);
+    if (dtype == 0 && fused)
+        gemm_f32_kernel<true><<<grid[KT_GEMM], 256, 0, s>>>(b);
+    else if (dtype == 0)
+        gemm_f32_kernel<false><<<grid[KT_GEMM], 256, 0, s>>>(b);
     else if (dtype == 1)
         gemm_lp_kernel<1><<<grid[KT_GEMM], 256, 0, s>>>(b);
     else
@@ -912,13 +1074,13 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
     if (dtype != 0) particle_fix_kernel<<<grid[KT_FIX], 256, 0, s>>>(b);
     mark(1);
     const bool lp = dtype != 0;
-    if (stencil == 0) {
+    if (!fused && stencil == 0) {
         if (lp) stream_collide_kernel<true><<<grid[KT_SC], 256, 0, s>>>(b);
         else stream_collide_kernel<false><<<grid[KT_SC], 256, 0, s>>>(b);
-    } else if (stencil == 1) {
+    } else if (!fused && stencil == 1) {
         if (lp) muscl_kernel<true, 1><<<grid[KT_SC], 256, 0, s>>>(b);
         else muscl_kernel<false, 1><<<grid[KT_SC], 256, 0, s>>>(b);
-    } else {
+    } else if (!fused) {
         if (lp) muscl_kernel<true, 2><<<grid[KT_SC], 256, 0, s>>>(b);
         else muscl_kernel<false, 2><<<grid[KT_SC], 256, 0, s>>>(b);
     }

@@ -69,6 +69,10 @@ struct StepArgs {
     int fin_blocks;
     // operand type: 0 FP32, 1 BF16, 2 FP16
     int dtype;
+    // 1: the stencil runs in the contraction's epilogue (FP32 forward Euler); the
+    // stencil decomposition is then the contraction's: tiles_x = P / kGemmBN cell
+    // tiles, tiles_y = 1, G = Qp / kGemmBM ordinate tiles
+    int fused;
     double W, area;
     // buffers
     const float* psi;
@@ -115,6 +119,9 @@ struct BatchArgs {
 
 // Blocks of each kernel kind for one problem.
 void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]);
+
+// Whether a problem runs the stencil inside the FP32 contraction.
+inline bool can_fuse(int dtype, int scheme) { return dtype == 0 && scheme == SCHEME_EULER; }
 
 // One step for every problem of the batch.  Euler: one pass of contraction,
 // stream + collide, finalize and budget, on the buffers selected by b.s_par.

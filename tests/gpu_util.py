@@ -11,10 +11,11 @@ from oracle import asn_oracle as o
 
 
 def gpu_run(asn, spec, n_steps, psi0=None, dtype="f32", norm="sym", eps_override=0.0,
-            scheme="euler", dt=0.0):
+            scheme="euler", dt=0.0, unfused=False):
     """Advance ``spec`` on the GPU; returns (state, phi, budget, info)."""
     p = asn.from_spec(spec, dtype=dtype, norm=norm, eps_override=eps_override,
-                      set_initial_state=psi0 is None, scheme=scheme, dt_override=dt)
+                      set_initial_state=psi0 is None, scheme=scheme, dt_override=dt,
+                      unfused=unfused)
     try:
         if psi0 is not None:
             asn.asn_set_state(p, psi0)

@@ -38,6 +38,23 @@ def test_one_step_matches_oracle(nx, ny, n_polar, n_azim):
     assert np.max(np.abs(phi - phi_ref)) <= 4e-6 * np.abs(phi_ref).max()
 
 
+@pytest.mark.parametrize("nx,ny", [(1, 1), (37, 9), (130, 67), (200, 3)])
+@pytest.mark.parametrize("n_polar,n_azim", [(2, 4), (8, 16), (12, 24)])
+def test_separate_kernels_match_fused_step(nx, ny, n_polar, n_azim):
+    # The FP32 Euler step runs its stencil inside the contraction kernel by default;
+    # the separate-kernel form (Y through memory) is the same arithmetic.
+    spec = wl.random_problem(nx * 31 + ny, nx, ny, n_polar=n_polar, n_azim=n_azim, beta=4.5)
+    psi0 = wl.random_state(nx + 3 * ny, spec.q, ny, nx)
+    fused, phi_f, bud_f, _ = gpu_run(asn, spec, 3, psi0=psi0)
+    split, phi_s, bud_s, _ = gpu_run(asn, spec, 3, psi0=psi0, unfused=True)
+    ref, phi_ref, _ = oracle_run(spec, 3, psi0=psi0)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(split - ref)) <= 8e-6 * scale
+    assert np.max(np.abs(fused - split)) <= 4e-6 * scale
+    assert bud_f["outflow"] == pytest.approx(bud_s["outflow"], rel=1e-6)
+    assert bud_f["mass"] == pytest.approx(bud_s["mass"], rel=1e-6)
+
+
 @pytest.mark.parametrize("norm", ["sym", "row"])
 def test_multi_step_random_fields(norm):
     spec = wl.random_problem(5, 70, 33, n_polar=4, n_azim=8, beta=4.5, t_final=0.3)

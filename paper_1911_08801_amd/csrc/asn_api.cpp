@@ -461,7 +461,9 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         Klp.assign((size_t)L.Qp * L.Qp, 0);
         quantise_kernel(Q, K.data(), p->dtype, L.Qp, Klp.data(), rdef.data());
     }
-    // k-steps per M-tile whose tile of the stored K (FP32 or 16-bit) has a nonzero entry
+    // k-steps per M-tile whose tile of the stored K (FP32 or 16-bit) has a nonzero entry.
+    // Steps inside the tile's own ordinate range come last: the fused epilogue then
+    // reads rows that the block (and its neighbours) has just streamed through L2.
     std::vector<int> ktab((size_t)L.ktab_len, 0);
     {
         const int mt_n = L.Qp / asn::kGemmBM;
@@ -472,6 +474,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         for (int mt = 0; mt < mt_n; ++mt) {
             ktab[mt] = (int)entries.size();
             const int m0 = mt * asn::kGemmBM, m1 = std::min(Q, m0 + asn::kGemmBM);
+            std::vector<int> own;
             for (int kt = 0; kt < nk; ++kt) {
                 const int k0 = kt * bk, k1 = std::min(Q, k0 + bk);
                 bool nz = false;
@@ -480,10 +483,11 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                         nz = L.lowp ? (Klp[(size_t)m * L.Qp + k] & 0x7FFFu) != 0
                                     : Kt[(size_t)k * L.Qp + m] != 0.f;
                 if (nz) {
-                    entries.push_back(kt);
+                    (k0 >= m0 && k0 < m0 + asn::kGemmBM ? own : entries).push_back(kt);
                     cover += (double)(m1 - m0) * (k1 - k0);
                 }
             }
+            entries.insert(entries.end(), own.begin(), own.end());
         }
         ktab[mt_n] = (int)entries.size();
         std::copy(entries.begin(), entries.end(), ktab.begin() + mt_n + 1);

@@ -1,0 +1,194 @@
+"""Pins for the oracle's implicit as-S_N scheme (paper Sections 3.4-3.5,
+Algorithms 1-3, Appendix B), each against something other than the oracle:
+dense direct solves assembled entry by entry, the matrix the paper prints for
+the implicit flux, second-order convergence to an exact steady solution,
+GMRES against a direct solve, the particle balance, and the paper's
+implicit parameter-study ratio."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import asn_oracle as o
+from oracle import implicit_oracle as io
+from oracle import linesource_ref as L
+
+
+def _problem(nx, ny, omega, w, s_s=0.0, s_a=0.0, s_as=0.0, q=0.0, eps=0.6, dt=0.1, seed=None):
+    rng = np.random.default_rng(seed)
+    f = (lambda v: np.full((ny, nx), v, dtype=np.float32)) if seed is None else \
+        (lambda v: (v * (0.5 + rng.random((ny, nx)))).astype(np.float32))
+    prob = wl.Problem(name="imp", nx=nx, ny=ny, x_min=0.0, x_max=1.0, y_min=0.0, y_max=ny / nx,
+                      n_polar=1, n_azim=1, sigma_s=f(s_s), sigma_a=f(s_a), sigma_as=f(s_as),
+                      source=f(q), psi0_cell=f(0.0), t_final=1.0)
+    return prob, o.setup(prob, omega=omega, w=w, eps=eps, dt=dt)
+
+
+def _ordinates():
+    # all four quadrants plus an ordinate with eta = 0
+    om = []
+    for xi, eta in [(0.5, 0.3), (-0.4, 0.6), (0.2, -0.7), (-0.6, -0.3), (0.7, 0.0)]:
+        om.append([xi, eta, math.sqrt(1 - xi * xi - eta * eta)])
+    om = np.array(om)
+    w = np.full(len(om), 4 * math.pi / len(om))
+    return om, w
+
+
+def _dense_streaming(st, dt):
+    """L_Delta for every ordinate as a dense matrix, from the face fluxes."""
+    Q, ny, nx = st.w.size, st.sigma_a.shape[0], st.sigma_a.shape[1]
+    n = Q * ny * nx
+    Lm = np.zeros((n, n))
+    idx = lambda q, j, i: (q * ny + j) * nx + i
+    sig = st.sigma_a + st.sigma_s + st.sigma_as + 1.0 / dt
+    for q in range(Q):
+        xi, eta = st.omega[q, 0], st.omega[q, 1]
+        for j in range(ny):
+            for i in range(nx):
+                r = idx(q, j, i)
+                Lm[r, r] += sig[j, i]
+                # face fluxes g(f) for f = right and left face of the cell: coefficients
+                # on cells; x-direction
+                for axis, vel, h in ((0, xi, st.dx), (1, eta, st.dy)):
+                    if vel == 0.0:
+                        continue
+                    s = 1 if vel > 0 else -1
+
+                    def cell(k):                   # k cells upwind along the axis (k may be 0)
+                        jj, ii = (j, i - s * k) if axis == 0 else (j - s * k, i)
+                        return (jj, ii) if 0 <= jj < ny and 0 <= ii < nx else None
+                    # outgoing face: a psi(0) + b psi(1); incoming face: a psi(1) + b psi(2)
+                    for coef, k in ((io.FLUX_A, 0), (io.FLUX_B, 1)):
+                        c = cell(k)
+                        if c is not None:
+                            Lm[r, idx(q, *c)] += abs(vel) / h * coef
+                    for coef, k in ((io.FLUX_A, 1), (io.FLUX_B, 2)):
+                        c = cell(k)
+                        if c is not None:
+                            Lm[r, idx(q, *c)] -= abs(vel) / h * coef
+    return Lm
+
+
+def test_sweep_solves_the_streaming_operator():
+    om, w = _ordinates()
+    prob, st = _problem(5, 4, om, w, s_s=0.5, s_a=0.25, s_as=1.0, dt=0.2, seed=1)
+    R = np.random.default_rng(2).random((len(w), 4, 5))
+    got = io.sweep(R, st, 0.2)
+    Lm = _dense_streaming(st, 0.2)
+    ref = np.linalg.solve(Lm, R.ravel()).reshape(R.shape)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.abs(ref).max()
+
+
+def test_flux_matrix_is_the_one_printed_in_appendix_b():
+    # 1-D, one ordinate xi = 1, dx = 1: L = B + sigma_t I with B the face-flux
+    # difference matrix; its symmetric part has 3/2, -1, 1/4 on the diagonals and
+    # is positive definite (the implicit flux is L2 stable).
+    n = 40
+    om = np.array([[1.0, 0.0, 0.0]])
+    prob, st = _problem(n, 1, om, np.array([4 * math.pi]), dt=1.0)
+    st.dx = 1.0
+    inv = np.stack([io.sweep(np.eye(n)[k][None, None, :], st, 1.0)[0, 0] for k in range(n)], axis=1)
+    B = np.linalg.inv(inv) - np.eye(n)          # sigma_t = 1 / dt = 1
+    S = 0.5 * (B + B.T)
+    assert np.allclose(np.diag(S), 1.5)
+    assert np.allclose(np.diag(S, 1), -1.0) and np.allclose(np.diag(S, 2), 0.25)
+    assert np.allclose(np.triu(S, 3), 0.0)
+    ev = np.linalg.eigvalsh(S)
+    assert ev.min() > 0.0 and ev.max() < 4.0
+    # the symbol of the interior stencil, Re(3/2 - 2 e^{-it} + 1/2 e^{-2it}) = (1 - cos t)^2
+    t = np.linspace(0, np.pi, 7)
+    sym = (1.5 - 2 * np.exp(-1j * t) + 0.5 * np.exp(-2j * t)).real
+    assert np.allclose(sym, (1 - np.cos(t)) ** 2)
+
+
+def test_steady_state_is_second_order_away_from_the_inflow():
+    # xi psi' + sigma psi = q on (0, 2), psi(0) = 0: psi = q/sigma (1 - exp(-sigma x/xi)).
+    errs, edge = [], []
+    for nx in (40, 80, 160):
+        om = np.array([[0.8, 0.0, 0.6]])
+        prob, st = _problem(nx, 1, om, np.array([4 * math.pi]), s_a=1.0, q=1.0, dt=1e12)
+        st.dx = 2.0 / nx
+        psi = io.sweep(np.full((1, 1, nx), 1.0), st, 1e12)[0, 0]
+        x = (np.arange(nx) + 0.5) * st.dx
+        e = np.abs(psi - (1 - np.exp(-x / 0.8)))
+        errs.append(e[nx // 4:].max())
+        edge.append(e.max())
+    assert errs[0] / errs[1] > 3.8 and errs[1] / errs[2] > 3.8
+    assert 1.7 < edge[0] / edge[1] < 2.3          # the zero ghost cells are first order at the inflow
+
+
+def test_source_iteration_converges_to_the_direct_solution():
+    om, w = _ordinates()
+    prob, st = _problem(4, 3, om, w, s_s=0.0, s_a=0.5, s_as=3.0, eps=0.9, dt=0.3, seed=3)
+    R = np.random.default_rng(4).random((len(w), 3, 4))
+    Lm = _dense_streaming(st, 0.3)
+    Q, n_c = len(w), 12
+    Kbig = np.kron(st.K, np.eye(n_c)) * np.tile(st.sigma_as.ravel(), Q)[:, None]
+    ref = np.linalg.solve(Lm - Kbig, R.ravel()).reshape(R.shape)
+    got, it = io.source_iteration(np.zeros_like(R), R, st, 0.3, eps=1e-10)
+    assert it > 3
+    assert np.max(np.abs(got - ref)) < 1e-8 * np.abs(ref).max()
+
+
+def test_gmres_against_a_direct_solve():
+    rng = np.random.default_rng(5)
+    n = 120
+    A = np.eye(n) + 0.4 * rng.standard_normal((n, n)) / math.sqrt(n)
+    b = rng.standard_normal(n)
+    x, n_mv = io.gmres(lambda v: A @ v, b, np.zeros(n), 1e-12, restart=30)
+    assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-9)
+    # a Krylov method solves an n x n system in at most n steps
+    A2 = A[:8, :8]
+    x2, n2 = io.gmres(lambda v: A2 @ v, b[:8], np.zeros(8), 1e-13, restart=30)
+    assert n2 <= 10 and np.allclose(x2, np.linalg.solve(A2, b[:8]), atol=1e-10)
+
+
+@pytest.mark.parametrize("mode", ["sym", "row"])
+def test_implicit_step_solves_the_full_system(mode):
+    # (L - sigma_s (isotropic) - sigma_as K) psi = q + psi_old / dt, dense.
+    om, w = _ordinates()
+    prob, st = _problem(4, 3, om, w, s_s=1.5, s_a=0.5, s_as=2.0, q=0.3, eps=0.9, dt=0.4, seed=6)
+    if mode == "row":
+        st.K = o.as_kernel_matrix(om, w, 0.9, "row")
+    psi_old = np.random.default_rng(7).random((len(w), 3, 4))
+    psi, phi = io.implicit_step(psi_old, st, 0.4, gmres_tol=1e-13, si_eps=1e-13)
+    Q, n_c = len(w), 12
+    Lm = _dense_streaming(st, 0.4)
+    sa = np.tile(st.sigma_as.ravel(), Q)[:, None]
+    ss = np.tile(st.sigma_s.ravel(), Q)[:, None]
+    Kbig = np.kron(st.K, np.eye(n_c)) * sa
+    Sbig = np.kron(np.outer(np.ones(Q), st.w) / st.W, np.eye(n_c)) * ss
+    rhs = (st.source[None] + psi_old / 0.4).ravel()
+    ref = np.linalg.solve(Lm - Kbig - Sbig, rhs).reshape(psi_old.shape)
+    assert np.max(np.abs(psi - ref)) < 1e-9 * np.abs(ref).max()
+    assert np.allclose(phi, o.scalar_flux(ref, st.w), rtol=1e-9)
+
+
+def test_implicit_particle_balance():
+    spec = wl.random_problem(9, 14, 11, n_polar=2, n_azim=4, beta=4.5)
+    st = o.setup(spec, dt=0.05)
+    psi_old = wl.random_state(3, spec.q, 11, 14).astype(np.float64)
+    psi, _ = io.implicit_step(psi_old, st, 0.05, gmres_tol=1e-13, si_eps=1e-12)
+    b = io.implicit_budget(psi_old, psi, st, 0.05)
+    res = b["mass_next"] - (b["mass"] + 0.05 * (-b["absorption"] - b["outflow"] + b["source"]
+                                                 + b["as_defect"]))
+    assert abs(res) < 1e-10 * b["mass"]
+    assert abs(b["as_defect"]) < 1e-12 * b["mass"]       # symmetric K conserves
+
+
+def test_implicit_twelve_ordinate_ratio_near_the_paper():
+    # Section 4.1 implicit parameter study: 12 icosahedron ordinates, 50^2 cells,
+    # dt = 2 dx, beta = 4, sigma_as = 7: 41.4 % of the sigma_as = 0 error of Phi.
+    # (The paper's 12-point table is not a regular icosahedron and its reference
+    # differs, so the band is wide.)
+    ref = 4 * math.pi * L.line_source_on_grid(50, 1.0, wl.LINE_SOURCE_DELTA, n_k=800, n_tau=1200)
+    err = {}
+    for s_as in (0.0, 7.0):
+        spec = wl.line_source(50, sigma_as=s_as, beta=4.0)
+        spec.ico_order = 2
+        psi, st = io.run_implicit(spec, dt=1.0 / 8, n_steps=8)
+        phi = o.scalar_flux(psi, st.w)
+        err[s_as] = np.linalg.norm(phi - ref) / np.linalg.norm(ref)
+    assert 0.3 < err[7.0] / err[0.0] < 0.65

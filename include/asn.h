@@ -66,7 +66,16 @@ enum { ASN_NORM_SYM = 0, ASN_NORM_ROW = 1 };
  *                   psi_{i+1} - psi_i), face value psi_i +- slope / 2 on the upwind
  *                   side, zero ghost cells); psi^1 = psi + dt R(psi),
  *                   psi^{n+1} = (psi + psi^1 + dt R(psi^1)) / 2. */
-enum { ASN_SCHEME_EULER = 0, ASN_SCHEME_HEUN = 1 };
+/* ASN_SCHEME_IMPLICIT: the paper's implicit scheme (Sections 3.4-3.5, Algorithms 1-3):
+ *                   implicit Euler, faces carry 3/2 psi_up - 1/2 psi_upup (no limiter),
+ *                   the artificial scattering is resolved inside the sweep by source
+ *                   iteration (relative stopping test source_tol with the a-priori
+ *                   contraction bound max sigma_as / (sigma_a + sigma_s + sigma_as + 1/dt)),
+ *                   and GMRES (restart 30, relative residual implicit_tol) solves for
+ *                   the scalar flux.  FP64 on the device; cfl above 1 is allowed;
+ *                   nx <= 2048; such problems step alone (no batches); asn_step blocks
+ *                   until its steps are done. */
+enum { ASN_SCHEME_EULER = 0, ASN_SCHEME_HEUN = 1, ASN_SCHEME_IMPLICIT = 2 };
 
 /* Time-step rule.  Both start from dt_max = cfl / max_q(|xi_q|/dx + |eta_q|/dy)
  * and take dt = t_final / n, n = ceil(t_final / dt_max).
@@ -114,6 +123,8 @@ typedef struct {
                                update in the contraction kernel's epilogue; 1: separate kernels
                                (the contraction output Y goes through memory).  Same
                                arithmetic, results agree to FP32 rounding.                      */
+    double implicit_tol;    /* ASN_SCHEME_IMPLICIT: GMRES relative residual (0: 1.5e-8, paper 4.1) */
+    double source_tol;      /* ASN_SCHEME_IMPLICIT: source-iteration tolerance (0: 1e-4)           */
 } asn_options;
 
 typedef struct asn_problem_s* asn_problem;
@@ -202,6 +213,10 @@ asn_status asn_batch_destroy(asn_batch b);
  * the run grow without bound (coarse grids, strong absorbers).
  * Errors: ASN_E_INVALID. */
 asn_status asn_stability(asn_problem p, double* z);
+
+/* ASN_SCHEME_IMPLICIT: transport sweeps and GMRES matrix-vector products since the
+ * last set_state (0 for the explicit schemes).  Errors: ASN_E_INVALID. */
+asn_status asn_iteration_counts(asn_problem p, int64_t* sweeps, int64_t* matvecs);
 
 /* Run n_steps exactly like asn_step while recording HIP events on the problem's
  * stream between its kernels; synchronises.  kernel_ms[k] receives the average

@@ -35,13 +35,13 @@ ASN_E_UNSUPPORTED = -6
 
 ASN_GEMM_F32, ASN_GEMM_BF16, ASN_GEMM_F16 = 0, 1, 2
 ASN_NORM_SYM, ASN_NORM_ROW = 0, 1
-ASN_SCHEME_EULER, ASN_SCHEME_HEUN = 0, 1
+ASN_SCHEME_EULER, ASN_SCHEME_HEUN, ASN_SCHEME_IMPLICIT = 0, 1, 2
 ASN_DT_STREAMING, ASN_DT_STIFF = 0, 1
 ASN_BUDGET_LEN = 8
 
 DTYPES = {"f32": ASN_GEMM_F32, "bf16": ASN_GEMM_BF16, "f16": ASN_GEMM_F16}
 NORMS = {"sym": ASN_NORM_SYM, "row": ASN_NORM_ROW}
-SCHEMES = {"euler": ASN_SCHEME_EULER, "heun": ASN_SCHEME_HEUN}
+SCHEMES = {"euler": ASN_SCHEME_EULER, "heun": ASN_SCHEME_HEUN, "implicit": ASN_SCHEME_IMPLICIT}
 DT_RULES = {"streaming": ASN_DT_STREAMING, "stiff": ASN_DT_STIFF}
 
 
@@ -69,7 +69,8 @@ class asn_options(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("eps_override", ctypes.c_double),
                 ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
                 ("scheme", ctypes.c_int32), ("dt_rule", ctypes.c_int32),
-                ("unfused", ctypes.c_int32)]
+                ("unfused", ctypes.c_int32), ("implicit_tol", ctypes.c_double),
+                ("source_tol", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -98,6 +99,7 @@ _SIG = {
     "asn_destroy": [_P],
     "asn_contraction_work": [_P, _D, _D],
     "asn_stability": [_P, _D],
+    "asn_iteration_counts": [_P, _I64, _I64],
     "asn_build_quadrature": [ctypes.c_int32, ctypes.c_int32, _D, _D],
     "asn_build_icosahedron": [ctypes.c_int32, _D, _D],
     "asn_build_kernel": [ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_int32, _D],
@@ -197,13 +199,16 @@ def asn_options_default() -> asn_options:
 def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                  eps_override: float = 0.0, dt_override: float = 0.0,
                  scheme: str = "euler", dt_rule: str = "streaming",
-                 unfused: bool = False) -> asn_options:
+                 unfused: bool = False, implicit_tol: float = 0.0,
+                 source_tol: float = 0.0) -> asn_options:
     o = asn_options_default()
     o.gemm_dtype = DTYPES[dtype]
     o.normalization = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.dt_rule = DT_RULES[dt_rule]
     o.unfused = 1 if unfused else 0
+    o.implicit_tol = implicit_tol
+    o.source_tol = source_tol
     o.cfl = cfl
     o.eps_override = eps_override
     o.dt_override = dt_override
@@ -397,6 +402,15 @@ def asn_info(p: AsnProblem) -> dict:
     return {"dt": dt.value, "steps_done": done.value, "steps_to_tfinal": tot.value, "q": q.value}
 
 
+def asn_iteration_counts(p: AsnProblem) -> dict:
+    """Implicit scheme: transport sweeps and GMRES products since the last set_state."""
+    sw = ctypes.c_int64()
+    mv = ctypes.c_int64()
+    _check(_lib.asn_iteration_counts(p.handle, ctypes.byref(sw), ctypes.byref(mv)),
+           "asn_iteration_counts")
+    return {"sweeps": sw.value, "matvecs": mv.value}
+
+
 def asn_stability(p: AsnProblem) -> float:
     """Stability number of the problem's dt (explicit schemes need <= 2)."""
     z = ctypes.c_double()
@@ -419,11 +433,13 @@ def asn_destroy(p: AsnProblem) -> None:
 def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               eps_override: float = 0.0, dt_override: float = 0.0,
               set_initial_state: bool = True, scheme: str = "euler",
-              dt_rule: str = "streaming", unfused: bool = False) -> AsnProblem:
+              dt_rule: str = "streaming", unfused: bool = False,
+              implicit_tol: float = 0.0, source_tol: float = 0.0) -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
-    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule, unfused)
+    opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule, unfused,
+                       implicit_tol, source_tol)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
                    spec.source, spec.beta, spec.t_final, opt, device=device,
                    icosahedron_order=getattr(spec, "ico_order", 0))

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasn.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["asn_host.cpp", "asn_kernels.hip", "asn_api.cpp"]
+SOURCES = ["asn_host.cpp", "asn_kernels.hip", "asn_implicit.hip", "asn_api.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (the compiler would
 # otherwise form v_pk_* FP32 ops from scalar/float2 arithmetic).

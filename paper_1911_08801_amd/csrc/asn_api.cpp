@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <cstdio>
 #include <cstring>
@@ -13,6 +14,7 @@
 #include <vector>
 
 #include "asn_host.hpp"
+#include "asn_implicit.hpp"
 #include "asn_kernels.hpp"
 
 using asn::QInfo;
@@ -36,6 +38,8 @@ asn_status fail(asn_status s, const std::string& msg) {
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+constexpr int kGmresRestart = 30;
+
 struct Layout {
     int Q = 0, Qp = 0, G = 1, qchunk = 1, tiles_x = 1, tiles_y = 1, fin_blocks = 1;
     int64_t C = 0, P = 0;
@@ -43,7 +47,7 @@ struct Layout {
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_bmax0, off_bmax1, off_rec,
-        off_tab, off_off, off_base, off_left,
+        off_tab, off_off, off_base, off_left, off_imp,
         total;
 };
 
@@ -114,6 +118,19 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     L.off_off = take(asn::KT_COUNT * 2 * sizeof(int));
     L.off_base = take(sizeof(int));
     L.off_left = take(sizeof(int));
+    // FP64 state and iteration vectors of the implicit scheme
+    size_t imp = 0;
+    if (scheme == ASN_SCHEME_IMPLICIT) {
+        asn::ImplicitParams ip{};
+        ip.nx = nx;
+        ip.ny = ny;
+        ip.Q = Q;
+        ip.C = L.C;
+        ip.P = L.P;
+        ip.gmres_restart = kGmresRestart;
+        imp = asn::ImplicitSolver::bytes(ip);
+    }
+    L.off_imp = take(imp);
     L.total = off;
     return L;
 }
@@ -135,6 +152,7 @@ struct asn_problem_s {
     double tile_entries = 0;  // K entries inside the multiplied tiles (real rows/cols)
     StepArgs tab[2];          // step arguments when psi buffer 0 / 1 holds the state
     int blocks[asn::KT_COUNT];
+    std::unique_ptr<asn::ImplicitSolver> imp;   // the implicit scheme's solver (else null)
 };
 
 struct asn_batch_s {
@@ -366,12 +384,15 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         return fail(ASN_E_INVALID, "unknown gemm_dtype");
     if (opt.normalization != ASN_NORM_SYM && opt.normalization != ASN_NORM_ROW)
         return fail(ASN_E_INVALID, "unknown normalization");
-    if (opt.scheme != ASN_SCHEME_EULER && opt.scheme != ASN_SCHEME_HEUN)
+    if (opt.scheme != ASN_SCHEME_EULER && opt.scheme != ASN_SCHEME_HEUN &&
+        opt.scheme != ASN_SCHEME_IMPLICIT)
         return fail(ASN_E_INVALID, "unknown scheme");
+    const bool implicit = opt.scheme == ASN_SCHEME_IMPLICIT;
     if (opt.dt_rule != ASN_DT_STREAMING && opt.dt_rule != ASN_DT_STIFF)
         return fail(ASN_E_INVALID, "unknown dt_rule");
     if (!(opt.cfl > 0.0)) return fail(ASN_E_INVALID, "cfl must be > 0");
-    if (opt.cfl > 1.0) return fail(ASN_E_UNSTABLE, "cfl above 1 is unstable for the explicit step");
+    if (opt.cfl > 1.0 && !implicit)
+        return fail(ASN_E_UNSTABLE, "cfl above 1 is unstable for the explicit step");
     if (!(t_final > 0.0) || !std::isfinite(t_final)) return fail(ASN_E_INVALID, "t_final must be > 0");
     if (!(kernel_beta > 0.0) && !(opt.eps_override > 0.0))
         return fail(ASN_E_INVALID, "kernel_beta must be > 0");
@@ -421,7 +442,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         double rate = 0.0;
         for (int q = 0; q < Q; ++q)
             rate = std::fmax(rate, std::fabs(om[3 * q]) / p->dx + std::fabs(om[3 * q + 1]) / p->dy);
-        if (opt.dt_override * rate > opt.cfl * (1.0 + 1e-12)) {
+        if (!implicit && opt.dt_override * rate > opt.cfl * (1.0 + 1e-12)) {
             delete p;
             return fail(ASN_E_UNSTABLE, "dt_override exceeds the CFL bound");
         }
@@ -548,6 +569,30 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     if (arm_single(p, 1) != hipSuccess ||
         asn::launch_init(p->tab[0], single_batch(p), p->stream) != hipSuccess)
         return bail(fail(ASN_E_HIP, "initial moment kernels failed to launch"));
+    if (implicit) {
+        asn::ImplicitParams ip{};
+        ip.nx = p->nx;
+        ip.ny = p->ny;
+        ip.Q = Q;
+        ip.C = C;
+        ip.P = L.P;
+        ip.dx = p->dx;
+        ip.dy = p->dy;
+        ip.dt = p->dt;
+        ip.W = p->W;
+        ip.gmres_tol = opt.implicit_tol > 0.0 ? opt.implicit_tol : 1.5e-8;
+        ip.source_tol = opt.source_tol > 0.0 ? opt.source_tol : 1e-4;
+        ip.gmres_restart = kGmresRestart;
+        p->imp.reset(new asn::ImplicitSolver());
+        std::string ierr;
+        if (!p->imp->init(ip, om.data(), w.data(), K.data(), sigma_s, sigma_a, sigma_as, source,
+                          b + L.off_imp, p->stream, ierr))
+            return bail(fail(ierr.find("nx must") != std::string::npos ? ASN_E_UNSUPPORTED : ASN_E_HIP,
+                             ierr));
+        if (!p->imp->set_state(reinterpret_cast<const float*>(b + L.off_psi0),
+                               reinterpret_cast<double*>(b + L.off_phi64), ierr))
+            return bail(fail(ASN_E_HIP, ierr));
+    }
     if (hipStreamSynchronize(p->stream) != hipSuccess)
         return bail(fail(ASN_E_HIP, "synchronising after set-up failed"));
     *out = p;
@@ -558,6 +603,13 @@ static asn_status finish_set_state(asn_problem p) {
     p->steps_done = 0;
     HIP_TRY(arm_single(p, 1));
     HIP_TRY(asn::launch_init(p->tab[p->cur], single_batch(p), p->stream));
+    if (p->imp) {
+        const Layout& L = p->L;
+        std::string ierr;
+        if (!p->imp->set_state(reinterpret_cast<const float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1)),
+                               reinterpret_cast<double*>(p->base + L.off_phi64), ierr))
+            return fail(ASN_E_HIP, ierr);
+    }
     return ASN_OK;
 }
 
@@ -588,6 +640,12 @@ asn_status asn_set_state_isotropic(asn_problem p, const float* cell, int32_t on_
 asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
     if (!p || !psi) return fail(ASN_E_INVALID, "NULL argument");
     const Layout& L = p->L;
+    if (p->imp) {          // the implicit state is FP64: round it into the FP32 buffer first
+        std::string ierr;
+        if (!p->imp->get_state(reinterpret_cast<float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1)),
+                               ierr))
+            return fail(ASN_E_HIP, ierr);
+    }
     const float* src = reinterpret_cast<const float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1));
     HIP_TRY(hipMemcpy2DAsync(psi, L.C * 4, src, L.P * 4, L.C * 4, L.Q,
                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
@@ -604,6 +662,13 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
     if (!p) return fail(ASN_E_INVALID, "problem is NULL");
     if (n_steps < 0 || n_steps > (1 << 30)) return fail(ASN_E_INVALID, "n_steps must be in [0, 2^30]");
     if (n_steps == 0) return ASN_OK;
+    if (p->imp) {
+        std::string ierr;
+        if (!p->imp->step(n_steps, reinterpret_cast<double*>(p->base + p->L.off_phi64), ierr))
+            return fail(ASN_E_HIP, ierr);
+        p->steps_done += n_steps;
+        return ASN_OK;
+    }
     HIP_TRY(arm_single(p, n_steps));
     asn::BatchArgs b = single_batch(p);
     for (int64_t i = 0; i < n_steps; ++i) {
@@ -618,6 +683,23 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
 asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     if (!p || !kernel_ms) return fail(ASN_E_INVALID, "NULL argument");
     if (n_steps < 1 || n_steps > (1 << 20)) return fail(ASN_E_INVALID, "n_steps must be in [1, 2^20]");
+    if (p->imp) {          // iterative steps: only the span of a whole step is reported
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, p->stream));
+        const asn_status st = asn_step(p, n_steps);
+        HIP_TRY(hipEventRecord(e1, p->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != ASN_OK) return st;
+        for (int k = 0; k < 4; ++k) kernel_ms[k] = 0.0;
+        kernel_ms[4] = ms / (double)n_steps;
+        return ASN_OK;
+    }
     const int passes = asn::passes_per_step(p->scheme);
     const size_t per = 5 * (size_t)passes;
     std::vector<hipEvent_t> ev((size_t)n_steps * per, nullptr);
@@ -676,6 +758,8 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
             return fail(ASN_E_INVALID, "problems of a batch must share the operand type");
         if (probs[i]->scheme != probs[0]->scheme)
             return fail(ASN_E_INVALID, "problems of a batch must share the time scheme");
+        if (probs[i]->imp)
+            return fail(ASN_E_UNSUPPORTED, "implicit problems step alone (asn_step)");
         if (probs[i]->L.fused != probs[0]->L.fused)
             return fail(ASN_E_INVALID, "problems of a batch must share the kernel fusion option");
         if (probs[i]->stream != probs[0]->stream)
@@ -812,6 +896,12 @@ asn_status asn_scalar_flux(asn_problem p, double* phi_host) {
 
 asn_status asn_mass_budget(asn_problem p, double out[ASN_BUDGET_LEN]) {
     if (!p || !out) return fail(ASN_E_INVALID, "NULL argument");
+    if (p->imp) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        for (int k = 0; k < ASN_BUDGET_LEN; ++k) out[k] = p->imp->budget[k];
+        if (!std::isfinite(out[0])) return fail(ASN_E_UNSTABLE, "mass is not finite");
+        return ASN_OK;
+    }
     double rec[asn::REC_LEN];
     HIP_TRY(hipMemcpyAsync(rec, p->base + p->L.off_rec, sizeof(rec), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -834,6 +924,13 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
     if (steps_done) *steps_done = p->steps_done;
     if (steps_to_tfinal) *steps_to_tfinal = p->n_to_tfinal;
     if (q) *q = p->L.Q;
+    return ASN_OK;
+}
+
+asn_status asn_iteration_counts(asn_problem p, int64_t* sweeps, int64_t* matvecs) {
+    if (!p) return fail(ASN_E_INVALID, "problem is NULL");
+    if (sweeps) *sweeps = p->imp ? p->imp->sweeps : 0;
+    if (matvecs) *matvecs = p->imp ? p->imp->matvecs : 0;
     return ASN_OK;
 }
 

@@ -1,0 +1,644 @@
+// Device kernels and host driver of the implicit as-S_N step (FP64).  See
+// asn_implicit.hpp.  Faces carry 3/2 psi_up - 1/2 psi_upup (paper Section 3.5,
+// no limiter); cells outside the grid are 0 (vacuum).
+#include "asn_implicit.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace asn {
+
+namespace {
+
+constexpr int kT = 64;      // GEMM tile (ordinates x cells)
+constexpr int kTK = 16;     // GEMM k-step
+constexpr int kVecBlock = 1024;   // vector elements per reduction block
+
+inline int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline unsigned ndiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+struct RhsArgs {
+    const double* K;        // [Q][Q]
+    const double* psi;      // [Q][P]
+    const double* psi_old;  // [Q][P]
+    const double* phi;      // [P] or null
+    const float4* coef;     // per cell {sigma_a, sigma_s, sigma_as, q}
+    double* rhs;            // [Q][P]
+    int Q;
+    int64_t C, P;
+    double alpha, beta, inv_dt, inv_W;
+};
+
+// rhs[q][c] = sigma_as (K psi)[q][c] + alpha sigma_s phi_c / W + beta (q_c + psi_old[q][c] / dt)
+__global__ __launch_bounds__(256) void imp_rhs_kernel(RhsArgs a) {
+    __shared__ double Ks[kTK][kT + 1];
+    __shared__ double Ps[kTK][kT];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int q0 = blockIdx.x * kT;
+    const int64_t c0 = (int64_t)blockIdx.y * kT;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < a.Q; k0 += kTK) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + 256 * l;
+            const int r = idx >> 4, kk = idx & 15;
+            const int q = q0 + r, k = k0 + kk;
+            Ks[kk][r] = (q < a.Q && k < a.Q) ? a.K[(size_t)q * a.Q + k] : 0.0;
+            const int pk = idx >> 6, cc = idx & 63;
+            Ps[pk][cc] = (k0 + pk < a.Q) ? a.psi[(size_t)(k0 + pk) * a.P + c0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTK; ++kk) {
+            double kv[4], pv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) kv[i] = Ks[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) pv[j] = Ps[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(kv[i], pv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t c = c0 + tx * 4 + j;
+        const bool cok = c < a.C;
+        const float4 cf = cok ? a.coef[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const double iso = (cok && a.phi) ? a.alpha * (double)cf.y * a.phi[c] * a.inv_W : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = q0 + ty * 4 + i;
+            if (q >= a.Q) continue;
+            const size_t o = (size_t)q * a.P + c;
+            double v = 0.0;
+            if (cok)
+                v = (double)cf.z * acc[i][j] + iso +
+                    a.beta * ((double)cf.w + a.psi_old[o] * a.inv_dt);
+            a.rhs[o] = v;
+        }
+    }
+}
+
+struct SweepArgs {
+    const double* rhs;      // [Q][P]
+    const double* dir;      // per ordinate {|xi|/dx, |eta|/dy, sign xi, sign eta}
+    const float4* coef;
+    double* out;            // [Q][P]
+    int nx, ny;
+    int64_t P;
+    double inv_dt;
+};
+
+// One wave per ordinate.  The grid is walked in strips of 64 rows from the upwind
+// side; lane j holds row j of the strip and, at step t, the cell t - j positions
+// from the upwind x boundary, so its x-upwind neighbours are its own two previous
+// results and its y-upwind neighbours are those of lanes j - 1 and j - 2 (lane
+// shuffles).  The strip's two downwind rows are kept in LDS for the next strip.
+__global__ __launch_bounds__(64) void imp_sweep_kernel(SweepArgs a) {
+    extern __shared__ double rowbuf[];      // [2 parity][2 rows][nx]
+    const int q = blockIdx.x, lane = threadIdx.x;
+    const int nx = a.nx, ny = a.ny;
+    const double ax = a.dir[4 * q + 0], ay = a.dir[4 * q + 1];
+    const bool xpos = a.dir[4 * q + 2] > 0.0, ypos = a.dir[4 * q + 3] > 0.0;
+    const double* rhs = a.rhs + (size_t)q * a.P;
+    double* out = a.out + (size_t)q * a.P;
+    const double dflux = 1.5 * (ax + ay);
+    const int nstrips = (ny + 63) / 64;
+    int par = 0;
+    for (int s = 0; s < nstrips; ++s) {
+        const int r = s * 64 + lane;                  // row in sweep order
+        const bool valid = r < ny;
+        const int y = ypos ? r : ny - 1 - r;
+        double last1 = 0.0, last2 = 0.0;              // x ghosts
+        const double* prev_top = rowbuf + (size_t)(par ^ 1) * 2 * nx;   // rows 62, 63 of strip s - 1
+        double* cur_top = rowbuf + (size_t)par * 2 * nx;
+        // prefetch of the first cell's right-hand side and rate
+        auto cell_of = [&](int k) -> int64_t {
+            const int x = xpos ? k : nx - 1 - k;
+            return (int64_t)y * nx + x;
+        };
+        double rhs_n = 0.0, sig_n = 0.0;
+        {
+            const int k = -lane;
+            if (valid && k >= 0 && k < nx) {
+                const int64_t c = cell_of(k);
+                const float4 cf = a.coef[c];
+                rhs_n = rhs[c];
+                sig_n = (double)cf.x + (double)cf.y + (double)cf.z + a.inv_dt;
+            }
+        }
+        for (int t = 0; t < nx + 63; ++t) {
+            const int k = t - lane;
+            const bool active = valid && k >= 0 && k < nx;
+            const double rhs_c = rhs_n, sig_c = sig_n;
+            if (valid && k + 1 >= 0 && k + 1 < nx) {      // next cell of this lane
+                const int64_t c = cell_of(k + 1);
+                const float4 cf = a.coef[c];
+                rhs_n = rhs[c];
+                sig_n = (double)cf.x + (double)cf.y + (double)cf.z + a.inv_dt;
+            }
+            double yn1 = __shfl_up(last1, 1, 64);
+            double yn2 = __shfl_up(last2, 2, 64);
+            const bool kin = k >= 0 && k < nx;
+            if (lane == 0) {
+                yn1 = (s > 0 && kin) ? prev_top[nx + k] : 0.0;
+                yn2 = (s > 0 && kin) ? prev_top[k] : 0.0;
+            } else if (lane == 1) {
+                yn2 = (s > 0 && kin) ? prev_top[nx + k] : 0.0;
+            }
+            // The history shifts every step once the lane has started, also past the
+            // end of its row: the lane two rows up reads this lane's previous value
+            // one step later than the lane just above.
+            if (k >= 0) {
+                double v = 0.0;
+                if (active) {
+                    v = (rhs_c + ax * (2.0 * last1 - 0.5 * last2) + ay * (2.0 * yn1 - 0.5 * yn2)) /
+                        (dflux + sig_c);
+                    out[cell_of(k)] = v;
+                    if (lane >= 62) cur_top[(size_t)(lane - 62) * nx + k] = v;
+                }
+                last2 = last1;
+                last1 = v;
+            }
+        }
+        __syncthreads();
+        par ^= 1;
+    }
+}
+
+// part[b] = {sum (x - y)^2, sum x^2} over this block's elements of [n]
+__global__ __launch_bounds__(256) void imp_diff_kernel(const double* x, const double* y, int64_t n,
+                                                       double* part) {
+    double d = 0.0, m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kVecBlock + threadIdx.x;
+         i < std::min<int64_t>(n, (int64_t)(blockIdx.x + 1) * kVecBlock); i += 256) {
+        const double e = x[i] - y[i];
+        d += e * e;
+        m += x[i] * x[i];
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = d;
+    red[1][threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = red[0][0];
+        part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+__global__ __launch_bounds__(256) void imp_dot_kernel(const double* x, const double* y, int64_t n,
+                                                      double* part) {
+    double d = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kVecBlock + threadIdx.x;
+         i < std::min<int64_t>(n, (int64_t)(blockIdx.x + 1) * kVecBlock); i += 256)
+        d += x[i] * y[i];
+    __shared__ double red[256];
+    red[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void imp_axpy_kernel(double* y, double alpha, const double* x, double beta, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = beta * y[i] + alpha * x[i];
+}
+
+// phi[c] = sum_q w_q psi[q][c] (c < C; padding 0)
+__global__ void imp_moments_kernel(const double* psi, const double* w, int Q, int64_t C, int64_t P,
+                                   double* phi) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= P) return;
+    double s = 0.0;
+    if (c < C)
+        for (int q = 0; q < Q; ++q) s += w[q] * psi[(size_t)q * P + c];
+    phi[c] = s;
+}
+
+__global__ void imp_to64_kernel(const float* src, double* dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
+
+__global__ void imp_to32_kernel(const double* src, float* dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
+__global__ void imp_copy_kernel(const double* src, double* dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+struct BudgetArgs {
+    const double* psi;      // [Q][P]
+    const double* w;        // [Q]
+    const double* dq;       // [Q]: (w^T K)_q - w_q
+    const double* dir;
+    const float4* coef;
+    int nx, ny, Q;
+    int64_t C, P;
+    double dx, dy;
+    double* part;           // [blocks][4]: Phi, sigma_a Phi, defect, outflow
+};
+
+// Per-block partials of the particle balance at the new level; the outflow
+// through a boundary face is the face flux 3/2 psi_last - 1/2 psi_before_last.
+__global__ __launch_bounds__(256) void imp_budget_kernel(BudgetArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c < a.C) {
+        const int y = (int)(c / a.nx), x = (int)(c - (int64_t)y * a.nx);
+        const float4 cf = a.coef[c];
+        double phi = 0.0, dd = 0.0, out = 0.0;
+        const bool edge = x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1;
+        for (int q = 0; q < a.Q; ++q) {
+            const double p = a.psi[(size_t)q * a.P + c];
+            phi += a.w[q] * p;
+            dd += a.dq[q] * p;
+            if (!edge) continue;
+            const double ax = a.dir[4 * q], ay = a.dir[4 * q + 1];
+            const bool xp = a.dir[4 * q + 2] > 0.0, yp = a.dir[4 * q + 3] > 0.0;
+            double f = 0.0;
+            if (ax > 0.0 && ((xp && x == a.nx - 1) || (!xp && x == 0))) {
+                const int xb = xp ? x - 1 : x + 1;
+                const double pb = (xb >= 0 && xb < a.nx) ? a.psi[(size_t)q * a.P + (int64_t)y * a.nx + xb] : 0.0;
+                f += ax * a.dx * a.dy * (1.5 * p - 0.5 * pb);
+            }
+            if (ay > 0.0 && ((yp && y == a.ny - 1) || (!yp && y == 0))) {
+                const int yb = yp ? y - 1 : y + 1;
+                const double pb = (yb >= 0 && yb < a.ny) ? a.psi[(size_t)q * a.P + (int64_t)yb * a.nx + x] : 0.0;
+                f += ay * a.dx * a.dy * (1.5 * p - 0.5 * pb);
+            }
+            out += a.w[q] * f;
+        }
+        v[0] = phi;
+        v[1] = (double)cf.x * phi;
+        v[2] = (double)cf.z * dd;
+        v[3] = out;
+    }
+    __shared__ double red[4][256];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.part[4 * blockIdx.x + k] = red[k][0];
+}
+
+}  // namespace
+
+#define IMP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            err = std::string(#expr ": ") + hipGetErrorString(e_);                             \
+            return false;                                                                      \
+        }                                                                                      \
+    } while (0)
+
+static size_t take(size_t& off, size_t bytes) {
+    const size_t o = off;
+    off += (size_t)rup((int64_t)bytes, 256);
+    return o;
+}
+
+size_t ImplicitSolver::bytes(const ImplicitParams& p) {
+    size_t off = 0;
+    const size_t plane = (size_t)p.Q * p.P * 8;
+    for (int i = 0; i < 4; ++i) take(off, plane);                 // psi_old, psi_a, psi_b, rhs
+    take(off, (size_t)p.Q * p.Q * 8);                             // K
+    take(off, (size_t)p.Q * 8 * 6);                               // w, dq, dir
+    take(off, (size_t)p.P * 16);                                  // coef
+    take(off, (size_t)p.P * 8);                                   // phi
+    take(off, (size_t)(p.gmres_restart + 6) * p.P * 8);           // GMRES vectors
+    take(off, (size_t)(ndiv(std::max<int64_t>(p.Q * p.P, p.P), kVecBlock) + 8) * 4 * 8);  // partials
+    return off;
+}
+
+bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const double* w,
+                          const double* K, const float* sigma_s, const float* sigma_a,
+                          const float* sigma_as, const float* source, char* base, hipStream_t s,
+                          std::string& err) {
+    p_ = p;
+    s_ = s;
+    if (p.nx > 2048) {
+        err = "the implicit sweep keeps two grid rows in LDS: nx must be <= 2048";
+        return false;
+    }
+    size_t off = 0;
+    const size_t plane = (size_t)p.Q * p.P * 8;
+    psi_old_ = reinterpret_cast<double*>(base + take(off, plane));
+    psi_a_ = reinterpret_cast<double*>(base + take(off, plane));
+    psi_b_ = reinterpret_cast<double*>(base + take(off, plane));
+    rhs_ = reinterpret_cast<double*>(base + take(off, plane));
+    K_ = reinterpret_cast<double*>(base + take(off, (size_t)p.Q * p.Q * 8));
+    double* small = reinterpret_cast<double*>(base + take(off, (size_t)p.Q * 8 * 6));
+    wq_ = small;
+    dq_ = small + p.Q;
+    dir_ = small + 2 * p.Q;
+    coef_ = reinterpret_cast<float4*>(base + take(off, (size_t)p.P * 16));
+    phi_ = reinterpret_cast<double*>(base + take(off, (size_t)p.P * 8));
+    vecs_ = reinterpret_cast<double*>(base + take(off, (size_t)(p.gmres_restart + 6) * p.P * 8));
+    nparts_ = (int)ndiv(std::max<int64_t>((int64_t)p.Q * p.P, p.P), kVecBlock) + 8;
+    part_ = reinterpret_cast<double*>(base + take(off, (size_t)nparts_ * 4 * 8));
+    hpart_.assign((size_t)nparts_ * 4, 0.0);
+
+    // host tables
+    std::vector<double> small_h((size_t)p.Q * 6, 0.0);
+    double tmax = 0.0;
+    for (int q = 0; q < p.Q; ++q) {
+        small_h[q] = w[q];
+        double col = 0.0;
+        for (int r = 0; r < p.Q; ++r) col += w[r] * K[(size_t)r * p.Q + q];
+        small_h[p.Q + q] = col - w[q];
+        const double xi = omega[3 * q], eta = omega[3 * q + 1];
+        small_h[2 * p.Q + 4 * q + 0] = std::fabs(xi) / p.dx;
+        small_h[2 * p.Q + 4 * q + 1] = std::fabs(eta) / p.dy;
+        small_h[2 * p.Q + 4 * q + 2] = xi >= 0.0 ? 1.0 : -1.0;
+        small_h[2 * p.Q + 4 * q + 3] = eta >= 0.0 ? 1.0 : -1.0;
+    }
+    std::vector<float4> coef((size_t)p.P, make_float4(0.f, 0.f, 0.f, 0.f));
+    for (int64_t c = 0; c < p.C; ++c) {
+        coef[c] = make_float4(sigma_a[c], sigma_s[c], sigma_as[c], source ? source[c] : 0.f);
+        const double st = (double)sigma_a[c] + sigma_s[c] + sigma_as[c] + 1.0 / p.dt;
+        tmax = std::max(tmax, (double)sigma_as[c] / st);
+    }
+    T_ = tmax;
+    double qs = 0.0;
+    if (source)
+        for (int64_t c = 0; c < p.C; ++c) qs += (double)source[c];
+    src_rate_ = p.dx * p.dy * p.W * qs;
+    IMP_TRY(hipMemcpyAsync(K_, K, (size_t)p.Q * p.Q * 8, hipMemcpyHostToDevice, s_));
+    IMP_TRY(hipMemcpyAsync(small, small_h.data(), small_h.size() * 8, hipMemcpyHostToDevice, s_));
+    IMP_TRY(hipMemcpyAsync(coef_, coef.data(), coef.size() * 16, hipMemcpyHostToDevice, s_));
+    const size_t lds = (size_t)4 * p.nx * 8;
+    if (lds > 65536) {
+        err = "sweep LDS request too large";
+        return false;
+    }
+    IMP_TRY(hipFuncSetAttribute((const void*)imp_sweep_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return true;
+}
+
+bool ImplicitSolver::set_state(const float* psi32, double* phi64_out, std::string& err) {
+    const int64_t n = (int64_t)p_.Q * p_.P;
+    imp_to64_kernel<<<ndiv(n, 256), 256, 0, s_>>>(psi32, psi_old_, n);
+    IMP_TRY(hipGetLastError());
+    if (!moments(psi_old_, phi_, err)) return false;
+    IMP_TRY(hipMemcpyAsync(phi64_out, phi_, (size_t)p_.C * 8, hipMemcpyDeviceToDevice, s_));
+    // budget start: M^0
+    std::vector<double> h((size_t)p_.P);
+    IMP_TRY(hipMemcpyAsync(h.data(), phi_, (size_t)p_.C * 8, hipMemcpyDeviceToHost, s_));
+    IMP_TRY(hipStreamSynchronize(s_));
+    double m = 0.0;
+    for (int64_t c = 0; c < p_.C; ++c) m += h[c];
+    m *= p_.dx * p_.dy;
+    std::memset(budget, 0, sizeof(budget));
+    budget[0] = m;
+    budget[1] = m;
+    sweeps = matvecs = 0;
+    return true;
+}
+
+bool ImplicitSolver::get_state(float* psi32, std::string& err) {
+    const int64_t n = (int64_t)p_.Q * p_.P;
+    imp_to32_kernel<<<ndiv(n, 256), 256, 0, s_>>>(psi_old_, psi32, n);
+    IMP_TRY(hipGetLastError());
+    return true;
+}
+
+bool ImplicitSolver::sweep_once(const double* psi_in, double* psi_out, const double* phi,
+                                double alpha, double beta, std::string& err) {
+    RhsArgs r{K_, psi_in, psi_old_, phi, coef_, rhs_, p_.Q, p_.C, p_.P, alpha, beta,
+              1.0 / p_.dt, 1.0 / p_.W};
+    dim3 g(ndiv(p_.Q, kT), (unsigned)(p_.P / kT));
+    imp_rhs_kernel<<<g, 256, 0, s_>>>(r);
+    IMP_TRY(hipGetLastError());
+    SweepArgs sa{rhs_, dir_, coef_, psi_out, p_.nx, p_.ny, p_.P, 1.0 / p_.dt};
+    imp_sweep_kernel<<<p_.Q, 64, (size_t)4 * p_.nx * 8, s_>>>(sa);
+    IMP_TRY(hipGetLastError());
+    ++sweeps;
+    return true;
+}
+
+double* ImplicitSolver::source_iteration(const double* phi, double alpha, double beta,
+                                         std::string& err, bool& ok) {
+    ok = false;
+    const double c = T_ > 0.0 ? (1.0 - T_) / T_ : 0.0;
+    const double* prev = psi_old_;
+    double* bufs[2] = {psi_a_, psi_b_};
+    int cur = 0;
+    if (!sweep_once(prev, bufs[cur], phi, alpha, beta, err)) return nullptr;
+    if (T_ == 0.0) {       // no artificial scattering: one sweep is the exact inverse
+        ok = true;
+        return bufs[cur];
+    }
+    const int64_t n = (int64_t)p_.Q * p_.P;
+    const unsigned nb = ndiv(n, kVecBlock);
+    for (int it = 1; it < 500; ++it) {
+        imp_diff_kernel<<<nb, 256, 0, s_>>>(bufs[cur], prev, n, part_);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(hpart_.data(), part_, (size_t)nb * 2 * 8, hipMemcpyDeviceToHost, s_) != hipSuccess ||
+            hipStreamSynchronize(s_) != hipSuccess) {
+            err = "source-iteration norm failed";
+            return nullptr;
+        }
+        double d = 0.0, m = 0.0;
+        for (unsigned b = 0; b < nb; ++b) {
+            d += hpart_[2 * b];
+            m += hpart_[2 * b + 1];
+        }
+        if (!(std::sqrt(d) >= p_.source_tol * c * std::sqrt(m))) break;
+        prev = bufs[cur];
+        cur ^= 1;
+        if (!sweep_once(prev, bufs[cur], phi, alpha, beta, err)) return nullptr;
+    }
+    ok = true;
+    return bufs[cur];
+}
+
+bool ImplicitSolver::moments(const double* psi, double* phi, std::string& err) {
+    imp_moments_kernel<<<ndiv(p_.P, 256), 256, 0, s_>>>(psi, wq_, p_.Q, p_.C, p_.P, phi);
+    IMP_TRY(hipGetLastError());
+    return true;
+}
+
+bool ImplicitSolver::dot(const double* a, const double* b, double& out, std::string& err) {
+    const unsigned nb = ndiv(p_.P, kVecBlock);
+    imp_dot_kernel<<<nb, 256, 0, s_>>>(a, b, p_.P, part_);
+    IMP_TRY(hipGetLastError());
+    IMP_TRY(hipMemcpyAsync(hpart_.data(), part_, (size_t)nb * 8, hipMemcpyDeviceToHost, s_));
+    IMP_TRY(hipStreamSynchronize(s_));
+    out = 0.0;
+    for (unsigned i = 0; i < nb; ++i) out += hpart_[i];
+    return true;
+}
+
+bool ImplicitSolver::axpy(double* y, double alpha, const double* x, std::string& err) {
+    imp_axpy_kernel<<<ndiv(p_.P, 256), 256, 0, s_>>>(y, alpha, x, 1.0, p_.P);
+    IMP_TRY(hipGetLastError());
+    return true;
+}
+
+bool ImplicitSolver::scale_copy(double* y, double alpha, const double* x, std::string& err) {
+    imp_axpy_kernel<<<ndiv(p_.P, 256), 256, 0, s_>>>(y, alpha, x, 0.0, p_.P);
+    IMP_TRY(hipGetLastError());
+    return true;
+}
+
+// out = v - M L~^-1 (sigma_s v / W), L~ = L - sigma_as K (Algorithm 2)
+bool ImplicitSolver::lhs(const double* v, double* out, std::string& err) {
+    bool ok = false;
+    double* psi = source_iteration(v, 1.0, 0.0, err, ok);
+    if (!ok) return false;
+    if (!moments(psi, out, err)) return false;
+    // out = v - out
+    imp_axpy_kernel<<<ndiv(p_.P, 256), 256, 0, s_>>>(out, 1.0, v, -1.0, p_.P);
+    IMP_TRY(hipGetLastError());
+    ++matvecs;
+    return true;
+}
+
+bool ImplicitSolver::fold_budget(const double* psi_new, double mass_prev, std::string& err) {
+    const unsigned nb = ndiv(p_.C, 256);
+    BudgetArgs b{psi_new, wq_, dq_, dir_, coef_, p_.nx, p_.ny, p_.Q, p_.C, p_.P, p_.dx, p_.dy, part_};
+    imp_budget_kernel<<<nb, 256, 0, s_>>>(b);
+    IMP_TRY(hipGetLastError());
+    std::vector<double> h((size_t)nb * 4);
+    IMP_TRY(hipMemcpyAsync(h.data(), part_, h.size() * 8, hipMemcpyDeviceToHost, s_));
+    IMP_TRY(hipStreamSynchronize(s_));
+    double t[4] = {0, 0, 0, 0};
+    for (unsigned i = 0; i < nb; ++i)
+        for (int k = 0; k < 4; ++k) t[k] += h[4 * i + k];
+    const double area = p_.dx * p_.dy;
+    const double m_next = area * t[0], absr = area * t[1], def = area * t[2], out = t[3];
+    const double src = src_rate_;
+    const double pred = mass_prev + p_.dt * (-absr - out + src + def);
+    const double ref = std::max(budget[1], mass_prev);
+    const double rel = ref > 0.0 ? std::fabs(m_next - pred) / ref : std::fabs(m_next - pred);
+    budget[0] = m_next;
+    budget[2] += p_.dt * absr;
+    budget[3] += p_.dt * out;
+    budget[4] += p_.dt * src;
+    budget[5] += p_.dt * def;
+    budget[6] = std::max(budget[6], rel);
+    budget[7] += 1.0;
+    return true;
+}
+
+bool ImplicitSolver::step(int64_t n, double* phi64_out, std::string& err) {
+    const int m = p_.gmres_restart;
+    double* V = vecs_;                  // V_0 .. V_m
+    double* wv = vec(m + 1);
+    double* bv = vec(m + 2);
+    double* xv = vec(m + 3);
+    double* rv = vec(m + 4);
+    double* tmp = vec(m + 5);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hat = [&](int i, int k) -> double& { return H[(size_t)i * m + k]; };
+    for (int64_t step = 0; step < n; ++step) {
+        const double mass_prev = budget[0];
+        bool ok = false;
+        // b = M L~^-1 (q + psi_old / dt)
+        double* psi = source_iteration(nullptr, 0.0, 1.0, err, ok);
+        if (!ok || !moments(psi, bv, err)) return false;
+        // GMRES on A phi = b from the previous scalar flux (Algorithm 3)
+        IMP_TRY(hipMemcpyAsync(xv, phi_, (size_t)p_.P * 8, hipMemcpyDeviceToDevice, s_));
+        double bnorm = 0.0;
+        if (!dot(bv, bv, bnorm, err)) return false;
+        bnorm = std::sqrt(bnorm);
+        const int max_mv = 300;
+        int n_mv = 0;
+        bool done = bnorm == 0.0;
+        if (done) IMP_TRY(hipMemsetAsync(xv, 0, (size_t)p_.P * 8, s_));
+        while (!done && n_mv < max_mv) {
+            if (!lhs(xv, wv, err)) return false;
+            ++n_mv;
+            if (!scale_copy(rv, 1.0, bv, err) || !axpy(rv, -1.0, wv, err)) return false;
+            double beta = 0.0;
+            if (!dot(rv, rv, beta, err)) return false;
+            beta = std::sqrt(beta);
+            if (beta <= p_.gmres_tol * bnorm) break;
+            if (!scale_copy(V, 1.0 / beta, rv, err)) return false;
+            std::fill(H.begin(), H.end(), 0.0);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int kd = 0;
+            for (int k = 0; k < m; ++k) {
+                double* Vk = V + (size_t)k * p_.P;
+                if (!lhs(Vk, wv, err)) return false;
+                ++n_mv;
+                for (int i = 0; i <= k; ++i) {
+                    double h = 0.0;
+                    if (!dot(wv, V + (size_t)i * p_.P, h, err)) return false;
+                    Hat(i, k) = h;
+                    if (!axpy(wv, -h, V + (size_t)i * p_.P, err)) return false;
+                }
+                double hn = 0.0;
+                if (!dot(wv, wv, hn, err)) return false;
+                hn = std::sqrt(hn);
+                Hat(k + 1, k) = hn;
+                for (int i = 0; i < k; ++i) {
+                    const double t = cs[i] * Hat(i, k) + sn[i] * Hat(i + 1, k);
+                    Hat(i + 1, k) = -sn[i] * Hat(i, k) + cs[i] * Hat(i + 1, k);
+                    Hat(i, k) = t;
+                }
+                const double den = std::hypot(Hat(k, k), Hat(k + 1, k));
+                cs[k] = Hat(k, k) / den;
+                sn[k] = Hat(k + 1, k) / den;
+                Hat(k, k) = den;
+                Hat(k + 1, k) = 0.0;
+                g[k + 1] = -sn[k] * g[k];
+                g[k] = cs[k] * g[k];
+                kd = k + 1;
+                if (std::fabs(g[k + 1]) <= p_.gmres_tol * bnorm || hn == 0.0 || n_mv >= max_mv) break;
+                if (!scale_copy(V + (size_t)(k + 1) * p_.P, 1.0 / hn, wv, err)) return false;
+            }
+            for (int i = kd - 1; i >= 0; --i) {       // back substitution
+                double s = g[i];
+                for (int j = i + 1; j < kd; ++j) s -= Hat(i, j) * y[j];
+                y[i] = s / Hat(i, i);
+            }
+            for (int i = 0; i < kd; ++i)
+                if (!axpy(xv, y[i], V + (size_t)i * p_.P, err)) return false;
+            if (std::fabs(g[kd]) <= p_.gmres_tol * bnorm) break;
+        }
+        // psi^{n+1} = L~^-1 (sigma_s phi / W + q + psi_old / dt)
+        psi = source_iteration(xv, 1.0, 1.0, err, ok);
+        if (!ok) return false;
+        IMP_TRY(hipMemcpyAsync(psi_old_, psi, (size_t)p_.Q * p_.P * 8, hipMemcpyDeviceToDevice, s_));
+        IMP_TRY(hipMemcpyAsync(phi_, xv, (size_t)p_.P * 8, hipMemcpyDeviceToDevice, s_));
+        if (!moments(psi_old_, tmp, err)) return false;
+        IMP_TRY(hipMemcpyAsync(phi64_out, tmp, (size_t)p_.C * 8, hipMemcpyDeviceToDevice, s_));
+        if (!fold_budget(psi_old_, mass_prev, err)) return false;
+    }
+    return true;
+}
+
+}  // namespace asn

@@ -1,0 +1,106 @@
+"""GPU parity of the implicit as-S_N scheme (paper Sections 3.4-3.5, Algorithms
+1-3) against the FP64 oracle.  Both sides run in FP64; with tight iteration
+tolerances they solve the same linear systems and agree to rounding, and with
+the paper's tolerances they take the same iteration decisions."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import asn_oracle as o
+from oracle import implicit_oracle as io
+from oracle import linesource_ref as L
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1911_08801_amd import asn  # noqa: E402
+
+
+def _gpu(spec, dt, n, psi0=None, tight=False):
+    p = asn.from_spec(spec, scheme="implicit", dt_override=dt, set_initial_state=psi0 is None,
+                      implicit_tol=1e-13 if tight else 0.0, source_tol=1e-13 if tight else 0.0)
+    try:
+        if psi0 is not None:
+            asn.asn_set_state(p, psi0)
+        asn.asn_step(p, n)
+        return (asn.asn_get_state(p), asn.asn_scalar_flux(p), asn.asn_mass_budget(p),
+                asn.asn_iteration_counts(p))
+    finally:
+        p.close()
+
+
+def _oracle(spec, dt, n, psi0=None, tight=False):
+    st = o.setup(spec, dt=dt)
+    psi = (spec.psi0() if psi0 is None else psi0).astype(np.float64)
+    phi = o.scalar_flux(psi, st.w)
+    stats = {"si_sweeps": 0, "gmres_matvecs": 0}
+    for _ in range(n):
+        s = {}
+        psi, phi = io.implicit_step(psi, st, dt, phi, gmres_tol=1e-13 if tight else 1.5e-8,
+                                    si_eps=1e-13 if tight else 1e-4, stats=s)
+        for k in stats:
+            stats[k] += s[k]
+    return psi, st, stats
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 3), (13, 11), (9, 70), (40, 130), (67, 5)])
+def test_tight_steps_match_oracle(nx, ny):
+    spec = wl.random_problem(nx * 7 + ny, nx, ny, n_polar=2, n_azim=4, beta=4.5)
+    psi0 = wl.random_state(nx + ny, spec.q, ny, nx)
+    dt = 0.05
+    state, phi, bud, _ = _gpu(spec, dt, 2, psi0, tight=True)
+    ref, st, _ = _oracle(spec, dt, 2, psi0, tight=True)
+    assert np.max(np.abs(state - ref)) <= 1e-6 * np.abs(ref).max()    # FP32 read-out of FP64
+    assert np.max(np.abs(phi - o.scalar_flux(ref, st.w))) <= 1e-10 * np.abs(phi).max()
+    assert bud["max_residual"] < 1e-10
+    assert bud["steps"] == 2
+
+
+def test_icosahedron_set_with_zero_eta_ordinates():
+    spec = wl.line_source(24, sigma_as=3.0, beta=4.0)
+    spec.ico_order = 3                      # 42 ordinates, some with eta = 0
+    dt = 2 * 3.0 / 24
+    state, phi, bud, _ = _gpu(spec, dt, 2, tight=True)
+    ref, st, _ = _oracle(spec, dt, 2, tight=True)
+    assert np.max(np.abs(phi - o.scalar_flux(ref, st.w))) <= 1e-10 * np.abs(phi).max()
+
+
+def test_paper_tolerances_take_the_oracles_iterations():
+    spec = wl.line_source(30, n_polar=4, sigma_as=5.0, beta=4.0)
+    dt = 2 * 3.0 / 30
+    state, phi, bud, counts = _gpu(spec, dt, 3)
+    ref, st, stats = _oracle(spec, dt, 3)
+    assert rel_l2(phi, o.scalar_flux(ref, st.w)) <= 1e-9
+    assert counts["sweeps"] == stats["si_sweeps"]
+    assert counts["matvecs"] == stats["gmres_matvecs"]
+
+
+def test_twelve_ordinate_implicit_ratio_and_parity():
+    ref = 4 * math.pi * L.line_source_on_grid(50, 1.0, wl.LINE_SOURCE_DELTA, n_k=800, n_tau=1200)
+    err = {}
+    for s_as in (0.0, 7.0):
+        spec = wl.line_source(50, sigma_as=s_as, beta=4.0)
+        spec.ico_order = 2
+        _, phi, bud, _ = _gpu(spec, 1.0 / 8, 8)
+        psi_o, st, _ = _oracle(spec, 1.0 / 8, 8)
+        assert rel_l2(phi, o.scalar_flux(psi_o, st.w)) <= 1e-8
+        err[s_as] = rel_l2(phi, ref)
+    assert 0.3 < err[7.0] / err[0.0] < 0.65
+
+
+def test_implicit_rejections():
+    spec = wl.line_source(20, n_polar=2)
+    p = asn.from_spec(spec, scheme="implicit", dt_override=0.3)      # cfl > 1 is allowed
+    with pytest.raises(asn.AsnError) as e:
+        asn.asn_batch_create([p])
+    assert e.value.status == asn.ASN_E_UNSUPPORTED
+    p.close()
+    wide = wl.random_problem(1, 2100, 2, n_polar=1, n_azim=4)
+    with pytest.raises(asn.AsnError) as e:
+        asn.from_spec(wide, scheme="implicit")
+    assert e.value.status == asn.ASN_E_UNSUPPORTED

@@ -11,6 +11,7 @@ Prints ONE JSON line (rank 0, N = 1).
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import platform
@@ -39,6 +40,7 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-heun", action="store_true", help="skip the Heun + minmod line")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-scheme line")
     ap.add_argument("--sweep", choices=["lattice700", "line1024"], default=None,
                     help="precision sweep to t_final on a configured workload (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -222,6 +224,38 @@ def serving_run(args):
     return out
 
 
+def implicit_run(steps=3):
+    """The paper's implicit line-source configuration: 200 x 200 cells, the 92-ordinate
+    icosahedron set (S4), sigma_as = 7, beta = 4, dt = 2 dx, FP64 sweeps + GMRES with
+    the paper's tolerances (1.5e-8 GMRES, 1e-4 source iteration)."""
+    import torch
+
+    import workloads as wl
+    from paper_1911_08801_amd import asn
+    spec = wl.line_source(200, sigma_as=7.0, beta=4.0)
+    spec.ico_order = 4
+    n_tot = int(math.ceil(1.0 / (2 * 3.0 / 200)))
+    dt = 1.0 / n_tot
+    p = asn.from_spec(spec, scheme="implicit", dt_override=dt)
+    asn.asn_step(p, 1)                      # warm-up step
+    torch.cuda.synchronize()
+    c0 = asn.asn_iteration_counts(p)
+    t0 = time.perf_counter()
+    asn.asn_step(p, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c1 = asn.asn_iteration_counts(p)
+    p.close()
+    sweeps = (c1["sweeps"] - c0["sweeps"]) / steps
+    mv = (c1["matvecs"] - c0["matvecs"]) / steps
+    return {"workload": f"line source 200x200, icosahedron S4 (92 ordinates), sigma_as=7, beta=4, "
+                        f"dt=2dx ({n_tot} steps to t=1), FP64",
+            "ms_per_step": 1e3 * wall / steps, "sweeps_per_step": sweeps,
+            "gmres_matvecs_per_step": mv,
+            "cell_ordinate_sweeps_per_s": spec.cells * spec.q * sweeps * steps / wall,
+            "steps_timed": steps}
+
+
 def precision_sweep(name):
     """Full runs to t_final with FP32, BF16 and FP16 contractions on one workload;
     updates/s per form and each reduced form's scalar-flux error against FP32."""
@@ -311,6 +345,8 @@ def main():
         r = timed_run(asn, spec, "f32", args.steps, args.warmup, scheme="heun")
         out["heun_f32"] = summary(r, spec, args.steps)
         out["heun_f32"]["roofline"] = roofline(r, spec, "f32")
+    if not args.no_implicit:
+        out["implicit"] = implicit_run()
     if not args.no_serving:
         out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:

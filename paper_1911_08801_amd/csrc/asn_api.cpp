@@ -46,7 +46,7 @@ struct Layout {
     bool lowp = false, fused = false;
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
-        off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_bmax0, off_bmax1, off_rec,
+        off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_delta, off_bmax0, off_bmax1, off_rec,
         off_tab, off_off, off_base, off_left, off_imp,
         total;
 };
@@ -106,9 +106,10 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     L.off_phi64 = take(plane * 8);
     L.off_phipart = take((size_t)L.G * plane * 8);
     L.off_blk = take((size_t)tiles * L.G * 2 * 8);
-    L.off_fin = take((size_t)L.fin_blocks * 3 * 8);
+    L.off_fin = take((size_t)L.fin_blocks * 4 * 8);
     L.off_ypart = take(L.lowp ? (size_t)(L.Qp / asn::kGemmBM) * plane * 8 : 0);
-    L.off_fix = take(L.lowp ? plane * 4 : 0);
+    L.off_fix = take(L.lowp && !fused ? plane * 4 : 0);
+    L.off_delta = take(L.lowp && fused ? plane * 4 : 0);
     L.off_bmax0 = take(plane / asn::kScaleBlock * 4);
     L.off_bmax1 = take(plane / asn::kScaleBlock * 4);
     L.off_rec = take(asn::REC_LEN * 8);
@@ -206,6 +207,7 @@ StepArgs make_args(asn_problem p, int cur) {
     a.fin_part = reinterpret_cast<double*>(b + L.off_fin);
     a.ypart = reinterpret_cast<double*>(b + L.off_ypart);
     a.fix = reinterpret_cast<float*>(b + L.off_fix);
+    a.delta = reinterpret_cast<float*>(b + L.off_delta);
     unsigned* bm0 = reinterpret_cast<unsigned*>(b + L.off_bmax0);
     unsigned* bm1 = reinterpret_cast<unsigned*>(b + L.off_bmax1);
     a.bmax_cur = cur == 0 ? bm0 : bm1;
@@ -640,6 +642,8 @@ asn_status asn_set_state_isotropic(asn_problem p, const float* cell, int32_t on_
 asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
     if (!p || !psi) return fail(ASN_E_INVALID, "NULL argument");
     const Layout& L = p->L;
+    if (p->L.lowp && p->L.fused)   // fold the pending correction into the stored state
+        HIP_TRY(asn::launch_materialize(p->tab[p->cur], p->stream));
     if (p->imp) {          // the implicit state is FP64: round it into the FP32 buffer first
         std::string ierr;
         if (!p->imp->get_state(reinterpret_cast<float*>(p->base + (p->cur == 0 ? L.off_psi0 : L.off_psi1)),

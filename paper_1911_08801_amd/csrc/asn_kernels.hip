@@ -53,6 +53,12 @@ __device__ __forceinline__ bool locate(const BatchArgs& B, int kind, int b, int&
     return gp(B.steps_left)[lo] > 0;
 }
 
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
 __device__ __forceinline__ StepArgs args_of(const BatchArgs& B, int i) {
     return gp(B.tab)[2 * i + (gp(B.base)[i] ^ B.s_par)];
 }
@@ -364,12 +370,14 @@ __device__ __forceinline__ f32x4 mfma_lp(const uint4& av, const uint4& bv, const
                                                       __builtin_bit_cast(f16x8, bv), c, 0, 0, 0);
 }
 
-template <int DT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void gemm_lp_kernel(BatchArgs B) {
+template <int DT, bool FUSED>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? 2 : 3, 3)))
+void gemm_lp_kernel(BatchArgs B) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][kGemmBM][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bl[DT == 1 ? 2 : 1][DT == 1 ? kGemmBN : 1][kRowL];
     __shared__ double red[2][kGemmBN];
+    __shared__ double yred[FUSED ? 2 : 1][FUSED ? kGemmBN : 1];
     int pi, tile;
     if (!locate(B, KT_GEMM, xcd_remap(blockIdx.x, gridDim.x), pi, tile)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
@@ -466,12 +474,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint4 bv = *reinterpret_cast<const uint4*>(&Bs[b][wn + j * 16 + r16][kofs]);
+            // FUSED: rows = cells (bv), columns = ordinates (av): acc[cell block][ordinate block]
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][j] = mfma_lp<DT>(av[i], bv, acc[i][j]);
+            for (int i = 0; i < 4; ++i) {
+                if constexpr (FUSED) acc[j][i] = mfma_lp<DT>(bv, av[i], acc[j][i]);
+                else acc[i][j] = mfma_lp<DT>(av[i], bv, acc[i][j]);
+            }
             if constexpr (DT == 1) {
                 const uint4 bl = *reinterpret_cast<const uint4*>(&Bl[b][wn + j * 16 + r16][kofs]);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i][j] = mfma_lp<DT>(av[i], bl, acc[i][j]);
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (FUSED) acc[j][i] = mfma_lp<DT>(bl, av[i], acc[j][i]);
+                    else acc[i][j] = mfma_lp<DT>(av[i], bl, acc[i][j]);
+                }
             }
         }
         if (kt + 1 < nkt) lstore(b ^ 1);
@@ -479,29 +494,186 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     }
 #undef ASN_GLOAD_LP
 
+    if constexpr (!FUSED) {
     double part[4] = {0.0, 0.0, 0.0, 0.0};
+    #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t n = n0 + wn + j * 16 + (lane & 15);
+            const float iso_n = iso[n];
+    #pragma unroll
+            for (int i = 0; i < 4; ++i)
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
+                    if (m < Q) {
+                        const float dev = psi[(size_t)m * P + n] - iso_n;
+                        const float y = iso_n + s_out * acc[i][j][v] + rdef[m] * dev;
+                        Yo[(size_t)m * P + n] = y;
+                        part[j] += qinfo[m].w * (double)y;
+                    }
+                }
+            part[j] += __shfl_xor(part[j], 16, 64);
+            part[j] += __shfl_xor(part[j], 32, 64);
+            if (lane < 16) red[wave & 1][wn + j * 16 + lane] = part[j];
+        }
+        __syncthreads();
+        if (tid < kGemmBN) ypart[(size_t)mt * P + n0 + tid] = red[0][tid] + red[1][tid];
+    } else {
+        // Stream + collide with the stored state psi^ and the per-cell pending particle
+        // correction delta: the true state is psi^ + delta (delta is isotropic, so it
+        // drops out of the quantised deviation psi^ - iso^; iso^ = Phi^ / W).
+        //   Y^  = (iso^ + delta) + 2^(e - E) T(K) x + r_q (psi^ - iso^)
+        //   new = psi - cx (psi - up_x) - cy (psi - up_y) - dt sigma_a psi + col^ + dt q
+        //   col^ = dt sigma_as (Y^ - psi) + dt sigma_s (iso - psi)
+        // The block writes psi^{n+1} without its own correction and the per-cell
+        // partials of Phi^, of sum_q w_q Y^ (for the next correction) and the budget.
+        const int nx = a.nx, ny = a.ny;
+        const int64_t C = a.C;
+        ASN_G float* __restrict__ out = gp(a.psi_new);
+        const ASN_G float* __restrict__ dl = gp(a.delta);
+        const bool rows4 = (nx & 3) == 0;
+        float rq[4], cxq[4], cyq[4];
+        int dq[4];
+        double wq[4];
+        bool qok[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t n = n0 + wn + j * 16 + (lane & 15);
-        const float iso_n = iso[n];
+        for (int j = 0; j < 4; ++j) {
+            const int q = m0 + wm + j * 16 + (lane & 15);
+            qok[j] = q < Q;
+            const QInfo qi = qinfo[qok[j] ? q : 0];
+            rq[j] = rdef[qok[j] ? q : 0];
+            cxq[j] = qi.cx;
+            cyq[j] = qi.cy;
+            dq[j] = qi.dir;
+            wq[j] = qi.w;
+        }
+        double defect = 0.0, outflow = 0.0;
+        float mx = 0.f;
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
+            const int64_t c0 = n0 + wn + i * 16 + 4 * (lane >> 4);
+            float aa[4], bs[4], gs[4], ss[4];
+            int xk[4], yk[4];
+            bool ck[4];
+            const float4 ih4 = *reinterpret_cast<const ASN_G float4*>(iso + c0);
+            const float4 d4 = *reinterpret_cast<const ASN_G float4*>(dl + c0);
+            const float ihv[4] = {ih4.x, ih4.y, ih4.z, ih4.w};
+            const float dv[4] = {d4.x, d4.y, d4.z, d4.w};
+            {
+                const int y0 = (int)(c0 / nx);
+                int x = (int)(c0 - (int64_t)y0 * nx), y = y0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
-                if (m < Q) {
-                    const float dev = psi[(size_t)m * P + n] - iso_n;
-                    const float y = iso_n + s_out * acc[i][j][v] + rdef[m] * dev;
-                    Yo[(size_t)m * P + n] = y;
-                    part[j] += qinfo[m].w * (double)y;
+                for (int k = 0; k < 4; ++k) {
+                    ck[k] = c0 + k < C;
+                    xk[k] = x;
+                    yk[k] = y;
+                    if (++x == nx) {
+                        x = 0;
+                        ++y;
+                    }
+                    const float4 cf = ck[k] ? gp(a.coef)[c0 + k] : z4;
+                    aa[k] = cf.x;
+                    bs[k] = cf.y;
+                    gs[k] = cf.z;
+                    ss[k] = cf.w;
                 }
             }
-        part[j] += __shfl_xor(part[j], 16, 64);
-        part[j] += __shfl_xor(part[j], 32, 64);
-        if (lane < 16) red[wave & 1][wn + j * 16 + lane] = part[j];
+            // pending corrections of the neighbouring cells
+            const float dprev = c0 >= 4 ? dl[c0 - 1] : 0.f;
+            const float dnext = c0 + 4 < P ? dl[c0 + 4] : 0.f;
+            double ph[4] = {0.0, 0.0, 0.0, 0.0}, yp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!qok[j]) continue;
+                const int q = m0 + wm + j * 16 + (lane & 15);
+                const ASN_G float* row = psi + (size_t)q * P;
+                const float4 v4 = *reinterpret_cast<const ASN_G float4*>(row + c0);
+                const float vh[4] = {v4.x, v4.y, v4.z, v4.w};
+                float ux[4] = {0.f, 0.f, 0.f, 0.f};
+                if (dq[j] & 1) {
+                    ux[0] = (c0 >= 4 ? row[c0 - 1] : 0.f) + dprev;
+#pragma unroll
+                    for (int k = 1; k < 4; ++k) ux[k] = vh[k - 1] + dv[k - 1];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (xk[k] == 0) ux[k] = 0.f;
+                } else if (dq[j] & 2) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) ux[k] = vh[k + 1] + dv[k + 1];
+                    ux[3] = (c0 + 4 < P ? row[c0 + 4] : 0.f) + dnext;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (xk[k] == nx - 1) ux[k] = 0.f;
+                }
+                float uy[4] = {0.f, 0.f, 0.f, 0.f};
+                if (dq[j] & 12) {
+                    const int64_t sh = (dq[j] & 4) ? -(int64_t)nx : (int64_t)nx;
+                    if (rows4) {
+                        const bool has = (dq[j] & 4) ? yk[0] > 0 : yk[0] < ny - 1;
+                        if (has && ck[0]) {
+                            const float4 u4 = *reinterpret_cast<const ASN_G float4*>(row + c0 + sh);
+                            const float4 e4 = *reinterpret_cast<const ASN_G float4*>(dl + c0 + sh);
+                            uy[0] = u4.x + e4.x;
+                            uy[1] = u4.y + e4.y;
+                            uy[2] = u4.z + e4.z;
+                            uy[3] = u4.w + e4.w;
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const bool has = ck[k] && ((dq[j] & 4) ? yk[k] > 0 : yk[k] < ny - 1);
+                            uy[k] = has ? row[c0 + k + sh] + dl[c0 + k + sh] : 0.f;
+                        }
+                    }
+                }
+                float nv[4];
+                float colsum = 0.f, o = 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float v = vh[k] + dv[k];
+                    const float dev = vh[k] - ihv[k];
+                    const float ya = s_out * acc[i][j][k] + rq[j] * dev;   // Y^ - iso
+                    const float col = gs[k] * ((ihv[k] + ya) - vh[k]) + bs[k] * (ihv[k] - vh[k]);
+                    const float r = v - cxq[j] * (v - ux[k]) - cyq[j] * (v - uy[k]) - aa[k] * v + col + ss[k];
+                    nv[k] = ck[k] ? r : 0.f;
+                    ph[k] += wq[j] * (double)nv[k];
+                    yp[k] += ck[k] ? wq[j] * ((double)(ihv[k] + dv[k]) + (double)ya) : 0.0;
+                    colsum += ck[k] ? col : 0.f;
+                    mx = fmaxf(mx, fabsf(nv[k]));
+                    if (ck[k]) {
+                        if (((dq[j] & 1) && xk[k] == nx - 1) || ((dq[j] & 2) && xk[k] == 0)) o += cxq[j] * v;
+                        if (((dq[j] & 4) && yk[k] == ny - 1) || ((dq[j] & 8) && yk[k] == 0)) o += cyq[j] * v;
+                    }
+                }
+                *reinterpret_cast<ASN_G float4*>(out + (size_t)q * P + c0) =
+                    make_float4(nv[0], nv[1], nv[2], nv[3]);
+                defect += wq[j] * (double)colsum;
+                outflow += wq[j] * (double)o;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+#pragma unroll
+                for (int sft = 1; sft < 16; sft <<= 1) {
+                    ph[k] += __shfl_xor(ph[k], sft, 64);
+                    yp[k] += __shfl_xor(yp[k], sft, 64);
+                }
+                if ((lane & 15) == 0) {
+                    red[wave & 1][wn + i * 16 + 4 * (lane >> 4) + k] = ph[k];
+                    yred[wave & 1][wn + i * 16 + 4 * (lane >> 4) + k] = yp[k];
+                }
+            }
+        }
+        // block max |psi^{n+1}| of the next operand scale: the tile lies in one block
+        const unsigned mbits = wave_max_u32(__float_as_uint(mx));
+        if (lane == 0 && mbits) atomicMax(&a.bmax_next[n0 / kScaleBlock], mbits);
+        double sums[2] = {defect, outflow};
+        block_sum_256<2>(sums, gp(a.blk_part) + 2 * (size_t)tile);   // synchronises the block
+        if (tid < kGemmBN) {
+            gp(a.phi_part)[(size_t)mt * P + n0 + tid] = red[0][tid] + red[1][tid];
+            ypart[(size_t)mt * P + n0 + tid] = yred[0][tid] + yred[1][tid];
+        }
     }
-    __syncthreads();
-    if (tid < kGemmBN) ypart[(size_t)mt * P + n0 + tid] = red[0][tid] + red[1][tid];
 }
 
 // ---------------------------------------------------------------------------
@@ -559,11 +731,6 @@ __device__ __forceinline__ void store_plane(float v, __amdgpu_buffer_rsrc_t r, u
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
 }
 
-__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off, 64));
-    return v;
-}
 
 template <bool LP>
 __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
@@ -914,20 +1081,54 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
     const int G = init ? 1 : a.G;
     ASN_G unsigned* bmax_zero = init ? nullptr : gp(a.bmax_cur);
     const int64_t c = (int64_t)local * 256 + threadIdx.x;
-    double s[3] = {0.0, 0.0, 0.0};
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < a.C) {
         double phi = 0.0;
         const ASN_G double* pp = gp(a.phi_part);
         for (int g = 0; g < G; ++g) phi += pp[(size_t)g * a.P + c];
-        gp(a.phi64)[c] = phi;
-        gp(a.iso)[c] = (float)(phi / a.W);
         const float4 cf = gp(a.coef)[c];
+        double corr = 0.0;   // W delta: particles of the pending correction (fused BF16 / FP16)
+        if (a.dtype != 0 && a.fused) {
+            if (init) {
+                gp(a.delta)[c] = 0.f;
+            } else {
+                // the particle correction of this step's reduced-precision Y: every
+                // ordinate of the cell gets delta = -dt sigma_as (sum_q w_q Y^ - Phi^n) / W
+                double ys = 0.0;
+                const ASN_G double* yp = gp(a.ypart);
+                for (int g = 0; g < G; ++g) ys += yp[(size_t)g * a.P + c];
+                const float d = (float)(-(double)cf.z * (ys - gp(a.phi64)[c]) / a.W);
+                gp(a.delta)[c] = d;
+                corr = a.W * (double)d;
+            }
+        }
+        // iso holds Phi^ / W of the stored state; phi64 the true Phi
+        gp(a.iso)[c] = (float)(phi / a.W);
+        phi += corr;
+        gp(a.phi64)[c] = phi;
         s[0] = phi;
         s[1] = (double)cf.x * phi;
         s[2] = (double)cf.w;
+        s[3] = corr;
     }
     if (bmax_zero != nullptr && c < a.P / kScaleBlock) bmax_zero[c] = 0u;
-    block_sum_256<3>(s, gp(a.fin_part) + 3 * (size_t)local);
+    block_sum_256<4>(s, gp(a.fin_part) + 4 * (size_t)local);
+}
+
+// The stored state of a fused reduced-precision problem plus its pending per-cell
+// correction becomes the plain state: psi[q][c] += delta[c], delta = 0, iso = Phi / W.
+__global__ void materialize_kernel(StepArgs a, float* psi) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.y;
+    if (c >= a.C || q >= a.Q) return;
+    psi[(size_t)q * a.P + c] += a.delta[c];
+}
+
+__global__ void materialize_done_kernel(StepArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.C) return;
+    a.delta[c] = 0.f;
+    a.iso[c] = (float)(a.phi64[c] / a.W);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,21 +1147,22 @@ __global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int mode) {
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const bool init = mode == BUD_INIT;
     const int n_blk = a.tiles_x * a.tiles_y * a.G;
-    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const ASN_G double* fp = gp(a.fin_part);
     const ASN_G double* bp = gp(a.blk_part);
     for (int i = threadIdx.x; i < a.fin_blocks; i += 256) {
-        s[0] += fp[3 * (size_t)i + 0];
-        s[1] += fp[3 * (size_t)i + 1];
-        s[2] += fp[3 * (size_t)i + 2];
+        s[0] += fp[4 * (size_t)i + 0];
+        s[1] += fp[4 * (size_t)i + 1];
+        s[2] += fp[4 * (size_t)i + 2];
+        s[5] += fp[4 * (size_t)i + 3];
     }
     if (!init)
         for (int i = threadIdx.x; i < n_blk; i += 256) {
             s[3] += bp[2 * (size_t)i + 0];
             s[4] += bp[2 * (size_t)i + 1];
         }
-    __shared__ double tot[5];
-    block_sum_256<5>(s, tot);
+    __shared__ double tot[6];
+    block_sum_256<6>(s, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (mode == BUD_STEP || mode == BUD_STAGE2) gp(B.steps_left)[pi] -= 1;
@@ -975,7 +1177,8 @@ __global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int mode) {
         rec[REC_SRC_STEP] = a.area * a.W * tot[2];
         return;
     }
-    const double def = a.area * tot[3];
+    // collision defect: the stencil's increments plus the pending correction's particles
+    const double def = a.area * (tot[3] + tot[5]);
     const double out = a.area * tot[4];
     const double ref = fmax(rec[REC_MASS0], rec[REC_MASS]);
     auto residual = [&](double got, double pred) {
@@ -1047,7 +1250,7 @@ static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b -
 
 void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
     out[KT_GEMM] = (a.Qp / kGemmBM) * (int)(a.P / kGemmBN);
-    out[KT_FIX] = a.dtype != 0 ? a.fin_blocks : 0;
+    out[KT_FIX] = (a.dtype != 0 && !a.fused) ? a.fin_blocks : 0;
     out[KT_SC] = a.fused ? 0 : a.tiles_x * a.tiles_y * a.G;
     out[KT_FIN] = a.fin_blocks;
     out[KT_BUDGET] = 1;
@@ -1067,11 +1270,15 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
         gemm_f32_kernel<true><<<grid[KT_GEMM], 256, 0, s>>>(b);
     else if (dtype == 0)
         gemm_f32_kernel<false><<<grid[KT_GEMM], 256, 0, s>>>(b);
+    else if (dtype == 1 && fused)
+        gemm_lp_kernel<1, true><<<grid[KT_GEMM], 256, 0, s>>>(b);
     else if (dtype == 1)
-        gemm_lp_kernel<1><<<grid[KT_GEMM], 256, 0, s>>>(b);
+        gemm_lp_kernel<1, false><<<grid[KT_GEMM], 256, 0, s>>>(b);
+    else if (fused)
+        gemm_lp_kernel<2, true><<<grid[KT_GEMM], 256, 0, s>>>(b);
     else
-        gemm_lp_kernel<2><<<grid[KT_GEMM], 256, 0, s>>>(b);
-    if (dtype != 0) particle_fix_kernel<<<grid[KT_FIX], 256, 0, s>>>(b);
+        gemm_lp_kernel<2, false><<<grid[KT_GEMM], 256, 0, s>>>(b);
+    if (dtype != 0 && !fused) particle_fix_kernel<<<grid[KT_FIX], 256, 0, s>>>(b);
     mark(1);
     const bool lp = dtype != 0;
     if (!fused && stencil == 0) {
@@ -1125,6 +1332,13 @@ hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s) {
     moments_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);
     finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(one, 1);
     budget_kernel<<<1, 256, 0, s>>>(one, BUD_INIT);
+    return hipGetLastError();
+}
+
+hipError_t launch_materialize(const StepArgs& a, hipStream_t s) {
+    dim3 g(div_up(a.C, 256), a.Q);
+    materialize_kernel<<<g, 256, 0, s>>>(a, const_cast<float*>(a.psi));
+    materialize_done_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

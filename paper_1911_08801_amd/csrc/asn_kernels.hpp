@@ -69,7 +69,7 @@ struct StepArgs {
     int fin_blocks;
     // operand type: 0 FP32, 1 BF16, 2 FP16
     int dtype;
-    // 1: the stencil runs in the contraction's epilogue (FP32 forward Euler); the
+    // 1: the stencil runs in the contraction's epilogue (forward Euler); the
     // stencil decomposition is then the contraction's: tiles_x = P / kGemmBN cell
     // tiles, tiles_y = 1, G = Qp / kGemmBM ordinate tiles
     int fused;
@@ -89,9 +89,12 @@ struct StepArgs {
     double* phi64;          // Phi (FP64)
     double* phi_part;       // [G][P]
     double* blk_part;       // stencil block partials [G * tiles][2]
-    double* fin_part;       // finalize block partials [fin_blocks][2]
+    double* fin_part;       // finalize block partials [fin_blocks][4]
     double* ypart;          // [Qp / kGemmBM][P] weighted row sums of Y (reduced precision)
     float* fix;             // [P] per-cell particle correction of the reduced-precision Y
+    float* delta;           // [P] fused reduced precision: pending isotropic correction of the
+                            // stored state (true state = psi + delta); iso then holds Phi^ / W
+                            // of the stored state and phi64 the true Phi
     unsigned* bmax_cur;     // block max |psi^n| (read by the GEMM), follows the psi buffer
     unsigned* bmax_next;    // block max |psi^{n+1}| (written by the stencil)
     double* rec;
@@ -121,7 +124,7 @@ struct BatchArgs {
 void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]);
 
 // Whether a problem runs the stencil inside the FP32 contraction.
-inline bool can_fuse(int dtype, int scheme) { return dtype == 0 && scheme == SCHEME_EULER; }
+inline bool can_fuse(int dtype, int scheme) { (void)dtype; return scheme == SCHEME_EULER; }
 
 // One step for every problem of the batch.  Euler: one pass of contraction,
 // stream + collide, finalize and budget, on the buffers selected by b.s_par.
@@ -141,6 +144,8 @@ struct ArmArgs {
 hipError_t launch_arm(int* steps_left, int* base, int n, const ArmArgs& v, hipStream_t s);
 // Moments of the current state (after set_state): phi64, iso, bmax, budget record.
 hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s);
+// Fused reduced precision: fold the pending correction into the stored state.
+hipError_t launch_materialize(const StepArgs& a, hipStream_t s);
 // psi[q][c] = cell[c] for all q (pitch P), zero padding.
 hipError_t launch_broadcast(float* psi, const float* cell, int Q, int64_t C, int64_t P,
                             hipStream_t s);

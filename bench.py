@@ -213,8 +213,15 @@ def serving_run(args):
     cap = Server(backend, chunk=16).serve(burst).summary()["aggregate_updates_per_s"]
     rate = args.serve_load * cap / mean_upd
     reqs = wl.serving_requests(0, args.serve_requests, rate=rate, n_range=(64, args.serve_nmax))
+    last = [time.perf_counter()]
+
+    def progress(srv):            # a line every 20 s so long runs show they are alive
+        if time.perf_counter() - last[0] > 20.0:
+            last[0] = time.perf_counter()
+            print(f"# serving: chunk done at {time.strftime('%H:%M:%S')}", file=sys.stderr,
+                  flush=True)
     rep = Server(backend, chunk=16).serve([Job(rid=r.rid, spec=r.problem(), arrival=r.arrival)
-                                           for r in reqs])
+                                           for r in reqs], on_chunk=progress)
     out = rep.summary()
     out.update({"arrival_rate_per_s": rate, "burst_capacity_updates_per_s": cap,
                 "mean_updates_per_request": mean_upd,

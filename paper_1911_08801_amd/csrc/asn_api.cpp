@@ -97,7 +97,7 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     {
         const int mt = L.Qp / asn::kGemmBM;
         const int bk = L.lowp ? asn::kBK_LP : asn::kBK_F32;
-        L.ktab_len = mt + 1 + mt * (L.Qp / bk);
+        L.ktab_len = mt + 1 + 2 * mt * (L.Qp / bk);   // offsets, k-steps, sub-block masks
         L.off_ktab = take((size_t)L.ktab_len * 4);
     }
     L.off_qi = take((size_t)Q * sizeof(QInfo));
@@ -487,33 +487,49 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     // k-steps per M-tile whose tile of the stored K (FP32 or 16-bit) has a nonzero entry.
     // Steps inside the tile's own ordinate range come last: the fused epilogue then
     // reads rows that the block (and its neighbours) has just streamed through L2.
+    // After the k-step list, one mask per entry: bit s is set when rows m0 + 16 s ..
+    // m0 + 16 s + 15 of the step's K tile have a nonzero entry (the FP32 kernel skips
+    // the products of the other 16-row sub-blocks).
     std::vector<int> ktab((size_t)L.ktab_len, 0);
     {
         const int mt_n = L.Qp / asn::kGemmBM;
         const int bk = L.lowp ? asn::kBK_LP : asn::kBK_F32;
         const int nk = (Q + bk - 1) / bk;
-        std::vector<int> entries;
+        std::vector<int> entries, masks;
         double cover = 0;
         for (int mt = 0; mt < mt_n; ++mt) {
             ktab[mt] = (int)entries.size();
             const int m0 = mt * asn::kGemmBM, m1 = std::min(Q, m0 + asn::kGemmBM);
-            std::vector<int> own;
+            std::vector<int> own, own_mask;
             for (int kt = 0; kt < nk; ++kt) {
                 const int k0 = kt * bk, k1 = std::min(Q, k0 + bk);
-                bool nz = false;
-                for (int m = m0; m < m1 && !nz; ++m)
-                    for (int k = k0; k < k1 && !nz; ++k)
-                        nz = L.lowp ? (Klp[(size_t)m * L.Qp + k] & 0x7FFFu) != 0
-                                    : Kt[(size_t)k * L.Qp + m] != 0.f;
-                if (nz) {
-                    (k0 >= m0 && k0 < m0 + asn::kGemmBM ? own : entries).push_back(kt);
-                    cover += (double)(m1 - m0) * (k1 - k0);
+                int mask = 0;
+                for (int m = m0; m < m1; ++m)
+                    for (int k = k0; k < k1; ++k)
+                        if (L.lowp ? (Klp[(size_t)m * L.Qp + k] & 0x7FFFu) != 0
+                                   : Kt[(size_t)k * L.Qp + m] != 0.f)
+                            mask |= 1 << ((m - m0) / 16);
+                if (mask) {
+                    const bool is_own = k0 >= m0 && k0 < m0 + asn::kGemmBM;
+                    (is_own ? own : entries).push_back(kt);
+                    (is_own ? own_mask : masks).push_back(mask);
+                    // K entries the kernel multiplies: whole tiles (16-bit operands) or
+                    // the nonzero 16-row sub-blocks (FP32)
+                    int rows = m1 - m0;
+                    if (!L.lowp) {
+                        rows = 0;
+                        for (int sb = 0; sb < asn::kGemmBM / 16; ++sb)
+                            if (mask & (1 << sb)) rows += std::max(0, std::min(m1, m0 + 16 * sb + 16) - (m0 + 16 * sb));
+                    }
+                    cover += (double)rows * (k1 - k0);
                 }
             }
             entries.insert(entries.end(), own.begin(), own.end());
+            masks.insert(masks.end(), own_mask.begin(), own_mask.end());
         }
         ktab[mt_n] = (int)entries.size();
         std::copy(entries.begin(), entries.end(), ktab.begin() + mt_n + 1);
+        std::copy(masks.begin(), masks.end(), ktab.begin() + mt_n + 1 + entries.size());
         p->tile_entries = cover;
     }
     std::vector<QInfo> qi(Q);

@@ -82,10 +82,13 @@ constexpr int kLdsPad = 16;
 template <int NV, typename OutPtr>
 __device__ __forceinline__ void block_sum_256(double (&v)[NV], OutPtr out);
 
+#ifndef ASN_F32_FUSED_WAVES
+#define ASN_F32_FUSED_WAVES 2
+#endif
 // The fused epilogue needs more registers; three resident blocks per CU keep the
 // MFMA pipes fed while some blocks run their epilogues.
 template <bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? 3 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? ASN_F32_FUSED_WAVES : 1)))
 void gemm_f32_kernel(BatchArgs B) {
     __shared__ float As[2][kBK][kGemmBM + kLdsPad];
     __shared__ float Bs[2][kBK][kGemmBN + kLdsPad];
@@ -106,28 +109,44 @@ void gemm_f32_kernel(BatchArgs B) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
 
-    // Staging of one k-step (16 ordinates): thread t moves float4 number t and t + 256 of
-    // the A tile (Kt rows) and of the B tile (psi rows); rows >= Q of psi read as zero.
-    const int kk0 = tid >> 5, kk1 = kk0 + 8, c4 = (tid & 31) << 2;
-    float4 ra0, ra1, rb0, rb1;
+    // Staging of one k-step (kBK ordinates): thread t moves float4 number t + 256 r
+    // (r < kBK / 8) of the A tile (Kt rows) and of the B tile (psi rows); rows >= Q of
+    // psi read as zero.
+    constexpr int kNR = kBK / 8;
+    const int kk0 = tid >> 5, c4 = (tid & 31) << 2;
     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-#define ASN_GLOAD(k0)                                                                          \
+    static_assert(kNR == 2 || kNR == 4, "staging of 16- or 32-row k-steps");
+#define ASN_GL1(r, k0)                                                                         \
     do {                                                                                       \
-        const int ka = (k0) + kk0, kb = (k0) + kk1;                                            \
-        ra0 = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)ka * Qp + m0 + c4);          \
-        ra1 = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)kb * Qp + m0 + c4);          \
-        rb0 = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(ka, Q - 1) * P + n0 + c4); \
-        rb1 = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(kb, Q - 1) * P + n0 + c4); \
-        if (ka >= Q) rb0 = zero4;                                                              \
-        if (kb >= Q) rb1 = zero4;                                                              \
+        const int ka = (k0) + kk0 + 8 * (r);                                                   \
+        ra##r = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)ka * Qp + m0 + c4);        \
+        rb##r = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(ka, Q - 1) * P + n0 + c4); \
+        if (ka >= Q) rb##r = zero4;                                                            \
     } while (0)
-#define ASN_LSTORE(b)                                                                          \
+#define ASN_LS1(r, b)                                                                          \
     do {                                                                                       \
-        *reinterpret_cast<float4*>(&As[b][kk0][c4]) = ra0;                                     \
-        *reinterpret_cast<float4*>(&As[b][kk1][c4]) = ra1;                                     \
-        *reinterpret_cast<float4*>(&Bs[b][kk0][c4]) = rb0;                                     \
-        *reinterpret_cast<float4*>(&Bs[b][kk1][c4]) = rb1;                                     \
+        *reinterpret_cast<float4*>(&As[b][kk0 + 8 * (r)][c4]) = ra##r;                         \
+        *reinterpret_cast<float4*>(&Bs[b][kk0 + 8 * (r)][c4]) = rb##r;                         \
     } while (0)
+    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    auto gload = [&](int k0) {
+        ASN_GL1(0, k0);
+        ASN_GL1(1, k0);
+        if constexpr (kNR == 4) {
+            ASN_GL1(2, k0);
+            ASN_GL1(3, k0);
+        }
+    };
+    auto lstore = [&](int b) {
+        ASN_LS1(0, b);
+        ASN_LS1(1, b);
+        if constexpr (kNR == 4) {
+            ASN_LS1(2, b);
+            ASN_LS1(3, b);
+        }
+    };
+#undef ASN_GL1
+#undef ASN_LS1
 
     f32x4 acc[4][4];
 #pragma unroll
@@ -135,17 +154,20 @@ void gemm_f32_kernel(BatchArgs B) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // Only k-steps whose K tile has a nonzero entry (the skipped products are +0).
+    // Only k-steps whose K tile has a nonzero entry, and in those only the 16-ordinate
+    // sub-blocks of the wave with a nonzero entry (the skipped products are +0).
     const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
+    const ASN_G int* __restrict__ mlist = klist + ktab[mtiles];
     const int nkt = ktab[mt + 1] - ktab[mt];
     if (nkt > 0) {
-        ASN_GLOAD(klist[0] * kBK);
-        ASN_LSTORE(0);
+        gload(klist[0] * kBK);
+        lstore(0);
     }
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        if (kt + 1 < nkt) ASN_GLOAD(klist[kt + 1] * kBK);
+        const int wmask = (mlist[kt] >> (4 * (wave & 1))) & 0xF;   // this wave's 64 ordinates
+        if (kt + 1 < nkt) gload(klist[kt + 1] * kBK);
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             float av[4], bv[4];
@@ -154,22 +176,26 @@ void gemm_f32_kernel(BatchArgs B) {
             for (int i = 0; i < 4; ++i) av[i] = As[b][kr][wm + i * 16 + cl];
 #pragma unroll
             for (int j = 0; j < 4; ++j) bv[j] = Bs[b][kr][wn + j * 16 + cl];
+            if constexpr (FUSED) {
+                // rows = cells (bv), columns = ordinates (av)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j)
+                    if (wmask & (1 << j))
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    // FUSED: rows = cells (bv), columns = ordinates (av)
-                    if constexpr (FUSED)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[i], av[j], acc[i][j], 0, 0, 0);
-                    else
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-                }
+                        for (int i = 0; i < 4; ++i)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[i], av[j], acc[i][j], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (wmask & (1 << i))
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
         }
-        if (kt + 1 < nkt) ASN_LSTORE(b ^ 1);
+        if (kt + 1 < nkt) lstore(b ^ 1);
         __syncthreads();
     }
-#undef ASN_GLOAD
-#undef ASN_LSTORE
     // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16.
     if constexpr (!FUSED) {
 #pragma unroll
@@ -186,120 +212,105 @@ void gemm_f32_kernel(BatchArgs B) {
         const int nx = a.nx, ny = a.ny;
         const int64_t C = a.C;
         const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+        const ASN_G float* __restrict__ isop = gp(a.iso);
+        const ASN_G float4* __restrict__ coef = gp(a.coef);
         ASN_G float* __restrict__ out = gp(a.psi_new);
         const bool rows4 = (nx & 3) == 0;   // then a float4 of cells never crosses a grid row
-        // the lane's four ordinates (columns j)
+        // The lane's four ordinates (columns j).  Padding ordinates (q >= Q) read row 0
+        // and store nothing.
         QInfo qi[4];
         bool qok[4];
+        const ASN_G float* rowp[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int q = m0 + wm + j * 16 + (lane & 15);
             qok[j] = q < Q;
             qi[j] = qtab[qok[j] ? q : 0];
+            rowp[j] = psi + (size_t)(qok[j] ? q : 0) * P;
         }
         __shared__ double phred[2][kGemmBN];
         double defect = 0.0, outflow = 0.0;
-        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            // four consecutive cells c0 .. c0 + 3 (c0 a multiple of 4)
+            // four consecutive cells c0 .. c0 + 3 (c0 a multiple of 4, c0 + 3 < P)
             const int64_t c0 = n0 + wn + i * 16 + 4 * (lane >> 4);
-            float aa[4], bs[4], gs[4], ss[4];
-            int xk[4], yk[4];
+            // All loads of this cell group first, at clamped in-range addresses, so that
+            // they are in flight together; ghost and padding values are masked below.
+            const float4 iso4 = *reinterpret_cast<const ASN_G float4*>(isop + c0);
+            float4 cf[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cf[k] = coef[c0 + k];
+            float4 v4[4], u4[4];
+            float xs[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const ASN_G float* row = rowp[j];
+                v4[j] = *reinterpret_cast<const ASN_G float4*>(row + c0);
+                // the x-upwind cell outside the float4: just before (xi > 0) or after it
+                const int64_t xi = (qi[j].dir & 1) ? c0 - 1 : c0 + 4;
+                xs[j] = row[min(max(xi, (int64_t)0), P - 1)];
+                // the y-upwind row: below (eta > 0) or above; one aligned float4 when nx
+                // is a multiple of 4, else four scalars
+                const int64_t yi = c0 + ((qi[j].dir & 4) ? -(int64_t)nx : (int64_t)nx);
+                if (rows4) {
+                    u4[j] = *reinterpret_cast<const ASN_G float4*>(row + min(max(yi, (int64_t)0), P - 4));
+                } else {
+                    u4[j].x = row[min(max(yi, (int64_t)0), P - 1)];
+                    u4[j].y = row[min(max(yi + 1, (int64_t)0), P - 1)];
+                    u4[j].z = row[min(max(yi + 2, (int64_t)0), P - 1)];
+                    u4[j].w = row[min(max(yi + 3, (int64_t)0), P - 1)];
+                }
+            }
+            // Per cell: live (a grid cell, not padding) and its boundary faces as the bits
+            // of the direction code (bit0 x = 0, bit1 x = nx - 1, bit2 y = 0, bit3
+            // y = ny - 1): the upwind neighbour of ordinate class d is a ghost where
+            // d & in_edge != 0 and the cell has an outflow face where d & out_edge != 0.
+            int in_edge[4], out_edge[4];
             bool ck[4];
-            const float4 iso4 = *reinterpret_cast<const ASN_G float4*>(gp(a.iso) + c0);
-            const float isv[4] = {iso4.x, iso4.y, iso4.z, iso4.w};
             {
                 const int y0 = (int)(c0 / nx);
                 int x = (int)(c0 - (int64_t)y0 * nx), y = y0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     ck[k] = c0 + k < C;
-                    xk[k] = x;
-                    yk[k] = y;
-                    if (++x == nx) {
-                        x = 0;
-                        ++y;
-                    }
-                    const float4 cf = ck[k] ? gp(a.coef)[c0 + k] : z4;
-                    aa[k] = cf.x;
-                    bs[k] = cf.y;
-                    gs[k] = cf.z;
-                    ss[k] = cf.w;
+                    const int e = (x == 0 ? 1 : 0) | (x == nx - 1 ? 2 : 0) | (y == 0 ? 4 : 0) |
+                                  (y == ny - 1 ? 8 : 0);
+                    in_edge[k] = e;
+                    out_edge[k] = ((e & 5) << 1) | ((e & 10) >> 1);
+                    x = x + 1 == nx ? 0 : x + 1;
+                    y = x == 0 ? y + 1 : y;
                 }
             }
+            const float isv[4] = {iso4.x, iso4.y, iso4.z, iso4.w};
             double ph[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (!qok[j]) continue;
                 const QInfo& qj = qi[j];
-                const int q = m0 + wm + j * 16 + (lane & 15);
-                const ASN_G float* row = psi + (size_t)q * P;
-                const float4 v4 = *reinterpret_cast<const ASN_G float4*>(row + c0);
-                const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
-                // upwind neighbour along x: inside the float4, or the cell just
-                // before / after it; a ghost (0) across the grid's x boundary
-                float ux[4];
-                if (qj.dir & 1) {
-                    const float prev = c0 >= 4 ? row[c0 - 1] : 0.f;
-                    ux[0] = prev;
-                    ux[1] = vv[0];
-                    ux[2] = vv[1];
-                    ux[3] = vv[2];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (xk[k] == 0) ux[k] = 0.f;
-                } else if (qj.dir & 2) {
-                    const float next = c0 + 4 < P ? row[c0 + 4] : 0.f;
-                    ux[0] = vv[1];
-                    ux[1] = vv[2];
-                    ux[2] = vv[3];
-                    ux[3] = next;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        if (xk[k] == nx - 1) ux[k] = 0.f;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) ux[k] = 0.f;
-                }
-                // upwind neighbour along y: the row below (eta > 0) or above
-                float uy[4] = {0.f, 0.f, 0.f, 0.f};
-                if (qj.dir & 12) {
-                    const int64_t sh = (qj.dir & 4) ? -(int64_t)nx : (int64_t)nx;
-                    if (rows4) {
-                        const bool has = (qj.dir & 4) ? yk[0] > 0 : yk[0] < ny - 1;
-                        if (has && ck[0]) {
-                            const float4 u4 = *reinterpret_cast<const ASN_G float4*>(row + c0 + sh);
-                            uy[0] = u4.x;
-                            uy[1] = u4.y;
-                            uy[2] = u4.z;
-                            uy[3] = u4.w;
-                        }
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const bool has = ck[k] && ((qj.dir & 4) ? yk[k] > 0 : yk[k] < ny - 1);
-                            uy[k] = has ? row[c0 + k + sh] : 0.f;
-                        }
-                    }
-                }
+                const int d = qj.dir;
+                const float vv[4] = {v4[j].x, v4[j].y, v4[j].z, v4[j].w};
+                const float uu[4] = {u4[j].x, u4[j].y, u4[j].z, u4[j].w};
+                const float lft[4] = {xs[j], vv[0], vv[1], vv[2]};
+                const float rgt[4] = {vv[1], vv[2], vv[3], xs[j]};
                 float nv[4];
                 float colsum = 0.f, o = 0.f;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
+                    // (cx = 0 when d & 3 = 0 and cy = 0 when d & 12 = 0)
+                    const int gi = d & in_edge[k], go = d & out_edge[k];
+                    const float ux = (gi & 3) ? 0.f : ((d & 1) ? lft[k] : rgt[k]);
+                    const float uy = (gi & 12) ? 0.f : uu[k];
                     const float v = vv[k];
-                    const float col = gs[k] * (acc[i][j][k] - v) + bs[k] * (isv[k] - v);
-                    const float r = v - qj.cx * (v - ux[k]) - qj.cy * (v - uy[k]) - aa[k] * v + col + ss[k];
-                    nv[k] = ck[k] ? r : 0.f;   // padding cells stay zero
+                    const float col = cf[k].z * (acc[i][j][k] - v) + cf[k].y * (isv[k] - v);
+                    const float r = v - qj.cx * (v - ux) - qj.cy * (v - uy) - cf[k].x * v + col + cf[k].w;
+                    const bool live = ck[k] & qok[j];
+                    nv[k] = live ? r : 0.f;   // padding cells stay zero
                     ph[k] += qj.w * (double)nv[k];
-                    colsum += ck[k] ? col : 0.f;
-                    if (ck[k]) {
-                        if (((qj.dir & 1) && xk[k] == nx - 1) || ((qj.dir & 2) && xk[k] == 0)) o += qj.cx * v;
-                        if (((qj.dir & 4) && yk[k] == ny - 1) || ((qj.dir & 8) && yk[k] == 0)) o += qj.cy * v;
-                    }
+                    colsum += live ? col : 0.f;
+                    o += live ? ((go & 3) ? qj.cx * v : 0.f) + ((go & 12) ? qj.cy * v : 0.f) : 0.f;
                 }
-                *reinterpret_cast<ASN_G float4*>(out + (size_t)q * P + c0) =
-                    make_float4(nv[0], nv[1], nv[2], nv[3]);
+                if (qok[j])
+                    *reinterpret_cast<ASN_G float4*>(out + (size_t)(m0 + wm + j * 16 + (lane & 15)) * P + c0) =
+                        make_float4(nv[0], nv[1], nv[2], nv[3]);
                 defect += qj.w * (double)colsum;
                 outflow += qj.w * (double)o;
             }

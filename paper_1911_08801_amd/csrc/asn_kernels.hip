@@ -283,6 +283,11 @@ void gemm_f32_kernel(BatchArgs B) {
             }
             const float isv[4] = {iso4.x, iso4.y, iso4.z, iso4.w};
             double ph[4] = {0.0, 0.0, 0.0, 0.0};
+            // An interior group (four live cells off the domain boundary) needs no ghost,
+            // padding or outflow handling.
+            bool interior = true;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) interior = interior && ck[k] && in_edge[k] == 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const QInfo& qj = qi[j];
@@ -293,26 +298,38 @@ void gemm_f32_kernel(BatchArgs B) {
                 const float rgt[4] = {vv[1], vv[2], vv[3], xs[j]};
                 float nv[4];
                 float colsum = 0.f, o = 0.f;
+                if (interior) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    // (cx = 0 when d & 3 = 0 and cy = 0 when d & 12 = 0)
-                    const int gi = d & in_edge[k], go = d & out_edge[k];
-                    const float ux = (gi & 3) ? 0.f : ((d & 1) ? lft[k] : rgt[k]);
-                    const float uy = (gi & 12) ? 0.f : uu[k];
-                    const float v = vv[k];
-                    const float col = cf[k].z * (acc[i][j][k] - v) + cf[k].y * (isv[k] - v);
-                    const float r = v - qj.cx * (v - ux) - qj.cy * (v - uy) - cf[k].x * v + col + cf[k].w;
-                    const bool live = ck[k] & qok[j];
-                    nv[k] = live ? r : 0.f;   // padding cells stay zero
-                    ph[k] += qj.w * (double)nv[k];
-                    colsum += live ? col : 0.f;
-                    o += live ? ((go & 3) ? qj.cx * v : 0.f) + ((go & 12) ? qj.cy * v : 0.f) : 0.f;
+                    for (int k = 0; k < 4; ++k) {
+                        // (cx = 0 when d & 3 = 0 and cy = 0 when d & 12 = 0)
+                        const float ux = (d & 1) ? lft[k] : rgt[k];
+                        const float v = vv[k];
+                        const float col = cf[k].z * (acc[i][j][k] - v) + cf[k].y * (isv[k] - v);
+                        nv[k] = v - qj.cx * (v - ux) - qj.cy * (v - uu[k]) - cf[k].x * v + col + cf[k].w;
+                        colsum += col;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int gi = d & in_edge[k], go = d & out_edge[k];
+                        const float ux = (gi & 3) ? 0.f : ((d & 1) ? lft[k] : rgt[k]);
+                        const float uy = (gi & 12) ? 0.f : uu[k];
+                        const float v = vv[k];
+                        const float col = cf[k].z * (acc[i][j][k] - v) + cf[k].y * (isv[k] - v);
+                        const float r = v - qj.cx * (v - ux) - qj.cy * (v - uy) - cf[k].x * v + col + cf[k].w;
+                        nv[k] = ck[k] ? r : 0.f;   // padding cells stay zero
+                        colsum += ck[k] ? col : 0.f;
+                        o += ck[k] ? ((go & 3) ? qj.cx * v : 0.f) + ((go & 12) ? qj.cy * v : 0.f) : 0.f;
+                    }
                 }
+                const double wj = qok[j] ? qj.w : 0.0;   // padding ordinates add nothing
+#pragma unroll
+                for (int k = 0; k < 4; ++k) ph[k] += wj * (double)nv[k];
                 if (qok[j])
                     *reinterpret_cast<ASN_G float4*>(out + (size_t)(m0 + wm + j * 16 + (lane & 15)) * P + c0) =
                         make_float4(nv[0], nv[1], nv[2], nv[3]);
-                defect += qj.w * (double)colsum;
-                outflow += qj.w * (double)o;
+                defect += wj * (double)colsum;
+                outflow += wj * (double)o;
             }
             // Phi partial of this wave's 64 ordinates: the 16 lanes of a row group
 #pragma unroll

@@ -367,25 +367,23 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 constexpr int kBKL = kBK_LP;
 constexpr int kRowL = kBKL + 8;  // LDS row length in 16-bit elements (padded)
 
-__device__ __forceinline__ uint32_t round_bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
-}
-__device__ __forceinline__ uint32_t round_f16_bits(float x) {
-    const _Float16 h = (_Float16)x;  // round to nearest even
-    return (uint32_t)__builtin_bit_cast(uint16_t, h);
-}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
+// Two FP32 values rounded to nearest even in the operand type, packed (lo in bits
+// 0..15): one v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32 on gfx950.
 template <int DT>
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
-    if (DT == 1) return round_bf16_bits(lo) | (round_bf16_bits(hi) << 16);
-    return round_f16_bits(lo) | (round_f16_bits(hi) << 16);
+    const f32x2_t w = {lo, hi};
+    if constexpr (DT == 1) return __builtin_bit_cast(uint32_t, __builtin_convertvector(w, bf16x2_t));
+    else return __builtin_bit_cast(uint32_t, __builtin_convertvector(w, f16x2_t));
 }
 
-// BF16 residual term: s - T(s) is exact in FP32; round it to BF16 as well.
-__device__ __forceinline__ float bf16_residual(float x) {
-    return x - __uint_as_float(round_bf16_bits(x) << 16);
+// BF16 residual terms of a packed pair p = pack2<1>(lo, hi): s - T(s) is exact in FP32;
+// the residuals are rounded to BF16 and packed as well.
+__device__ __forceinline__ uint32_t bf16_residual2(uint32_t p, float lo, float hi) {
+    return pack2<1>(lo - __uint_as_float(p << 16), hi - __uint_as_float(p & 0xFFFF0000u));
 }
 
 template <int DT>
@@ -457,14 +455,16 @@ void gemm_lp_kernel(BatchArgs B) {
     auto lstore = [&](int b) {
         *reinterpret_cast<uint4*>(&As[b][arow0][akq]) = ra0;
         *reinterpret_cast<uint4*>(&As[b][arow1][akq]) = ra1;
-        const float iv[4] = {iso4.x, iso4.y, iso4.z, iso4.w};
+        // (v - iso) 2^(E - e_b): the scale is a power of two, so one FMA with the
+        // scaled iso rounds exactly as the difference would
+        const float ivs[4] = {iso4.x * s_in, iso4.y * s_in, iso4.z * s_in, iso4.w * s_in};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             float x[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float v = c == 0 ? rb[j].x : c == 1 ? rb[j].y : c == 2 ? rb[j].z : rb[j].w;
-                x[j] = (v - iv[c]) * s_in;
+                x[j] = __builtin_fmaf(v, s_in, -ivs[c]);
             }
             uint2 pk;
             pk.x = pack2<DT>(x[0], x[1]);
@@ -472,8 +472,8 @@ void gemm_lp_kernel(BatchArgs B) {
             *reinterpret_cast<uint2*>(&Bs[b][4 * cg + c][4 * kg]) = pk;
             if constexpr (DT == 1) {
                 uint2 pl;
-                pl.x = pack2<1>(bf16_residual(x[0]), bf16_residual(x[1]));
-                pl.y = pack2<1>(bf16_residual(x[2]), bf16_residual(x[3]));
+                pl.x = bf16_residual2(pk.x, x[0], x[1]);
+                pl.y = bf16_residual2(pk.y, x[2], x[3]);
                 *reinterpret_cast<uint2*>(&Bl[b][4 * cg + c][4 * kg]) = pl;
             }
         }
@@ -611,6 +611,61 @@ void gemm_lp_kernel(BatchArgs B) {
             const float dprev = c0 >= 4 ? dl[c0 - 1] : 0.f;
             const float dnext = c0 + 4 < P ? dl[c0 + 4] : 0.f;
             double ph[4] = {0.0, 0.0, 0.0, 0.0}, yp[4] = {0.0, 0.0, 0.0, 0.0};
+            // An interior group (four live cells of one grid row, off the domain
+            // boundary) needs no ghost, padding or outflow handling.
+            const bool interior = ck[3] && xk[0] >= 1 && xk[3] == xk[0] + 3 && xk[3] <= nx - 2 &&
+                                  yk[0] >= 1 && yk[0] <= ny - 2;
+            if (interior) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!qok[j]) continue;
+                const int q = m0 + wm + j * 16 + (lane & 15);
+                const ASN_G float* row = psi + (size_t)q * P;
+                const float4 v4 = *reinterpret_cast<const ASN_G float4*>(row + c0);
+                const float vh[4] = {v4.x, v4.y, v4.z, v4.w};
+                // x-upwind value outside the group (before it for xi > 0, else after it)
+                // and the y-upwind row; for xi = 0 (eta = 0) cx (cy) is 0 and any finite
+                // value serves
+                const bool xp = dq[j] & 1;
+                const float xsv = row[xp ? c0 - 1 : c0 + 4] + (xp ? dprev : dnext);
+                const int64_t sh = (dq[j] & 4) ? -(int64_t)nx : (int64_t)nx;
+                float uy[4];
+                if (rows4) {
+                    const float4 u4 = *reinterpret_cast<const ASN_G float4*>(row + c0 + sh);
+                    const float4 e4 = *reinterpret_cast<const ASN_G float4*>(dl + c0 + sh);
+                    uy[0] = u4.x + e4.x;
+                    uy[1] = u4.y + e4.y;
+                    uy[2] = u4.z + e4.z;
+                    uy[3] = u4.w + e4.w;
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) uy[k] = row[c0 + k + sh] + dl[c0 + k + sh];
+                }
+                float tv[4];   // true state psi^ + delta
+#pragma unroll
+                for (int k = 0; k < 4; ++k) tv[k] = vh[k] + dv[k];
+                const float lft[4] = {xsv, tv[0], tv[1], tv[2]};
+                const float rgt[4] = {tv[1], tv[2], tv[3], xsv};
+                float nv[4];
+                float colsum = 0.f;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float v = tv[k];
+                    const float ux = xp ? lft[k] : rgt[k];
+                    const float dev = vh[k] - ihv[k];
+                    const float ya = s_out * acc[i][j][k] + rq[j] * dev;   // Y^ - iso
+                    const float col = gs[k] * ((ihv[k] + ya) - vh[k]) + bs[k] * (ihv[k] - vh[k]);
+                    nv[k] = v - cxq[j] * (v - ux) - cyq[j] * (v - uy[k]) - aa[k] * v + col + ss[k];
+                    ph[k] += wq[j] * (double)nv[k];
+                    yp[k] += wq[j] * ((double)(ihv[k] + dv[k]) + (double)ya);
+                    colsum += col;
+                    mx = fmaxf(mx, fabsf(nv[k]));
+                }
+                *reinterpret_cast<ASN_G float4*>(out + (size_t)q * P + c0) =
+                    make_float4(nv[0], nv[1], nv[2], nv[3]);
+                defect += wq[j] * (double)colsum;
+            }
+            } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (!qok[j]) continue;
@@ -678,6 +733,7 @@ void gemm_lp_kernel(BatchArgs B) {
                     make_float4(nv[0], nv[1], nv[2], nv[3]);
                 defect += wq[j] * (double)colsum;
                 outflow += wq[j] * (double)o;
+            }
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {

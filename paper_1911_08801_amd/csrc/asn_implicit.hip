@@ -90,21 +90,51 @@ __global__ __launch_bounds__(256) void imp_rhs_kernel(RhsArgs a) {
 struct SweepArgs {
     const double* rhs;      // [Q][P]
     const double* dir;      // per ordinate {|xi|/dx, |eta|/dy, sign xi, sign eta}
-    const float4* coef;
+    const double* sig;      // per cell sigma_a + sigma_s + sigma_as + 1/dt
     double* out;            // [Q][P]
     int nx, ny;
     int64_t P;
-    double inv_dt;
 };
 
-// One wave per ordinate.  The grid is walked in strips of 64 rows from the upwind
-// side; lane j holds row j of the strip and, at step t, the cell t - j positions
-// from the upwind x boundary, so its x-upwind neighbours are its own two previous
-// results and its y-upwind neighbours are those of lanes j - 1 and j - 2 (lane
-// shuffles).  The strip's two downwind rows are kept in LDS for the next strip.
-__global__ __launch_bounds__(64) void imp_sweep_kernel(SweepArgs a) {
+// Lane l receives the value of lane l - 1 (lane 0 receives 0): DPP wave_shr:1, one
+// VALU move per 32-bit half, no LDS round trip.
+__device__ __forceinline__ double wave_shr1(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One block per ordinate.  The grid is walked in strips of 64 rows from the upwind
+// side; lane j of a wave holds row j of its strip and, at its step t, the cell t - j
+// positions from the upwind x boundary, so its x-upwind neighbours are its own two
+// previous results and its y-upwind neighbours are those of lanes j - 1 and j - 2:
+// lane j - 1's value comes by a lane shift of the current step, lane j - 2's is what
+// lane j - 1 received one step earlier.  The block's W waves take W consecutive strips
+// at once, wave w starting 64 steps after wave w - 1 (a wavefront over strips): lanes
+// 0 and 1 of wave w then read the rows 62 and 63 of wave w - 1 that were written to
+// LDS one and two block steps before, with a barrier after every block step.  The last
+// strip of a round of W strips keeps its two downwind rows for the next round.
+// Everything a step reads that does not depend on the sweep (right-hand side and
+// coefficients) is fetched kSweepAhead steps ahead into a register ring, so the
+// dependent chain of a step is the update and one lane shift.
+// Block barrier that orders LDS only: the sweep's waves exchange rows through LDS, and
+// a full barrier would also wait for every global load in flight (the prefetch ring).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kSweepAhead = 8;
+constexpr int kSweepWaves = 8;    // strips in flight per ordinate
+constexpr int kSweepRing = 8;     // columns of a strip's rows 62, 63 kept for the next wave
+__global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a) {
     extern __shared__ double rowbuf[];      // [2 parity][2 rows][nx]
-    const int q = blockIdx.x, lane = threadIdx.x;
+    __shared__ double ring[kSweepWaves][2][kSweepRing];
+    constexpr int D = kSweepAhead;
+    static_assert(64 % D == 0 && kSweepRing >= 4, "wave start offsets must keep the ring slots");
+    const int q = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
     const int nx = a.nx, ny = a.ny;
     const double ax = a.dir[4 * q + 0], ay = a.dir[4 * q + 1];
     const bool xpos = a.dir[4 * q + 2] > 0.0, ypos = a.dir[4 * q + 3] > 0.0;
@@ -112,64 +142,99 @@ __global__ __launch_bounds__(64) void imp_sweep_kernel(SweepArgs a) {
     double* out = a.out + (size_t)q * a.P;
     const double dflux = 1.5 * (ax + ay);
     const int nstrips = (ny + 63) / 64;
+    const int Tw = nx + 63;   // steps of one strip
     int par = 0;
-    for (int s = 0; s < nstrips; ++s) {
-        const int r = s * 64 + lane;                  // row in sweep order
-        const bool valid = r < ny;
+    for (int g0 = 0; g0 < nstrips; g0 += W) {
+        const int Wg = min(W, nstrips - g0);   // strips of this round
+        const int s = g0 + w;                  // this wave's strip (idle if w >= Wg)
+        const bool wave_on = w < Wg;
+        const bool last_wave = w == Wg - 1;
+        const int r = s * 64 + lane;           // row in sweep order
+        const bool valid = wave_on && r < ny;
         const int y = ypos ? r : ny - 1 - r;
-        double last1 = 0.0, last2 = 0.0;              // x ghosts
-        const double* prev_top = rowbuf + (size_t)(par ^ 1) * 2 * nx;   // rows 62, 63 of strip s - 1
+        const double* prev_top = rowbuf + (size_t)(par ^ 1) * 2 * nx;   // previous round
         double* cur_top = rowbuf + (size_t)par * 2 * nx;
-        // prefetch of the first cell's right-hand side and rate
         auto cell_of = [&](int k) -> int64_t {
             const int x = xpos ? k : nx - 1 - k;
             return (int64_t)y * nx + x;
         };
-        double rhs_n = 0.0, sig_n = 0.0;
-        {
-            const int k = -lane;
-            if (valid && k >= 0 && k < nx) {
-                const int64_t c = cell_of(k);
-                const float4 cf = a.coef[c];
-                rhs_n = rhs[c];
-                sig_n = (double)cf.x + (double)cf.y + (double)cf.z + a.inv_dt;
-            }
-        }
-        for (int t = 0; t < nx + 63; ++t) {
-            const int k = t - lane;
-            const bool active = valid && k >= 0 && k < nx;
-            const double rhs_c = rhs_n, sig_c = sig_n;
-            if (valid && k + 1 >= 0 && k + 1 < nx) {      // next cell of this lane
-                const int64_t c = cell_of(k + 1);
-                const float4 cf = a.coef[c];
-                rhs_n = rhs[c];
-                sig_n = (double)cf.x + (double)cf.y + (double)cf.z + a.inv_dt;
-            }
-            double yn1 = __shfl_up(last1, 1, 64);
-            double yn2 = __shfl_up(last2, 2, 64);
-            const bool kin = k >= 0 && k < nx;
+        // Ring slot u holds the inputs of local step tau with tau mod D = u: the lane's
+        // cell k = tau - lane (loads at clamped in-range addresses without branches, so
+        // that the compiler waits for each only where it is used).
+        double rr[D], sg[D];
+        const int yc = min(max(y, 0), ny - 1);
+        const double* rrow = rhs + (size_t)yc * nx;
+        const double* srow = a.sig + (size_t)yc * nx;
+        auto fetch = [&](int tau, int u) {
+            const int kc = min(max(tau - lane, 0), nx - 1);
+            const int x = xpos ? kc : nx - 1 - kc;
+            rr[u] = rrow[x];
+            sg[u] = srow[x];
+        };
+#pragma unroll
+        for (int u = 0; u < D; ++u) fetch(u, u);
+        double last1 = 0.0, last2 = 0.0;   // x ghosts
+        double y1prev = 0.0;               // y-upwind value this lane received last step
+        auto step = [&](int tau, double rhs_c, double sig) {
+            const int k = tau - lane;
+            double yn1 = wave_shr1(last1);    // lane - 1: row r - 1, column k
+            double yn2 = wave_shr1(y1prev);   // lane - 2: row r - 2, column k
             if (lane == 0) {
-                yn1 = (s > 0 && kin) ? prev_top[nx + k] : 0.0;
-                yn2 = (s > 0 && kin) ? prev_top[k] : 0.0;
-            } else if (lane == 1) {
-                yn2 = (s > 0 && kin) ? prev_top[nx + k] : 0.0;
+                // rows 63 and 62 of the strip above: wave w - 1 (written one and two
+                // block steps ago), the last strip of the previous round, or ghosts
+                const bool kin = k < nx;
+                double t63 = 0.0, t62 = 0.0;
+                if (w > 0) {
+                    t63 = ring[w - 1][1][k & (kSweepRing - 1)];
+                    t62 = ring[w - 1][0][k & (kSweepRing - 1)];
+                } else if (g0 > 0) {
+                    t63 = prev_top[nx + min(k, nx - 1)];
+                    t62 = prev_top[min(k, nx - 1)];
+                }
+                yn1 = kin ? t63 : 0.0;
+                yn2 = kin ? t62 : 0.0;
             }
+            y1prev = yn1;
             // The history shifts every step once the lane has started, also past the
-            // end of its row: the lane two rows up reads this lane's previous value
-            // one step later than the lane just above.
+            // end of its row: the lane two rows up reads this lane's previous value one
+            // step later than the lane just above.
             if (k >= 0) {
                 double v = 0.0;
-                if (active) {
+                if (valid && k < nx) {
                     v = (rhs_c + ax * (2.0 * last1 - 0.5 * last2) + ay * (2.0 * yn1 - 0.5 * yn2)) /
-                        (dflux + sig_c);
+                        (dflux + sig);
                     out[cell_of(k)] = v;
-                    if (lane >= 62) cur_top[(size_t)(lane - 62) * nx + k] = v;
+                }
+                if (lane >= 62 && k < nx) {
+                    ring[w][lane - 62][k & (kSweepRing - 1)] = v;
+                    if (last_wave) cur_top[(size_t)(lane - 62) * nx + k] = v;
                 }
                 last2 = last1;
                 last1 = v;
             }
+        };
+        // Block step t: wave w runs its step tau = t - 64 w.  The ring slot of step tau
+        // is refilled (for tau + D) at every block step, also before the wave starts and
+        // after it ends, so that the slot registers are never merged across a branch
+        // (which would wait for the loads in flight).  Whole rounds of D block steps,
+        // then the remaining ones (the slot, tau mod D, is fixed at compile time in both
+        // loops since 64 w is a multiple of D).
+        auto block_step = [&](int t, int u) {
+            const int tau = t - 64 * w;
+            const double rhs_c = rr[u], sig = sg[u];
+            fetch(tau + D, u);
+            if (wave_on && tau >= 0 && tau < Tw) step(tau, rhs_c, sig);
+            lds_barrier();
+        };
+        const int T = Tw + 64 * (Wg - 1);
+        int t0 = 0;
+        for (; t0 + D <= T; t0 += D) {
+#pragma unroll
+            for (int u = 0; u < D; ++u) block_step(t0 + u, u);
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < D; ++u)
+            if (t0 + u < T) block_step(t0 + u, u);
         par ^= 1;
     }
 }
@@ -334,6 +399,7 @@ size_t ImplicitSolver::bytes(const ImplicitParams& p) {
     take(off, (size_t)p.Q * p.Q * 8);                             // K
     take(off, (size_t)p.Q * 8 * 6);                               // w, dq, dir
     take(off, (size_t)p.P * 16);                                  // coef
+    take(off, (size_t)p.P * 8);                                   // sig
     take(off, (size_t)p.P * 8);                                   // phi
     take(off, (size_t)(p.gmres_restart + 6) * p.P * 8);           // GMRES vectors
     take(off, (size_t)(ndiv(std::max<int64_t>(p.Q * p.P, p.P), kVecBlock) + 8) * 4 * 8);  // partials
@@ -362,6 +428,7 @@ bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const do
     dq_ = small + p.Q;
     dir_ = small + 2 * p.Q;
     coef_ = reinterpret_cast<float4*>(base + take(off, (size_t)p.P * 16));
+    sig_ = reinterpret_cast<double*>(base + take(off, (size_t)p.P * 8));
     phi_ = reinterpret_cast<double*>(base + take(off, (size_t)p.P * 8));
     vecs_ = reinterpret_cast<double*>(base + take(off, (size_t)(p.gmres_restart + 6) * p.P * 8));
     nparts_ = (int)ndiv(std::max<int64_t>((int64_t)p.Q * p.P, p.P), kVecBlock) + 8;
@@ -383,8 +450,11 @@ bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const do
         small_h[2 * p.Q + 4 * q + 3] = eta >= 0.0 ? 1.0 : -1.0;
     }
     std::vector<float4> coef((size_t)p.P, make_float4(0.f, 0.f, 0.f, 0.f));
+    // total rate of the implicit update per cell, sigma_a + sigma_s + sigma_as + 1/dt
+    std::vector<double> sig((size_t)p.P, 0.0);
     for (int64_t c = 0; c < p.C; ++c) {
         coef[c] = make_float4(sigma_a[c], sigma_s[c], sigma_as[c], source ? source[c] : 0.f);
+        sig[c] = (double)sigma_a[c] + (double)sigma_s[c] + (double)sigma_as[c] + 1.0 / p.dt;
         const double st = (double)sigma_a[c] + sigma_s[c] + sigma_as[c] + 1.0 / p.dt;
         tmax = std::max(tmax, (double)sigma_as[c] / st);
     }
@@ -396,6 +466,7 @@ bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const do
     IMP_TRY(hipMemcpyAsync(K_, K, (size_t)p.Q * p.Q * 8, hipMemcpyHostToDevice, s_));
     IMP_TRY(hipMemcpyAsync(small, small_h.data(), small_h.size() * 8, hipMemcpyHostToDevice, s_));
     IMP_TRY(hipMemcpyAsync(coef_, coef.data(), coef.size() * 16, hipMemcpyHostToDevice, s_));
+    IMP_TRY(hipMemcpyAsync(sig_, sig.data(), sig.size() * 8, hipMemcpyHostToDevice, s_));
     const size_t lds = (size_t)4 * p.nx * 8;
     if (lds > 65536) {
         err = "sweep LDS request too large";
@@ -440,8 +511,9 @@ bool ImplicitSolver::sweep_once(const double* psi_in, double* psi_out, const dou
     dim3 g(ndiv(p_.Q, kT), (unsigned)(p_.P / kT));
     imp_rhs_kernel<<<g, 256, 0, s_>>>(r);
     IMP_TRY(hipGetLastError());
-    SweepArgs sa{rhs_, dir_, coef_, psi_out, p_.nx, p_.ny, p_.P, 1.0 / p_.dt};
-    imp_sweep_kernel<<<p_.Q, 64, (size_t)4 * p_.nx * 8, s_>>>(sa);
+    SweepArgs sa{rhs_, dir_, sig_, psi_out, p_.nx, p_.ny, p_.P};
+    const int strips = (p_.ny + 63) / 64;
+    imp_sweep_kernel<<<p_.Q, 64 * std::min(strips, kSweepWaves), (size_t)4 * p_.nx * 8, s_>>>(sa);
     IMP_TRY(hipGetLastError());
     ++sweeps;
     return true;

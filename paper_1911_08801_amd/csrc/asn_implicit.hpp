@@ -49,6 +49,7 @@ private:
     double *psi_old_ = nullptr, *psi_a_ = nullptr, *psi_b_ = nullptr, *rhs_ = nullptr;
     double *K_ = nullptr, *wq_ = nullptr, *dq_ = nullptr, *dir_ = nullptr;
     float4* coef_ = nullptr;            // per cell {sigma_a, sigma_s, sigma_as, q}
+    double* sig_ = nullptr;             // per cell sigma_a + sigma_s + sigma_as + 1/dt
     double *phi_ = nullptr, *vecs_ = nullptr, *part_ = nullptr;
     std::vector<double> hpart_;
     int nparts_ = 0;

@@ -881,16 +881,13 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
         pn.hy = load_plane(rp, oh);
     };
 
-    Plane cur, nxt;
+    // Ordinate q updates from plane slot q & 1 while the next plane loads into the
+    // other slot.  The slots are fixed per unrolled half and every load is issued
+    // unconditionally (the last ordinate of the chunk is loaded again at the end), so
+    // no slot is ever copied or merged across a branch, which would wait for the
+    // loads in flight.
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
-    QInfo qc = qtab[q0 < q1 ? q0 : 0];
-    if (q0 < q1) load(q0, qc.dir, cur);
-    for (int q = q0; q < q1; ++q) {
-        QInfo qn = qc;
-        if (q + 1 < q1) {
-            qn = qtab[q + 1];
-            load(q + 1, qn.dir, nxt);
-        }
+    auto body = [&](int q, const QInfo& qc, const Plane& cur) {
         const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
         float colsum = 0.f;
 #pragma unroll
@@ -923,8 +920,20 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
             }
             outflow += qc.w * (double)o;
         }
-        cur = nxt;
-        qc = qn;
+    };
+    Plane pa, pb;
+    QInfo qa = qtab[min(q0, a.Q - 1)], qb;
+    load(min(q0, a.Q - 1), qa.dir, pa);
+    for (int q = q0; q < q1; q += 2) {
+        const int qn = min(q + 1, q1 - 1);
+        qb = qtab[qn];
+        load(qn, qb.dir, pb);
+        body(q, qa, pa);
+        if (q + 1 >= q1) break;
+        const int qn2 = min(q + 2, q1 - 1);
+        qa = qtab[qn2];
+        load(qn2, qa.dir, pa);
+        body(q + 1, qb, pb);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -1045,16 +1054,9 @@ __global__ __launch_bounds__(256) void muscl_kernel(BatchArgs B) {
         }
     };
 
-    Plane cur, nxt;
+    // Two plane slots used alternately, loads unconditional (as in stream + collide).
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
-    QInfo qc = qtab[q0 < q1 ? q0 : 0];
-    if (q0 < q1) load(q0, qc.dir, cur);
-    for (int q = q0; q < q1; ++q) {
-        QInfo qn = qc;
-        if (q + 1 < q1) {
-            qn = qtab[q + 1];
-            load(q + 1, qn.dir, nxt);
-        }
+    auto body = [&](int q, const QInfo& qc, const Plane& cur) {
         const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
         // column e[k] = row ybase - 2 + k
         float e[R + 4];
@@ -1114,8 +1116,20 @@ __global__ __launch_bounds__(256) void muscl_kernel(BatchArgs B) {
         }
         defect += qc.w * (double)colsum;
         outflow += qc.w * (double)o;
-        cur = nxt;
-        qc = qn;
+    };
+    Plane pa, pb;
+    QInfo qa = qtab[min(q0, a.Q - 1)], qb;
+    load(min(q0, a.Q - 1), qa.dir, pa);
+    for (int q = q0; q < q1; q += 2) {
+        const int qn = min(q + 1, q1 - 1);
+        qb = qtab[qn];
+        load(qn, qb.dir, pb);
+        body(q, qa, pa);
+        if (q + 1 >= q1) break;
+        const int qn2 = min(q + 2, q1 - 1);
+        qa = qtab[qn2];
+        load(qn2, qa.dir, pa);
+        body(q + 1, qb, pb);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)

@@ -783,6 +783,26 @@ __device__ __forceinline__ void block_sum_256(double (&v)[NV], OutPtr out) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
+// The same for a block of NW waves (block size 64 NW).
+template <int NW, int NV, typename OutPtr>
+__device__ __forceinline__ void block_sum_waves(double (&v)[NV], OutPtr out) {
+    __shared__ double red[NW][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double t = red[0][k];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) t += red[w][k];
+            out[k] = t;
+        }
+}
 
 // ---------------------------------------------------------------------------
 // 2. Stream + collide.  Block = 4 waves; wave w owns rows y0 + w R .. + R - 1
@@ -1239,28 +1259,53 @@ __global__ void materialize_done_kernel(StepArgs a) {
 //                increment (the new level is the mean of psi^n and psi^1 +
 //                dt R(psi^1)).
 //    BUD_INIT    after set_state: M^0.
-__global__ __launch_bounds__(256) void budget_kernel(BatchArgs B, int mode) {
+// One block of 1024 threads per problem.  Each thread folds a strided share of the
+// partials, four independent loads at a time (the fold is one round trip per four
+// partials instead of per partial), then the block folds the threads in a fixed order.
+constexpr int kBudgetThreads = 1024;
+__global__ __launch_bounds__(kBudgetThreads) void budget_kernel(BatchArgs B, int mode) {
     int pi, local;
     if (!locate(B, KT_BUDGET, blockIdx.x, pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const bool init = mode == BUD_INIT;
     const int n_blk = a.tiles_x * a.tiles_y * a.G;
     double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const ASN_G double* fp = gp(a.fin_part);
-    const ASN_G double* bp = gp(a.blk_part);
-    for (int i = threadIdx.x; i < a.fin_blocks; i += 256) {
-        s[0] += fp[4 * (size_t)i + 0];
-        s[1] += fp[4 * (size_t)i + 1];
-        s[2] += fp[4 * (size_t)i + 2];
-        s[5] += fp[4 * (size_t)i + 3];
+    const ASN_G double4* fp = reinterpret_cast<const ASN_G double4*>(gp(a.fin_part));
+    const ASN_G double2* bp = reinterpret_cast<const ASN_G double2*>(gp(a.blk_part));
+    constexpr int T = kBudgetThreads, U = 4;
+    for (int i0 = threadIdx.x; i0 < a.fin_blocks; i0 += T * U) {
+        double4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * T;
+            const double4 t = fp[min(i, a.fin_blocks - 1)];
+            v[u] = i < a.fin_blocks ? t : double4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s[0] += v[u].x;
+            s[1] += v[u].y;
+            s[2] += v[u].z;
+            s[5] += v[u].w;
+        }
     }
     if (!init)
-        for (int i = threadIdx.x; i < n_blk; i += 256) {
-            s[3] += bp[2 * (size_t)i + 0];
-            s[4] += bp[2 * (size_t)i + 1];
+        for (int i0 = threadIdx.x; i0 < n_blk; i0 += T * U) {
+            double2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * T;
+                const double2 t = bp[min(i, n_blk - 1)];
+                v[u] = i < n_blk ? t : double2{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                s[3] += v[u].x;
+                s[4] += v[u].y;
+            }
         }
     __shared__ double tot[6];
-    block_sum_256<6>(s, tot);
+    block_sum_waves<T / 64, 6>(s, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (mode == BUD_STEP || mode == BUD_STAGE2) gp(B.steps_left)[pi] -= 1;
@@ -1392,7 +1437,7 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
     mark(2);
     finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
     mark(3);
-    budget_kernel<<<grid[KT_BUDGET], 256, 0, s>>>(b, bud);
+    budget_kernel<<<grid[KT_BUDGET], kBudgetThreads, 0, s>>>(b, bud);
     mark(4);
     if (e != hipSuccess) return e;
     return hipGetLastError();
@@ -1429,7 +1474,7 @@ hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s) {
     fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_next, nb, 0u);
     moments_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);
     finalize_kernel<<<a.fin_blocks, 256, 0, s>>>(one, 1);
-    budget_kernel<<<1, 256, 0, s>>>(one, BUD_INIT);
+    budget_kernel<<<1, kBudgetThreads, 0, s>>>(one, BUD_INIT);
     return hipGetLastError();
 }
 

@@ -61,6 +61,18 @@ def test_tight_steps_match_oracle(nx, ny):
     assert bud["steps"] == 2
 
 
+def test_tall_grid_sweeps_strips_in_several_rounds():
+    # more than eight 64-row strips: the sweep carries the last strip's rows of one
+    # round of strips in flight into the next round
+    nx, ny = 2, 530
+    spec = wl.random_problem(17, nx, ny, n_polar=2, n_azim=4, beta=4.5)
+    psi0 = wl.random_state(23, spec.q, ny, nx)
+    state, phi, bud, _ = _gpu(spec, 0.05, 1, psi0, tight=True)
+    ref, st, _ = _oracle(spec, 0.05, 1, psi0, tight=True)
+    assert np.max(np.abs(state - ref)) <= 1e-6 * np.abs(ref).max()
+    assert np.max(np.abs(phi - o.scalar_flux(ref, st.w))) <= 1e-10 * np.abs(phi).max()
+
+
 def test_icosahedron_set_with_zero_eta_ordinates():
     spec = wl.line_source(24, sigma_as=3.0, beta=4.0)
     spec.ico_order = 3                      # 42 ordinates, some with eta = 0

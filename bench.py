@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-heun", action="store_true", help="skip the Heun + minmod line")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip the FP32 Euler line with separate contraction and stencil kernels")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-scheme line")
     ap.add_argument("--sweep", choices=["lattice700", "line1024"], default=None,
                     help="precision sweep to t_final on a configured workload (one JSON line)")
@@ -79,13 +81,13 @@ def cpu_baseline(spec, steps):
 PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
 
 
-def timed_run(asn, spec, dtype, steps, warmup, scheme="euler"):
+def timed_run(asn, spec, dtype, steps, warmup, scheme="euler", unfused=False):
     """Warm up, time `steps` steps as the library runs them (no timing events between
     the kernels), then run `steps` more with HIP events recorded on the problem's stream
     between the kernels for the per-kernel durations.  The event markers themselves add
     a few microseconds per kernel boundary, so the throughput comes from the first pass."""
     import torch
-    p = asn.from_spec(spec, dtype=dtype, scheme=scheme)
+    p = asn.from_spec(spec, dtype=dtype, scheme=scheme, unfused=unfused)
     info = asn.asn_info(p)
     work = asn.asn_contraction_work(p)
     asn.asn_step(p, warmup)
@@ -134,31 +136,37 @@ def measured_traffic(kernel, spec):
     return total
 
 
-def roofline(res, spec, dtype):
-    """Roofline entry of the kernel with the largest share of the step."""
-    C, Q = spec.cells, spec.q
+def contraction_roofline(res, spec, dtype):
+    """MFMA roofline of the contraction kernel (fused or separate) of a run."""
     kms = res["kms"]
     scheme = res.get("scheme", "euler")
-    t_gemm, t_sc = kms["contraction"] * 1e-3, kms["stream_collide"] * 1e-3
-    sc_bytes = STENCIL_BYTES[scheme] * Q * C
+    t_gemm = kms["contraction"] * 1e-3
     fused = fused_run(res, dtype)
-    if t_gemm >= t_sc:
-        flops = PASSES[scheme] * res["work"]["tile_flops"]
-        peak = PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS
-        ach = flops / t_gemm / 1e12
-        if dtype == "f32":
-            prof = "gemm_f32_kernel<true>" if fused else "gemm_f32_kernel<false>"
-        else:
-            prof = f"gemm_lp_kernel<{1 if dtype == 'bf16' else 2}, {'true' if fused else 'false'}>"
-        traffic = measured_traffic(prof, spec)
-        return {"bound": "mfma", "kernel": prof + (" (contraction + stream/collide)" if fused else ""),
-                "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak,
-                "traffic": None if traffic is None else PASSES[scheme] * traffic,
-                "algorithmic": f"2*C*(K entries in nonzero tiles) = {flops:.4g} flop per step "
-                               f"(dense 2*Q*Q*C = {res['work']['dense_flops']:.4g} per launch)",
-                "dense_equivalent_TFLOPs": PASSES[scheme] * res["work"]["dense_flops"]
-                / t_gemm / 1e12}
+    flops = PASSES[scheme] * res["work"]["tile_flops"]
+    peak = PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS
+    ach = flops / t_gemm / 1e12
+    if dtype == "f32":
+        prof = "gemm_f32_kernel<true>" if fused else "gemm_f32_kernel<false>"
+    else:
+        prof = f"gemm_lp_kernel<{1 if dtype == 'bf16' else 2}, {'true' if fused else 'false'}>"
+    traffic = measured_traffic(prof, spec)
+    return {"bound": "mfma", "kernel": prof + (" (contraction + stream/collide)" if fused else ""),
+            "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": ach / peak,
+            "traffic": None if traffic is None else PASSES[scheme] * traffic,
+            "algorithmic": f"2*C*(K entries in the multiplied sub-blocks) = {flops:.4g} flop per "
+                           f"step (dense 2*Q*Q*C = {res['work']['dense_flops']:.4g} per launch)",
+            "dense_equivalent_TFLOPs": PASSES[scheme] * res["work"]["dense_flops"] / t_gemm / 1e12}
+
+
+def stencil_roofline(res, spec, dtype):
+    """HBM roofline of the separate stencil kernel(s) of a run (None when fused)."""
+    if fused_run(res, dtype):
+        return None
+    C, Q = spec.cells, spec.q
+    scheme = res.get("scheme", "euler")
+    t_sc = res["kms"]["stream_collide"] * 1e-3
+    sc_bytes = STENCIL_BYTES[scheme] * Q * C
     ach = sc_bytes / t_sc / 1e9
     lp = "false" if dtype == "f32" else "true"
     prof = [f"stream_collide_kernel<{lp}>"] if scheme == "euler" else \
@@ -167,6 +175,23 @@ def roofline(res, spec, dtype):
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
             "traffic": measured_traffic(prof, spec),
             "algorithmic": f"{STENCIL_BYTES[scheme]:g}*Q*C = {sc_bytes:.4g} bytes per step"}
+
+
+def roofline(res, spec, dtype):
+    """Roofline entry of the kernel with the largest share of the step."""
+    kms = res["kms"]
+    if kms["contraction"] >= kms["stream_collide"]:
+        return contraction_roofline(res, spec, dtype)
+    return stencil_roofline(res, spec, dtype)
+
+
+def rooflines(res, spec, dtype):
+    """Both rooflines of a run: MFMA for the contraction, HBM for a separate stencil."""
+    out = {"contraction": contraction_roofline(res, spec, dtype)}
+    st = stencil_roofline(res, spec, dtype)
+    if st is not None:
+        out["stencil"] = st
+    return out
 
 
 def fused_run(res, dtype):
@@ -351,16 +376,25 @@ def main():
         "f32": head,
         "roofline": roofline(res, spec, "f32"),
     }
+    out["f32"]["rooflines"] = rooflines(res, spec, "f32")
+    if not args.no_separate:
+        # the same FP32 Euler step as separate contraction and stencil kernels (Y through
+        # memory): the stencil's own HBM roofline
+        r = timed_run(asn, spec, "f32", args.steps, args.warmup, unfused=True)
+        out["f32_separate"] = summary(r, spec, args.steps)
+        out["f32_separate"]["rooflines"] = rooflines(r, spec, "f32")
     if not args.no_lowp:
         for dt in ("bf16", "f16"):
             r = timed_run(asn, spec, dt, args.steps, args.warmup)
             out[dt] = summary(r, spec, args.steps, dt)
             out[dt]["roofline"] = roofline(r, spec, dt)
+            out[dt]["rooflines"] = rooflines(r, spec, dt)
     if not args.no_heun:
         # the paper's own explicit scheme (Heun + minmod), same workload, FP32 contraction
         r = timed_run(asn, spec, "f32", args.steps, args.warmup, scheme="heun")
         out["heun_f32"] = summary(r, spec, args.steps)
         out["heun_f32"]["roofline"] = roofline(r, spec, "f32")
+        out["heun_f32"]["rooflines"] = rooflines(r, spec, "f32")
     if not args.no_implicit:
         out["implicit"] = implicit_run()
     if not args.no_serving:

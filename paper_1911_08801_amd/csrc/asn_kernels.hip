@@ -230,6 +230,7 @@ void gemm_f32_kernel(BatchArgs B) {
         }
         __shared__ double phred[2][kGemmBN];
         double defect = 0.0, outflow = 0.0;
+        float4 held[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             // four consecutive cells c0 .. c0 + 3 (c0 a multiple of 4, c0 + 3 < P)
@@ -325,9 +326,16 @@ void gemm_f32_kernel(BatchArgs B) {
                 const double wj = qok[j] ? qj.w : 0.0;   // padding ordinates add nothing
 #pragma unroll
                 for (int k = 0; k < 4; ++k) ph[k] += wj * (double)nv[k];
-                if (qok[j])
-                    *reinterpret_cast<ASN_G float4*>(out + (size_t)(m0 + wm + j * 16 + (lane & 15)) * P + c0) =
-                        make_float4(nv[0], nv[1], nv[2], nv[3]);
+                // Groups i and i + 1 are the two halves of a 128-byte line of the row: the
+                // even group's result is held and both are stored together.
+                const float4 res = make_float4(nv[0], nv[1], nv[2], nv[3]);
+                if ((i & 1) == 0) {
+                    held[j] = res;
+                } else if (qok[j]) {
+                    ASN_G float* o = out + (size_t)(m0 + wm + j * 16 + (lane & 15)) * P + c0;
+                    *reinterpret_cast<ASN_G float4*>(o - 16) = held[j];
+                    *reinterpret_cast<ASN_G float4*>(o) = res;
+                }
                 defect += wj * (double)colsum;
                 outflow += wj * (double)o;
             }
@@ -578,9 +586,21 @@ void gemm_lp_kernel(BatchArgs B) {
         double defect = 0.0, outflow = 0.0;
         float mx = 0.f;
         const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 held[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t c0 = n0 + wn + i * 16 + 4 * (lane >> 4);
+            // Groups i and i + 1 are the two halves of a 128-byte line of the row: the
+            // even group's result is held and both are stored together.
+            auto emit = [&](int j, int q, const float4& res) {
+                if ((i & 1) == 0) {
+                    held[j] = res;
+                } else {
+                    ASN_G float* o = out + (size_t)q * P + c0;
+                    *reinterpret_cast<ASN_G float4*>(o - 16) = held[j];
+                    *reinterpret_cast<ASN_G float4*>(o) = res;
+                }
+            };
             float aa[4], bs[4], gs[4], ss[4];
             int xk[4], yk[4];
             bool ck[4];
@@ -661,8 +681,7 @@ void gemm_lp_kernel(BatchArgs B) {
                     colsum += col;
                     mx = fmaxf(mx, fabsf(nv[k]));
                 }
-                *reinterpret_cast<ASN_G float4*>(out + (size_t)q * P + c0) =
-                    make_float4(nv[0], nv[1], nv[2], nv[3]);
+                emit(j, q, make_float4(nv[0], nv[1], nv[2], nv[3]));
                 defect += wq[j] * (double)colsum;
             }
             } else {
@@ -729,8 +748,7 @@ void gemm_lp_kernel(BatchArgs B) {
                         if (((dq[j] & 4) && yk[k] == ny - 1) || ((dq[j] & 8) && yk[k] == 0)) o += cyq[j] * v;
                     }
                 }
-                *reinterpret_cast<ASN_G float4*>(out + (size_t)q * P + c0) =
-                    make_float4(nv[0], nv[1], nv[2], nv[3]);
+                emit(j, q, make_float4(nv[0], nv[1], nv[2], nv[3]));
                 defect += wq[j] * (double)colsum;
                 outflow += wq[j] * (double)o;
             }

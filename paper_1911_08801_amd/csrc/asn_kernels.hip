@@ -854,6 +854,14 @@ __device__ __forceinline__ void store_plane(float v, __amdgpu_buffer_rsrc_t r, u
 }
 
 
+// Block barrier that orders LDS only (the stencil waves exchange their rows through LDS;
+// a full barrier would also wait for the next plane's global loads in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <bool LP>
 __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     constexpr int R = kRows;
@@ -915,9 +923,17 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
             pn.v[r] = load_plane(rp, off_ld[r]);
             pn.y[r] = load_plane(ry, off_ld[r]);
         }
-        const uint32_t oh = (dir & 4) ? off_hlo : ((dir & 8) ? off_hhi : kOOB);
+        // only the block's outer halo rows come from memory (wave 0 the row below the
+        // tile for eta > 0, wave 3 the row above it for eta < 0); the others are the
+        // neighbouring waves' own rows, exchanged through LDS
+        const uint32_t oh = ((dir & 4) && wave == 0) ? off_hlo : (((dir & 8) && wave == 3) ? off_hhi : kOOB);
         pn.hy = load_plane(rp, oh);
     };
+    // xr[q & 1][row of the tile][lane]: the tile's 16 rows of plane q; hr[q & 1][wave]: the
+    // halo row each wave loaded (only waves 0 and 3 load one; every wave stores its
+    // slot so that no store depends on the wave index)
+    __shared__ float xr[2][kTileY][64];
+    __shared__ float hr[2][4][64];
 
     // Ordinate q updates from plane slot q & 1 while the next plane loads into the
     // other slot.  The slots are fixed per unrolled half and every load is issued
@@ -927,13 +943,22 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
     auto body = [&](int q, const QInfo& qc, const Plane& cur) {
         const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
+        float (*xq)[64] = xr[q & 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) xq[wave * R + r][lane] = cur.v[r];
+        hr[q & 1][wave][lane] = cur.hy;
+        lds_barrier();
+        // the row below the wave's rows (eta > 0) or above them (eta < 0)
+        const float* hsrc = (qc.dir & 4) ? (wave == 0 ? &hr[q & 1][0][0] : &xq[wave * R - 1][0])
+                                         : (wave == 3 ? &hr[q & 1][3][0] : &xq[(wave + 1) * R][0]);
+        const float hy = hsrc[lane];
         float colsum = 0.f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const float v = cur.v[r];
             float uy = 0.f;
-            if (qc.dir & 4) uy = (r == 0) ? cur.hy : cur.v[r - 1];
-            else if (qc.dir & 8) uy = (r == R - 1) ? cur.hy : cur.v[r + 1];
+            if (qc.dir & 4) uy = (r == 0) ? hy : cur.v[r - 1];
+            else if (qc.dir & 8) uy = (r == R - 1) ? hy : cur.v[r + 1];
             float ux = 0.f;
             if (qc.dir & 1) ux = __shfl_up(v, 1, 64);
             else if (qc.dir & 2) ux = __shfl_down(v, 1, 64);
@@ -1080,11 +1105,13 @@ __global__ __launch_bounds__(256) void muscl_kernel(BatchArgs B) {
             pn.v[r] = load_plane(rp, off_ld[r]);
             pn.y[r] = load_plane(ry, off_ld[r]);
         }
-        // eta > 0 takes two rows below and one above, eta < 0 the mirror image
-        pn.h[0] = load_plane(rp, (dir & 4) ? off_h[0] : kOOB);
-        pn.h[1] = load_plane(rp, (dir & 12) ? off_h[1] : kOOB);
-        pn.h[2] = load_plane(rp, (dir & 12) ? off_h[2] : kOOB);
-        pn.h[3] = load_plane(rp, (dir & 8) ? off_h[3] : kOOB);
+        // eta > 0 takes two rows below and one above, eta < 0 the mirror image; only
+        // the block's outer halo rows come from memory (wave 0 below the tile, wave 3
+        // above it), the others are the neighbouring waves' own rows, through LDS
+        pn.h[0] = load_plane(rp, ((dir & 4) && wave == 0) ? off_h[0] : kOOB);
+        pn.h[1] = load_plane(rp, ((dir & 12) && wave == 0) ? off_h[1] : kOOB);
+        pn.h[2] = load_plane(rp, ((dir & 12) && wave == 3) ? off_h[2] : kOOB);
+        pn.h[3] = load_plane(rp, ((dir & 8) && wave == 3) ? off_h[3] : kOOB);
         if (STAGE == 2) {
             const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
 #pragma unroll
@@ -1094,16 +1121,30 @@ __global__ __launch_bounds__(256) void muscl_kernel(BatchArgs B) {
 
     // Two plane slots used alternately, loads unconditional (as in stream + collide).
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    // xr[q & 1][row of the tile][lane]: the tile's 16 rows of plane q; hr[q & 1][wave][k]:
+    // the halo rows each wave loaded (only waves 0 and 3 load any; every wave stores its
+    // slots so that no store depends on the wave index)
+    __shared__ float xr[2][kTileY][64];
+    __shared__ float hr[2][4][4][64];
     auto body = [&](int q, const QInfo& qc, const Plane& cur) {
         const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * P, C);
-        // column e[k] = row ybase - 2 + k
+        float (*xq)[64] = xr[q & 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) xq[wave * R + r][lane] = cur.v[r];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hr[q & 1][wave][k][lane] = cur.h[k];
+        lds_barrier();
+        // column e[k] = row ybase - 2 + k: two rows below the wave's rows (the tile's
+        // outer halo for wave 0), its own rows, two rows above (outer halo for wave 3)
+        const float* lo = wave == 0 ? &hr[q & 1][0][0][0] : &xq[wave * R - 2][0];
+        const float* hi = wave == 3 ? &hr[q & 1][3][2][0] : &xq[(wave + 1) * R][0];
         float e[R + 4];
-        e[0] = cur.h[0];
-        e[1] = cur.h[1];
+        e[0] = lo[lane];
+        e[1] = lo[64 + lane];
 #pragma unroll
         for (int r = 0; r < R; ++r) e[r + 2] = cur.v[r];
-        e[R + 2] = cur.h[2];
-        e[R + 3] = cur.h[3];
+        e[R + 2] = hi[lane];
+        e[R + 3] = hi[64 + lane];
         // upwind face values along y: fy[k] = value on the face above row k - 2
         // (eta > 0, k = 1..R+1 used) or below row k - 2 (eta < 0, k = 2..R+2 used)
         float fy[R + 4];

@@ -247,11 +247,12 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
                     int32_t* q);
 
 /* Arithmetic of one contraction Y = K Psi: dense_flops = 2 Q^2 C; tile_flops =
- * 2 C times the number of K entries in the tiles the kernel multiplies.  K is
+ * 2 C times the number of K entries in the blocks the kernel multiplies.  K is
  * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
- * sparse matrix), so tiles whose entries are all zero in the stored operand type
- * are skipped; the skipped products are exact zeros and the result is unchanged.
- * Either pointer may be NULL. */
+ * sparse matrix), so blocks whose entries are all zero in the stored operand type
+ * are skipped: 128-row x 32-column tiles for BF16/FP16, and for FP32 the 16-row x
+ * 16-column sub-blocks.  The skipped products are exact zeros and the result is
+ * unchanged.  Either pointer may be NULL. */
 asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile_flops);
 
 /* Free the handle and any memory the library allocated.  NULL is accepted. */

@@ -67,14 +67,16 @@ __device__ __forceinline__ StepArgs args_of(const BatchArgs& B, int i) {
 // 1a. FP32 contraction Y[q][c] = sum_p K[q][p] psi[p][c] on MFMA 16x16x4 f32.
 //     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
 //     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q read as 0.
+//     Only k-steps whose K tile has a nonzero are visited, and in those each wave
+//     multiplies only the 16-ordinate sub-blocks of its 64 rows that have one.
 //     FUSED: the forward-Euler stream + collide update is applied in the
 //     epilogue instead of storing Y.  The products are taken with the operands
 //     swapped (Y^T = Psi^T K^T), so each lane's accumulator holds four
 //     consecutive cells of one ordinate: the lane reads their old values and
-//     upwind neighbours as aligned float4 rows (cache hits: the block and its
-//     neighbours in the XCD have just streamed these rows), writes psi^{n+1}
-//     as a float4, and the block emits the Phi partial of its 128 ordinates for
-//     its 128 cells plus its budget partials.  Y never reaches memory.
+//     upwind neighbours as aligned float4 rows, writes psi^{n+1} as a float4
+//     (two cell groups, the halves of one 128-byte line, stored together), and
+//     the block emits the Phi partial of its 128 ordinates for its 128 cells
+//     plus its budget partials.  Y never reaches memory.
 // ---------------------------------------------------------------------------
 constexpr int kBK = kBK_F32;
 constexpr int kLdsPad = 16;

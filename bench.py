@@ -116,16 +116,26 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_line_source_400_q512.
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1911_08801_amd", "csrc", "asn_kernels.hip")
 
 
+def kernel_source_hash(path=KERNEL_SOURCE):
+    """sha256 of the kernel source with its comments and blank space removed, so that a
+    change of comments alone keeps a traffic record valid and any code change voids it."""
+    import hashlib
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()
+
+
 def measured_traffic(kernel, spec):
     """HBM bytes per dispatch (read + write) from the committed counter summary, or None
     if the kernels changed since it was taken or the workload is not the one measured."""
-    import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != sha or (spec.nx, spec.q) != (400, 512):
+    if rec.get("kernel_code_sha256") != kernel_source_hash() or (spec.nx, spec.q) != (400, 512):
         return None
     total = 0.0
     for name in kernel if isinstance(kernel, (list, tuple)) else [kernel]:

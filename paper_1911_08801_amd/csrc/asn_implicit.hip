@@ -42,17 +42,29 @@ __global__ __launch_bounds__(256) void imp_rhs_kernel(RhsArgs a) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < a.Q; k0 += kTK) {
+    // the next k-step's tiles are fetched into registers while this one is multiplied
+    double kr[4], pr[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const int idx = tid + 256 * l;
             const int r = idx >> 4, kk = idx & 15;
             const int q = q0 + r, k = k0 + kk;
-            Ks[kk][r] = (q < a.Q && k < a.Q) ? a.K[(size_t)q * a.Q + k] : 0.0;
+            kr[l] = (q < a.Q && k < a.Q) ? a.K[(size_t)q * a.Q + k] : 0.0;
             const int pk = idx >> 6, cc = idx & 63;
-            Ps[pk][cc] = (k0 + pk < a.Q) ? a.psi[(size_t)(k0 + pk) * a.P + c0 + cc] : 0.0;
+            pr[l] = (k0 + pk < a.Q) ? a.psi[(size_t)(k0 + pk) * a.P + c0 + cc] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < a.Q; k0 += kTK) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int idx = tid + 256 * l;
+            Ks[idx & 15][idx >> 4] = kr[l];
+            Ps[idx >> 6][idx & 63] = pr[l];
         }
         __syncthreads();
+        if (k0 + kTK < a.Q) fetch(k0 + kTK);
 #pragma unroll
         for (int kk = 0; kk < kTK; ++kk) {
             double kv[4], pv[4];
@@ -67,23 +79,35 @@ __global__ __launch_bounds__(256) void imp_rhs_kernel(RhsArgs a) {
         }
         __syncthreads();
     }
+    // the thread's four consecutive cells (32 bytes of each ordinate's row, read and
+    // written as one piece; cb + 3 < P since the pitch is a multiple of the tile)
+    const int64_t cb = c0 + tx * 4;
+    float4 cf[4];
+    double iso[4];
+    bool cok[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int64_t c = c0 + tx * 4 + j;
-        const bool cok = c < a.C;
-        const float4 cf = cok ? a.coef[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const double iso = (cok && a.phi) ? a.alpha * (double)cf.y * a.phi[c] * a.inv_W : 0.0;
+        const int64_t c = cb + j;
+        cok[j] = c < a.C;
+        cf[j] = cok[j] ? a.coef[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        iso[j] = (cok[j] && a.phi) ? a.alpha * (double)cf[j].y * a.phi[c] * a.inv_W : 0.0;
+    }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q = q0 + ty * 4 + i;
-            if (q >= a.Q) continue;
-            const size_t o = (size_t)q * a.P + c;
-            double v = 0.0;
-            if (cok)
-                v = (double)cf.z * acc[i][j] + iso +
-                    a.beta * ((double)cf.w + a.psi_old[o] * a.inv_dt);
-            a.rhs[o] = v;
-        }
+    for (int i = 0; i < 4; ++i) {
+        const int q = q0 + ty * 4 + i;
+        if (q >= a.Q) continue;
+        const size_t o = (size_t)q * a.P + cb;
+        const double2 o01 = *reinterpret_cast<const double2*>(a.psi_old + o);
+        const double2 o23 = *reinterpret_cast<const double2*>(a.psi_old + o + 2);
+        const double old[4] = {o01.x, o01.y, o23.x, o23.y};
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            v[j] = cok[j] ? (double)cf[j].z * acc[i][j] + iso[j] +
+                                a.beta * ((double)cf[j].w + old[j] * a.inv_dt)
+                          : 0.0;
+        *reinterpret_cast<double2*>(a.rhs + o) = make_double2(v[0], v[1]);
+        *reinterpret_cast<double2*>(a.rhs + o + 2) = make_double2(v[2], v[3]);
     }
 }
 

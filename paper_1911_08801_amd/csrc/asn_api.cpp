@@ -44,6 +44,7 @@ struct Layout {
     int Q = 0, Qp = 0, G = 1, qchunk = 1, tiles_x = 1, tiles_y = 1, fin_blocks = 1;
     int64_t C = 0, P = 0;
     bool lowp = false, fused = false;
+    bool flat = false;   // separate Euler stencil over flat cell chunks (stream_collide_flat)
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_delta, off_bmax0, off_bmax1, off_rec,
@@ -65,6 +66,11 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     // Split the ordinates into chunks so that the stream + collide grid holds about
     // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
     // keeps the last, partial round small.
+    L.flat = !fused && scheme == ASN_SCHEME_EULER && nx <= asn::kFlatMaxNx;
+    if (L.flat) {
+        L.tiles_x = (int)((L.P + asn::kFlatCells - 1) / asn::kFlatCells);
+        L.tiles_y = 1;
+    }
     int tiles = L.tiles_x * L.tiles_y;
     if (fused) {
         // the stencil runs in the contraction's epilogue: its blocks are the
@@ -159,6 +165,7 @@ struct asn_problem_s {
 struct asn_batch_s {
     std::vector<asn_problem> probs;
     int n = 0, dtype = 0, scheme = 0;
+    int launch_scheme = 0;   // scheme, or the flat-stencil form of a separate Euler step
     hipStream_t stream = nullptr;
     std::vector<StepArgs> tab;
     std::vector<int> off;
@@ -673,6 +680,12 @@ asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
     return ASN_OK;
 }
 
+// The scheme the kernels are launched with: a separate forward-Euler step whose
+// stencil runs over flat cell chunks has a launch form of its own.
+static int launch_scheme(asn_problem p) {
+    return p->L.flat ? asn::SCHEME_EULER_FLAT : p->scheme;
+}
+
 // An Euler step moves the state to the other buffer; a Heun step brings it back.
 static int state_flip(int scheme, int64_t n_steps) {
     return scheme == ASN_SCHEME_HEUN ? 0 : (int)(n_steps & 1);
@@ -693,7 +706,7 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
     asn::BatchArgs b = single_batch(p);
     for (int64_t i = 0; i < n_steps; ++i) {
         b.s_par = (int)(i & 1);
-        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, p->scheme, p->stream));
+        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, launch_scheme(p), p->stream));
     }
     p->cur ^= state_flip(p->scheme, n_steps);
     p->steps_done += n_steps;
@@ -735,7 +748,7 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
         bt.s_par = (int)(i & 1);
         const hipError_t e =
-            asn::launch_step(bt, p->blocks, p->dtype, p->scheme, p->stream, &ev[(size_t)i * per]);
+            asn::launch_step(bt, p->blocks, p->dtype, launch_scheme(p), p->stream, &ev[(size_t)i * per]);
         if (e != hipSuccess) {
             st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
             break;
@@ -782,6 +795,9 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
             return fail(ASN_E_UNSUPPORTED, "implicit problems step alone (asn_step)");
         if (probs[i]->L.fused != probs[0]->L.fused)
             return fail(ASN_E_INVALID, "problems of a batch must share the kernel fusion option");
+        if (probs[i]->L.flat != probs[0]->L.flat)
+            return fail(ASN_E_INVALID, "separate-kernel Euler problems of a batch must all have nx <= "
+                                       + std::to_string(asn::kFlatMaxNx) + " or all wider grids");
         if (probs[i]->stream != probs[0]->stream)
             return fail(ASN_E_INVALID, "problems of a batch must share the HIP stream");
         for (int32_t j = 0; j < i; ++j)
@@ -792,6 +808,7 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
     b->n = n;
     b->dtype = probs[0]->dtype;
     b->scheme = probs[0]->scheme;
+    b->launch_scheme = launch_scheme(probs[0]);
     b->stream = probs[0]->stream;
     b->tab.resize(2 * (size_t)n);
     b->off.assign((size_t)asn::KT_COUNT * (n + 1), 0);
@@ -855,7 +872,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
             hipError_t e = hipSuccess;
             for (int64_t j = 0; j < n_steps && e == hipSuccess; ++j) {
                 args.s_par = (int)(j & 1);
-                e = asn::launch_step(args, b->grid, b->dtype, b->scheme, b->stream);
+                e = asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream);
             }
             const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -873,7 +890,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
     } else {
         for (int64_t j = 0; j < n_steps; ++j) {
             args.s_par = (int)(j & 1);
-            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->scheme, b->stream));
+            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream));
         }
     }
     for (int i = 0; i < b->n; ++i) {

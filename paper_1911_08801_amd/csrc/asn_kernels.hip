@@ -1025,6 +1025,153 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
 }
 
 // ---------------------------------------------------------------------------
+// 2'. Stream + collide over flat cell chunks (separate forward-Euler stencil).
+//     Block (chunk bt, ordinate chunk g) updates cells b0 .. b0 + kFlatCells - 1 for
+//     the ordinates of chunk g; thread t owns cells b0 + 4 t .. b0 + 4 t + 3 (one
+//     aligned float4), so every row segment read or written is whole 128-byte lines.
+//     Per ordinate the plane segment [b0 - 1, b0 + L + 1) plus the row below it
+//     (eta > 0) or above it (eta < 0) is staged in LDS (float4 loads from a 16-byte
+//     aligned start, cells outside the planes read as 0 through the buffer bounds), the
+//     x- and y-upwind values are read from there with ghost masks at the domain
+//     boundary, and the next ordinate's segment is fetched meanwhile into the other
+//     register slot.  Same arithmetic and partials as stream_collide_kernel.
+// ---------------------------------------------------------------------------
+template <bool LP>
+__global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(BatchArgs B) {
+    constexpr int T = kFlatThreads, L = kFlatCells, NR = kFlatRounds;
+    int pi, local;
+    if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int tiles = a.tiles_x;
+    const int bt = local % tiles, g = local / tiles;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nx = a.nx, ny = a.ny;
+    const int C = (int)a.C, Pi = (int)a.P;
+    const int b0 = bt * L;
+    const int c0 = b0 + 4 * tid;
+    const int q0 = g * a.qchunk;
+    const int q1 = min(a.Q, q0 + a.qchunk);
+
+    // the thread's four cells c0 + j
+    float aa[4], bs[4], gs[4], ss[4], isov[4], fix[4];
+    int e_in = 0;      // 4 bits per cell: boundary faces as the bits of the direction code
+    int live = 0;      // bit j: cell c0 + j is a grid cell (not padding)
+    double phacc[4] = {0.0, 0.0, 0.0, 0.0};
+    {
+        const int y0 = c0 / nx;
+        int x = c0 - y0 * nx, y = y0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + j;
+            const bool in = c < C;
+            float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (in) cf = gp(a.coef)[c];
+            aa[j] = cf.x;
+            bs[j] = cf.y;
+            gs[j] = cf.z;
+            ss[j] = cf.w;
+            isov[j] = in ? gp(a.iso)[c] : 0.f;
+            fix[j] = (LP && in) ? gp(a.fix)[c] : 0.f;
+            // bit0 x = 0, bit1 x = nx - 1, bit2 y = 0, bit3 y = ny - 1: the upwind
+            // neighbour of direction d is a ghost where d & e != 0
+            const int e = (x == 0 ? 1 : 0) | (x == nx - 1 ? 2 : 0) | (y == 0 ? 4 : 0) |
+                          (y == ny - 1 ? 8 : 0);
+            e_in |= e << (4 * j);
+            live |= in ? 1 << j : 0;
+            x = x + 1 == nx ? 0 : x + 1;
+            y = x == 0 ? y + 1 : y;
+        }
+    }
+    double defect = 0.0, outflow = 0.0;
+    float mx = 0.f;
+
+    // staged segment start (16-byte aligned, may be negative)
+    auto seg_start = [&](int dir) { return (dir & 4) ? ((b0 - nx - 1) & ~3) : ((b0 - 1) & ~3); };
+    struct Plane {
+        float4 r[NR];
+        float4 y;
+    };
+    auto load = [&](int q, int dir, Plane& pn) {
+        // bounds at the pitch (cells C .. P - 1 hold zeros), so a float4 never straddles
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.psi + (size_t)q * a.P, a.P);
+        const __amdgpu_buffer_rsrc_t ry = plane_rsrc(a.Y + (size_t)q * a.P, a.P);
+        const int st = seg_start(dir);
+        const int seg_len = L + nx + 8;   // floats the update reads (rounds past it are not fetched)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int i = 4 * (tid + T * r);
+            const int c = st + i;
+            const uint32_t off = (c >= 0 && i < seg_len) ? 4u * (uint32_t)c : kOOB;
+            pn.r[r] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rp, off, 0, 0));
+        }
+        pn.y = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(ry, 4u * (uint32_t)c0, 0, 0));
+    };
+    __shared__ float4 seg[2][NR * T];
+    const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    auto body = [&](int q, const QInfo& qc, const Plane& cur) {
+        float4* sq = seg[q & 1];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sq[tid + T * r] = cur.r[r];
+        lds_barrier();
+        const float* sf = reinterpret_cast<const float*>(sq);
+        const int d = qc.dir;
+        const int i0 = c0 - seg_start(d);
+        const int ysh = (d & 4) ? -nx : nx;   // y-upwind cell (cy = 0 when d & 12 = 0)
+        const int xsh = (d & 1) ? -1 : 1;     // x-upwind cell (cx = 0 when d & 3 = 0)
+        const int dout = ((d & 5) << 1) | ((d & 10) >> 1);   // outflow faces of d
+        const float yv[4] = {cur.y.x, cur.y.y, cur.y.z, cur.y.w};
+        float nv[4];
+        float colsum = 0.f, o = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = (e_in >> (4 * j)) & 15;
+            const bool in = (live >> j) & 1;
+            const float v = sf[i0 + j];
+            const float ux = (d & e & 3) ? 0.f : sf[i0 + j + xsh];
+            const float uy = (d & e & 12) ? 0.f : sf[i0 + j + ysh];
+            const float col = gs[j] * ((yv[j] - fix[j]) - v) + bs[j] * (isov[j] - v);
+            const float r = v - qc.cx * (v - ux) - qc.cy * (v - uy) - aa[j] * v + col + ss[j];
+            nv[j] = in ? r : 0.f;   // padding cells stay zero
+            phacc[j] += qc.w * (double)nv[j];
+            colsum += in ? col : 0.f;
+            const int go = dout & e;
+            o += in ? ((go & 3) ? qc.cx * v : 0.f) + ((go & 12) ? qc.cy * v : 0.f) : 0.f;
+            if (LP) mx = fmaxf(mx, fabsf(nv[j]));
+        }
+        if (c0 < Pi)
+            *reinterpret_cast<ASN_G float4*>(gp(a.psi_new) + (size_t)q * a.P + c0) =
+                make_float4(nv[0], nv[1], nv[2], nv[3]);
+        defect += qc.w * (double)colsum;
+        outflow += qc.w * (double)o;
+    };
+    // two plane slots used alternately, loads unconditional (as in stream + collide)
+    Plane pa, pb;
+    QInfo qa = qtab[min(q0, a.Q - 1)], qb;
+    load(min(q0, a.Q - 1), qa.dir, pa);
+    for (int q = q0; q < q1; q += 2) {
+        const int qn = min(q + 1, q1 - 1);
+        qb = qtab[qn];
+        load(qn, qb.dir, pb);
+        body(q, qa, pa);
+        if (q + 1 >= q1) break;
+        const int qn2 = min(q + 2, q1 - 1);
+        qa = qtab[qn2];
+        load(qn2, qa.dir, pa);
+        body(q + 1, qb, pb);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if ((live >> j) & 1) gp(a.phi_part)[(size_t)g * a.P + c0 + j] = phacc[j];
+    if (LP) {
+        // the 256 cells of a wave are one scale block of the next operand
+        const unsigned m = wave_max_u32(__float_as_uint(mx));
+        if (lane == 0 && m && c0 < Pi) atomicMax(&a.bmax_next[c0 / kScaleBlock], m);
+    }
+    double sums[2] = {defect, outflow};
+    block_sum_waves<T / 64, 2>(sums, gp(a.blk_part) + 2 * (size_t)local);
+}
+
+// ---------------------------------------------------------------------------
 // 2b. Heun stage with limited second-order upwind fluxes (paper Section 3.1).
 //     Per ordinate and axis a cell's slope is minmod(psi_i - psi_{i-1},
 //     psi_{i+1} - psi_i); a face carries the value reconstructed on its upwind
@@ -1488,6 +1635,9 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
     if (!fused && stencil == 0) {
         if (lp) stream_collide_kernel<true><<<grid[KT_SC], 256, 0, s>>>(b);
         else stream_collide_kernel<false><<<grid[KT_SC], 256, 0, s>>>(b);
+    } else if (!fused && stencil == 3) {
+        if (lp) stream_collide_flat_kernel<true><<<grid[KT_SC], kFlatThreads, 0, s>>>(b);
+        else stream_collide_flat_kernel<false><<<grid[KT_SC], kFlatThreads, 0, s>>>(b);
     } else if (!fused && stencil == 1) {
         if (lp) muscl_kernel<true, 1><<<grid[KT_SC], 256, 0, s>>>(b);
         else muscl_kernel<false, 1><<<grid[KT_SC], 256, 0, s>>>(b);
@@ -1506,7 +1656,8 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
 
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
                        hipEvent_t* ev) {
-    if (scheme != SCHEME_HEUN) return launch_pass(b, grid, dtype, 0, BUD_STEP, s, ev);
+    if (scheme != SCHEME_HEUN)
+        return launch_pass(b, grid, dtype, scheme == SCHEME_EULER_FLAT ? 3 : 0, BUD_STEP, s, ev);
     BatchArgs b1 = b;
     b1.s_par = 0;
     hipError_t e = launch_pass(b1, grid, dtype, 1, BUD_STAGE1, s, ev);

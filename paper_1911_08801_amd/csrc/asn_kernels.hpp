@@ -35,6 +35,18 @@ enum {
 
 // Time schemes: forward Euler + donor cell; Heun + minmod-limited fluxes.
 enum { SCHEME_EULER = 0, SCHEME_HEUN = 1 };
+// Launch form of a forward-Euler step with separate kernels whose stencil runs over
+// flat cell chunks (see kFlatCells); the scheme is Euler.
+constexpr int SCHEME_EULER_FLAT = 3;
+
+// Separate forward-Euler stencil over flat chunks of kFlatCells consecutive cells (512
+// threads, 4 cells each): each ordinate's plane segment, with the row below or above it,
+// is staged in LDS in rounds of 2048 floats, at most kFlatRounds.  Used when
+// nx <= kFlatMaxNx.
+constexpr int kFlatThreads = 512;
+constexpr int kFlatCells = 4 * kFlatThreads;
+constexpr int kFlatRounds = 3;
+constexpr int kFlatMaxNx = kFlatRounds * kFlatCells - kFlatCells - 8;
 
 // Modes of the budget kernel.
 enum { BUD_STEP = 0, BUD_INIT = 1, BUD_STAGE1 = 2, BUD_STAGE2 = 3 };

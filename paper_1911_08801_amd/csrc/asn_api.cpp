@@ -44,7 +44,7 @@ struct Layout {
     int Q = 0, Qp = 0, G = 1, qchunk = 1, tiles_x = 1, tiles_y = 1, fin_blocks = 1;
     int64_t C = 0, P = 0;
     bool lowp = false, fused = false;
-    bool flat = false;   // separate Euler stencil over flat cell chunks (stream_collide_flat)
+    bool flat = false;   // separate-kernel stencil over flat cell chunks (not column strips)
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_delta, off_bmax0, off_bmax1, off_rec,
@@ -66,7 +66,8 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     // Split the ordinates into chunks so that the stream + collide grid holds about
     // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
     // keeps the last, partial round small.
-    L.flat = !fused && scheme == ASN_SCHEME_EULER && nx <= asn::kFlatMaxNx;
+    L.flat = !fused && ((scheme == ASN_SCHEME_EULER && nx <= asn::kFlatMaxNx) ||
+                        (scheme == ASN_SCHEME_HEUN && nx <= asn::kFlatMaxNxM));
     if (L.flat) {
         L.tiles_x = (int)((L.P + asn::kFlatCells - 1) / asn::kFlatCells);
         L.tiles_y = 1;
@@ -165,7 +166,7 @@ struct asn_problem_s {
 struct asn_batch_s {
     std::vector<asn_problem> probs;
     int n = 0, dtype = 0, scheme = 0;
-    int launch_scheme = 0;   // scheme, or the flat-stencil form of a separate Euler step
+    int launch_scheme = 0;   // scheme, or its flat-chunk stencil form
     hipStream_t stream = nullptr;
     std::vector<StepArgs> tab;
     std::vector<int> off;
@@ -680,10 +681,11 @@ asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
     return ASN_OK;
 }
 
-// The scheme the kernels are launched with: a separate forward-Euler step whose
-// stencil runs over flat cell chunks has a launch form of its own.
+// The scheme the kernels are launched with: a separate-kernel step whose stencil
+// runs over flat cell chunks (Euler or Heun) has a launch form of its own.
 static int launch_scheme(asn_problem p) {
-    return p->L.flat ? asn::SCHEME_EULER_FLAT : p->scheme;
+    if (!p->L.flat) return p->scheme;
+    return p->scheme == ASN_SCHEME_HEUN ? asn::SCHEME_HEUN_FLAT : asn::SCHEME_EULER_FLAT;
 }
 
 // An Euler step moves the state to the other buffer; a Heun step brings it back.
@@ -796,8 +798,10 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
         if (probs[i]->L.fused != probs[0]->L.fused)
             return fail(ASN_E_INVALID, "problems of a batch must share the kernel fusion option");
         if (probs[i]->L.flat != probs[0]->L.flat)
-            return fail(ASN_E_INVALID, "separate-kernel Euler problems of a batch must all have nx <= "
-                                       + std::to_string(asn::kFlatMaxNx) + " or all wider grids");
+            return fail(ASN_E_INVALID, std::string("problems of a batch must share the stencil form: ") +
+                                       "separate-kernel steps use flat cell chunks up to nx = " +
+                                       std::to_string(asn::kFlatMaxNx) + " (Euler) or " +
+                                       std::to_string(asn::kFlatMaxNxM) + " (Heun), strips beyond");
         if (probs[i]->stream != probs[0]->stream)
             return fail(ASN_E_INVALID, "problems of a batch must share the HIP stream");
         for (int32_t j = 0; j < i; ++j)

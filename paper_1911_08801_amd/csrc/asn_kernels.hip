@@ -1027,18 +1027,19 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
 // ---------------------------------------------------------------------------
 // 2'. Stream + collide over flat cell chunks (separate forward-Euler stencil).
 //     Block (chunk bt, ordinate chunk g) updates cells b0 .. b0 + kFlatCells - 1 for
-//     the ordinates of chunk g; thread t owns cells b0 + 4 t .. b0 + 4 t + 3 (one
-//     aligned float4), so every row segment read or written is whole 128-byte lines.
-//     Per ordinate the plane segment [b0 - 1, b0 + L + 1) plus the row below it
-//     (eta > 0) or above it (eta < 0) is staged in LDS (float4 loads from a 16-byte
-//     aligned start, cells outside the planes read as 0 through the buffer bounds), the
-//     x- and y-upwind values are read from there with ghost masks at the domain
+//     the ordinates of chunk g.  Per ordinate the plane segment [b0 - 1, b0 + L + 1)
+//     plus the row below it (eta > 0) or above it (eta < 0) is staged in LDS (float4
+//     loads from a 16-byte aligned start, so every row segment is read as whole
+//     128-byte lines; cells outside the planes read as 0 through the buffer bounds),
+//     the x- and y-upwind values are read from there with ghost masks at the domain
 //     boundary, and the next ordinate's segment is fetched meanwhile into the other
-//     register slot.  Same arithmetic and partials as stream_collide_kernel.
+//     register slot.  Thread t updates cells b0 + t + 512 j, j = 0..3: a wave's 64
+//     lanes read 64 consecutive LDS words (no bank conflicts) and store 256 contiguous
+//     bytes.  Same arithmetic and partials as stream_collide_kernel.
 // ---------------------------------------------------------------------------
 template <bool LP>
 __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(BatchArgs B) {
-    constexpr int T = kFlatThreads, L = kFlatCells, NR = kFlatRounds;
+    constexpr int T = kFlatThreads, L = kFlatCells, NR = kFlatRounds, J = L / T;
     int pi, local;
     if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
@@ -1048,48 +1049,45 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
     const int nx = a.nx, ny = a.ny;
     const int C = (int)a.C, Pi = (int)a.P;
     const int b0 = bt * L;
-    const int c0 = b0 + 4 * tid;
     const int q0 = g * a.qchunk;
     const int q1 = min(a.Q, q0 + a.qchunk);
 
-    // the thread's four cells c0 + j
-    float aa[4], bs[4], gs[4], ss[4], isov[4], fix[4];
+    // the thread's cells b0 + tid + T j
+    float aa[J], bs[J], gs[J], ss[J], isov[J], fix[J], mx[J];
+    uint32_t off[J];   // byte offset of the cell in a plane, out of range beyond the pitch
+    double phacc[J];
     int e_in = 0;      // 4 bits per cell: boundary faces as the bits of the direction code
-    int live = 0;      // bit j: cell c0 + j is a grid cell (not padding)
-    double phacc[4] = {0.0, 0.0, 0.0, 0.0};
-    {
-        const int y0 = c0 / nx;
-        int x = c0 - y0 * nx, y = y0;
+    int live = 0;      // bit j: cell j is a grid cell (not padding)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = c0 + j;
-            const bool in = c < C;
-            float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (in) cf = gp(a.coef)[c];
-            aa[j] = cf.x;
-            bs[j] = cf.y;
-            gs[j] = cf.z;
-            ss[j] = cf.w;
-            isov[j] = in ? gp(a.iso)[c] : 0.f;
-            fix[j] = (LP && in) ? gp(a.fix)[c] : 0.f;
-            // bit0 x = 0, bit1 x = nx - 1, bit2 y = 0, bit3 y = ny - 1: the upwind
-            // neighbour of direction d is a ghost where d & e != 0
-            const int e = (x == 0 ? 1 : 0) | (x == nx - 1 ? 2 : 0) | (y == 0 ? 4 : 0) |
-                          (y == ny - 1 ? 8 : 0);
-            e_in |= e << (4 * j);
-            live |= in ? 1 << j : 0;
-            x = x + 1 == nx ? 0 : x + 1;
-            y = x == 0 ? y + 1 : y;
-        }
+    for (int j = 0; j < J; ++j) {
+        const int c = b0 + tid + T * j;
+        const bool in = c < C;
+        const int y = c / nx, x = c - y * nx;
+        float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (in) cf = gp(a.coef)[c];
+        aa[j] = cf.x;
+        bs[j] = cf.y;
+        gs[j] = cf.z;
+        ss[j] = cf.w;
+        isov[j] = in ? gp(a.iso)[c] : 0.f;
+        fix[j] = (LP && in) ? gp(a.fix)[c] : 0.f;
+        mx[j] = 0.f;
+        phacc[j] = 0.0;
+        off[j] = c < Pi ? 4u * (uint32_t)c : kOOB;
+        // bit0 x = 0, bit1 x = nx - 1, bit2 y = 0, bit3 y = ny - 1: the upwind
+        // neighbour of direction d is a ghost where d & e != 0
+        const int e = (x == 0 ? 1 : 0) | (x == nx - 1 ? 2 : 0) | (y == 0 ? 4 : 0) |
+                      (y == ny - 1 ? 8 : 0);
+        e_in |= e << (4 * j);
+        live |= in ? 1 << j : 0;
     }
     double defect = 0.0, outflow = 0.0;
-    float mx = 0.f;
 
     // staged segment start (16-byte aligned, may be negative)
     auto seg_start = [&](int dir) { return (dir & 4) ? ((b0 - nx - 1) & ~3) : ((b0 - 1) & ~3); };
     struct Plane {
         float4 r[NR];
-        float4 y;
+        float y[J];
     };
     auto load = [&](int q, int dir, Plane& pn) {
         // bounds at the pitch (cells C .. P - 1 hold zeros), so a float4 never straddles
@@ -1101,10 +1099,11 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
         for (int r = 0; r < NR; ++r) {
             const int i = 4 * (tid + T * r);
             const int c = st + i;
-            const uint32_t off = (c >= 0 && i < seg_len) ? 4u * (uint32_t)c : kOOB;
-            pn.r[r] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rp, off, 0, 0));
+            const uint32_t o = (c >= 0 && i < seg_len) ? 4u * (uint32_t)c : kOOB;
+            pn.r[r] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rp, o, 0, 0));
         }
-        pn.y = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(ry, 4u * (uint32_t)c0, 0, 0));
+#pragma unroll
+        for (int j = 0; j < J; ++j) pn.y[j] = load_plane(ry, off[j]);
     };
     __shared__ float4 seg[2][NR * T];
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
@@ -1113,34 +1112,31 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
 #pragma unroll
         for (int r = 0; r < NR; ++r) sq[tid + T * r] = cur.r[r];
         lds_barrier();
-        const float* sf = reinterpret_cast<const float*>(sq);
         const int d = qc.dir;
-        const int i0 = c0 - seg_start(d);
+        const float* sf = reinterpret_cast<const float*>(sq) + (b0 - seg_start(d) + tid);
+        const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * a.P, a.P);
         const int ysh = (d & 4) ? -nx : nx;   // y-upwind cell (cy = 0 when d & 12 = 0)
         const int xsh = (d & 1) ? -1 : 1;     // x-upwind cell (cx = 0 when d & 3 = 0)
         const int dout = ((d & 5) << 1) | ((d & 10) >> 1);   // outflow faces of d
-        const float yv[4] = {cur.y.x, cur.y.y, cur.y.z, cur.y.w};
-        float nv[4];
         float colsum = 0.f, o = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < J; ++j) {
+            const float* pc = sf + T * j;
             const int e = (e_in >> (4 * j)) & 15;
             const bool in = (live >> j) & 1;
-            const float v = sf[i0 + j];
-            const float ux = (d & e & 3) ? 0.f : sf[i0 + j + xsh];
-            const float uy = (d & e & 12) ? 0.f : sf[i0 + j + ysh];
-            const float col = gs[j] * ((yv[j] - fix[j]) - v) + bs[j] * (isov[j] - v);
+            const float v = pc[0];
+            const float ux = (d & e & 3) ? 0.f : pc[xsh];
+            const float uy = (d & e & 12) ? 0.f : pc[ysh];
+            const float col = gs[j] * ((cur.y[j] - fix[j]) - v) + bs[j] * (isov[j] - v);
             const float r = v - qc.cx * (v - ux) - qc.cy * (v - uy) - aa[j] * v + col + ss[j];
-            nv[j] = in ? r : 0.f;   // padding cells stay zero
-            phacc[j] += qc.w * (double)nv[j];
+            const float nv = in ? r : 0.f;   // padding cells stay zero
+            store_plane(nv, ro, off[j]);
+            phacc[j] += qc.w * (double)nv;
             colsum += in ? col : 0.f;
             const int go = dout & e;
             o += in ? ((go & 3) ? qc.cx * v : 0.f) + ((go & 12) ? qc.cy * v : 0.f) : 0.f;
-            if (LP) mx = fmaxf(mx, fabsf(nv[j]));
+            if (LP) mx[j] = fmaxf(mx[j], fabsf(nv));
         }
-        if (c0 < Pi)
-            *reinterpret_cast<ASN_G float4*>(gp(a.psi_new) + (size_t)q * a.P + c0) =
-                make_float4(nv[0], nv[1], nv[2], nv[3]);
         defect += qc.w * (double)colsum;
         outflow += qc.w * (double)o;
     };
@@ -1160,12 +1156,16 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
         body(q + 1, qb, pb);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if ((live >> j) & 1) gp(a.phi_part)[(size_t)g * a.P + c0 + j] = phacc[j];
+    for (int j = 0; j < J; ++j)
+        if ((live >> j) & 1) gp(a.phi_part)[(size_t)g * a.P + b0 + tid + T * j] = phacc[j];
     if (LP) {
-        // the 256 cells of a wave are one scale block of the next operand
-        const unsigned m = wave_max_u32(__float_as_uint(mx));
-        if (lane == 0 && m && c0 < Pi) atomicMax(&a.bmax_next[c0 / kScaleBlock], m);
+        // a wave's 64 cells j lie in one scale block of the next operand
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const unsigned m = wave_max_u32(__float_as_uint(mx[j]));
+            const int cw = b0 + (tid & ~63) + T * j;
+            if (lane == 0 && m && cw < Pi) atomicMax(&a.bmax_next[cw / kScaleBlock], m);
+        }
     }
     double sums[2] = {defect, outflow};
     block_sum_waves<T / 64, 2>(sums, gp(a.blk_part) + 2 * (size_t)local);
@@ -1184,9 +1184,10 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
 //     In stage 2 the output buffer holds psi^n: every lane reads its own cell
 //     of it before overwriting that cell, and no other lane reads it.
 // ---------------------------------------------------------------------------
+// minmod(a, b) is the median of a, b and 0: the operand of smaller magnitude when the
+// signs agree, else 0 (one v_med3_f32).
 __device__ __forceinline__ float minmod(float a, float b) {
-    const float m = fminf(fabsf(a), fabsf(b));
-    return (a > 0.f && b > 0.f) ? m : ((a < 0.f && b < 0.f) ? -m : 0.f);
+    return __builtin_amdgcn_fmed3f(a, b, 0.f);
 }
 
 template <bool LP, int STAGE>
@@ -1395,6 +1396,196 @@ __global__ __launch_bounds__(256) void particle_fix_kernel(BatchArgs B) {
     const ASN_G double* yp = gp(a.ypart);
     for (int t = 0; t < nparts; ++t) m += yp[(size_t)t * a.P + c];
     gp(a.fix)[c] = (float)(m / a.W);
+}
+
+// ---------------------------------------------------------------------------
+// 2c. Heun pass over flat cell chunks: the MUSCL update of muscl_kernel (same
+//     arithmetic) in the flat-chunk form of stream_collide_flat_kernel.  The staged
+//     segment holds the chunk with two cells of x context and the two rows below and
+//     one above it (eta > 0) or the mirror image (eta < 0).  Cells beyond the grid's
+//     rows read as zero; x ghosts (two per side) are masked from the cell's x.  Thread
+//     t updates cells b0 + t + 512 j, j = 0..3, so that the 64 lanes of a wave read
+//     64 consecutive LDS words (no bank conflicts) and store 256 contiguous bytes.
+// ---------------------------------------------------------------------------
+template <bool LP, int STAGE>
+__global__ __launch_bounds__(kFlatThreads) void muscl_flat_kernel(BatchArgs B) {
+    constexpr int T = kFlatThreads, L = kFlatCells, NR = kFlatRounds, J = L / T;
+    int pi, local;
+    if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int tiles = a.tiles_x;
+    const int bt = local % tiles, g = local / tiles;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nx = a.nx, ny = a.ny;
+    const int C = (int)a.C, Pi = (int)a.P;
+    const int b0 = bt * L;
+    const int q0 = g * a.qchunk;
+    const int q1 = min(a.Q, q0 + a.qchunk);
+
+    float aa[J], bs[J], gs[J], ss[J], isov[J], fix[J], mx[J];
+    int xk[J];
+    uint32_t off[J];   // byte offset of the cell in a plane, out of range beyond the pitch
+    double phacc[J];
+    int live = 0;      // bit j: cell j is a grid cell (not padding)
+    unsigned ex = 0;   // 4 bits per cell: the direction bits that leave the grid there
+    int wexit = 0;     // bit j: some lane of the wave holds a boundary cell j (uniform)
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int c = b0 + tid + T * j;
+        const bool in = c < C;
+        const int y = c / nx, x = c - y * nx;
+        float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (in) cf = gp(a.coef)[c];
+        aa[j] = cf.x;
+        bs[j] = cf.y;
+        gs[j] = cf.z;
+        ss[j] = cf.w;
+        isov[j] = in ? gp(a.iso)[c] : 0.f;
+        fix[j] = (LP && in) ? gp(a.fix)[c] : 0.f;
+        mx[j] = 0.f;
+        phacc[j] = 0.0;
+        xk[j] = x;
+        off[j] = c < Pi ? 4u * (uint32_t)c : kOOB;
+        live |= in ? 1 << j : 0;
+        // +x leaves at x = nx - 1, -x at x = 0, +y at y = ny - 1, -y at y = 0
+        const unsigned e = in ? (unsigned)(x == nx - 1) | (unsigned)(x == 0) << 1 |
+                                    (unsigned)(y == ny - 1) << 2 | (unsigned)(y == 0) << 3
+                              : 0u;
+        ex |= e << (4 * j);
+        wexit |= __ballot(e != 0) ? 1 << j : 0;
+    }
+    double defect = 0.0, outflow = 0.0;
+
+    // staged segment start (16-byte aligned, may be negative)
+    auto seg_start = [&](int dir) {
+        return (dir & 4) ? ((b0 - 2 * nx - 2) & ~3) : ((dir & 8) ? ((b0 - nx - 2) & ~3) : ((b0 - 2) & ~3));
+    };
+    struct Plane {
+        float4 r[NR];
+        float y[J], o[J];
+    };
+    auto load = [&](int q, int dir, Plane& pn) {
+        // bounds at the pitch (cells C .. P - 1 hold zeros), so a float4 never straddles
+        const __amdgpu_buffer_rsrc_t rp = plane_rsrc(a.psi + (size_t)q * a.P, a.P);
+        const __amdgpu_buffer_rsrc_t ry = plane_rsrc(a.Y + (size_t)q * a.P, a.P);
+        const int st = seg_start(dir);
+        const int seg_len = L + 3 * nx + 8;   // floats the update reads
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int i = 4 * (tid + T * r);
+            const int c = st + i;
+            const uint32_t o = (c >= 0 && i < seg_len) ? 4u * (uint32_t)c : kOOB;
+            pn.r[r] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rp, o, 0, 0));
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) pn.y[j] = load_plane(ry, off[j]);
+        if (STAGE == 2) {   // the old level, stored where the result goes
+            const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * a.P, a.P);
+#pragma unroll
+            for (int j = 0; j < J; ++j) pn.o[j] = load_plane(ro, off[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < J; ++j) pn.o[j] = 0.f;
+        }
+    };
+    __shared__ float4 seg[2][NR * T];
+    const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    auto body = [&](int q, const QInfo& qc, const Plane& cur) {
+        float4* sq = seg[q & 1];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) sq[tid + T * r] = cur.r[r];
+        lds_barrier();
+        const int d = qc.dir;
+        const float* sf = reinterpret_cast<const float*>(sq) + (b0 - seg_start(d) + tid);
+        const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * a.P, a.P);
+        float colsum = 0.f, o = 0.f;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const float* pc = sf + T * j;
+            const int x = xk[j];
+            const float v = pc[0];
+            // x neighbours, zero ghosts outside the row
+            const float vm1 = x >= 1 ? pc[-1] : 0.f;
+            const float vp1 = x <= nx - 2 ? pc[1] : 0.f;
+            const float sx = minmod(v - vm1, vp1 - v);
+            float dfx = 0.f, fout_x = 0.f;
+            if (d & 1) {
+                const float vm2 = x >= 2 ? pc[-2] : 0.f;
+                const float f = v + 0.5f * sx;
+                const float fl = vm1 + 0.5f * minmod(vm1 - vm2, v - vm1);
+                dfx = f - fl;
+                fout_x = f;
+            } else if (d & 2) {
+                const float vp2 = x <= nx - 3 ? pc[2] : 0.f;
+                const float gl = v - 0.5f * sx;
+                const float gr = vp1 - 0.5f * minmod(vp1 - v, vp2 - vp1);
+                dfx = gl - gr;
+                fout_x = gl;
+            }
+            // y neighbours (rows beyond the grid read as zero)
+            float dfy = 0.f, fout_y = 0.f;
+            if (d & 4) {
+                const float ym2 = pc[-2 * nx], ym1 = pc[-nx], yp1 = pc[nx];
+                const float f = v + 0.5f * minmod(v - ym1, yp1 - v);
+                const float fb = ym1 + 0.5f * minmod(ym1 - ym2, v - ym1);
+                dfy = f - fb;
+                fout_y = f;
+            } else if (d & 8) {
+                const float ym1 = pc[-nx], yp1 = pc[nx], yp2 = pc[2 * nx];
+                const float gb = v - 0.5f * minmod(v - ym1, yp1 - v);
+                const float ga = yp1 - 0.5f * minmod(yp1 - v, yp2 - yp1);
+                dfy = gb - ga;
+                fout_y = gb;
+            }
+            const bool in = (live >> j) & 1;
+            const float col = gs[j] * ((cur.y[j] - fix[j]) - v) + bs[j] * (isov[j] - v);
+            const float nv = v - qc.cx * dfx - qc.cy * dfy - aa[j] * v + col + ss[j];
+            const float res = STAGE == 2 ? 0.5f * (cur.o[j] + nv) : nv;
+            const float rv = in ? res : 0.f;   // padding cells stay zero
+            store_plane(rv, ro, off[j]);
+            phacc[j] += qc.w * (double)rv;
+            colsum += in ? col : 0.f;
+            if (LP) mx[j] = fmaxf(mx[j], fabsf(rv));
+            if ((wexit >> j) & 1) {
+                // particles leaving through a boundary face: the reconstructed value on
+                // the face of the last cell, for directions that exit there
+                const unsigned e = (ex >> (4 * j)) & (unsigned)d;
+                if (e & 3u) o += qc.cx * fout_x;
+                if (e & 12u) o += qc.cy * fout_y;
+            }
+        }
+        defect += qc.w * (double)colsum;
+        outflow += qc.w * (double)o;
+    };
+    // two plane slots used alternately, loads unconditional (as in stream + collide)
+    Plane pa, pb;
+    QInfo qa = qtab[min(q0, a.Q - 1)], qb;
+    load(min(q0, a.Q - 1), qa.dir, pa);
+    for (int q = q0; q < q1; q += 2) {
+        const int qn = min(q + 1, q1 - 1);
+        qb = qtab[qn];
+        load(qn, qb.dir, pb);
+        body(q, qa, pa);
+        if (q + 1 >= q1) break;
+        const int qn2 = min(q + 2, q1 - 1);
+        qa = qtab[qn2];
+        load(qn2, qa.dir, pa);
+        body(q + 1, qb, pb);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if ((live >> j) & 1) gp(a.phi_part)[(size_t)g * a.P + b0 + tid + T * j] = phacc[j];
+    if (LP) {
+        // a wave's 64 cells j lie in one scale block of the next operand
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const unsigned m = wave_max_u32(__float_as_uint(mx[j]));
+            const int cw = b0 + (tid & ~63) + T * j;
+            if (lane == 0 && m && cw < Pi) atomicMax(&a.bmax_next[cw / kScaleBlock], m);
+        }
+    }
+    double sums[2] = {defect, outflow};
+    block_sum_waves<T / 64, 2>(sums, gp(a.blk_part) + 2 * (size_t)local);
 }
 
 // ---------------------------------------------------------------------------
@@ -1641,9 +1832,15 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
     } else if (!fused && stencil == 1) {
         if (lp) muscl_kernel<true, 1><<<grid[KT_SC], 256, 0, s>>>(b);
         else muscl_kernel<false, 1><<<grid[KT_SC], 256, 0, s>>>(b);
-    } else if (!fused) {
+    } else if (!fused && stencil == 2) {
         if (lp) muscl_kernel<true, 2><<<grid[KT_SC], 256, 0, s>>>(b);
         else muscl_kernel<false, 2><<<grid[KT_SC], 256, 0, s>>>(b);
+    } else if (!fused && stencil == 4) {
+        if (lp) muscl_flat_kernel<true, 1><<<grid[KT_SC], kFlatThreads, 0, s>>>(b);
+        else muscl_flat_kernel<false, 1><<<grid[KT_SC], kFlatThreads, 0, s>>>(b);
+    } else if (!fused && stencil == 5) {
+        if (lp) muscl_flat_kernel<true, 2><<<grid[KT_SC], kFlatThreads, 0, s>>>(b);
+        else muscl_flat_kernel<false, 2><<<grid[KT_SC], kFlatThreads, 0, s>>>(b);
     }
     mark(2);
     finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
@@ -1656,14 +1853,15 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
 
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
                        hipEvent_t* ev) {
-    if (scheme != SCHEME_HEUN)
+    if (scheme != SCHEME_HEUN && scheme != SCHEME_HEUN_FLAT)
         return launch_pass(b, grid, dtype, scheme == SCHEME_EULER_FLAT ? 3 : 0, BUD_STEP, s, ev);
+    const int st = scheme == SCHEME_HEUN_FLAT ? 4 : 1;   // stencil of the first pass
     BatchArgs b1 = b;
     b1.s_par = 0;
-    hipError_t e = launch_pass(b1, grid, dtype, 1, BUD_STAGE1, s, ev);
+    hipError_t e = launch_pass(b1, grid, dtype, st, BUD_STAGE1, s, ev);
     if (e != hipSuccess) return e;
     b1.s_par = 1;
-    return launch_pass(b1, grid, dtype, 2, BUD_STAGE2, s, ev ? ev + 5 : nullptr);
+    return launch_pass(b1, grid, dtype, st + 1, BUD_STAGE2, s, ev ? ev + 5 : nullptr);
 }
 
 __global__ void arm_kernel(int* steps_left, int* base, int n, ArmArgs v) {

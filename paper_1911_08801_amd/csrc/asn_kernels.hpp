@@ -47,6 +47,10 @@ constexpr int kFlatThreads = 512;
 constexpr int kFlatCells = 4 * kFlatThreads;
 constexpr int kFlatRounds = 3;
 constexpr int kFlatMaxNx = kFlatRounds * kFlatCells - kFlatCells - 8;
+// Heun passes in the same form: the limited stencil reads two rows on one side and one
+// on the other, so the segment is kFlatCells + 3 nx + 8 floats.
+constexpr int SCHEME_HEUN_FLAT = 4;
+constexpr int kFlatMaxNxM = (kFlatRounds * kFlatCells - kFlatCells - 8) / 3;
 
 // Modes of the budget kernel.
 enum { BUD_STEP = 0, BUD_INIT = 1, BUD_STAGE1 = 2, BUD_STAGE2 = 3 };
@@ -146,7 +150,9 @@ inline bool can_fuse(int dtype, int scheme) { (void)dtype; return scheme == SCHE
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
                        hipEvent_t* ev = nullptr);
 // Passes per step of a scheme.
-inline int passes_per_step(int scheme) { return scheme == SCHEME_HEUN ? 2 : 1; }
+inline int passes_per_step(int scheme) {
+    return scheme == SCHEME_HEUN || scheme == SCHEME_HEUN_FLAT ? 2 : 1;
+}
 // Arm a batch: steps_left[i] = limit[i] and base[i] = cur[i], i < n <= kMaxArm.
 constexpr int kMaxArm = 64;
 struct ArmArgs {

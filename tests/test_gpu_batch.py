@@ -62,6 +62,25 @@ def test_batch_rejects_mixed_operand_types_and_duplicates():
     p2.close()
 
 
+def test_batch_rejects_mixed_separate_stencil_forms():
+    # separate-kernel Euler steps use the flat-chunk stencil up to nx = 4088 and the
+    # strip stencil beyond; one launch serves one form
+    narrow = wl.random_problem(3, 40, 4, n_polar=2, n_azim=4, beta=4.5)
+    wide = wl.random_problem(4, 4100, 1, n_polar=2, n_azim=4, beta=4.5)
+    p1 = asn.from_spec(narrow, unfused=True)
+    p2 = asn.from_spec(wide, unfused=True)
+    p3 = asn.from_spec(wide, unfused=True)
+    try:
+        with pytest.raises(asn.AsnError):
+            asn.asn_batch_create([p1, p2])
+        b = asn.asn_batch_create([p2, p3])   # same form: fine
+        asn.asn_batch_step(b, 2)
+        b.close()
+    finally:
+        for p in (p1, p2, p3):
+            p.close()
+
+
 def test_step_batch_one_shot_matches_alone():
     specs = _specs()[:2]
     alone = [_alone(s, 6, "f32") for s in specs]

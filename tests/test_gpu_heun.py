@@ -36,6 +36,24 @@ def test_one_step_matches_oracle(nx, ny, n_polar, n_azim):
     assert np.max(np.abs(phi - phi_ref)) <= 8e-6 * np.abs(phi_ref).max()
 
 
+@pytest.mark.parametrize("nx,ny", [(130, 67), (1362, 3), (1363, 3), (2049, 2)])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_flat_chunk_and_strip_forms_match_oracle(nx, ny, dtype):
+    # grids up to 1362 columns run the stencil over flat 2048-cell chunks (the
+    # first crosses several chunk edges mid-row), wider ones over column strips
+    spec = wl.random_problem(nx + 3 * ny, nx, ny, n_polar=2, n_azim=4, beta=4.5)
+    psi0 = wl.random_state(nx * 7 + ny, spec.q, ny, nx)
+    state, phi, _, info = gpu_run(asn, spec, 2, psi0=psi0, dtype=dtype, scheme="heun")
+    ref, phi_ref, _ = oracle_run(spec, 2, psi0=psi0, scheme="heun")
+    assert info["steps_done"] == 2
+    if dtype == "f32":
+        assert np.max(np.abs(state - ref)) <= 8e-6 * np.abs(ref).max()
+        assert np.max(np.abs(phi - phi_ref)) <= 8e-6 * np.abs(phi_ref).max()
+    else:
+        assert rel_l2(state, ref) <= 2e-3
+        assert rel_l2(phi, phi_ref) <= 2e-3
+
+
 @pytest.mark.parametrize("norm", ["sym", "row"])
 def test_multi_step_random_fields(norm):
     spec = wl.random_problem(15, 70, 33, n_polar=4, n_azim=8, beta=4.5, t_final=0.3)

@@ -38,9 +38,11 @@ def test_one_step_matches_oracle(nx, ny, n_polar, n_azim):
     assert np.max(np.abs(phi - phi_ref)) <= 4e-6 * np.abs(phi_ref).max()
 
 
-@pytest.mark.parametrize("nx,ny", [(1, 1), (37, 9), (130, 67), (200, 3)])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (37, 9), (130, 67), (200, 3), (4100, 2)])
 @pytest.mark.parametrize("n_polar,n_azim", [(2, 4), (8, 16), (12, 24)])
 def test_separate_kernels_match_fused_step(nx, ny, n_polar, n_azim):
+    # (the separate stencil runs over flat cell chunks up to nx = 4088, over 62-column
+    # strips beyond: the 4100-wide grid takes the strip kernel)
     # The FP32 Euler step runs its stencil inside the contraction kernel by default;
     # the separate-kernel form (Y through memory) is the same arithmetic.
     spec = wl.random_problem(nx * 31 + ny, nx, ny, n_polar=n_polar, n_azim=n_azim, beta=4.5)

@@ -109,6 +109,9 @@ def timed_run(asn, spec, dtype, steps, warmup, scheme="euler", unfused=False):
 # Stencil bytes per update per step: Euler reads psi and Y and writes psi^{n+1}; a Heun
 # step is two passes, the second also reading psi^n.
 STENCIL_BYTES = {"euler": 12.0, "heun": 28.0}
+# widest grid whose separate stencil runs over flat 2048-cell chunks (three staged
+# rounds of 2048 floats hold the chunk and its neighbour rows); column strips beyond
+FLAT_MAX_NX = {"euler": 3 * 2048 - 2048 - 8, "heun": (3 * 2048 - 2048 - 8) // 3}
 PASSES = {"euler": 1, "heun": 2}
 
 
@@ -179,8 +182,9 @@ def stencil_roofline(res, spec, dtype):
     sc_bytes = STENCIL_BYTES[scheme] * Q * C
     ach = sc_bytes / t_sc / 1e9
     lp = "false" if dtype == "f32" else "true"
-    prof = [f"stream_collide_kernel<{lp}>"] if scheme == "euler" else \
-        [f"muscl_kernel<{lp}, 1>", f"muscl_kernel<{lp}, 2>"]
+    flat = "_flat" if spec.nx <= FLAT_MAX_NX[scheme] else ""
+    prof = [f"stream_collide{flat}_kernel<{lp}>"] if scheme == "euler" else \
+        [f"muscl{flat}_kernel<{lp}, 1>", f"muscl{flat}_kernel<{lp}, 2>"]
     return {"bound": "hbm", "kernel": " + ".join(prof), "achieved": ach,
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
             "traffic": measured_traffic(prof, spec),

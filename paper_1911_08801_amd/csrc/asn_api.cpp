@@ -63,9 +63,8 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     const int strip = scheme == ASN_SCHEME_HEUN ? asn::kStripXM : asn::kStripX;
     L.tiles_x = (nx + strip - 1) / strip;
     L.tiles_y = (ny + asn::kTileY - 1) / asn::kTileY;
-    // Split the ordinates into chunks so that the stream + collide grid holds about
-    // four rounds of the 1024 blocks the chip keeps resident (256 CUs x 4), which
-    // keeps the last, partial round small.
+    // Separate stencils up to a width run over flat cell chunks, wider grids over
+    // column strips; the ordinates are split into chunks sized to the grid below.
     L.flat = !fused && ((scheme == ASN_SCHEME_EULER && nx <= asn::kFlatMaxNx) ||
                         (scheme == ASN_SCHEME_HEUN && nx <= asn::kFlatMaxNxM));
     if (L.flat) {
@@ -82,7 +81,10 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
         L.qchunk = asn::kGemmBM;
         L.G = L.Qp / asn::kGemmBM;
     } else {
-        int G = (int)std::lround(4096.0 / tiles);
+        // strip blocks: about four rounds of the 1024 resident; flat-chunk blocks: one
+        // round of the 512 resident (a partial last round would cost a whole one, and
+        // fewer chunks leave fewer Phi partials to sum)
+        int G = L.flat ? asn::kFlatResident / tiles : (int)std::lround(4096.0 / tiles);
         G = std::max(1, std::min(G, std::min(64, std::max(1, Q / 2))));
         L.qchunk = (Q + G - 1) / G;
         L.G = (Q + L.qchunk - 1) / L.qchunk;

@@ -50,6 +50,9 @@ constexpr int kFlatMaxNx = kFlatRounds * kFlatCells - kFlatCells - 8;
 // Heun passes in the same form: the limited stencil reads two rows on one side and one
 // on the other, so the segment is kFlatCells + 3 nx + 8 floats.
 constexpr int SCHEME_HEUN_FLAT = 4;
+// Flat-chunk stencil blocks the chip keeps resident at once: 256 CUs x 2 blocks of
+// 8 waves (at most 4 waves per SIMD at their register use, 48 KB of LDS each).
+constexpr int kFlatResident = 512;
 constexpr int kFlatMaxNxM = (kFlatRounds * kFlatCells - kFlatCells - 8) / 3;
 
 // Modes of the budget kernel.

@@ -251,8 +251,8 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
  * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
  * sparse matrix), so blocks whose entries are all zero in the stored operand type
  * are skipped: 128-row x 32-column tiles for BF16/FP16, and for FP32 the 16-row x
- * 16-column sub-blocks.  The skipped products are exact zeros and the result is
- * unchanged.  Either pointer may be NULL. */
+ * 4-column blocks (one MFMA operand).  The skipped products are exact zeros and the
+ * result is unchanged.  Either pointer may be NULL. */
 asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile_flops);
 
 /* Free the handle and any memory the library allocated.  NULL is accepted. */

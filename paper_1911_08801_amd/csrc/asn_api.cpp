@@ -497,9 +497,11 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     // k-steps per M-tile whose tile of the stored K (FP32 or 16-bit) has a nonzero entry.
     // Steps inside the tile's own ordinate range come last: the fused epilogue then
     // reads rows that the block (and its neighbours) has just streamed through L2.
-    // After the k-step list, one mask per entry: bit s is set when rows m0 + 16 s ..
-    // m0 + 16 s + 15 of the step's K tile have a nonzero entry (the FP32 kernel skips
-    // the products of the other 16-row sub-blocks).
+    // After the k-step list, one mask per entry.  FP32: bit 4 s + g is set when rows
+    // m0 + 16 s .. m0 + 16 s + 15 and columns k0 + 4 g .. k0 + 4 g + 3 of the step's K tile
+    // (one MFMA operand block) have a nonzero entry; the kernel skips the products of the
+    // other blocks.  16-bit operands: bit s for the 16-row sub-block (whole tiles are
+    // multiplied).
     std::vector<int> ktab((size_t)L.ktab_len, 0);
     {
         const int mt_n = L.Qp / asn::kGemmBM;
@@ -513,25 +515,28 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
             std::vector<int> own, own_mask;
             for (int kt = 0; kt < nk; ++kt) {
                 const int k0 = kt * bk, k1 = std::min(Q, k0 + bk);
-                int mask = 0;
+                uint32_t mask = 0;
                 for (int m = m0; m < m1; ++m)
                     for (int k = k0; k < k1; ++k)
                         if (L.lowp ? (Klp[(size_t)m * L.Qp + k] & 0x7FFFu) != 0
                                    : Kt[(size_t)k * L.Qp + m] != 0.f)
-                            mask |= 1 << ((m - m0) / 16);
+                            mask |= L.lowp ? 1u << ((m - m0) / 16) : 1u << (4 * ((m - m0) / 16) + (k - k0) / 4);
                 if (mask) {
                     const bool is_own = k0 >= m0 && k0 < m0 + asn::kGemmBM;
                     (is_own ? own : entries).push_back(kt);
-                    (is_own ? own_mask : masks).push_back(mask);
+                    (is_own ? own_mask : masks).push_back((int)mask);
                     // K entries the kernel multiplies: whole tiles (16-bit operands) or
-                    // the nonzero 16-row sub-blocks (FP32)
-                    int rows = m1 - m0;
-                    if (!L.lowp) {
-                        rows = 0;
-                        for (int sb = 0; sb < asn::kGemmBM / 16; ++sb)
-                            if (mask & (1 << sb)) rows += std::max(0, std::min(m1, m0 + 16 * sb + 16) - (m0 + 16 * sb));
+                    // the nonzero 16 x 4 blocks (FP32)
+                    if (L.lowp) {
+                        cover += (double)(m1 - m0) * (k1 - k0);
+                    } else {
+                        for (int b = 0; b < 32; ++b) {
+                            if (!(mask & (1u << b))) continue;
+                            const int r0 = m0 + 16 * (b / 4), c0 = k0 + 4 * (b % 4);
+                            cover += (double)std::max(0, std::min(m1, r0 + 16) - r0) *
+                                     std::max(0, std::min(k1, c0 + 4) - c0);
+                        }
                     }
-                    cover += (double)rows * (k1 - k0);
                 }
             }
             entries.insert(entries.end(), own.begin(), own.end());

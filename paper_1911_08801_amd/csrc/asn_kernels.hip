@@ -68,7 +68,7 @@ __device__ __forceinline__ StepArgs args_of(const BatchArgs& B, int i) {
 //     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
 //     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q read as 0.
 //     Only k-steps whose K tile has a nonzero are visited, and in those each wave
-//     multiplies only the 16-ordinate sub-blocks of its 64 rows that have one.
+//     multiplies only the 16-ordinate x 4 blocks of its 64 rows that have one.
 //     FUSED: the forward-Euler stream + collide update is applied in the
 //     epilogue instead of storing Y.  The products are taken with the operands
 //     swapped (Y^T = Psi^T K^T), so each lane's accumulator holds four
@@ -156,8 +156,8 @@ void gemm_f32_kernel(BatchArgs B) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // Only k-steps whose K tile has a nonzero entry, and in those only the 16-ordinate
-    // sub-blocks of the wave with a nonzero entry (the skipped products are +0).
+    // Only k-steps whose K tile has a nonzero entry, and in those only the 16 x 4 operand
+    // blocks of the wave with a nonzero entry (the skipped products are +0).
     const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
     const ASN_G int* __restrict__ mlist = klist + ktab[mtiles];
     const int nkt = ktab[mt + 1] - ktab[mt];
@@ -168,7 +168,10 @@ void gemm_f32_kernel(BatchArgs B) {
     __syncthreads();
     for (int kt = 0; kt < nkt; ++kt) {
         const int b = kt & 1;
-        const int wmask = (mlist[kt] >> (4 * (wave & 1))) & 0xF;   // this wave's 64 ordinates
+        // this wave's 64 ordinates: bit 4 i + g for sub-block i and k-group g (4 k each)
+        // (wave-uniform: kept in a scalar register, tested with scalar branches)
+        const unsigned wmask = (unsigned)__builtin_amdgcn_readfirstlane(
+            (int)(((unsigned)mlist[kt] >> (16 * (wave & 1))) & 0xFFFFu));
         if (kt + 1 < nkt) gload(klist[kt + 1] * kBK);
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
@@ -182,14 +185,14 @@ void gemm_f32_kernel(BatchArgs B) {
                 // rows = cells (bv), columns = ordinates (av)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (wmask & (1 << j))
+                    if (wmask & (1u << (4 * j + kk / 4)))
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[i], av[j], acc[i][j], 0, 0, 0);
             } else {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (wmask & (1 << i))
+                    if (wmask & (1u << (4 * i + kk / 4)))
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);

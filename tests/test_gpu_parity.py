@@ -255,10 +255,11 @@ def test_contraction_work_reports_skipped_zero_tiles():
     work = asn.asn_contraction_work(p)
     p.close()
     assert work["dense_flops"] == 2.0 * 512 * 512 * 256
-    # K is forward peaked: the FP32 kernel multiplies only the 16 x 16 sub-blocks (16
-    # ordinates x one 16-ordinate k-step) of the stored K that hold a nonzero.
+    # K is forward peaked: the FP32 kernel multiplies only the 16 x 4 blocks (16
+    # ordinates x 4 ordinates of a k-step, one MFMA operand) of the stored K that hold
+    # a nonzero.
     om, w = asn.asn_build_quadrature(16, 32)
     K = asn.asn_build_kernel(om, w, spec.beta / 512).astype(np.float32)
-    blocks = (K.reshape(32, 16, 32, 16) != 0).any(axis=(1, 3)).sum()
-    assert work["tile_flops"] == 2.0 * blocks * 256 * 256
-    assert 0.2 * work["dense_flops"] < work["tile_flops"] < 0.4 * work["dense_flops"]
+    blocks = (K.reshape(32, 16, 128, 4) != 0).any(axis=(1, 3)).sum()
+    assert work["tile_flops"] == 2.0 * blocks * 64 * 256
+    assert 0.15 * work["dense_flops"] < work["tile_flops"] < 0.3 * work["dense_flops"]

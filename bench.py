@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-heun", action="store_true", help="skip the Heun + minmod line")
     ap.add_argument("--no-separate", action="store_true",
-                    help="skip the FP32 Euler line with separate contraction and stencil kernels")
+                    help="skip the FP32 Euler line in the other kernel form (fused or separate) "
+                         "than the one the library chooses")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-scheme line")
     ap.add_argument("--sweep", choices=["lattice700", "line1024"], default=None,
                     help="precision sweep to t_final on a configured workload (one JSON line)")
@@ -81,7 +82,7 @@ def cpu_baseline(spec, steps):
 PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
 
 
-def timed_run(asn, spec, dtype, steps, warmup, scheme="euler", unfused=False):
+def timed_run(asn, spec, dtype, steps, warmup, scheme="euler", unfused=None):
     """Warm up, time `steps` steps as the library runs them (no timing events between
     the kernels), then run `steps` more with HIP events recorded on the problem's stream
     between the kernels for the per-kernel durations.  The event markers themselves add
@@ -392,11 +393,14 @@ def main():
     }
     out["f32"]["rooflines"] = rooflines(res, spec, "f32")
     if not args.no_separate:
-        # the same FP32 Euler step as separate contraction and stencil kernels (Y through
-        # memory): the stencil's own HBM roofline
-        r = timed_run(asn, spec, "f32", args.steps, args.warmup, unfused=True)
-        out["f32_separate"] = summary(r, spec, args.steps)
-        out["f32_separate"]["rooflines"] = rooflines(r, spec, "f32")
+        # the same FP32 Euler step in the other kernel form than the library chose
+        # (separate: Y through memory and the stencil's own HBM roofline; fused: the
+        # stencil in the contraction's epilogue)
+        sep = head["fused_step"]
+        r = timed_run(asn, spec, "f32", args.steps, args.warmup, unfused=sep)
+        key = "f32_separate" if sep else "f32_fused"
+        out[key] = summary(r, spec, args.steps)
+        out[key]["rooflines"] = rooflines(r, spec, "f32")
     if not args.no_lowp:
         for dt in ("bf16", "f16"):
             r = timed_run(asn, spec, dt, args.steps, args.warmup)

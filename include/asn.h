@@ -87,6 +87,15 @@ enum { ASN_SCHEME_EULER = 0, ASN_SCHEME_HEUN = 1, ASN_SCHEME_IMPLICIT = 2 };
  *                   without bound; this rule keeps every problem inside it. */
 enum { ASN_DT_STREAMING = 0, ASN_DT_STIFF = 1 };
 
+/* Kernel form of a forward-Euler step (results agree to FP32 rounding across forms).
+ * ASN_FORM_FUSED:    the stream + collide update runs in the contraction kernel's
+ *                    epilogue; the contraction output Y never reaches memory.
+ * ASN_FORM_SEPARATE: contraction, then a separate stencil kernel (Y through memory).
+ * ASN_FORM_AUTO:     BF16/FP16 fuse; FP32 runs separate kernels from 2^25
+ *                    cell-ordinates (nx <= 4088) and fuses smaller problems, the
+ *                    faster form on MI355X at the sizes measured. */
+enum { ASN_FORM_AUTO = 0, ASN_FORM_SEPARATE = 1, ASN_FORM_FUSED = 2 };
+
 #define ASN_BUDGET_LEN 8
 
 /* Uniform grid of nx * ny cells covering [x_min, x_max] x [y_min, y_max]. */
@@ -119,10 +128,8 @@ typedef struct {
     int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
     int32_t scheme;         /* ASN_SCHEME_EULER (default) or ASN_SCHEME_HEUN                     */
     int32_t dt_rule;        /* ASN_DT_STREAMING (default) or ASN_DT_STIFF                        */
-    int32_t unfused;        /* 0 (default): FP32 forward-Euler steps apply the stream + collide
-                               update in the contraction kernel's epilogue; 1: separate kernels
-                               (the contraction output Y goes through memory).  Same
-                               arithmetic, results agree to FP32 rounding.                      */
+    int32_t step_form;      /* ASN_FORM_AUTO (default), ASN_FORM_SEPARATE or ASN_FORM_FUSED:
+                               kernel form of forward-Euler steps (other schemes: separate)   */
     double implicit_tol;    /* ASN_SCHEME_IMPLICIT: GMRES relative residual (0: 1.5e-8, paper 4.1) */
     double source_tol;      /* ASN_SCHEME_IMPLICIT: source-iteration tolerance (0: 1e-4)           */
 } asn_options;
@@ -251,8 +258,8 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
  * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
  * sparse matrix), so blocks whose entries are all zero in the stored operand type
  * are skipped: 128-row x 32-column tiles for BF16/FP16, and for FP32 the 16-row x
- * 4-column blocks (one MFMA operand).  The skipped products are exact zeros and the
- * result is unchanged.  Either pointer may be NULL. */
+ * 4-column blocks (the K operand of one MFMA).  The skipped products are exact zeros
+ * and the result is unchanged.  Either pointer may be NULL. */
 asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile_flops);
 
 /* Free the handle and any memory the library allocated.  NULL is accepted. */

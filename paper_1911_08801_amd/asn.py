@@ -37,6 +37,7 @@ ASN_GEMM_F32, ASN_GEMM_BF16, ASN_GEMM_F16 = 0, 1, 2
 ASN_NORM_SYM, ASN_NORM_ROW = 0, 1
 ASN_SCHEME_EULER, ASN_SCHEME_HEUN, ASN_SCHEME_IMPLICIT = 0, 1, 2
 ASN_DT_STREAMING, ASN_DT_STIFF = 0, 1
+ASN_FORM_AUTO, ASN_FORM_SEPARATE, ASN_FORM_FUSED = 0, 1, 2
 ASN_BUDGET_LEN = 8
 
 DTYPES = {"f32": ASN_GEMM_F32, "bf16": ASN_GEMM_BF16, "f16": ASN_GEMM_F16}
@@ -69,7 +70,7 @@ class asn_options(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("eps_override", ctypes.c_double),
                 ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
                 ("scheme", ctypes.c_int32), ("dt_rule", ctypes.c_int32),
-                ("unfused", ctypes.c_int32), ("implicit_tol", ctypes.c_double),
+                ("step_form", ctypes.c_int32), ("implicit_tol", ctypes.c_double),
                 ("source_tol", ctypes.c_double)]
 
 
@@ -199,14 +200,17 @@ def asn_options_default() -> asn_options:
 def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                  eps_override: float = 0.0, dt_override: float = 0.0,
                  scheme: str = "euler", dt_rule: str = "streaming",
-                 unfused: bool = False, implicit_tol: float = 0.0,
+                 unfused: Optional[bool] = None, implicit_tol: float = 0.0,
                  source_tol: float = 0.0) -> asn_options:
+    """Options for asn_create; unfused: None lets the library choose the kernel form of
+    forward-Euler steps, True asks for separate kernels, False for the fused one."""
     o = asn_options_default()
     o.gemm_dtype = DTYPES[dtype]
     o.normalization = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.dt_rule = DT_RULES[dt_rule]
-    o.unfused = 1 if unfused else 0
+    o.step_form = (ASN_FORM_AUTO if unfused is None else
+                   ASN_FORM_SEPARATE if unfused else ASN_FORM_FUSED)
     o.implicit_tol = implicit_tol
     o.source_tol = source_tol
     o.cfl = cfl
@@ -433,7 +437,7 @@ def asn_destroy(p: AsnProblem) -> None:
 def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               eps_override: float = 0.0, dt_override: float = 0.0,
               set_initial_state: bool = True, scheme: str = "euler",
-              dt_rule: str = "streaming", unfused: bool = False,
+              dt_rule: str = "streaming", unfused: Optional[bool] = None,
               implicit_tol: float = 0.0, source_tol: float = 0.0) -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""

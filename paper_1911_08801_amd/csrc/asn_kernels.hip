@@ -87,10 +87,10 @@ __device__ __forceinline__ void block_sum_256(double (&v)[NV], OutPtr out);
 #ifndef ASN_F32_FUSED_WAVES
 #define ASN_F32_FUSED_WAVES 2
 #endif
-// The fused epilogue needs more registers; three resident blocks per CU keep the
-// MFMA pipes fed while some blocks run their epilogues.
+// The fused epilogue needs more registers (two resident blocks per CU); the plain
+// contraction fits four, whose loads then hide behind the others' products.
 template <bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? ASN_F32_FUSED_WAVES : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? ASN_F32_FUSED_WAVES : 4)))
 void gemm_f32_kernel(BatchArgs B) {
     __shared__ float As[2][kBK][kGemmBM + kLdsPad];
     __shared__ float Bs[2][kBK][kGemmBN + kLdsPad];
@@ -112,41 +112,30 @@ void gemm_f32_kernel(BatchArgs B) {
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
 
     // Staging of one k-step (kBK ordinates): thread t moves float4 number t + 256 r
-    // (r < kBK / 8) of the A tile (Kt rows) and of the B tile (psi rows); rows >= Q of
-    // psi read as zero.
+    // (r < kBK / 8) of the A tile (Kt rows) and of the B tile (psi rows).  Steps past
+    // row Q - 1 of psi read that row again: the matching rows of Kt are zero, so they
+    // add exact zeros (a conditional overwrite of the loaded value would make the
+    // wait for it count all loads in flight).
     constexpr int kNR = kBK / 8;
     const int kk0 = tid >> 5, c4 = (tid & 31) << 2;
-    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    static_assert(kNR == 2 || kNR == 4, "staging of 16- or 32-row k-steps");
-#define ASN_GL1(r, k0)                                                                         \
+#define ASN_GL1(S, r, k0)                                                                      \
     do {                                                                                       \
         const int ka = (k0) + kk0 + 8 * (r);                                                   \
-        ra##r = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)ka * Qp + m0 + c4);        \
-        rb##r = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(ka, Q - 1) * P + n0 + c4); \
-        if (ka >= Q) rb##r = zero4;                                                            \
+        ra##S##r = *reinterpret_cast<const ASN_G float4*>(Kt + (size_t)ka * Qp + m0 + c4);     \
+        rb##S##r = *reinterpret_cast<const ASN_G float4*>(psi + (size_t)min(ka, Q - 1) * P + n0 + c4); \
     } while (0)
-#define ASN_LS1(r, b)                                                                          \
+#define ASN_LS1(S, r, b)                                                                       \
     do {                                                                                       \
-        *reinterpret_cast<float4*>(&As[b][kk0 + 8 * (r)][c4]) = ra##r;                         \
-        *reinterpret_cast<float4*>(&Bs[b][kk0 + 8 * (r)][c4]) = rb##r;                         \
+        *reinterpret_cast<float4*>(&As[b][kk0 + 8 * (r)][c4]) = ra##S##r;                      \
+        *reinterpret_cast<float4*>(&Bs[b][kk0 + 8 * (r)][c4]) = rb##S##r;                      \
     } while (0)
-    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-    auto gload = [&](int k0) {
-        ASN_GL1(0, k0);
-        ASN_GL1(1, k0);
-        if constexpr (kNR == 4) {
-            ASN_GL1(2, k0);
-            ASN_GL1(3, k0);
-        }
-    };
-    auto lstore = [&](int b) {
-        ASN_LS1(0, b);
-        ASN_LS1(1, b);
-        if constexpr (kNR == 4) {
-            ASN_LS1(2, b);
-            ASN_LS1(3, b);
-        }
-    };
+    static_assert(kNR == 2, "staging of 16-row k-steps");
+    // register set X, and (plain contraction) set Y for a second step in flight
+    float4 raX0, raX1, rbX0, rbX1, raY0, raY1, rbY0, rbY1;
+    auto gloadX = [&](int k0) { ASN_GL1(X, 0, k0); ASN_GL1(X, 1, k0); };
+    auto gloadY = [&](int k0) { ASN_GL1(Y, 0, k0); ASN_GL1(Y, 1, k0); };
+    auto lstoreX = [&](int b) { ASN_LS1(X, 0, b); ASN_LS1(X, 1, b); };
+    auto lstoreY = [&](int b) { ASN_LS1(Y, 0, b); ASN_LS1(Y, 1, b); };
 #undef ASN_GL1
 #undef ASN_LS1
 
@@ -161,18 +150,14 @@ void gemm_f32_kernel(BatchArgs B) {
     const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
     const ASN_G int* __restrict__ mlist = klist + ktab[mtiles];
     const int nkt = ktab[mt + 1] - ktab[mt];
-    if (nkt > 0) {
-        gload(klist[0] * kBK);
-        lstore(0);
-    }
-    __syncthreads();
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int b = kt & 1;
+    // products of visited step kt from LDS buffer b (none for kt = nkt, the padding
+    // step of an odd count)
+    auto mma = [&](int kt, int b) {
         // this wave's 64 ordinates: bit 4 i + g for sub-block i and k-group g (4 k each)
         // (wave-uniform: kept in a scalar register, tested with scalar branches)
-        const unsigned wmask = (unsigned)__builtin_amdgcn_readfirstlane(
-            (int)(((unsigned)mlist[kt] >> (16 * (wave & 1))) & 0xFFFFu));
-        if (kt + 1 < nkt) gload(klist[kt + 1] * kBK);
+        const unsigned m = kt < nkt ? (unsigned)mlist[kt] : 0u;
+        const unsigned wmask =
+            (unsigned)__builtin_amdgcn_readfirstlane((int)((m >> (16 * (wave & 1))) & 0xFFFFu));
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 4) {
             float av[4], bv[4];
@@ -198,8 +183,42 @@ void gemm_f32_kernel(BatchArgs B) {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
             }
         }
-        if (kt + 1 < nkt) lstore(b ^ 1);
+    };
+    if constexpr (FUSED) {
+        // one step in flight: loaded during the products of the previous one
+        if (nkt > 0) {
+            gloadX(klist[0] * kBK);
+            lstoreX(0);
+        }
         __syncthreads();
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int b = kt & 1;
+            if (kt + 1 < nkt) gloadX(klist[kt + 1] * kBK);
+            mma(kt, b);
+            if (kt + 1 < nkt) lstoreX(b ^ 1);
+            __syncthreads();
+        }
+    } else {
+        // two steps in flight: set X holds even steps, set Y odd ones; a step's
+        // registers are loaded two product phases before they go to LDS.  The loop is
+        // entered, and goes round, with both sets in flight, the one stored next the
+        // older, and has no conditional store or exit, so every wait counts only the
+        // older set.  Loads past the last step repeat it; an odd count ends with a
+        // padding step that multiplies nothing.
+        if (nkt > 0) {
+            gloadX(klist[0] * kBK);
+            gloadY(klist[min(1, nkt - 1)] * kBK);
+        }
+        for (int kt = 0; kt < nkt; kt += 2) {
+            lstoreX(0);
+            __syncthreads();
+            gloadX(klist[min(kt + 2, nkt - 1)] * kBK);
+            mma(kt, 0);
+            lstoreY(1);
+            __syncthreads();
+            gloadY(klist[min(kt + 3, nkt - 1)] * kBK);
+            mma(kt + 1, 1);
+        }
     }
     // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16.
     if constexpr (!FUSED) {
@@ -498,6 +517,8 @@ void gemm_lp_kernel(BatchArgs B) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Only k-steps whose T(K) tile has a nonzero entry (whole tiles are multiplied:
+    // tests per operand block cost more issue slots than the products they skip).
     const ASN_G int* __restrict__ klist = ktab + (mtiles + 1) + ktab[mt];
     const int nkt = ktab[mt + 1] - ktab[mt];
     if (nkt > 0) {

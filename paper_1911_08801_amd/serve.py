@@ -67,14 +67,17 @@ class GpuBackend:
         grid = a.make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
         quad = a.asn_quadrature(spec.n_polar, spec.n_azim, 0, None, None,
                                 getattr(spec, "ico_order", 0))
-        return a.asn_workspace_size(grid, quad, a.make_options(dtype, cfl=spec.cfl, scheme=scheme))
+        # batched problems share one kernel form: the fused one, at every size
+        return a.asn_workspace_size(grid, quad, a.make_options(dtype, cfl=spec.cfl, scheme=scheme,
+                                                               unfused=False))
 
     def free_bytes(self) -> int:
         return int(self.torch.cuda.mem_get_info()[0])
 
     def create(self, spec, dtype: str, scheme: str = "euler"):
         with self.torch.cuda.stream(self.stream):
-            p = self.asn.from_spec(spec, dtype=dtype, scheme=scheme, dt_rule=self.dt_rule)
+            p = self.asn.from_spec(spec, dtype=dtype, scheme=scheme, dt_rule=self.dt_rule,
+                                   unfused=False)
         return p, self.asn.asn_info(p)["steps_to_tfinal"]
 
     def make_batch(self, handles):

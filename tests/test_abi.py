@@ -168,6 +168,28 @@ def test_create_rejects_unknown_scheme():
     assert e - f > 0.95 * plane
 
 
+def test_step_form_choice_by_size_and_operand_type():
+    # the automatic form: FP32 from 2^25 cell-ordinates runs separate kernels (its
+    # workspace holds the contraction output Y), smaller problems, 16-bit operands and
+    # grids wider than the flat stencil fuse; the explicit forms are taken as asked
+    def ws(nx, ny, n_polar, dtype="f32", unfused=None):
+        g = asn.make_grid(nx, ny, 0.0, 1.0, 0.0, 1.0)
+        q = asn.asn_quadrature(n_polar, 2 * n_polar, 0, None, None, 0)
+        return asn.asn_workspace_size(g, q, asn.make_options(dtype=dtype, unfused=unfused))
+    for nx, ny, npol, dtype, sep in ((400, 400, 16, "f32", True), (128, 128, 16, "f32", False),
+                                     (400, 400, 16, "bf16", False), (5000, 20, 16, "f32", False),
+                                     (256, 256, 16, "f32", True), (255, 256, 16, "f32", False)):
+        auto = ws(nx, ny, npol, dtype)
+        assert auto == ws(nx, ny, npol, dtype, unfused=sep)
+        assert auto != ws(nx, ny, npol, dtype, unfused=not sep)
+    opt = asn.make_options()
+    opt.step_form = 3
+    g = asn.make_grid(8, 8, 0.0, 1.0, 0.0, 1.0)
+    q = asn.asn_quadrature(2, 4, 0, None, None, 0)
+    with pytest.raises(asn.AsnError):
+        asn.asn_workspace_size(g, q, opt)
+
+
 def test_destroy_accepts_null_and_status_strings():
     assert asn._lib.asn_destroy(None) == asn.ASN_OK
     for s in range(-6, 1):

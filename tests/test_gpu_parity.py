@@ -263,3 +263,19 @@ def test_contraction_work_reports_skipped_zero_tiles():
     blocks = (K.reshape(32, 16, 128, 4) != 0).any(axis=(1, 3)).sum()
     assert work["tile_flops"] == 2.0 * blocks * 64 * 256
     assert 0.15 * work["dense_flops"] < work["tile_flops"] < 0.3 * work["dense_flops"]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_contraction_work_reduced_precision_blocks(dtype):
+    # 16-bit operands: the kernel multiplies the whole 128 x 32 tiles of T(K) (128
+    # ordinates x one 32-ordinate k-step) that hold a nonzero 16-bit pattern
+    spec = wl.line_source(16, n_polar=16, sigma_as=5.0)
+    p = asn.from_spec(spec, dtype=dtype)
+    work = asn.asn_contraction_work(p)
+    p.close()
+    om, w = asn.asn_build_quadrature(16, 32)
+    K = asn.asn_build_kernel(om, w, spec.beta / 512)
+    bits, _ = asn.asn_build_kernel_lowp(K, dtype)
+    tiles = ((bits & 0x7FFF) != 0).reshape(4, 128, 16, 32).any(axis=(1, 3)).sum()
+    assert work["tile_flops"] == 2.0 * tiles * 128 * 32 * 256
+    assert work["tile_flops"] < 0.5 * work["dense_flops"]

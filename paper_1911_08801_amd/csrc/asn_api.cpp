@@ -539,7 +539,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                                    : Kt[(size_t)k * L.Qp + m] != 0.f)
                             mask |= L.lowp ? 1u << ((m - m0) / 16) : 1u << (4 * ((m - m0) / 16) + (k - k0) / 4);
                 if (mask) {
-                    const bool is_own = k0 >= m0 && k0 < m0 + asn::kGemmBM;
+                    const bool is_own = L.fused && k0 >= m0 && k0 < m0 + asn::kGemmBM;
                     (is_own ? own : entries).push_back(kt);
                     (is_own ? own_mask : masks).push_back((int)mask);
                     // K entries the kernel multiplies: whole tiles (16-bit operands) or

@@ -1065,7 +1065,9 @@ template <bool LP>
 __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(BatchArgs B) {
     constexpr int T = kFlatThreads, L = kFlatCells, NR = kFlatRounds, J = L / T;
     int pi, local;
-    if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
+    // consecutive chunks on one XCD: the rows a chunk stages beyond its own cells are
+    // its neighbours' cells, read at about the same time through the same L2
+    if (!locate(B, KT_SC, xcd_remap(blockIdx.x, gridDim.x), pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const int tiles = a.tiles_x;
     const int bt = local % tiles, g = local / tiles;
@@ -1082,6 +1084,7 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
     double phacc[J];
     int e_in = 0;      // 4 bits per cell: boundary faces as the bits of the direction code
     int live = 0;      // bit j: cell j is a grid cell (not padding)
+    int wedge = 0;     // bit j: some lane of the wave holds a boundary cell j (uniform)
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int c = b0 + tid + T * j;
@@ -1104,6 +1107,7 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
                       (y == ny - 1 ? 8 : 0);
         e_in |= e << (4 * j);
         live |= in ? 1 << j : 0;
+        wedge |= __ballot(in && e != 0) ? 1 << j : 0;
     }
     double defect = 0.0, outflow = 0.0;
 
@@ -1131,13 +1135,17 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
     };
     __shared__ float4 seg[2][NR * T];
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
-    auto body = [&](int q, const QInfo& qc, const Plane& cur) {
+    // stage: the plane's segment into LDS buffer q & 1 (consumes the slot's segment)
+    auto stage = [&](int q, const Plane& cur) {
         float4* sq = seg[q & 1];
 #pragma unroll
         for (int r = 0; r < NR; ++r) sq[tid + T * r] = cur.r[r];
+    };
+    // compute: the update of plane q from LDS buffer q & 1 and the slot's Y values
+    auto compute = [&](int q, const QInfo& qc, const Plane& cur) {
         lds_barrier();
         const int d = qc.dir;
-        const float* sf = reinterpret_cast<const float*>(sq) + (b0 - seg_start(d) + tid);
+        const float* sf = reinterpret_cast<const float*>(seg[q & 1]) + (b0 - seg_start(d) + tid);
         const __amdgpu_buffer_rsrc_t ro = plane_rsrc(a.psi_new + (size_t)q * a.P, a.P);
         const int ysh = (d & 4) ? -nx : nx;   // y-upwind cell (cy = 0 when d & 12 = 0)
         const int xsh = (d & 1) ? -1 : 1;     // x-upwind cell (cx = 0 when d & 3 = 0)
@@ -1157,27 +1165,34 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
             store_plane(nv, ro, off[j]);
             phacc[j] += qc.w * (double)nv;
             colsum += in ? col : 0.f;
-            const int go = dout & e;
-            o += in ? ((go & 3) ? qc.cx * v : 0.f) + ((go & 12) ? qc.cy * v : 0.f) : 0.f;
+            if ((wedge >> j) & 1) {   // only waves holding a boundary cell j
+                const int go = dout & e;
+                o += in ? ((go & 3) ? qc.cx * v : 0.f) + ((go & 12) ? qc.cy * v : 0.f) : 0.f;
+            }
             if (LP) mx[j] = fmaxf(mx[j], fabsf(nv));
         }
         defect += qc.w * (double)colsum;
         outflow += qc.w * (double)o;
     };
-    // two plane slots used alternately, loads unconditional (as in stream + collide)
+    // two plane slots used alternately, loads unconditional (as in stream + collide).
+    // Loads and stores share one counter, so the wait for a slot also waits for loads
+    // issued after it: more slots or planes per wait did not help (measured).
+    const int ql = max(q1 - 1, 0);
     Plane pa, pb;
-    QInfo qa = qtab[min(q0, a.Q - 1)], qb;
-    load(min(q0, a.Q - 1), qa.dir, pa);
+    QInfo qa = qtab[min(q0, ql)], qb;
+    load(min(q0, ql), qa.dir, pa);
     for (int q = q0; q < q1; q += 2) {
-        const int qn = min(q + 1, q1 - 1);
+        const int qn = min(q + 1, ql);
         qb = qtab[qn];
         load(qn, qb.dir, pb);
-        body(q, qa, pa);
+        stage(q, pa);
+        compute(q, qa, pa);
         if (q + 1 >= q1) break;
-        const int qn2 = min(q + 2, q1 - 1);
+        const int qn2 = min(q + 2, ql);
         qa = qtab[qn2];
         load(qn2, qa.dir, pa);
-        body(q + 1, qb, pb);
+        stage(q + 1, pb);
+        compute(q + 1, qb, pb);
     }
 #pragma unroll
     for (int j = 0; j < J; ++j)
@@ -1435,7 +1450,9 @@ template <bool LP, int STAGE>
 __global__ __launch_bounds__(kFlatThreads) void muscl_flat_kernel(BatchArgs B) {
     constexpr int T = kFlatThreads, L = kFlatCells, NR = kFlatRounds, J = L / T;
     int pi, local;
-    if (!locate(B, KT_SC, blockIdx.x, pi, local)) return;
+    // consecutive chunks on one XCD: the rows a chunk stages beyond its own cells are
+    // its neighbours' cells, read at about the same time through the same L2
+    if (!locate(B, KT_SC, xcd_remap(blockIdx.x, gridDim.x), pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const int tiles = a.tiles_x;
     const int bt = local % tiles, g = local / tiles;

@@ -66,14 +66,15 @@ __device__ __forceinline__ StepArgs args_of(const BatchArgs& B, int i) {
 // ---------------------------------------------------------------------------
 // 1a. FP32 contraction Y[q][c] = sum_p K[q][p] psi[p][c] on MFMA 16x16x4 f32.
 //     Block tile 128 (ordinates) x 128 (cells), k-step 16, 4 waves of 64x64.
-//     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q read as 0.
-//     Only k-steps whose K tile has a nonzero are visited, and in those each wave
-//     multiplies only the 16-ordinate x 4 blocks of its 64 rows that have one.
+//     Kt is K transposed and zero-padded to Qp x Qp; psi rows >= Q meet zero rows
+//     of Kt.  Only k-steps whose K tile has a nonzero are visited, and in those
+//     each wave multiplies only the 16-ordinate x 4 blocks of its 64 rows that
+//     have one.  The products are taken with the operands swapped (Y^T = Psi^T
+//     K^T), so each lane's accumulator holds four consecutive cells of one
+//     ordinate: Y is stored as float4 rows.
 //     FUSED: the forward-Euler stream + collide update is applied in the
-//     epilogue instead of storing Y.  The products are taken with the operands
-//     swapped (Y^T = Psi^T K^T), so each lane's accumulator holds four
-//     consecutive cells of one ordinate: the lane reads their old values and
-//     upwind neighbours as aligned float4 rows, writes psi^{n+1} as a float4
+//     epilogue instead of storing Y: the lane reads the old values and upwind
+//     neighbours of its cells as aligned float4 rows, writes psi^{n+1} as a float4
 //     (two cell groups, the halves of one 128-byte line, stored together), and
 //     the block emits the Phi partial of its 128 ordinates for its 128 cells
 //     plus its budget partials.  Y never reaches memory.
@@ -152,10 +153,11 @@ void gemm_f32_kernel(BatchArgs B) {
     const int nkt = ktab[mt + 1] - ktab[mt];
     // products of visited step kt from LDS buffer b (none for kt = nkt, the padding
     // step of an odd count)
-    auto mma = [&](int kt, int b) {
+    // mask of visited step kt (0 for the padding step kt = nkt)
+    auto step_mask = [&](int kt) { return kt < nkt ? (unsigned)mlist[kt] : 0u; };
+    auto mma = [&](unsigned m, int b) {
         // this wave's 64 ordinates: bit 4 i + g for sub-block i and k-group g (4 k each)
         // (wave-uniform: kept in a scalar register, tested with scalar branches)
-        const unsigned m = kt < nkt ? (unsigned)mlist[kt] : 0u;
         const unsigned wmask =
             (unsigned)__builtin_amdgcn_readfirstlane((int)((m >> (16 * (wave & 1))) & 0xFFFFu));
 #pragma unroll
@@ -166,22 +168,14 @@ void gemm_f32_kernel(BatchArgs B) {
             for (int i = 0; i < 4; ++i) av[i] = As[b][kr][wm + i * 16 + cl];
 #pragma unroll
             for (int j = 0; j < 4; ++j) bv[j] = Bs[b][kr][wn + j * 16 + cl];
-            if constexpr (FUSED) {
-                // rows = cells (bv), columns = ordinates (av)
+            // rows = cells (bv), columns = ordinates (av): acc[i][j] holds cells block i of
+            // ordinate block j, four consecutive cells of one ordinate per lane
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (wmask & (1u << (4 * j + kk / 4)))
+            for (int j = 0; j < 4; ++j)
+                if (wmask & (1u << (4 * j + kk / 4)))
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[i], av[j], acc[i][j], 0, 0, 0);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (wmask & (1u << (4 * i + kk / 4)))
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-            }
+                    for (int i = 0; i < 4; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[i], av[j], acc[i][j], 0, 0, 0);
         }
     };
     if constexpr (FUSED) {
@@ -194,7 +188,7 @@ void gemm_f32_kernel(BatchArgs B) {
         for (int kt = 0; kt < nkt; ++kt) {
             const int b = kt & 1;
             if (kt + 1 < nkt) gloadX(klist[kt + 1] * kBK);
-            mma(kt, b);
+            mma(step_mask(kt), b);
             if (kt + 1 < nkt) lstoreX(b ^ 1);
             __syncthreads();
         }
@@ -205,33 +199,47 @@ void gemm_f32_kernel(BatchArgs B) {
         // older, and has no conditional store or exit, so every wait counts only the
         // older set.  Loads past the last step repeat it; an odd count ends with a
         // padding step that multiplies nothing.
+        // The step numbers and masks (scalar loads) are fetched one use ahead, so no
+        // step waits on a scalar load issued in it.
         if (nkt > 0) {
             gloadX(klist[0] * kBK);
             gloadY(klist[min(1, nkt - 1)] * kBK);
         }
+        int kx = klist[min(2, max(nkt - 1, 0))], ky = klist[min(3, max(nkt - 1, 0))];
+        unsigned mx = step_mask(0), my = step_mask(1);
         for (int kt = 0; kt < nkt; kt += 2) {
             lstoreX(0);
             __syncthreads();
-            gloadX(klist[min(kt + 2, nkt - 1)] * kBK);
-            mma(kt, 0);
+            gloadX(kx * kBK);
+            kx = klist[min(kt + 4, nkt - 1)];
+            mma(mx, 0);
+            mx = step_mask(kt + 2);
             lstoreY(1);
             __syncthreads();
-            gloadY(klist[min(kt + 3, nkt - 1)] * kBK);
-            mma(kt + 1, 1);
+            gloadY(ky * kBK);
+            ky = klist[min(kt + 5, nkt - 1)];
+            mma(my, 1);
+            my = step_mask(kt + 3);
         }
     }
-    // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16.
+    // D layout of the 16x16 MFMA: lane holds rows 4 (lane / 16) + v, column lane % 16, so
+    // acc[i][j] is cells n0 + wn + 16 i + 4 (lane / 16) + v of ordinate m0 + wm + 16 j +
+    // lane % 16.
     if constexpr (!FUSED) {
+        // one float4 store per cell group; groups i and i + 1 (the halves of a 128-byte
+        // line of the ordinate's row) back to back
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            const int q = m0 + wm + j * 16 + (lane & 15);
+            if (q < Q) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + v;
-                    const int64_t n = n0 + wn + j * 16 + (lane & 15);
-                    if (m < Q) Y[(size_t)m * P + n] = acc[i][j][v];
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t c0 = n0 + wn + i * 16 + 4 * (lane >> 4);
+                    *reinterpret_cast<ASN_G float4*>(Y + (size_t)q * P + c0) =
+                        make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
                 }
+            }
+        }
     } else {
         const int nx = a.nx, ny = a.ny;
         const int64_t C = a.C;

@@ -248,6 +248,12 @@ asn_status asn_scalar_flux(asn_problem p, double* phi_host);
  * Errors: ASN_E_UNSTABLE if the mass is not finite, ASN_E_HIP. */
 asn_status asn_mass_budget(asn_problem p, double out[ASN_BUDGET_LEN]);
 
+/* Kernel form of the problem's steps: ASN_FORM_FUSED or ASN_FORM_SEPARATE (what
+ * ASN_FORM_AUTO chose at asn_create; Heun and implicit steps report
+ * ASN_FORM_SEPARATE).  Problems of one batch must share it.  Errors: ASN_E_INVALID
+ * for a NULL argument. */
+asn_status asn_step_form(asn_problem p, int32_t* form);
+
 /* Problem facts: time step, steps taken, steps to t_final, ordinate count.
  * Any output pointer may be NULL. */
 asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* steps_to_tfinal,

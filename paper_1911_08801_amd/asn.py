@@ -97,6 +97,7 @@ _SIG = {
     "asn_scalar_flux": [_P, _D],
     "asn_mass_budget": [_P, _D],
     "asn_info": [_P, _D, _I64, _I64, ctypes.POINTER(ctypes.c_int32)],
+    "asn_step_form": [_P, ctypes.POINTER(ctypes.c_int32)],
     "asn_destroy": [_P],
     "asn_contraction_work": [_P, _D, _D],
     "asn_stability": [_P, _D],
@@ -404,6 +405,13 @@ def asn_info(p: AsnProblem) -> dict:
     _check(_lib.asn_info(p.handle, ctypes.byref(dt), ctypes.byref(done), ctypes.byref(tot),
                          ctypes.byref(q)), "asn_info")
     return {"dt": dt.value, "steps_done": done.value, "steps_to_tfinal": tot.value, "q": q.value}
+
+
+def asn_step_form(p: AsnProblem) -> str:
+    """Kernel form of the problem's steps: "fused" or "separate"."""
+    f = ctypes.c_int32()
+    _check(_lib.asn_step_form(p.handle, ctypes.byref(f)), "asn_step_form")
+    return "fused" if f.value == ASN_FORM_FUSED else "separate"
 
 
 def asn_iteration_counts(p: AsnProblem) -> dict:

@@ -992,6 +992,12 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
     return ASN_OK;
 }
 
+asn_status asn_step_form(asn_problem p, int32_t* form) {
+    if (!p || !form) return fail(ASN_E_INVALID, "NULL argument");
+    *form = p->L.fused ? ASN_FORM_FUSED : ASN_FORM_SEPARATE;
+    return ASN_OK;
+}
+
 asn_status asn_iteration_counts(asn_problem p, int64_t* sweeps, int64_t* matvecs) {
     if (!p) return fail(ASN_E_INVALID, "problem is NULL");
     if (sweeps) *sweeps = p->imp ? p->imp->sweeps : 0;

@@ -106,3 +106,16 @@ def test_problem_can_step_alone_between_batch_steps():
         for p, a in zip(probs, alone):
             assert np.array_equal(asn.asn_get_state(p), a[0])
             p.close()
+
+
+def test_step_form_reports_the_library_choice():
+    big = wl.line_source(256, n_polar=16, t_final=0.02)      # 2^25 cell-ordinates
+    small = wl.line_source(48, n_polar=8, t_final=0.05)
+    for spec, kw, want in ((big, {}, "separate"), (small, {}, "fused"),
+                           (big, {"unfused": False}, "fused"), (small, {"unfused": True}, "separate"),
+                           (big, {"dtype": "bf16"}, "fused"), (small, {"scheme": "heun"}, "separate")):
+        p = asn.from_spec(spec, **kw)
+        try:
+            assert asn.asn_step_form(p) == want, (spec.name, kw)
+        finally:
+            p.close()

@@ -43,6 +43,23 @@ def test_each_result_equals_the_request_alone(mixed):
         assert j.budget["steps"] == j.steps_total
 
 
+def test_large_and_small_requests_share_the_fused_form():
+    # a request of 2^25 cell-ordinates would run separate kernels alone; the server
+    # asks for the fused form so that it batches with the small ones
+    big = [wl.line_source(256, n_polar=16, sigma_as=5.0, t_final=0.02) for _ in range(2)]
+    small = [wl.line_source(48, n_polar=8, sigma_as=5.0, t_final=0.05) for _ in range(3)]
+    jobs = [Job(rid=k, spec=s, arrival=0.0) for k, s in enumerate(big + small)]
+    rep = Server(GpuBackend(), hbm_budget=4 * 1024 ** 3, max_slots=8, chunk=4).serve(jobs)
+    assert all(j.status == "done" for j in rep.jobs)
+    assert [j.form for j in rep.jobs] == ["fused"] * 5
+    for j in rep.jobs:
+        p = asn.from_spec(j.spec, dt_rule="stiff", unfused=False)
+        asn.asn_step(p, j.steps_total)
+        alone = asn.asn_scalar_flux(p)
+        p.close()
+        assert np.array_equal(j.phi, alone), j.rid
+
+
 def test_unstable_request_fails_alone_and_others_finish():
     jobs = _jobs(12, 5, False)
     # a NaN source makes one request blow up; the library rejects NaN fields, so

@@ -44,8 +44,12 @@ class FakeBackend:
         self.peak = max(self.peak, self.used)
         self.created.append((dtype, scheme))
         h = FakeHandle(spec, max(1, int(round(spec.t_final * 20))))
-        self.kinds[id(h)] = (dtype, scheme)
+        self.kinds[id(h)] = (dtype, scheme, self.form(h))
         return h, h.total
+
+    def form(self, h):
+        # stands in for the library's size rule
+        return "separate" if h.spec.nx * h.spec.ny >= 300 else "fused"
 
     def make_batch(self, handles):
         assert len({self.kinds.get(id(h)) for h in handles}) == 1
@@ -157,6 +161,17 @@ def test_cancellation_releases_the_request():
     st = {j.rid: j.status for j in rep.jobs}
     assert st[jobs[0].rid] == "cancelled" and be.used == 0
     assert sum(v == "done" for v in st.values()) == 5
+
+
+def test_batches_never_mix_kernel_forms():
+    clk = Clock()
+    be = FakeBackend(clk)
+    jobs = _jobs(24, seed=5, rate=100.0)
+    forms = {be.form(FakeHandle(j.spec, 1)) for j in jobs}
+    assert forms == {"fused", "separate"}          # the stream holds both kinds
+    rep = Server(be, hbm_budget=10 ** 9, chunk=4, clock=clk, sleep=clk.sleep).serve(jobs)
+    assert all(j.status == "done" for j in rep.jobs)
+    assert {j.form for j in rep.jobs} == {"fused", "separate"}
 
 
 def test_batches_never_mix_operand_types_or_schemes():

@@ -187,8 +187,9 @@ asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps);
 /* A batch groups 1..64 problems for fused stepping: every kernel of a step covers
  * all of them in one launch.  Problems keep their own grid, ordinates, kernel
  * matrix and buffers (ordinate counts may differ); they must share the operand
- * type, the time scheme, the fusion option and the HIP stream.  The batch holds
- * small device tables (hipMalloc).
+ * type, the time scheme, the kernel form (asn_step_form: with ASN_FORM_AUTO it
+ * follows the problem size, so ask for one form for problems of different sizes)
+ * and the HIP stream.  The batch holds small device tables (hipMalloc).
  * A problem may be stepped alone while in a batch; the batch reads each
  * problem's current buffer at every asn_batch_step.  Errors: ASN_E_INVALID,
  * ASN_E_OOM, ASN_E_HIP. */

@@ -820,7 +820,9 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
         if (probs[i]->imp)
             return fail(ASN_E_UNSUPPORTED, "implicit problems step alone (asn_step)");
         if (probs[i]->L.fused != probs[0]->L.fused)
-            return fail(ASN_E_INVALID, "problems of a batch must share the kernel fusion option");
+            return fail(ASN_E_INVALID, "problems of a batch must share the kernel form "
+                                       "(asn_step_form; ask for ASN_FORM_FUSED or ASN_FORM_SEPARATE "
+                                       "when their sizes differ)");
         if (probs[i]->L.flat != probs[0]->L.flat)
             return fail(ASN_E_INVALID, std::string("problems of a batch must share the stencil form: ") +
                                        "separate-kernel steps use flat cell chunks up to nx = " +

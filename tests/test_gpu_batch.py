@@ -81,6 +81,26 @@ def test_batch_rejects_mixed_separate_stencil_forms():
             p.close()
 
 
+def test_batch_of_sizes_with_different_automatic_forms():
+    # the automatic form follows the size: a 2^25 cell-ordinate problem runs separate
+    # kernels, a small one fused; they batch once both ask for the same form
+    big = wl.line_source(256, n_polar=16, t_final=0.02)
+    small = wl.line_source(48, n_polar=16, t_final=0.02)
+    a1, a2 = asn.from_spec(big), asn.from_spec(small)
+    f1, f2 = asn.from_spec(big, unfused=False), asn.from_spec(small, unfused=False)
+    try:
+        with pytest.raises(asn.AsnError):
+            asn.asn_batch_create([a1, a2])
+        b = asn.asn_batch_create([f1, f2])
+        asn.asn_batch_step(b, 2)
+        b.close()
+        asn.asn_step(a2, 2)                          # the small one fuses either way
+        assert np.array_equal(asn.asn_scalar_flux(f2), asn.asn_scalar_flux(a2))
+    finally:
+        for p in (a1, a2, f1, f2):
+            p.close()
+
+
 def test_step_batch_one_shot_matches_alone():
     specs = _specs()[:2]
     alone = [_alone(s, 6, "f32") for s in specs]

@@ -206,16 +206,18 @@ def test_cfl_above_one_is_rejected():
 
 # ---------------------------------------------------------------- full-size sampled parity
 
-def _sampled_one_step(spec, seed, n_samples=400):
+def _sampled_one_step(spec, seed, n_samples=400, unfused=None):
     """One step at full size on a structured anisotropic state; the oracle
-    evaluates sampled entries one by one (plus every corner / edge class)."""
+    evaluates sampled entries one by one (plus every corner / edge class).
+    unfused: None takes the kernel form the library chooses (separate at these
+    sizes), False / True ask for the fused / separate form."""
     rng = np.random.default_rng(seed)
     Q, ny, nx = spec.q, spec.ny, spec.nx
     a1 = (0.5 + rng.random(Q)).astype(np.float32)
     a2 = rng.standard_normal(Q).astype(np.float32) * np.float32(0.3)
     psi0 = (a1[:, None, None] * spec.psi0_cell[None] + a2[:, None, None]
             * np.float32(spec.psi0_cell.mean())).astype(np.float32)
-    p = asn.from_spec(spec, set_initial_state=False)
+    p = asn.from_spec(spec, set_initial_state=False, unfused=unfused)
     asn.asn_set_state(p, psi0)
     asn.asn_step(p, 1)
     got = asn.asn_get_state(p)
@@ -237,9 +239,10 @@ def _sampled_one_step(spec, seed, n_samples=400):
 
 
 @pytest.mark.slow
-def test_full_size_400_q512_one_step_sampled():
+@pytest.mark.parametrize("unfused", [None, False])
+def test_full_size_400_q512_one_step_sampled(unfused):
     spec = wl.line_source(400, n_polar=16, sigma_as=5.0)
-    assert _sampled_one_step(spec, 1) <= 4e-6
+    assert _sampled_one_step(spec, 1, unfused=unfused) <= 4e-6
 
 
 @pytest.mark.slow

@@ -865,7 +865,8 @@ __device__ __forceinline__ void block_sum_waves(double (&v)[NV], OutPtr out) {
 //    one halo row per wave; along x: the neighbouring lane (shuffle).
 //    Memory goes through buffer descriptors of one ordinate plane each: offsets
 //    outside the grid read as 0 (the vacuum ghost value) and stores to them are
-//    dropped, so the loop has no per-cell branches.
+//    dropped, so the loop has no per-cell branches.  Runs for grids wider than the
+//    flat-chunk form takes (stream_collide_flat_kernel, below).
 //      col  = dt sigma_as (Y - fix - psi) + dt sigma_s (Phi/W - psi)
 //      new  = psi - cx (psi - up_x) - cy (psi - up_y) - dt sigma_a psi + col + dt q
 //    LP: fix is the per-cell particle correction of the reduced-precision Y, and
@@ -1223,9 +1224,10 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
 //     Per ordinate and axis a cell's slope is minmod(psi_i - psi_{i-1},
 //     psi_{i+1} - psi_i); a face carries the value reconstructed on its upwind
 //     side, psi_i + s_i / 2 or psi_{i+1} - s_{i+1} / 2, and cells outside the
-//     grid read 0 (vacuum, also for their slopes).  Same block shape as above,
-//     with a strip of 60 columns: lane l holds column x0 + l - 2, lanes 2..61
-//     update, and each wave reads two halo rows on each side.
+//     grid read 0 (vacuum, also for their slopes).  Same block shape as
+//     stream_collide_kernel, with a strip of 60 columns: lane l holds column
+//     x0 + l - 2, lanes 2..61 update, and each wave reads two halo rows on each side.
+//     Runs for grids wider than the flat-chunk form takes (muscl_flat_kernel).
 //       STAGE 1: out = psi + dt R(psi)                 (psi^n  -> psi^1)
 //       STAGE 2: out = (old + psi + dt R(psi)) / 2     (psi^1, old = psi^n)
 //     In stage 2 the output buffer holds psi^n: every lane reads its own cell

@@ -134,29 +134,38 @@ __device__ __forceinline__ double wave_shr1(double v) {
 // previous results and its y-upwind neighbours are those of lanes j - 1 and j - 2:
 // lane j - 1's value comes by a lane shift of the current step, lane j - 2's is what
 // lane j - 1 received one step earlier.  The block's W waves take W consecutive strips
-// at once, wave w starting 64 steps after wave w - 1 (a wavefront over strips): lanes
-// 0 and 1 of wave w then read the rows 62 and 63 of wave w - 1 that were written to
-// LDS one and two block steps before, with a barrier after every block step.  The last
-// strip of a round of W strips keeps its two downwind rows for the next round.
-// Everything a step reads that does not depend on the sweep (right-hand side and
-// coefficients) is fetched kSweepAhead steps ahead into a register ring, so the
-// dependent chain of a step is the update and one lane shift.
+// at once, wave w starting 72 steps after wave w - 1 (a wavefront over strips): the
+// rows 62 and 63 of wave w - 1 that lane 0 of wave w needs in a window of 8 steps were
+// written to an LDS ring at least two block steps before the window starts, so lane 0
+// reads them at the window start and the block synchronises once per window, not per
+// step.  The last strip of a round of W strips keeps its two downwind rows for the
+// next round.
+// The cells a wave touches in one step lie on a diagonal (one per row), so its inputs
+// (right-hand side and rate) and outputs go through LDS in windows of 8 steps: for each
+// row the 8 cells of a window are consecutive, and 8 lanes move them as one 64-byte
+// segment (a window is loaded 8 steps before it is used and its results are stored 8
+// steps after), instead of every load and store of a step touching 64 cache lines.
 // Block barrier that orders LDS only: the sweep's waves exchange rows through LDS, and
-// a full barrier would also wait for every global load in flight (the prefetch ring).
+// a full barrier would also wait for every global load in flight (the next window).
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int kSweepAhead = 8;
-constexpr int kSweepWaves = 8;    // strips in flight per ordinate
-constexpr int kSweepRing = 8;     // columns of a strip's rows 62, 63 kept for the next wave
+constexpr int kSweepAhead = 8;    // steps per staged window
+constexpr int kSweepWaves = 8;    // strips in flight per ordinate (at most)
+constexpr int kSweepRing = 32;    // columns of a strip's rows 62, 63 kept for the next wave
+constexpr int kSweepLag = 64 + kSweepAhead;   // steps between the starts of waves w - 1, w
+constexpr int kSweepWinPitch = kSweepAhead + 1;                  // padded LDS row (doubles)
+constexpr int kSweepWinDoubles = 3 * 64 * kSweepWinPitch;        // inputs x 2, outputs
 __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a) {
-    extern __shared__ double rowbuf[];      // [2 parity][2 rows][nx]
+    extern __shared__ double smem[];   // [2 parity][2 rows][nx], then [W][3][64][pitch]
     __shared__ double ring[kSweepWaves][2][kSweepRing];
-    constexpr int D = kSweepAhead;
-    static_assert(64 % D == 0 && kSweepRing >= 4, "wave start offsets must keep the ring slots");
+    constexpr int D = kSweepAhead, DP = kSweepWinPitch;
+    // the slot u = tau mod D is the same for every wave (kSweepLag is a multiple of D);
+    // wave w - 1 writes ring column k + kSweepRing 23 block steps after wave w read k
+    static_assert(kSweepLag % D == 0 && kSweepRing >= 4 * D, "ring slots must outlive their reads");
     const int q = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
     const int nx = a.nx, ny = a.ny;
@@ -167,6 +176,12 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
     const double dflux = 1.5 * (ax + ay);
     const int nstrips = (ny + 63) / 64;
     const int Tw = nx + 63;   // steps of one strip
+    double* rowbuf = smem;
+    double* win_r = smem + 4 * (size_t)nx + (size_t)w * kSweepWinDoubles;   // this wave's
+    double* win_s = win_r + 64 * DP;
+    double* win_o = win_s + 64 * DP;
+    // window lanes: lane l moves column l % 8 of strip rows l / 8 + 8 i, i = 0..7
+    const int wrow = lane >> 3, wcol = lane & 7;
     int par = 0;
     for (int g0 = 0; g0 < nstrips; g0 += W) {
         const int Wg = min(W, nstrips - g0);   // strips of this round
@@ -175,48 +190,53 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
         const bool last_wave = w == Wg - 1;
         const int r = s * 64 + lane;           // row in sweep order
         const bool valid = wave_on && r < ny;
-        const int y = ypos ? r : ny - 1 - r;
         const double* prev_top = rowbuf + (size_t)(par ^ 1) * 2 * nx;   // previous round
         double* cur_top = rowbuf + (size_t)par * 2 * nx;
-        auto cell_of = [&](int k) -> int64_t {
-            const int x = xpos ? k : nx - 1 - k;
-            return (int64_t)y * nx + x;
-        };
-        // Ring slot u holds the inputs of local step tau with tau mod D = u: the lane's
-        // cell k = tau - lane (loads at clamped in-range addresses without branches, so
-        // that the compiler waits for each only where it is used).
-        double rr[D], sg[D];
-        const int yc = min(max(y, 0), ny - 1);
-        const double* rrow = rhs + (size_t)yc * nx;
-        const double* srow = a.sig + (size_t)yc * nx;
-        auto fetch = [&](int tau, int u) {
-            const int kc = min(max(tau - lane, 0), nx - 1);
-            const int x = xpos ? kc : nx - 1 - kc;
-            rr[u] = rrow[x];
-            sg[u] = srow[x];
-        };
+        auto grid_y = [&](int row) { return ypos ? row : ny - 1 - row; };
+        auto grid_x = [&](int k) { return xpos ? k : nx - 1 - k; };
+        // Window of steps T0 .. T0 + 7: strip row rl needs columns T0 - rl .. T0 - rl + 7.
+        // Loads at clamped in-range addresses (values outside the grid are not used).
+        double nr[8], ns[8];
+        auto load_win = [&](int T0) {
 #pragma unroll
-        for (int u = 0; u < D; ++u) fetch(u, u);
+            for (int i = 0; i < 8; ++i) {
+                const int rl = wrow + 8 * i;
+                const int yc = grid_y(min(s * 64 + rl, ny - 1));
+                const int kc = min(max(T0 + wcol - rl, 0), nx - 1);
+                const size_t c = (size_t)yc * nx + grid_x(kc);
+                nr[i] = rhs[c];
+                ns[i] = a.sig[c];
+            }
+        };
+        auto stage_win = [&]() {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                win_r[(wrow + 8 * i) * DP + wcol] = nr[i];
+                win_s[(wrow + 8 * i) * DP + wcol] = ns[i];
+            }
+        };
+        auto flush_win = [&](int T0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int rl = wrow + 8 * i, row = s * 64 + rl;
+                const int k = T0 + wcol - rl;
+                const double v = win_o[rl * DP + wcol];
+                if (wave_on && row < ny && k >= 0 && k < nx)
+                    out[(size_t)grid_y(row) * nx + grid_x(k)] = v;
+            }
+        };
+        load_win(0);
+        double er = 0.0, es = 0.0;         // this lane's inputs of its current step
+        double t62r[8], t63r[8];           // lane 0: rows 62, 63 above, columns of the window
         double last1 = 0.0, last2 = 0.0;   // x ghosts
         double y1prev = 0.0;               // y-upwind value this lane received last step
-        auto step = [&](int tau, double rhs_c, double sig) {
+        auto step = [&](int tau, int u) {
             const int k = tau - lane;
             double yn1 = wave_shr1(last1);    // lane - 1: row r - 1, column k
             double yn2 = wave_shr1(y1prev);   // lane - 2: row r - 2, column k
-            if (lane == 0) {
-                // rows 63 and 62 of the strip above: wave w - 1 (written one and two
-                // block steps ago), the last strip of the previous round, or ghosts
-                const bool kin = k < nx;
-                double t63 = 0.0, t62 = 0.0;
-                if (w > 0) {
-                    t63 = ring[w - 1][1][k & (kSweepRing - 1)];
-                    t62 = ring[w - 1][0][k & (kSweepRing - 1)];
-                } else if (g0 > 0) {
-                    t63 = prev_top[nx + min(k, nx - 1)];
-                    t62 = prev_top[min(k, nx - 1)];
-                }
-                yn1 = kin ? t63 : 0.0;
-                yn2 = kin ? t62 : 0.0;
+            if (lane == 0) {   // rows 63 and 62 of the strip above (read at the window start)
+                yn1 = t63r[u];
+                yn2 = t62r[u];
             }
             y1prev = yn1;
             // The history shifts every step once the lane has started, also past the
@@ -224,11 +244,10 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
             // step later than the lane just above.
             if (k >= 0) {
                 double v = 0.0;
-                if (valid && k < nx) {
-                    v = (rhs_c + ax * (2.0 * last1 - 0.5 * last2) + ay * (2.0 * yn1 - 0.5 * yn2)) /
-                        (dflux + sig);
-                    out[cell_of(k)] = v;
-                }
+                if (valid && k < nx)
+                    v = (er + ax * (2.0 * last1 - 0.5 * last2) + ay * (2.0 * yn1 - 0.5 * yn2)) /
+                        (dflux + es);
+                win_o[lane * DP + u] = v;
                 if (lane >= 62 && k < nx) {
                     ring[w][lane - 62][k & (kSweepRing - 1)] = v;
                     if (last_wave) cur_top[(size_t)(lane - 62) * nx + k] = v;
@@ -237,20 +256,53 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
                 last1 = v;
             }
         };
-        // Block step t: wave w runs its step tau = t - 64 w.  The ring slot of step tau
-        // is refilled (for tau + D) at every block step, also before the wave starts and
-        // after it ends, so that the slot registers are never merged across a branch
-        // (which would wait for the loads in flight).  Whole rounds of D block steps,
-        // then the remaining ones (the slot, tau mod D, is fixed at compile time in both
-        // loops since 64 w is a multiple of D).
+        // Block step t: wave w runs its step tau = t - 72 w (slot u = tau mod 8, fixed at
+        // compile time in the unrolled loops since 72 w is a multiple of 8).  At a window
+        // start the wave stores the results of the window before, puts this window's
+        // inputs into LDS and loads the next window.  A lane reads the inputs of its next
+        // step from LDS while the current one runs (off the steps' dependent chain).  The
+        // barrier at each window start orders the LDS traffic between waves; within a
+        // wave, LDS operations run in program order.
         auto block_step = [&](int t, int u) {
-            const int tau = t - 64 * w;
-            const double rhs_c = rr[u], sig = sg[u];
-            fetch(tau + D, u);
-            if (wave_on && tau >= 0 && tau < Tw) step(tau, rhs_c, sig);
-            lds_barrier();
+            const int tau = t - kSweepLag * w;
+            if (u == 0) {   // u is the same for every wave: all of them reach this barrier
+                const bool win_on = tau >= 0 && tau < Tw + D;
+                if (win_on) {
+                    if (tau >= D) flush_win(tau - D);
+                    if (tau < Tw) {
+                        stage_win();
+                        load_win(tau + D);
+                    }
+                }
+                lds_barrier();
+                er = win_r[lane * DP];
+                es = win_s[lane * DP];
+                // rows 63 and 62 of the strip above for the window's columns tau .. tau + 7:
+                // wave w - 1 (its ring), the last strip of the previous round, or ghosts
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const int k = tau + i;
+                    double t63 = 0.0, t62 = 0.0;
+                    if (w > 0) {
+                        t63 = ring[w - 1][1][k & (kSweepRing - 1)];
+                        t62 = ring[w - 1][0][k & (kSweepRing - 1)];
+                    } else if (g0 > 0) {
+                        t63 = prev_top[nx + min(max(k, 0), nx - 1)];
+                        t62 = prev_top[min(max(k, 0), nx - 1)];
+                    }
+                    const bool kin = k >= 0 && k < nx;
+                    t63r[i] = kin ? t63 : 0.0;
+                    t62r[i] = kin ? t62 : 0.0;
+                }
+            }
+            // inputs of the next step of this window (slot u + 1), read now
+            const double er1 = u + 1 < D ? win_r[lane * DP + u + 1] : 0.0;
+            const double es1 = u + 1 < D ? win_s[lane * DP + u + 1] : 0.0;
+            if (wave_on && tau >= 0 && tau < Tw) step(tau, u);
+            er = er1;
+            es = es1;
         };
-        const int T = Tw + 64 * (Wg - 1);
+        const int T = Tw + kSweepLag * (Wg - 1);
         int t0 = 0;
         for (; t0 + D <= T; t0 += D) {
 #pragma unroll
@@ -259,8 +311,26 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
 #pragma unroll
         for (int u = 0; u < D; ++u)
             if (t0 + u < T) block_step(t0 + u, u);
+        // the window of the wave's last block step has not been stored yet (for a window
+        // past the row's end every column is outside the grid and nothing is stored)
+        const int tau_end = T - kSweepLag * w;
+        if (tau_end > 0) flush_win(((tau_end - 1) / D) * D);
+        lds_barrier();
         par ^= 1;
     }
+}
+
+// Dynamic LDS of the sweep: two parities of two carried rows, then W wave windows.
+size_t sweep_lds_bytes(int nx, int W) {
+    return ((size_t)4 * nx + (size_t)W * kSweepWinDoubles) * sizeof(double);
+}
+// Strips in flight per ordinate: at most kSweepWaves, and as many as the LDS holds next to
+// the carried rows (nx <= 2048 keeps those within 64 KB, so one wave always fits).
+int sweep_waves(int nx, int ny) {
+    constexpr size_t kLdsBudget = 156 * 1024;   // of 160 KB, the rest for the static ring
+    int W = std::min((ny + 63) / 64, kSweepWaves);
+    while (W > 1 && sweep_lds_bytes(nx, W) > kLdsBudget) --W;
+    return W;
 }
 
 // part[b] = {sum (x - y)^2, sum x^2} over this block's elements of [n]
@@ -491,13 +561,13 @@ bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const do
     IMP_TRY(hipMemcpyAsync(small, small_h.data(), small_h.size() * 8, hipMemcpyHostToDevice, s_));
     IMP_TRY(hipMemcpyAsync(coef_, coef.data(), coef.size() * 16, hipMemcpyHostToDevice, s_));
     IMP_TRY(hipMemcpyAsync(sig_, sig.data(), sig.size() * 8, hipMemcpyHostToDevice, s_));
-    const size_t lds = (size_t)4 * p.nx * 8;
-    if (lds > 65536) {
+    if ((size_t)4 * p.nx * 8 > 65536) {
         err = "sweep LDS request too large";
         return false;
     }
     IMP_TRY(hipFuncSetAttribute((const void*)imp_sweep_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)sweep_lds_bytes(p.nx, sweep_waves(p.nx, p.ny))));
     return true;
 }
 
@@ -536,8 +606,8 @@ bool ImplicitSolver::sweep_once(const double* psi_in, double* psi_out, const dou
     imp_rhs_kernel<<<g, 256, 0, s_>>>(r);
     IMP_TRY(hipGetLastError());
     SweepArgs sa{rhs_, dir_, sig_, psi_out, p_.nx, p_.ny, p_.P};
-    const int strips = (p_.ny + 63) / 64;
-    imp_sweep_kernel<<<p_.Q, 64 * std::min(strips, kSweepWaves), (size_t)4 * p_.nx * 8, s_>>>(sa);
+    const int W = sweep_waves(p_.nx, p_.ny);
+    imp_sweep_kernel<<<p_.Q, 64 * W, sweep_lds_bytes(p_.nx, W), s_>>>(sa);
     IMP_TRY(hipGetLastError());
     ++sweeps;
     return true;

@@ -437,7 +437,7 @@ __device__ __forceinline__ f32x4 mfma_lp(const uint4& av, const uint4& bv, const
 }
 
 template <int DT, bool FUSED>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED ? 2 : 3, 3)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((FUSED || DT == 1) ? 2 : 3, 3)))
 void gemm_lp_kernel(BatchArgs B) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][kGemmBM][kRowL];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kGemmBN][kRowL];

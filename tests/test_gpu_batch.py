@@ -111,6 +111,30 @@ def test_step_batch_one_shot_matches_alone():
         p.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_separate_form_batch_matches_alone(dtype):
+    # separate kernels (flat-chunk stencil): one launch per kernel covers all problems'
+    # blocks, placed per XCD over the whole batch; each result equals the problem alone
+    specs = _specs()
+    alone = []
+    for s in specs:
+        p = asn.from_spec(s, dtype=dtype, unfused=True)
+        asn.asn_step(p, 5)
+        alone.append((asn.asn_get_state(p), asn.asn_scalar_flux(p), asn.asn_mass_budget(p)))
+        p.close()
+    probs = [asn.from_spec(s, dtype=dtype, unfused=True) for s in specs]
+    try:
+        assert {asn.asn_step_form(p) for p in probs} == {"separate"}
+        asn.asn_step_batch(probs, 5)
+        for p, a in zip(probs, alone):
+            assert np.array_equal(asn.asn_get_state(p), a[0])
+            assert np.array_equal(asn.asn_scalar_flux(p), a[1])
+            assert asn.asn_mass_budget(p)["mass"] == a[2]["mass"]
+    finally:
+        for p in probs:
+            p.close()
+
+
 def test_problem_can_step_alone_between_batch_steps():
     specs = _specs()[:3]
     alone = [_alone(s, 7, "f32") for s in specs]

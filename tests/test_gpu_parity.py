@@ -215,8 +215,10 @@ def _sampled_one_step(spec, seed, n_samples=400, unfused=None):
     Q, ny, nx = spec.q, spec.ny, spec.nx
     a1 = (0.5 + rng.random(Q)).astype(np.float32)
     a2 = rng.standard_normal(Q).astype(np.float32) * np.float32(0.3)
-    psi0 = (a1[:, None, None] * spec.psi0_cell[None] + a2[:, None, None]
-            * np.float32(spec.psi0_cell.mean())).astype(np.float32)
+    # psi0 = a1 * cell + a2 * mean, built in place (FP32 products, then FP32 sums)
+    psi0 = np.empty((Q, ny, nx), dtype=np.float32)
+    np.multiply(a1[:, None, None], spec.psi0_cell[None], out=psi0)
+    psi0 += (a2 * np.float32(spec.psi0_cell.mean()))[:, None, None]
     p = asn.from_spec(spec, set_initial_state=False, unfused=unfused)
     asn.asn_set_state(p, psi0)
     asn.asn_step(p, 1)
@@ -232,7 +234,9 @@ def _sampled_one_step(spec, seed, n_samples=400, unfused=None):
     js[:k] = np.repeat(edge[:, 0], 4)
     iis[:k] = np.repeat(edge[:, 1], 4)
     qs[:k] = np.tile([0, Q // 4 + 1, Q // 2 + 3, Q - 1], len(edge))
-    phi = np.tensordot(st.w, psi0, axes=(0, 0))
+    # the scalar flux of psi0 is needed only at the sampled cells
+    phi = np.zeros((ny, nx))
+    phi[js, iis] = st.w @ psi0[:, js, iis].astype(np.float64)
     ref = o.step_entries(psi0, st, qs, js, iis, phi=phi)
     diff = np.abs(got[qs, js, iis].astype(np.float64) - ref)
     return float(np.max(diff / np.maximum(np.abs(ref), 1e-3 * np.abs(psi0).max())))
@@ -250,6 +254,15 @@ def test_full_size_700_q1152_checkerboard_one_step_sampled():
     spec = wl.checkerboard(700, n_polar=24, sigma_as=5.0)
     spec.psi0_cell[:] = wl.random_state(5, 1, 700, 700)[0]
     assert _sampled_one_step(spec, 2, n_samples=300) <= 4e-6
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("unfused", [None, False])
+def test_full_size_1024_q2048_one_step_sampled(unfused):
+    # the largest configured problem (8 GiB a state copy): the separate kernels the
+    # library picks at this size and the fused form
+    spec = wl.line_source(1024, n_polar=32, sigma_as=5.0)
+    assert _sampled_one_step(spec, 3, n_samples=300, unfused=unfused) <= 4e-6
 
 
 def test_contraction_work_reports_skipped_zero_tiles():

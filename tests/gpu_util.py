@@ -43,3 +43,37 @@ def fp32_budget_floor(state, w):
     """Relative size of the FP32 storage rounding of the mass: 2^-24 ||w psi||_2 / ||w psi||_1."""
     wp = np.abs(state.astype(np.float64) * w[:, None, None])
     return 2.0 ** -24 * math.sqrt(float(np.sum(wp * wp))) / float(np.sum(wp))
+
+
+def structured_state(spec, rng):
+    """A full-size anisotropic state psi0 = a1_q * cell + a2_q * mean(cell) (FP32
+    products, then FP32 sums), built in place."""
+    Q, ny, nx = spec.q, spec.ny, spec.nx
+    a1 = (0.5 + rng.random(Q)).astype(np.float32)
+    a2 = rng.standard_normal(Q).astype(np.float32) * np.float32(0.3)
+    psi0 = np.empty((Q, ny, nx), dtype=np.float32)
+    np.multiply(a1[:, None, None], spec.psi0_cell[None], out=psi0)
+    psi0 += (a2 * np.float32(spec.psi0_cell.mean()))[:, None, None]
+    return psi0
+
+
+def sampled_entries(rng, Q, ny, nx, n_samples):
+    """(q, j, i) sample: uniform entries plus every corner / edge-midpoint class at
+    four ordinates (first, two interior, last)."""
+    qs = rng.integers(0, Q, n_samples)
+    js = rng.integers(0, ny, n_samples)
+    iis = rng.integers(0, nx, n_samples)
+    edge = np.array([[0, 0], [0, nx - 1], [ny - 1, 0], [ny - 1, nx - 1], [0, nx // 2],
+                     [ny // 2, 0], [ny - 1, nx // 2], [ny // 2, nx - 1]])
+    k = len(edge) * 4
+    js[:k] = np.repeat(edge[:, 0], 4)
+    iis[:k] = np.repeat(edge[:, 1], 4)
+    qs[:k] = np.tile([0, Q // 4 + 1, Q // 2 + 3, Q - 1], len(edge))
+    return qs, js, iis
+
+
+def sampled_phi(psi0, w, js, iis):
+    """The scalar flux of psi0 (FP64) at the sampled cells; zero elsewhere."""
+    phi = np.zeros(psi0.shape[1:])
+    phi[js, iis] = w @ psi0[:, js, iis].astype(np.float64)
+    return phi

@@ -8,7 +8,8 @@ import pytest
 
 import workloads as wl
 from oracle import asn_oracle as o
-from gpu_util import fp32_budget_floor, gpu_run, oracle_run, rel_l2
+from gpu_util import (fp32_budget_floor, gpu_run, oracle_run, rel_l2, sampled_entries,
+                      sampled_phi, structured_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -102,3 +103,37 @@ def test_reduced_precision_runs_are_bitwise_reproducible():
     a = gpu_run(asn, spec, 7, psi0=psi0, dtype="bf16")
     b = gpu_run(asn, spec, 7, psi0=psi0, dtype="bf16")
     assert np.array_equal(a[0], b[0]) and a[2] == b[2]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("n,n_polar", [(400, 16), (1024, 32)])
+def test_full_size_one_step_sampled_within_rounding_bound(dtype, n, n_polar):
+    # Full size (up to 2^31 cell-ordinates): sampled entries of one step against the
+    # exact FP64 oracle.  The reduced-precision Y differs from K psi by the rounding of
+    # T(K) (unit roundoff u), of the operand (two BF16 terms, or FP16 after the block
+    # scaling) and of the row defect, each at most about u * sum_k |K_qk| * max_k |dev_k|
+    # with dev = psi - Phi / W of the cell; the particle fix adds at most the same
+    # again.  8 u |K|_row max|dev| covers them twice over (FP16: plus the subnormal
+    # spacing of the small K entries, 2^-25 each); a misplaced operand or output would
+    # be off by about max|dev| itself.
+    spec = wl.line_source(n, n_polar=n_polar, sigma_as=5.0)
+    rng = np.random.default_rng(n + n_polar)
+    psi0 = structured_state(spec, rng)
+    p = asn.from_spec(spec, dtype=dtype, set_initial_state=False)
+    asn.asn_set_state(p, psi0)
+    asn.asn_step(p, 1)
+    got = asn.asn_get_state(p)
+    p.close()
+    st = o.setup(spec)
+    Q = spec.q
+    qs, js, iis = sampled_entries(rng, Q, spec.ny, spec.nx, 300)
+    ref = o.step_entries(psi0, st, qs, js, iis, phi=sampled_phi(psi0, st.w, js, iis))
+    u = 2.0 ** -9 if dtype == "bf16" else 2.0 ** -11 + 2.0 ** -25 * Q
+    col = psi0[:, js, iis].astype(np.float64)
+    iso = (st.w @ col / st.W).astype(np.float32).astype(np.float64)
+    dev_max = np.abs(col - iso[None, :]).max(axis=0)
+    bound = st.dt * st.sigma_as[js, iis] * 8 * u * np.abs(st.K).sum(axis=1).max() * dev_max
+    floor = 4e-6 * np.maximum(np.abs(ref), 1e-3 * np.abs(psi0).max())
+    err = np.abs(got[qs, js, iis].astype(np.float64) - ref)
+    assert np.all(err <= bound + floor), float(np.max(err / (bound + floor)))

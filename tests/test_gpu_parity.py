@@ -8,7 +8,8 @@ import pytest
 
 import workloads as wl
 from oracle import asn_oracle as o
-from gpu_util import fp32_budget_floor, gpu_run, oracle_run, rel_l2
+from gpu_util import (fp32_budget_floor, gpu_run, oracle_run, rel_l2, sampled_entries,
+                      sampled_phi, structured_state)
 
 pytestmark = pytest.mark.gpu
 
@@ -212,32 +213,15 @@ def _sampled_one_step(spec, seed, n_samples=400, unfused=None):
     unfused: None takes the kernel form the library chooses (separate at these
     sizes), False / True ask for the fused / separate form."""
     rng = np.random.default_rng(seed)
-    Q, ny, nx = spec.q, spec.ny, spec.nx
-    a1 = (0.5 + rng.random(Q)).astype(np.float32)
-    a2 = rng.standard_normal(Q).astype(np.float32) * np.float32(0.3)
-    # psi0 = a1 * cell + a2 * mean, built in place (FP32 products, then FP32 sums)
-    psi0 = np.empty((Q, ny, nx), dtype=np.float32)
-    np.multiply(a1[:, None, None], spec.psi0_cell[None], out=psi0)
-    psi0 += (a2 * np.float32(spec.psi0_cell.mean()))[:, None, None]
+    psi0 = structured_state(spec, rng)
     p = asn.from_spec(spec, set_initial_state=False, unfused=unfused)
     asn.asn_set_state(p, psi0)
     asn.asn_step(p, 1)
     got = asn.asn_get_state(p)
     p.close()
     st = o.setup(spec)
-    qs = rng.integers(0, Q, n_samples)
-    js = rng.integers(0, ny, n_samples)
-    iis = rng.integers(0, nx, n_samples)
-    edge = np.array([[0, 0], [0, nx - 1], [ny - 1, 0], [ny - 1, nx - 1], [0, nx // 2],
-                     [ny // 2, 0], [ny - 1, nx // 2], [ny // 2, nx - 1]])
-    k = len(edge) * 4
-    js[:k] = np.repeat(edge[:, 0], 4)
-    iis[:k] = np.repeat(edge[:, 1], 4)
-    qs[:k] = np.tile([0, Q // 4 + 1, Q // 2 + 3, Q - 1], len(edge))
-    # the scalar flux of psi0 is needed only at the sampled cells
-    phi = np.zeros((ny, nx))
-    phi[js, iis] = st.w @ psi0[:, js, iis].astype(np.float64)
-    ref = o.step_entries(psi0, st, qs, js, iis, phi=phi)
+    qs, js, iis = sampled_entries(rng, spec.q, spec.ny, spec.nx, n_samples)
+    ref = o.step_entries(psi0, st, qs, js, iis, phi=sampled_phi(psi0, st.w, js, iis))
     diff = np.abs(got[qs, js, iis].astype(np.float64) - ref)
     return float(np.max(diff / np.maximum(np.abs(ref), 1e-3 * np.abs(psi0).max())))
 

@@ -1642,6 +1642,22 @@ __global__ __launch_bounds__(kFlatThreads) void muscl_flat_kernel(BatchArgs B) {
 // ---------------------------------------------------------------------------
 // 3. Finalize: Phi = sum of the G partials (fixed order), Phi/W, mass partials.
 // ---------------------------------------------------------------------------
+// sum over g < G of p[g P + c], added in the order g = 0, 1, ...; the loads of eight
+// partials are issued together (one memory round trip per eight, not per partial)
+__device__ __forceinline__ double sum_partials(const ASN_G double* p, int G, int64_t P,
+                                               int64_t c) {
+    double s = 0.0;
+    for (int g0 = 0; g0 < G; g0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)min(g0 + u, G - 1) * P + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (g0 + u < G) s += v[u];
+    }
+    return s;
+}
+
 __global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
     int pi, local;
     if (!locate(B, KT_FIN, blockIdx.x, pi, local)) return;
@@ -1651,21 +1667,19 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
     const int64_t c = (int64_t)local * 256 + threadIdx.x;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (c < a.C) {
-        double phi = 0.0;
-        const ASN_G double* pp = gp(a.phi_part);
-        for (int g = 0; g < G; ++g) phi += pp[(size_t)g * a.P + c];
         const float4 cf = gp(a.coef)[c];
+        const bool lp_fused = a.dtype != 0 && a.fused;
+        const double phi_old = lp_fused && !init ? gp(a.phi64)[c] : 0.0;
+        double phi = sum_partials(gp(a.phi_part), G, a.P, c);
         double corr = 0.0;   // W delta: particles of the pending correction (fused BF16 / FP16)
-        if (a.dtype != 0 && a.fused) {
+        if (lp_fused) {
             if (init) {
                 gp(a.delta)[c] = 0.f;
             } else {
                 // the particle correction of this step's reduced-precision Y: every
                 // ordinate of the cell gets delta = -dt sigma_as (sum_q w_q Y^ - Phi^n) / W
-                double ys = 0.0;
-                const ASN_G double* yp = gp(a.ypart);
-                for (int g = 0; g < G; ++g) ys += yp[(size_t)g * a.P + c];
-                const float d = (float)(-(double)cf.z * (ys - gp(a.phi64)[c]) / a.W);
+                const double ys = sum_partials(gp(a.ypart), G, a.P, c);
+                const float d = (float)(-(double)cf.z * (ys - phi_old) / a.W);
                 gp(a.delta)[c] = d;
                 corr = a.W * (double)d;
             }
@@ -1710,102 +1724,111 @@ __global__ void materialize_done_kernel(StepArgs a) {
 //                dt R(psi^1)).
 //    BUD_INIT    after set_state: M^0.
 // One block of 1024 threads per problem.  Each thread folds a strided share of the
-// partials, four independent loads at a time (the fold is one round trip per four
-// partials instead of per partial), then the block folds the threads in a fixed order.
+// partials, the loads of both kinds issued together, four of each at a time (one
+// round trip per four partials instead of per partial), then the block folds the
+// threads in a fixed order.  Thread 0 reads the record while the partials arrive and
+// writes it back whole.
 constexpr int kBudgetThreads = 1024;
 __global__ __launch_bounds__(kBudgetThreads) void budget_kernel(BatchArgs B, int mode) {
     int pi, local;
     if (!locate(B, KT_BUDGET, blockIdx.x, pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
     const bool init = mode == BUD_INIT;
-    const int n_blk = a.tiles_x * a.tiles_y * a.G;
+    ASN_G double* rec = gp(a.rec);
+    double r[REC_LEN];
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < REC_LEN; ++k) r[k] = rec[k];
+    const int n_fin = a.fin_blocks;
+    const int n_blk = init ? 0 : a.tiles_x * a.tiles_y * a.G;
     double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const ASN_G double4* fp = reinterpret_cast<const ASN_G double4*>(gp(a.fin_part));
     const ASN_G double2* bp = reinterpret_cast<const ASN_G double2*>(gp(a.blk_part));
     constexpr int T = kBudgetThreads, U = 4;
-    for (int i0 = threadIdx.x; i0 < a.fin_blocks; i0 += T * U) {
+    for (int i0 = threadIdx.x; i0 < max(n_fin, n_blk); i0 += T * U) {
         double4 v[U];
+        double2 w[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u * T;
-            const double4 t = fp[min(i, a.fin_blocks - 1)];
-            v[u] = i < a.fin_blocks ? t : double4{0.0, 0.0, 0.0, 0.0};
+            v[u] = fp[min(i, n_fin - 1)];
+            w[u] = double2{0.0, 0.0};
+            if (n_blk > 0) w[u] = bp[min(i, n_blk - 1)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            s[0] += v[u].x;
-            s[1] += v[u].y;
-            s[2] += v[u].z;
-            s[5] += v[u].w;
+            const int i = i0 + u * T;
+            if (i < n_fin) {
+                s[0] += v[u].x;
+                s[1] += v[u].y;
+                s[2] += v[u].z;
+                s[5] += v[u].w;
+            }
+            if (i < n_blk) {
+                s[3] += w[u].x;
+                s[4] += w[u].y;
+            }
         }
     }
-    if (!init)
-        for (int i0 = threadIdx.x; i0 < n_blk; i0 += T * U) {
-            double2 v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * T;
-                const double2 t = bp[min(i, n_blk - 1)];
-                v[u] = i < n_blk ? t : double2{0.0, 0.0};
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                s[3] += v[u].x;
-                s[4] += v[u].y;
-            }
-        }
     __shared__ double tot[6];
     block_sum_waves<T / 64, 6>(s, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (mode == BUD_STEP || mode == BUD_STAGE2) gp(B.steps_left)[pi] -= 1;
-    ASN_G double* rec = gp(a.rec);
     const double m_next = a.area * tot[0];
     const double abs_next = a.area * tot[1];
+    auto store = [&]() {
+#pragma unroll
+        for (int k = 0; k < REC_LEN; ++k) rec[k] = r[k];
+    };
     if (init) {
-        for (int k = 0; k < REC_LEN; ++k) rec[k] = 0.0;
-        rec[REC_MASS] = m_next;
-        rec[REC_MASS0] = m_next;
-        rec[REC_ABS_NEXT] = abs_next;
-        rec[REC_SRC_STEP] = a.area * a.W * tot[2];
+#pragma unroll
+        for (int k = 0; k < REC_LEN; ++k) r[k] = 0.0;
+        r[REC_MASS] = m_next;
+        r[REC_MASS0] = m_next;
+        r[REC_ABS_NEXT] = abs_next;
+        r[REC_SRC_STEP] = a.area * a.W * tot[2];
+        store();
         return;
     }
     // collision defect: the stencil's increments plus the pending correction's particles
     const double def = a.area * (tot[3] + tot[5]);
     const double out = a.area * tot[4];
-    const double ref = fmax(rec[REC_MASS0], rec[REC_MASS]);
+    const double ref = fmax(r[REC_MASS0], r[REC_MASS]);
     auto residual = [&](double got, double pred) {
         const double rel = ref > 0.0 ? fabs(got - pred) / ref : fabs(got - pred);
-        rec[REC_RES] = fmax(rec[REC_RES], rel);
+        r[REC_RES] = fmax(r[REC_RES], rel);
     };
     if (mode == BUD_STEP) {
-        residual(m_next, rec[REC_MASS] - rec[REC_ABS_NEXT] - out + rec[REC_SRC_STEP] + def);
-        rec[REC_ABS] += rec[REC_ABS_NEXT];
-        rec[REC_OUT] += out;
-        rec[REC_SRC] += rec[REC_SRC_STEP];
-        rec[REC_DEF] += def;
-        rec[REC_STEPS] += 1.0;
-        rec[REC_MASS] = m_next;
-        rec[REC_ABS_NEXT] = abs_next;
+        residual(m_next, r[REC_MASS] - r[REC_ABS_NEXT] - out + r[REC_SRC_STEP] + def);
+        r[REC_ABS] += r[REC_ABS_NEXT];
+        r[REC_OUT] += out;
+        r[REC_SRC] += r[REC_SRC_STEP];
+        r[REC_DEF] += def;
+        r[REC_STEPS] += 1.0;
+        r[REC_MASS] = m_next;
+        r[REC_ABS_NEXT] = abs_next;
+        store();
         return;
     }
     // Heun passes: each contributes half of its increment to the step
-    const double abs_in = mode == BUD_STAGE1 ? rec[REC_ABS_NEXT] : rec[REC_ABS_STAGE];
-    const double inc = -abs_in - out + rec[REC_SRC_STEP] + def;
-    rec[REC_ABS] += 0.5 * abs_in;
-    rec[REC_OUT] += 0.5 * out;
-    rec[REC_SRC] += 0.5 * rec[REC_SRC_STEP];
-    rec[REC_DEF] += 0.5 * def;
+    const double abs_in = mode == BUD_STAGE1 ? r[REC_ABS_NEXT] : r[REC_ABS_STAGE];
+    const double inc = -abs_in - out + r[REC_SRC_STEP] + def;
+    r[REC_ABS] += 0.5 * abs_in;
+    r[REC_OUT] += 0.5 * out;
+    r[REC_SRC] += 0.5 * r[REC_SRC_STEP];
+    r[REC_DEF] += 0.5 * def;
     if (mode == BUD_STAGE1) {
-        residual(m_next, rec[REC_MASS] + inc);
-        rec[REC_HALF] = 0.5 * inc;
-        rec[REC_ABS_STAGE] = abs_next;
-        return;
+        residual(m_next, r[REC_MASS] + inc);
+        r[REC_HALF] = 0.5 * inc;
+        r[REC_ABS_STAGE] = abs_next;
+    } else {
+        residual(m_next, r[REC_MASS] + r[REC_HALF] + 0.5 * inc);
+        r[REC_STEPS] += 1.0;
+        r[REC_MASS] = m_next;
+        r[REC_ABS_NEXT] = abs_next;
     }
-    residual(m_next, rec[REC_MASS] + rec[REC_HALF] + 0.5 * inc);
-    rec[REC_STEPS] += 1.0;
-    rec[REC_MASS] = m_next;
-    rec[REC_ABS_NEXT] = abs_next;
+    store();
 }
 
 // ---------------------------------------------------------------------------

@@ -28,10 +28,12 @@ struct RhsArgs {
     int Q;
     int64_t C, P;
     double alpha, beta, inv_dt, inv_W;
+    const int* stop;        // nonzero *stop: the source iteration has converged, do nothing
 };
 
 // rhs[q][c] = sigma_as (K psi)[q][c] + alpha sigma_s phi_c / W + beta (q_c + psi_old[q][c] / dt)
 __global__ __launch_bounds__(256) void imp_rhs_kernel(RhsArgs a) {
+    if (a.stop != nullptr && *a.stop) return;   // block-uniform, before any barrier
     __shared__ double Ks[kTK][kT + 1];
     __shared__ double Ps[kTK][kT];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -118,6 +120,7 @@ struct SweepArgs {
     double* out;            // [Q][P]
     int nx, ny;
     int64_t P;
+    const int* stop;        // as in RhsArgs
 };
 
 // Lane l receives the value of lane l - 1 (lane 0 receives 0): DPP wave_shr:1, one
@@ -166,6 +169,7 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
     // the slot u = tau mod D is the same for every wave (kSweepLag is a multiple of D);
     // wave w - 1 writes ring column k + kSweepRing 23 block steps after wave w read k
     static_assert(kSweepLag % D == 0 && kSweepRing >= 4 * D, "ring slots must outlive their reads");
+    if (a.stop != nullptr && *a.stop) return;   // block-uniform, before any barrier
     const int q = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
     const int nx = a.nx, ny = a.ny;
@@ -333,9 +337,11 @@ int sweep_waves(int nx, int ny) {
     return W;
 }
 
-// part[b] = {sum (x - y)^2, sum x^2} over this block's elements of [n]
+// part[b] = {sum (x - y)^2, sum x^2} over this block's elements of [n]; nothing once
+// *stop is set
 __global__ __launch_bounds__(256) void imp_diff_kernel(const double* x, const double* y, int64_t n,
-                                                       double* part) {
+                                                       double* part, const int* stop) {
+    if (*stop) return;
     double d = 0.0, m = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kVecBlock + threadIdx.x;
          i < std::min<int64_t>(n, (int64_t)(blockIdx.x + 1) * kVecBlock); i += 256) {
@@ -358,6 +364,38 @@ __global__ __launch_bounds__(256) void imp_diff_kernel(const double* x, const do
         part[2 * blockIdx.x] = red[0][0];
         part[2 * blockIdx.x + 1] = red[1][0];
     }
+}
+
+// The stopping test of a source iteration, on the device: ||x - y|| < thr ||x|| over the
+// difference partials of imp_diff_kernel (strided shares, then a fixed-order tree).
+// stat = {done, iteration that met the test}; once done is set, nothing changes it.
+__global__ __launch_bounds__(256) void imp_test_kernel(const double* part, int nb, double thr,
+                                                       int it, int* stat) {
+    if (stat[0]) return;
+    double d = 0.0, m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        d += part[2 * b];
+        m += part[2 * b + 1];
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = d;
+    red[1][threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && !(sqrt(red[0][0]) >= thr * sqrt(red[1][0]))) {
+        stat[0] = 1;
+        stat[1] = it;
+    }
+}
+
+__global__ void imp_stat_clear_kernel(int* stat) {
+    if (threadIdx.x < 2) stat[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void imp_dot_kernel(const double* x, const double* y, int64_t n,
@@ -497,6 +535,7 @@ size_t ImplicitSolver::bytes(const ImplicitParams& p) {
     take(off, (size_t)p.P * 8);                                   // phi
     take(off, (size_t)(p.gmres_restart + 6) * p.P * 8);           // GMRES vectors
     take(off, (size_t)(ndiv(std::max<int64_t>(p.Q * p.P, p.P), kVecBlock) + 8) * 4 * 8);  // partials
+    take(off, 256);                                               // stopping-test status
     return off;
 }
 
@@ -528,6 +567,7 @@ bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const do
     nparts_ = (int)ndiv(std::max<int64_t>((int64_t)p.Q * p.P, p.P), kVecBlock) + 8;
     part_ = reinterpret_cast<double*>(base + take(off, (size_t)nparts_ * 4 * 8));
     hpart_.assign((size_t)nparts_ * 4, 0.0);
+    stat_ = reinterpret_cast<int*>(base + take(off, 256));
 
     // host tables
     std::vector<double> small_h((size_t)p.Q * 6, 0.0);
@@ -599,17 +639,17 @@ bool ImplicitSolver::get_state(float* psi32, std::string& err) {
 }
 
 bool ImplicitSolver::sweep_once(const double* psi_in, double* psi_out, const double* phi,
-                                double alpha, double beta, std::string& err) {
+                                double alpha, double beta, std::string& err, const int* stop) {
     RhsArgs r{K_, psi_in, psi_old_, phi, coef_, rhs_, p_.Q, p_.C, p_.P, alpha, beta,
-              1.0 / p_.dt, 1.0 / p_.W};
+              1.0 / p_.dt, 1.0 / p_.W, stop};
     dim3 g(ndiv(p_.Q, kT), (unsigned)(p_.P / kT));
     imp_rhs_kernel<<<g, 256, 0, s_>>>(r);
     IMP_TRY(hipGetLastError());
-    SweepArgs sa{rhs_, dir_, sig_, psi_out, p_.nx, p_.ny, p_.P};
+    SweepArgs sa{rhs_, dir_, sig_, psi_out, p_.nx, p_.ny, p_.P, stop};
     const int W = sweep_waves(p_.nx, p_.ny);
     imp_sweep_kernel<<<p_.Q, 64 * W, sweep_lds_bytes(p_.nx, W), s_>>>(sa);
     IMP_TRY(hipGetLastError());
-    ++sweeps;
+    if (stop == nullptr) ++sweeps;   // queued sweeps are counted once the test has run
     return true;
 }
 
@@ -627,24 +667,38 @@ double* ImplicitSolver::source_iteration(const double* phi, double alpha, double
     }
     const int64_t n = (int64_t)p_.Q * p_.P;
     const unsigned nb = ndiv(n, kVecBlock);
-    for (int it = 1; it < 500; ++it) {
-        imp_diff_kernel<<<nb, 256, 0, s_>>>(bufs[cur], prev, n, part_);
+    const double thr = p_.source_tol * c;
+    // Iteration it compares sweep it with sweep it - 1 and stops when the change is below
+    // the tolerance.  The test runs on the device, so iterations are queued in groups with
+    // no host round trip between them; the kernels of iterations after the one that met
+    // the test exit at once, leaving its result in place.  The host reads the status once
+    // per group.
+    constexpr int kGroup = 4, kMaxIt = 500;
+    imp_stat_clear_kernel<<<1, 64, 0, s_>>>(stat_);
+    int it = 1;
+    while (it < kMaxIt) {
+        const int end = std::min(it + kGroup, kMaxIt);
+        for (; it < end; ++it) {
+            imp_diff_kernel<<<nb, 256, 0, s_>>>(bufs[cur], prev, n, part_, stat_);
+            imp_test_kernel<<<1, 256, 0, s_>>>(part_, (int)nb, thr, it, stat_);
+            prev = bufs[cur];
+            cur ^= 1;
+            if (!sweep_once(prev, bufs[cur], phi, alpha, beta, err, stat_)) return nullptr;
+        }
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(hpart_.data(), part_, (size_t)nb * 2 * 8, hipMemcpyDeviceToHost, s_) != hipSuccess ||
+            hipMemcpyAsync(hstat_, stat_, sizeof(hstat_), hipMemcpyDeviceToHost, s_) != hipSuccess ||
             hipStreamSynchronize(s_) != hipSuccess) {
-            err = "source-iteration norm failed";
+            err = "source-iteration test failed";
             return nullptr;
         }
-        double d = 0.0, m = 0.0;
-        for (unsigned b = 0; b < nb; ++b) {
-            d += hpart_[2 * b];
-            m += hpart_[2 * b + 1];
+        if (hstat_[0]) {                 // met at iteration k: sweeps 1 .. k ran
+            const int k = hstat_[1];
+            sweeps += k - 1;
+            ok = true;
+            return bufs[(k - 1) & 1];
         }
-        if (!(std::sqrt(d) >= p_.source_tol * c * std::sqrt(m))) break;
-        prev = bufs[cur];
-        cur ^= 1;
-        if (!sweep_once(prev, bufs[cur], phi, alpha, beta, err)) return nullptr;
     }
+    sweeps += kMaxIt - 1;
     ok = true;
     return bufs[cur];
 }

@@ -53,11 +53,13 @@ private:
     double *phi_ = nullptr, *vecs_ = nullptr, *part_ = nullptr;
     std::vector<double> hpart_;
     int nparts_ = 0;
+    int* stat_ = nullptr;               // device: {stopping test met, its iteration}
+    int hstat_[2] = {0, 0};
 
     double* vec(int i) const { return vecs_ + (size_t)i * p_.P; }
     // psi_out = L^-1 (sigma_as K psi_in + alpha sigma_s phi / W + beta (q + psi_old / dt))
     bool sweep_once(const double* psi_in, double* psi_out, const double* phi, double alpha,
-                    double beta, std::string& err);
+                    double beta, std::string& err, const int* stop = nullptr);
     // Algorithm 1 from psi_old; returns the buffer holding the result (psi_a_ or psi_b_)
     double* source_iteration(const double* phi, double alpha, double beta, std::string& err,
                              bool& ok);

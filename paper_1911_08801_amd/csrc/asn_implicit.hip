@@ -373,9 +373,17 @@ __global__ __launch_bounds__(256) void imp_test_kernel(const double* part, int n
                                                        int it, int* stat) {
     if (stat[0]) return;
     double d = 0.0, m = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
-        d += part[2 * b];
-        m += part[2 * b + 1];
+    const double2* p2 = reinterpret_cast<const double2*>(part);
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 256 * 8) {   // eight loads in flight
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p2[min(b0 + 256 * u, nb - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b0 + 256 * u < nb) {
+                d += v[u].x;
+                m += v[u].y;
+            }
     }
     __shared__ double red[2][256];
     red[0][threadIdx.x] = d;

@@ -116,3 +116,33 @@ def test_implicit_rejections():
     with pytest.raises(asn.AsnError) as e:
         asn.from_spec(wide, scheme="implicit")
     assert e.value.status == asn.ASN_E_UNSUPPORTED
+
+
+def test_source_iterations_that_reach_the_cap_match_oracle():
+    # Contraction bound T = 0.995 and a tolerance no change can meet: every source
+    # iteration of the step runs its 500 sweeps on both sides (the GPU queues them in
+    # groups and must stop at the 500th), and GMRES takes the same number of products.
+    # The scalar flux itself is not compared: GMRES over products from unconverged
+    # source iterations is not a well-posed parity case (the two sides differ there
+    # by tens of percent, with every count equal).
+    spec = wl.random_problem(11, 6, 5, n_polar=2, n_azim=4, beta=4.5)
+    spec.sigma_as[:] = 400.0
+    dt = 1.0
+    psi0 = wl.random_state(3, spec.q, 5, 6)
+    p = asn.from_spec(spec, scheme="implicit", dt_override=dt, set_initial_state=False,
+                      source_tol=1e-300)
+    try:
+        asn.asn_set_state(p, psi0)
+        asn.asn_step(p, 1)
+        phi = asn.asn_scalar_flux(p)
+        counts = asn.asn_iteration_counts(p)
+    finally:
+        p.close()
+    st = o.setup(spec, dt=dt)
+    assert io.lipschitz_estimate(st, dt) > 0.99
+    s = {}
+    _, phi_ref = io.implicit_step(psi0.astype(np.float64), st, dt, None, gmres_tol=1.5e-8,
+                                  si_eps=1e-300, stats=s)
+    assert counts["matvecs"] == s["gmres_matvecs"]
+    assert counts["sweeps"] == s["si_sweeps"] == 500 * (s["gmres_matvecs"] + 2)
+    assert np.all(np.isfinite(phi)) and np.all(np.isfinite(phi_ref))

@@ -17,10 +17,17 @@ isotropic, so its moment expansion needs the scalar flux only: M psi = Phi =
 sum_q w_q psi_q, and sigma_s O Sigma phi = sigma_s phi / W for every ordinate.
 
 Readings (also listed in the design notes):
-  * the source-iteration stopping test of Algorithm 1 is taken relative to the
-    iterate, ||psi^(l+1) - psi^(l)||_2 < eps c~ ||psi^(l+1)||_2, and the
-    Lipschitz estimate T is the a-priori contraction bound
-    max_c sigma_as / (sigma_a + sigma_s + sigma_as + 1/dt);
+  * the source iteration of Algorithm 1 stops once ||psi^(l+1) - psi^(l)||_2 <
+    eps c~ with c~ = (1 - T)/T, the absolute test as printed: the a-posteriori
+    estimate T/(1-T) ||psi^(l+1) - psi^(l)||_2 of the distance to the fixed point
+    is below eps (Section 4.1 sets that estimated error to 1e-4).  The 2-norm is the
+    plain Euclidean norm over all ordinates and cells.  The Lipschitz estimate T
+    is the a-priori contraction bound max_c sigma_as / (sigma_a + sigma_s +
+    sigma_as + 1/dt).  A test relative to the iterate, ... < eps c~
+    ||psi^(l+1)||_2, is available as an option (relative=True) for right-hand
+    sides whose scale is far from one; it is not the paper's form;
+  * the loop is capped at 500 sweeps (the paper states no cap) and then returns
+    its last iterate;
   * the final sweep of Algorithm 3 keeps the source q beside psi_old / dt
     (the printed line drops it; the right-hand side b of the same step has it);
   * GMRES stops at a relative residual of its tolerance, restarted every 30
@@ -86,15 +93,21 @@ def lipschitz_estimate(st: o.Setup, dt: float) -> float:
 
 
 def source_iteration(psi0: np.ndarray, R: np.ndarray, st: o.Setup, dt: float,
-                     eps: float = 1e-4, max_iter: int = 500) -> Tuple[np.ndarray, int]:
+                     eps: float = 1e-4, max_iter: int = 500,
+                     relative: bool = False) -> Tuple[np.ndarray, int]:
     """Algorithm 1: psi^(l+1) = L^-1 (sigma_as K psi^(l) + R) until the estimated
-    error T/(1-T) ||psi^(l+1) - psi^(l)|| falls below eps ||psi^(l+1)||."""
+    error T/(1-T) ||psi^(l+1) - psi^(l)||_2 falls below eps (times ||psi^(l+1)||_2
+    when relative).  Returns (last iterate, sweeps)."""
     T = lipschitz_estimate(st, dt)
     c = math.inf if T == 0.0 else (1.0 - T) / T
     prev = np.asarray(psi0, np.float64)
     new = sweep(st.sigma_as[None] * o.as_in_scattering(prev, st.K) + R, st, dt)
     it = 1
-    while np.linalg.norm(new - prev) >= eps * c * np.linalg.norm(new) and it < max_iter:
+
+    def threshold(v):
+        return eps * c * (np.linalg.norm(v) if relative else 1.0)
+
+    while np.linalg.norm(new - prev) >= threshold(new) and it < max_iter:
         prev = new
         new = sweep(st.sigma_as[None] * o.as_in_scattering(prev, st.K) + R, st, dt)
         it += 1
@@ -153,19 +166,23 @@ def gmres(matvec: Callable[[np.ndarray], np.ndarray], b: np.ndarray, x0: np.ndar
 
 def implicit_step(psi_old: np.ndarray, st: o.Setup, dt: float, phi_old: Optional[np.ndarray] = None,
                   gmres_tol: float = 1.5e-8, si_eps: float = 1e-4,
-                  stats: Optional[Dict[str, int]] = None):
-    """Algorithm 3, one time step: returns (psi_new, phi_new)."""
+                  stats: Optional[Dict[str, int]] = None, si_relative: bool = False):
+    """Algorithm 3, one time step: returns (psi_new, phi_new), where phi_new is the
+    GMRES solution of A phi = b and psi_new the final source iteration driven by it.
+    The scalar flux of the new state is M psi_new; it equals phi_new only when every
+    source iteration has converged (their difference is the iteration error)."""
     psi_old = np.asarray(psi_old, np.float64)
     src = st.source[None] + psi_old / dt                 # q~ = q + psi_old / dt
     if phi_old is None:
         phi_old = o.scalar_flux(psi_old, st.w)
-    psi_b, n_b = source_iteration(psi_old, np.broadcast_to(src, psi_old.shape), st, dt, si_eps)
+    psi_b, n_b = source_iteration(psi_old, np.broadcast_to(src, psi_old.shape), st, dt, si_eps,
+                                  relative=si_relative)
     b = o.scalar_flux(psi_b, st.w)
     counts = {"si_sweeps": n_b}
 
     def lhs(phi):                                         # Algorithm 2
         R = np.broadcast_to((st.sigma_s * phi / st.W)[None], psi_old.shape)
-        psi_t, n = source_iteration(psi_old, R, st, dt, si_eps)
+        psi_t, n = source_iteration(psi_old, R, st, dt, si_eps, relative=si_relative)
         counts["si_sweeps"] += n
         return phi - o.scalar_flux(psi_t, st.w)
 
@@ -173,7 +190,7 @@ def implicit_step(psi_old: np.ndarray, st: o.Setup, dt: float, phi_old: Optional
     x, n_mv = gmres(lambda v: lhs(v.reshape(shape)).ravel(), b.ravel(), phi_old.ravel(), gmres_tol)
     phi_new = x.reshape(shape)
     psi_new, n_f = source_iteration(psi_old, (st.sigma_s * phi_new / st.W)[None] + src, st, dt,
-                                    si_eps)
+                                    si_eps, relative=si_relative)
     counts["si_sweeps"] += n_f
     counts["gmres_matvecs"] = n_mv
     if stats is not None:
@@ -214,11 +231,12 @@ def implicit_budget(psi_old: np.ndarray, psi_new: np.ndarray, st: o.Setup, dt: f
 
 
 def run_implicit(problem, dt: float, n_steps: int, mode: str = "sym", gmres_tol: float = 1.5e-8,
-                 si_eps: float = 1e-4, psi0: Optional[np.ndarray] = None):
+                 si_eps: float = 1e-4, psi0: Optional[np.ndarray] = None,
+                 si_relative: bool = False):
     """Advance a problem n_steps implicit steps of size dt; returns (psi, setup)."""
     st = o.setup(problem, mode, dt=dt)
     psi = (problem.psi0() if psi0 is None else psi0).astype(np.float64)
     phi = o.scalar_flux(psi, st.w)
     for _ in range(n_steps):
-        psi, phi = implicit_step(psi, st, dt, phi, gmres_tol, si_eps)
+        psi, phi = implicit_step(psi, st, dt, phi, gmres_tol, si_eps, si_relative=si_relative)
     return psi, st

@@ -192,3 +192,58 @@ def test_implicit_twelve_ordinate_ratio_near_the_paper():
         phi = o.scalar_flux(psi, st.w)
         err[s_as] = np.linalg.norm(phi - ref) / np.linalg.norm(ref)
     assert 0.3 < err[7.0] / err[0.0] < 0.65
+
+
+def _geometric_count(first, ratio, thr, cap=500):
+    """Sweeps of a scalar fixed-point iteration whose successive changes are
+    first * ratio^k (k = 0, 1, ...), stopped once a change falls below thr."""
+    it, change = 1, first
+    while change >= thr and it < cap:
+        change *= ratio
+        it += 1
+    return it
+
+
+@pytest.mark.parametrize("scale", [1.0, 1e3, 1e-3])
+def test_source_iteration_stops_on_the_printed_absolute_test(scale):
+    # One cell, one ordinate, K = [1]: the sweep is a division by
+    # d = 3/2 (|xi|/dx + |eta|/dy) + sigma_t, so from psi^(0) = 0 the iterates are
+    # partial sums of a geometric series, the change after sweep k + 1 being
+    # (R/d)(sigma_as/d)^k.  Algorithm 1 (Section 3.5) stops at the first change
+    # below eps (1 - T)/T with T = sigma_as / sigma_t: an absolute test, so the
+    # count grows with the scale of R; the relative option's count does not.
+    om = np.array([[0.6, 0.0, 0.8]])
+    prob, st = _problem(1, 1, om, np.array([4 * math.pi]), s_a=0.5, s_as=6.0, dt=0.25)
+    sig_t = 0.5 + 6.0 + 4.0
+    d = 1.5 * 0.6 / st.dx + sig_t
+    T, eps, R = 6.0 / sig_t, 1e-4, 2.0 * scale
+    want = _geometric_count(R / d, 6.0 / d, eps * (1 - T) / T)
+    psi, it = io.source_iteration(np.zeros((1, 1, 1)), np.full((1, 1, 1), R), st, 0.25, eps=eps)
+    assert it == want
+    fixed = R / (d - 6.0)
+    assert abs(psi[0, 0, 0] - fixed) <= (T / (1 - T)) * eps * (6.0 / d) / (1 - 6.0 / d) * 1.01 + 1e-15
+    # relative form: stops once change < eps c~ |psi^(l+1)|, independent of the scale
+    rel_want = None
+    it_r, change, s = 1, R / d, R / d
+    while change >= eps * (1 - T) / T * s and it_r < 500:
+        change *= 6.0 / d
+        s += change
+        it_r += 1
+    rel_want = it_r
+    _, it2 = io.source_iteration(np.zeros((1, 1, 1)), np.full((1, 1, 1), R), st, 0.25, eps=eps,
+                                 relative=True)
+    assert it2 == rel_want
+
+
+def test_absolute_and_relative_tests_differ_only_through_the_scale():
+    # R of norm far from one: the absolute test needs more sweeps when R grows
+    om, w = _ordinates()
+    prob, st = _problem(4, 3, om, w, s_a=0.5, s_as=3.0, eps=0.9, dt=0.3, seed=3)
+    R = np.random.default_rng(4).random((len(w), 3, 4))
+    n = {}
+    for scale in (1.0, 1e4):
+        _, n[("abs", scale)] = io.source_iteration(np.zeros_like(R), scale * R, st, 0.3, eps=1e-4)
+        _, n[("rel", scale)] = io.source_iteration(np.zeros_like(R), scale * R, st, 0.3, eps=1e-4,
+                                                   relative=True)
+    assert n[("abs", 1e4)] > n[("abs", 1.0)]
+    assert n[("rel", 1e4)] == n[("rel", 1.0)]

@@ -69,13 +69,22 @@ enum { ASN_NORM_SYM = 0, ASN_NORM_ROW = 1 };
 /* ASN_SCHEME_IMPLICIT: the paper's implicit scheme (Sections 3.4-3.5, Algorithms 1-3):
  *                   implicit Euler, faces carry 3/2 psi_up - 1/2 psi_upup (no limiter),
  *                   the artificial scattering is resolved inside the sweep by source
- *                   iteration (relative stopping test source_tol with the a-priori
- *                   contraction bound max sigma_as / (sigma_a + sigma_s + sigma_as + 1/dt)),
+ *                   iteration (Algorithm 1: stop once ||psi^(l+1) - psi^(l)||_2 <
+ *                   source_tol (1 - T)/T, T the a-priori contraction bound
+ *                   max sigma_as / (sigma_a + sigma_s + sigma_as + 1/dt); the norm is
+ *                   Euclidean over all ordinates and cells; at most 500 sweeps),
  *                   and GMRES (restart 30, relative residual implicit_tol) solves for
  *                   the scalar flux.  FP64 on the device; cfl above 1 is allowed;
  *                   nx <= 2048; such problems step alone (no batches); asn_step blocks
  *                   until its steps are done. */
 enum { ASN_SCHEME_EULER = 0, ASN_SCHEME_HEUN = 1, ASN_SCHEME_IMPLICIT = 2 };
+
+/* Stopping test of the implicit scheme's source iteration (Algorithm 1).
+ * ASN_SOURCE_TEST_ABSOLUTE: ||psi^(l+1) - psi^(l)||_2 < source_tol (1 - T)/T, as printed
+ *                           (the estimated distance to the fixed point below source_tol).
+ * ASN_SOURCE_TEST_RELATIVE: ... < source_tol (1 - T)/T ||psi^(l+1)||_2, a scale-free
+ *                           variant for right-hand sides far from unit size. */
+enum { ASN_SOURCE_TEST_ABSOLUTE = 0, ASN_SOURCE_TEST_RELATIVE = 1 };
 
 /* Time-step rule.  Both start from dt_max = cfl / max_q(|xi_q|/dx + |eta_q|/dy)
  * and take dt = t_final / n, n = ceil(t_final / dt_max).
@@ -131,7 +140,8 @@ typedef struct {
     int32_t step_form;      /* ASN_FORM_AUTO (default), ASN_FORM_SEPARATE or ASN_FORM_FUSED:
                                kernel form of forward-Euler steps (other schemes: separate)   */
     double implicit_tol;    /* ASN_SCHEME_IMPLICIT: GMRES relative residual (0: 1.5e-8, paper 4.1) */
-    double source_tol;      /* ASN_SCHEME_IMPLICIT: source-iteration tolerance (0: 1e-4)           */
+    double source_tol;      /* ASN_SCHEME_IMPLICIT: source-iteration tolerance (0: 1e-4, paper 4.1) */
+    int32_t source_test;    /* ASN_SCHEME_IMPLICIT: ASN_SOURCE_TEST_ABSOLUTE (default) or _RELATIVE */
 } asn_options;
 
 typedef struct asn_problem_s* asn_problem;

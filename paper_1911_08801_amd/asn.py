@@ -37,6 +37,7 @@ ASN_GEMM_F32, ASN_GEMM_BF16, ASN_GEMM_F16 = 0, 1, 2
 ASN_NORM_SYM, ASN_NORM_ROW = 0, 1
 ASN_SCHEME_EULER, ASN_SCHEME_HEUN, ASN_SCHEME_IMPLICIT = 0, 1, 2
 ASN_DT_STREAMING, ASN_DT_STIFF = 0, 1
+ASN_SOURCE_TEST_ABSOLUTE, ASN_SOURCE_TEST_RELATIVE = 0, 1
 ASN_FORM_AUTO, ASN_FORM_SEPARATE, ASN_FORM_FUSED = 0, 1, 2
 ASN_BUDGET_LEN = 8
 
@@ -44,6 +45,7 @@ DTYPES = {"f32": ASN_GEMM_F32, "bf16": ASN_GEMM_BF16, "f16": ASN_GEMM_F16}
 NORMS = {"sym": ASN_NORM_SYM, "row": ASN_NORM_ROW}
 SCHEMES = {"euler": ASN_SCHEME_EULER, "heun": ASN_SCHEME_HEUN, "implicit": ASN_SCHEME_IMPLICIT}
 DT_RULES = {"streaming": ASN_DT_STREAMING, "stiff": ASN_DT_STIFF}
+SOURCE_TESTS = {"absolute": ASN_SOURCE_TEST_ABSOLUTE, "relative": ASN_SOURCE_TEST_RELATIVE}
 
 
 class AsnError(RuntimeError):
@@ -71,7 +73,7 @@ class asn_options(ctypes.Structure):
                 ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
                 ("scheme", ctypes.c_int32), ("dt_rule", ctypes.c_int32),
                 ("step_form", ctypes.c_int32), ("implicit_tol", ctypes.c_double),
-                ("source_tol", ctypes.c_double)]
+                ("source_tol", ctypes.c_double), ("source_test", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -183,6 +185,11 @@ def make_grid(nx, ny, x_min, x_max, y_min, y_max) -> asn_grid:
     return asn_grid(nx, ny, x_min, x_max, y_min, y_max)
 
 
+def make_quadrature(n_polar: int, n_azim: int) -> asn_quadrature:
+    """The product set of n_polar Gauss-Legendre nodes times n_azim azimuths."""
+    return asn_quadrature(n_polar, n_azim, 0, None, None, 0)
+
+
 def asn_time_step(grid: asn_grid, omega: np.ndarray, cfl: float, t_final: float):
     omega = np.ascontiguousarray(omega, dtype=np.float64)
     dt = ctypes.c_double()
@@ -202,7 +209,7 @@ def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                  eps_override: float = 0.0, dt_override: float = 0.0,
                  scheme: str = "euler", dt_rule: str = "streaming",
                  unfused: Optional[bool] = None, implicit_tol: float = 0.0,
-                 source_tol: float = 0.0) -> asn_options:
+                 source_tol: float = 0.0, source_test: str = "absolute") -> asn_options:
     """Options for asn_create; unfused: None lets the library choose the kernel form of
     forward-Euler steps, True asks for separate kernels, False for the fused one."""
     o = asn_options_default()
@@ -214,6 +221,7 @@ def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                    ASN_FORM_SEPARATE if unfused else ASN_FORM_FUSED)
     o.implicit_tol = implicit_tol
     o.source_tol = source_tol
+    o.source_test = SOURCE_TESTS[source_test]
     o.cfl = cfl
     o.eps_override = eps_override
     o.dt_override = dt_override
@@ -255,11 +263,14 @@ def asn_create(grid: asn_grid, n_polar: int = 0, n_azim: int = 0, sigma_s=None, 
                sigma_as=None, source=None, beta: float = 4.5, t_final: float = 1.0,
                options: Optional[asn_options] = None, omega: Optional[np.ndarray] = None,
                weights: Optional[np.ndarray] = None, device: str = "cuda",
-               torch_workspace: bool = True, icosahedron_order: int = 0) -> AsnProblem:
+               torch_workspace: bool = True, icosahedron_order: int = 0,
+               workspace=None) -> AsnProblem:
     """Create a problem on the current torch device and stream.
 
-    The workspace is a torch uint8 tensor (so torch's allocator accounts for it);
-    the library enqueues all work on torch's current stream.
+    The workspace is a torch uint8 tensor (so torch's allocator accounts for it):
+    the caller's `workspace` (contiguous, on the device) if given, else a new one of
+    asn_workspace_size bytes; torch_workspace=False lets the library allocate.
+    The library enqueues all work on torch's current stream.
     """
     import torch
     opt = options if options is not None else asn_options_default()
@@ -285,7 +296,12 @@ def asn_create(grid: asn_grid, n_polar: int = 0, n_azim: int = 0, sigma_s=None, 
             raise ValueError("fields must have nx * ny entries")
     ws = None
     ws_ptr, ws_bytes = None, 0
-    if torch_workspace:
+    if workspace is not None:
+        if workspace.dtype != torch.uint8 or not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
+        ws, ws_bytes = workspace, workspace.numel()
+        ws_ptr = ws.data_ptr()
+    elif torch_workspace:
         ws_bytes = asn_workspace_size(grid, quad, opt)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
         ws_ptr = ws.data_ptr()
@@ -446,12 +462,13 @@ def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               eps_override: float = 0.0, dt_override: float = 0.0,
               set_initial_state: bool = True, scheme: str = "euler",
               dt_rule: str = "streaming", unfused: Optional[bool] = None,
-              implicit_tol: float = 0.0, source_tol: float = 0.0) -> AsnProblem:
+              implicit_tol: float = 0.0, source_tol: float = 0.0,
+              source_test: str = "absolute") -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
     opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule, unfused,
-                       implicit_tol, source_tol)
+                       implicit_tol, source_tol, source_test)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
                    spec.source, spec.beta, spec.t_final, opt, device=device,
                    icosahedron_order=getattr(spec, "ico_order", 0))

@@ -417,6 +417,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     const bool implicit = opt.scheme == ASN_SCHEME_IMPLICIT;
     if (opt.step_form < ASN_FORM_AUTO || opt.step_form > ASN_FORM_FUSED)
         return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, ASN_FORM_SEPARATE or ASN_FORM_FUSED");
+    if (opt.source_test != ASN_SOURCE_TEST_ABSOLUTE && opt.source_test != ASN_SOURCE_TEST_RELATIVE)
+        return fail(ASN_E_INVALID, "source_test must be ASN_SOURCE_TEST_ABSOLUTE or ASN_SOURCE_TEST_RELATIVE");
     if (opt.dt_rule != ASN_DT_STREAMING && opt.dt_rule != ASN_DT_STIFF)
         return fail(ASN_E_INVALID, "unknown dt_rule");
     if (!(opt.cfl > 0.0)) return fail(ASN_E_INVALID, "cfl must be > 0");
@@ -632,6 +634,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         ip.W = p->W;
         ip.gmres_tol = opt.implicit_tol > 0.0 ? opt.implicit_tol : 1.5e-8;
         ip.source_tol = opt.source_tol > 0.0 ? opt.source_tol : 1e-4;
+        ip.source_relative = opt.source_test == ASN_SOURCE_TEST_RELATIVE;
         ip.gmres_restart = kGmresRestart;
         p->imp.reset(new asn::ImplicitSolver());
         std::string ierr;

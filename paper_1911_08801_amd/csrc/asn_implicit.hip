@@ -366,11 +366,12 @@ __global__ __launch_bounds__(256) void imp_diff_kernel(const double* x, const do
     }
 }
 
-// The stopping test of a source iteration, on the device: ||x - y|| < thr ||x|| over the
-// difference partials of imp_diff_kernel (strided shares, then a fixed-order tree).
-// stat = {done, iteration that met the test}; once done is set, nothing changes it.
+// The stopping test of a source iteration, on the device: ||x - y|| < thr (absolute) or
+// ||x - y|| < thr ||x|| (relative) over the difference partials of imp_diff_kernel
+// (strided shares, then a fixed-order tree).  stat = {done, iteration that met the test};
+// once done is set, nothing changes it.
 __global__ __launch_bounds__(256) void imp_test_kernel(const double* part, int nb, double thr,
-                                                       int it, int* stat) {
+                                                       int relative, int it, int* stat) {
     if (stat[0]) return;
     double d = 0.0, m = 0.0;
     const double2* p2 = reinterpret_cast<const double2*>(part);
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(256) void imp_test_kernel(const double* part, int n
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && !(sqrt(red[0][0]) >= thr * sqrt(red[1][0]))) {
+    if (threadIdx.x == 0 && !(sqrt(red[0][0]) >= thr * (relative ? sqrt(red[1][0]) : 1.0))) {
         stat[0] = 1;
         stat[1] = it;
     }
@@ -526,6 +527,15 @@ __global__ __launch_bounds__(256) void imp_budget_kernel(BudgetArgs a) {
         }                                                                                      \
     } while (0)
 
+// Slots of four doubles in the partials buffer: one per reduction block of the widest
+// user, the difference/dot kernels (kVecBlock elements of Q * P or P) and the budget
+// kernel (256 cells of C), plus spare.
+static int64_t partial_blocks(const ImplicitParams& p) {
+    const int64_t vec = ndiv(std::max<int64_t>((int64_t)p.Q * p.P, p.P), kVecBlock);
+    const int64_t bud = ndiv(p.C, 256);
+    return std::max(vec, bud) + 8;
+}
+
 static size_t take(size_t& off, size_t bytes) {
     const size_t o = off;
     off += (size_t)rup((int64_t)bytes, 256);
@@ -542,7 +552,7 @@ size_t ImplicitSolver::bytes(const ImplicitParams& p) {
     take(off, (size_t)p.P * 8);                                   // sig
     take(off, (size_t)p.P * 8);                                   // phi
     take(off, (size_t)(p.gmres_restart + 6) * p.P * 8);           // GMRES vectors
-    take(off, (size_t)(ndiv(std::max<int64_t>(p.Q * p.P, p.P), kVecBlock) + 8) * 4 * 8);  // partials
+    take(off, (size_t)partial_blocks(p) * 4 * 8);                 // partials
     take(off, 256);                                               // stopping-test status
     return off;
 }
@@ -572,7 +582,7 @@ bool ImplicitSolver::init(const ImplicitParams& p, const double* omega, const do
     sig_ = reinterpret_cast<double*>(base + take(off, (size_t)p.P * 8));
     phi_ = reinterpret_cast<double*>(base + take(off, (size_t)p.P * 8));
     vecs_ = reinterpret_cast<double*>(base + take(off, (size_t)(p.gmres_restart + 6) * p.P * 8));
-    nparts_ = (int)ndiv(std::max<int64_t>((int64_t)p.Q * p.P, p.P), kVecBlock) + 8;
+    nparts_ = partial_blocks(p);
     part_ = reinterpret_cast<double*>(base + take(off, (size_t)nparts_ * 4 * 8));
     hpart_.assign((size_t)nparts_ * 4, 0.0);
     stat_ = reinterpret_cast<int*>(base + take(off, 256));
@@ -688,7 +698,8 @@ double* ImplicitSolver::source_iteration(const double* phi, double alpha, double
         const int end = std::min(it + kGroup, kMaxIt);
         for (; it < end; ++it) {
             imp_diff_kernel<<<nb, 256, 0, s_>>>(bufs[cur], prev, n, part_, stat_);
-            imp_test_kernel<<<1, 256, 0, s_>>>(part_, (int)nb, thr, it, stat_);
+            imp_test_kernel<<<1, 256, 0, s_>>>(part_, (int)nb, thr, p_.source_relative ? 1 : 0,
+                                               it, stat_);
             prev = bufs[cur];
             cur ^= 1;
             if (!sweep_once(prev, bufs[cur], phi, alpha, beta, err, stat_)) return nullptr;
@@ -755,6 +766,10 @@ bool ImplicitSolver::lhs(const double* v, double* out, std::string& err) {
 
 bool ImplicitSolver::fold_budget(const double* psi_new, double mass_prev, std::string& err) {
     const unsigned nb = ndiv(p_.C, 256);
+    if ((int64_t)nb > nparts_) {
+        err = "implicit budget: more blocks than partial slots";
+        return false;
+    }
     BudgetArgs b{psi_new, wq_, dq_, dir_, coef_, p_.nx, p_.ny, p_.Q, p_.C, p_.P, p_.dx, p_.dy, part_};
     imp_budget_kernel<<<nb, 256, 0, s_>>>(b);
     IMP_TRY(hipGetLastError());

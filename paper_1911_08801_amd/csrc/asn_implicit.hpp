@@ -18,7 +18,8 @@ struct ImplicitParams {
     int64_t C, P;            // cells, plane pitch
     double dx, dy, dt, W;
     double gmres_tol;        // relative residual of the scalar-flux system
-    double source_tol;       // estimated relative error of each source iteration
+    double source_tol;       // estimated error at which a source iteration stops
+    bool source_relative;    // that error relative to the iterate's norm (else absolute)
     int gmres_restart;
 };
 

@@ -100,10 +100,19 @@ enum { ASN_DT_STREAMING = 0, ASN_DT_STIFF = 1 };
  * ASN_FORM_FUSED:    the stream + collide update runs in the contraction kernel's
  *                    epilogue; the contraction output Y never reaches memory.
  * ASN_FORM_SEPARATE: contraction, then a separate stencil kernel (Y through memory).
- * ASN_FORM_AUTO:     BF16/FP16 fuse; FP32 runs separate kernels from 2^25
- *                    cell-ordinates (nx <= 4088) and fuses smaller problems, the
- *                    faster form on MI355X at the sizes measured. */
-enum { ASN_FORM_AUTO = 0, ASN_FORM_SEPARATE = 1, ASN_FORM_FUSED = 2 };
+ * ASN_FORM_BANDED:   FP32 on a product set only: the set is invariant under rotation
+ *                    by 2 pi / n_azim about the polar axis, so K restricted to two polar
+ *                    levels is circulant along the azimuth, and K couples only nearby
+ *                    levels (forward peak, Section 3.5 notes S_as^+ is sparse).  One kernel
+ *                    per step applies K as short circular convolutions and the update,
+ *                    reading psi^n once.  Needs n_azim in {8, 16, ..., 64}, levels at most
+ *                    3 apart coupled, and the FP32 K exactly circulant (checked at
+ *                    asn_create; ASN_E_UNSUPPORTED otherwise).
+ * ASN_FORM_AUTO:     the banded form where it applies; else BF16/FP16 fuse, and FP32
+ *                    runs separate kernels from 2^25 cell-ordinates (nx <= 4088) and
+ *                    fuses smaller problems, the faster forms on MI355X at the sizes
+ *                    measured.  asn_workspace_size covers every form AUTO may take. */
+enum { ASN_FORM_AUTO = 0, ASN_FORM_SEPARATE = 1, ASN_FORM_FUSED = 2, ASN_FORM_BANDED = 3 };
 
 #define ASN_BUDGET_LEN 8
 
@@ -137,7 +146,7 @@ typedef struct {
     int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
     int32_t scheme;         /* ASN_SCHEME_EULER (default) or ASN_SCHEME_HEUN                     */
     int32_t dt_rule;        /* ASN_DT_STREAMING (default) or ASN_DT_STIFF                        */
-    int32_t step_form;      /* ASN_FORM_AUTO (default), ASN_FORM_SEPARATE or ASN_FORM_FUSED:
+    int32_t step_form;      /* ASN_FORM_AUTO (default), _SEPARATE, _FUSED or _BANDED:       
                                kernel form of forward-Euler steps (other schemes: separate)   */
     double implicit_tol;    /* ASN_SCHEME_IMPLICIT: GMRES relative residual (0: 1.5e-8, paper 4.1) */
     double source_tol;      /* ASN_SCHEME_IMPLICIT: source-iteration tolerance (0: 1e-4, paper 4.1) */
@@ -259,9 +268,9 @@ asn_status asn_scalar_flux(asn_problem p, double* phi_host);
  * Errors: ASN_E_UNSTABLE if the mass is not finite, ASN_E_HIP. */
 asn_status asn_mass_budget(asn_problem p, double out[ASN_BUDGET_LEN]);
 
-/* Kernel form of the problem's steps: ASN_FORM_FUSED or ASN_FORM_SEPARATE (what
- * ASN_FORM_AUTO chose at asn_create; Heun and implicit steps report
- * ASN_FORM_SEPARATE).  Problems of one batch must share it.  Errors: ASN_E_INVALID
+/* Kernel form of the problem's steps: ASN_FORM_FUSED, ASN_FORM_SEPARATE or
+ * ASN_FORM_BANDED (what ASN_FORM_AUTO chose at asn_create; Heun and implicit steps
+ * report ASN_FORM_SEPARATE).  Problems of one batch must share it.  Errors: ASN_E_INVALID
  * for a NULL argument. */
 asn_status asn_step_form(asn_problem p, int32_t* form);
 
@@ -314,6 +323,17 @@ asn_status asn_build_kernel(int32_t q, const double* omega_xyz, const double* we
  * Errors: ASN_E_INVALID. */
 asn_status asn_build_kernel_lowp(int32_t q, const double* k_in, int32_t gemm_dtype,
                                  uint16_t* k_bits, float* row_defect);
+
+/* The banded form ASN_FORM_BANDED takes of a product set's kernel matrix, expanded
+ * back (host only): from fp32(k_in) (double[Q][Q] row-major, Q = n_polar * n_azim,
+ * ordinate q = i * n_azim + k) the library builds per pair of polar levels i, j one
+ * row of coefficients c_ij(delta) over azimuth offsets, and k_out[Q][Q] receives
+ * k_out[(i,k)][(j,k')] = c_ij(k' - k mod n_azim) (zero outside the stored runs);
+ * *reach is the largest level distance coupled.  The step applies K in this form.
+ * Errors: ASN_E_INVALID (NULL, sizes); ASN_E_UNSUPPORTED if fp32(K) is not circulant
+ * along the azimuth per level pair, couples levels more than 3 apart, or n_azim is odd. */
+asn_status asn_band_expand(int32_t n_polar, int32_t n_azim, const double* k_in, float* k_out,
+                           int32_t* reach);
 
 /* Time step for a grid: dt = t_final / n, n = ceil(t_final / dt_max),
  * dt_max = cfl / max_q(|xi_q|/dx + |eta_q|/dy).  Errors: ASN_E_INVALID, ASN_E_UNSTABLE. */

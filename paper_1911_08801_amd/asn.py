@@ -38,7 +38,9 @@ ASN_NORM_SYM, ASN_NORM_ROW = 0, 1
 ASN_SCHEME_EULER, ASN_SCHEME_HEUN, ASN_SCHEME_IMPLICIT = 0, 1, 2
 ASN_DT_STREAMING, ASN_DT_STIFF = 0, 1
 ASN_SOURCE_TEST_ABSOLUTE, ASN_SOURCE_TEST_RELATIVE = 0, 1
-ASN_FORM_AUTO, ASN_FORM_SEPARATE, ASN_FORM_FUSED = 0, 1, 2
+ASN_FORM_AUTO, ASN_FORM_SEPARATE, ASN_FORM_FUSED, ASN_FORM_BANDED = 0, 1, 2, 3
+FORMS = {"auto": ASN_FORM_AUTO, "separate": ASN_FORM_SEPARATE, "fused": ASN_FORM_FUSED,
+         "banded": ASN_FORM_BANDED}
 ASN_BUDGET_LEN = 8
 
 DTYPES = {"f32": ASN_GEMM_F32, "bf16": ASN_GEMM_BF16, "f16": ASN_GEMM_F16}
@@ -111,6 +113,7 @@ _SIG = {
                               ctypes.POINTER(ctypes.c_uint16), _F],
     "asn_time_step": [ctypes.POINTER(asn_grid), ctypes.c_int32, _D, ctypes.c_double,
                       ctypes.c_double, _D, _I64],
+    "asn_band_expand": [ctypes.c_int32, ctypes.c_int32, _D, _F, ctypes.POINTER(ctypes.c_int32)],
 }
 for _name, _args in _SIG.items():
     _fn = getattr(_lib, _name)
@@ -169,6 +172,19 @@ def asn_build_kernel(omega: np.ndarray, w: np.ndarray, eps: float, norm: str = "
     return K
 
 
+def asn_band_expand(n_polar: int, n_azim: int, K: np.ndarray):
+    """(dense FP32 K rebuilt from the banded form the library builds of fp32(K), reach)."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    q = n_polar * n_azim
+    if K.shape != (q, q):
+        raise ValueError("K must be Q x Q with Q = n_polar * n_azim")
+    out = np.zeros((q, q), dtype=np.float32)
+    reach = ctypes.c_int32()
+    _check(_lib.asn_band_expand(n_polar, n_azim, _dptr(K), _fptr(out), ctypes.byref(reach)),
+           "asn_band_expand")
+    return out, reach.value
+
+
 def asn_build_kernel_lowp(K: np.ndarray, dtype: str):
     """(16-bit patterns of T(fp32(K)), row defects) for dtype "bf16" or "f16"."""
     K = np.ascontiguousarray(K, dtype=np.float64)
@@ -209,16 +225,21 @@ def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                  eps_override: float = 0.0, dt_override: float = 0.0,
                  scheme: str = "euler", dt_rule: str = "streaming",
                  unfused: Optional[bool] = None, implicit_tol: float = 0.0,
-                 source_tol: float = 0.0, source_test: str = "absolute") -> asn_options:
-    """Options for asn_create; unfused: None lets the library choose the kernel form of
-    forward-Euler steps, True asks for separate kernels, False for the fused one."""
+                 source_tol: float = 0.0, source_test: str = "absolute",
+                 form: Optional[str] = None) -> asn_options:
+    """Options for asn_create.  Kernel form of forward-Euler steps: form "auto",
+    "separate", "fused" or "banded"; or unfused (when form is None): None lets the
+    library choose, True asks for separate kernels, False for the fused one."""
     o = asn_options_default()
     o.gemm_dtype = DTYPES[dtype]
     o.normalization = NORMS[norm]
     o.scheme = SCHEMES[scheme]
     o.dt_rule = DT_RULES[dt_rule]
-    o.step_form = (ASN_FORM_AUTO if unfused is None else
-                   ASN_FORM_SEPARATE if unfused else ASN_FORM_FUSED)
+    if form is not None:
+        o.step_form = FORMS[form]
+    else:
+        o.step_form = (ASN_FORM_AUTO if unfused is None else
+                       ASN_FORM_SEPARATE if unfused else ASN_FORM_FUSED)
     o.implicit_tol = implicit_tol
     o.source_tol = source_tol
     o.source_test = SOURCE_TESTS[source_test]
@@ -424,10 +445,10 @@ def asn_info(p: AsnProblem) -> dict:
 
 
 def asn_step_form(p: AsnProblem) -> str:
-    """Kernel form of the problem's steps: "fused" or "separate"."""
+    """Kernel form of the problem's steps: "fused", "separate" or "banded"."""
     f = ctypes.c_int32()
     _check(_lib.asn_step_form(p.handle, ctypes.byref(f)), "asn_step_form")
-    return "fused" if f.value == ASN_FORM_FUSED else "separate"
+    return {ASN_FORM_FUSED: "fused", ASN_FORM_BANDED: "banded"}.get(f.value, "separate")
 
 
 def asn_iteration_counts(p: AsnProblem) -> dict:
@@ -463,12 +484,12 @@ def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               set_initial_state: bool = True, scheme: str = "euler",
               dt_rule: str = "streaming", unfused: Optional[bool] = None,
               implicit_tol: float = 0.0, source_tol: float = 0.0,
-              source_test: str = "absolute") -> AsnProblem:
+              source_test: str = "absolute", form: Optional[str] = None) -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
     opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule, unfused,
-                       implicit_tol, source_tol, source_test)
+                       implicit_tol, source_tol, source_test, form)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
                    spec.source, spec.beta, spec.t_final, opt, device=device,
                    icosahedron_order=getattr(spec, "ico_order", 0))

@@ -45,15 +45,27 @@ struct Layout {
     int64_t C = 0, P = 0;
     bool lowp = false, fused = false;
     bool flat = false;   // separate-kernel stencil over flat cell chunks (not column strips)
+    bool banded = false; // banded step: one kernel per step for a product ordinate set
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
+        off_band, off_brange, off_bcoef,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_delta, off_bmax0, off_bmax1, off_rec,
         off_tab, off_off, off_base, off_left, off_imp,
         total;
 };
 
-Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
+// Coefficients the banded form of a set of `levels` polar levels of `azim` azimuths
+// can need at most (reach up to kBandMaxReach, runs padded to 4).
+static size_t band_coef_capacity(int levels, int azim) {
+    const int span = 2 * asn::kBandMaxReach + 1;
+    return (size_t)levels * span * (size_t)round_up(azim, 4);
+}
+
+Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int band_levels = 0,
+                   int band_azim = 0) {
     Layout L;
+    L.banded = band_levels > 0;
+    if (L.banded) fused = false;
     L.fused = fused;
     L.Q = Q;
     L.Qp = (int)round_up(Q, asn::kGemmBM);
@@ -65,14 +77,21 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     L.tiles_y = (ny + asn::kTileY - 1) / asn::kTileY;
     // Separate stencils up to a width run over flat cell chunks, wider grids over
     // column strips; the ordinates are split into chunks sized to the grid below.
-    L.flat = !fused && ((scheme == ASN_SCHEME_EULER && nx <= asn::kFlatMaxNx) ||
-                        (scheme == ASN_SCHEME_HEUN && nx <= asn::kFlatMaxNxM));
+    L.flat = !fused && !L.banded && ((scheme == ASN_SCHEME_EULER && nx <= asn::kFlatMaxNx) ||
+                                     (scheme == ASN_SCHEME_HEUN && nx <= asn::kFlatMaxNxM));
     if (L.flat) {
         L.tiles_x = (int)((L.P + asn::kFlatCells - 1) / asn::kFlatCells);
         L.tiles_y = 1;
     }
     int tiles = L.tiles_x * L.tiles_y;
-    if (fused) {
+    if (L.banded) {
+        // one block per kBandCells cells, every ordinate: each cell's Phi complete
+        L.tiles_x = (int)((L.C + asn::kBandCells - 1) / asn::kBandCells);
+        L.tiles_y = 1;
+        tiles = L.tiles_x;
+        L.qchunk = Q;
+        L.G = 1;
+    } else if (fused) {
         // the stencil runs in the contraction's epilogue: its blocks are the
         // contraction's 128 x 128 tiles, one Phi partial per ordinate tile
         L.tiles_x = (int)(L.P / asn::kGemmBN);
@@ -99,7 +118,8 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
     const size_t plane = (size_t)L.P;
     L.off_psi0 = take((size_t)Q * plane * 4);
     L.off_psi1 = take((size_t)Q * plane * 4);
-    L.off_Y = take(fused ? 0 : (size_t)Q * plane * 4);   // the fused step keeps Y in registers
+    // the fused and banded steps keep Y in registers
+    L.off_Y = take(fused || L.banded ? 0 : (size_t)Q * plane * 4);
     L.off_Kt = take((size_t)L.Qp * L.Qp * 4);
     L.off_Klp = take(L.lowp ? (size_t)L.Qp * L.Qp * 2 : 0);
     L.off_rdef = take((size_t)L.Qp * 4);
@@ -109,6 +129,9 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused) {
         L.ktab_len = mt + 1 + 2 * mt * (L.Qp / bk);   // offsets, k-steps, sub-block masks
         L.off_ktab = take((size_t)L.ktab_len * 4);
     }
+    L.off_band = take(L.banded ? (size_t)band_levels * 32 : 0);     // level descriptors, 8 words
+    L.off_brange = take(L.banded ? (size_t)band_levels * 8 : 0);    // coefficient ranges, int2
+    L.off_bcoef = take(L.banded ? band_coef_capacity(band_levels, band_azim) * 4 : 0);
     L.off_qi = take((size_t)Q * sizeof(QInfo));
     L.off_coef = take(plane * 16);
     L.off_iso = take(plane * 4);
@@ -163,12 +186,16 @@ struct asn_problem_s {
     StepArgs tab[2];          // step arguments when psi buffer 0 / 1 holds the state
     int blocks[asn::KT_COUNT];
     std::unique_ptr<asn::ImplicitSolver> imp;   // the implicit scheme's solver (else null)
+    int band_levels = 0, band_azim = 0, band_reach = 0, band_cmax = 0;   // banded step (else 0)
+    size_t band_lds() const { return asn::band_lds_bytes(band_azim, band_reach, band_cmax); }
 };
 
 struct asn_batch_s {
     std::vector<asn_problem> probs;
     int n = 0, dtype = 0, scheme = 0;
     int launch_scheme = 0;   // scheme, or its flat-chunk stencil form
+    int band_az = 0;         // banded batches: the azimuth count and LDS bytes per block
+    size_t band_lds = 0;
     hipStream_t stream = nullptr;
     std::vector<StepArgs> tab;
     std::vector<int> off;
@@ -223,6 +250,15 @@ StepArgs make_args(asn_problem p, int cur) {
     a.bmax_cur = cur == 0 ? bm0 : bm1;
     a.bmax_next = cur == 0 ? bm1 : bm0;
     a.rec = reinterpret_cast<double*>(b + L.off_rec);
+    if (L.banded) {
+        a.band = reinterpret_cast<const uint4*>(b + L.off_band);   // two per level
+        a.brange = reinterpret_cast<const int2*>(b + L.off_brange);
+        a.bcoef = reinterpret_cast<const float*>(b + L.off_bcoef);
+        a.n_lev = p->band_levels;
+        a.n_az = p->band_azim;
+        a.reach = p->band_reach;
+        a.bcmax = p->band_cmax;
+    }
     return a;
 }
 
@@ -358,8 +394,22 @@ asn_status check_field(const float* f, int64_t n, const char* name, bool allow_n
 // 0.078 ms).  Wider grids than the flat stencil takes fuse.
 bool use_fused(int dtype, int scheme, int form, int nx, int ny, int Q) {
     if (!asn::can_fuse(dtype, scheme) || form == ASN_FORM_SEPARATE) return false;
+    if (form == ASN_FORM_BANDED) return false;
     if (form == ASN_FORM_FUSED || dtype != ASN_GEMM_F32) return true;
     return !(nx <= asn::kFlatMaxNx && (double)nx * ny * Q >= 33554432.0);
+}
+
+// Whether a problem may take the banded step: FP32 forward Euler on a product set
+// whose azimuth count has a kernel instance (ASN_FORM_AUTO or ASN_FORM_BANDED); the
+// stored K must then also have the banded form (band_form).
+bool band_candidate(int dtype, int scheme, int form, const asn_quadrature* q, int64_t C) {
+    // the kernel addresses one polar level of planes (n_azim * P floats) with byte
+    // offsets below 2^31
+    const int64_t P = round_up(C, asn::kScaleBlock);
+    return dtype == ASN_GEMM_F32 && scheme == ASN_SCHEME_EULER &&
+           (int64_t)std::max(q->n_azim, 1) * P * 4 < ((int64_t)1 << 31) &&
+           (form == ASN_FORM_AUTO || form == ASN_FORM_BANDED) && q->q_custom == 0 &&
+           q->icosahedron_order == 0 && q->n_polar >= 1 && asn::band_azimuths_supported(q->n_azim);
 }
 
 }  // namespace
@@ -388,10 +438,23 @@ asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
     const int dtype = opt ? opt->gemm_dtype : d.gemm_dtype;
     const int scheme = opt ? opt->scheme : d.scheme;
     const int form = opt ? opt->step_form : d.step_form;
-    if (form < ASN_FORM_AUTO || form > ASN_FORM_FUSED)
-        return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, ASN_FORM_SEPARATE or ASN_FORM_FUSED");
+    if (form < ASN_FORM_AUTO || form > ASN_FORM_BANDED)
+        return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, _SEPARATE, _FUSED or _BANDED");
+    if (form == ASN_FORM_BANDED) {
+        if (!band_candidate(dtype, scheme, form, quad, (int64_t)grid->nx * grid->ny))
+            return fail(ASN_E_UNSUPPORTED, "ASN_FORM_BANDED needs FP32 forward Euler on a product "
+                                           "set with n_azim in {8, 16, ..., 64}");
+        *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme, false, quad->n_polar,
+                             quad->n_azim).total;
+        return ASN_OK;
+    }
     const bool fused = use_fused(dtype, scheme, form, grid->nx, grid->ny, Q);
-    *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme, fused).total;
+    size_t total = make_layout(grid->nx, grid->ny, Q, dtype, scheme, fused).total;
+    // whether K has the banded form is known only once K is built: cover both layouts
+    if (band_candidate(dtype, scheme, form, quad, (int64_t)grid->nx * grid->ny))
+        total = std::max(total, make_layout(grid->nx, grid->ny, Q, dtype, scheme, false, quad->n_polar,
+                                            quad->n_azim).total);
+    *bytes = total;
     return ASN_OK;
 }
 
@@ -415,8 +478,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         opt.scheme != ASN_SCHEME_IMPLICIT)
         return fail(ASN_E_INVALID, "unknown scheme");
     const bool implicit = opt.scheme == ASN_SCHEME_IMPLICIT;
-    if (opt.step_form < ASN_FORM_AUTO || opt.step_form > ASN_FORM_FUSED)
-        return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, ASN_FORM_SEPARATE or ASN_FORM_FUSED");
+    if (opt.step_form < ASN_FORM_AUTO || opt.step_form > ASN_FORM_BANDED)
+        return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, _SEPARATE, _FUSED or _BANDED");
     if (opt.source_test != ASN_SOURCE_TEST_ABSOLUTE && opt.source_test != ASN_SOURCE_TEST_RELATIVE)
         return fail(ASN_E_INVALID, "source_test must be ASN_SOURCE_TEST_ABSOLUTE or ASN_SOURCE_TEST_RELATIVE");
     if (opt.dt_rule != ASN_DT_STREAMING && opt.dt_rule != ASN_DT_STIFF)
@@ -482,8 +545,32 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     }
     p->stability = p->dt * srate;
 
-    p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme,
-                       use_fused(p->dtype, p->scheme, opt.step_form, p->nx, p->ny, Q));
+    // banded step when K has that form (ASN_FORM_AUTO) or on request (ASN_FORM_BANDED)
+    asn::BandForm bf;
+    bool banded = false;
+    if (band_candidate(p->dtype, p->scheme, opt.step_form, quad, C)) {
+        std::vector<float> K32((size_t)Q * Q);
+        for (size_t i = 0; i < K32.size(); ++i) K32[i] = (float)K[i];
+        banded = asn::band_form(quad->n_polar, quad->n_azim, K32.data(), asn::kBandMaxReach,
+                                asn::kBandNarrow, bf);
+    }
+    if (opt.step_form == ASN_FORM_BANDED && !banded) {
+        delete p;
+        return fail(ASN_E_UNSUPPORTED,
+                    "ASN_FORM_BANDED needs FP32 forward Euler on a product set with n_azim in "
+                    "{8, 16, ..., 64}, n_azim * cells below 2^29, and a K that couples polar "
+                    "levels at most 3 apart and is circulant along the azimuth in FP32");
+    }
+    if (banded) {
+        p->band_levels = bf.levels;
+        p->band_azim = bf.azim;
+        p->band_reach = bf.reach;
+        p->band_cmax = bf.cmax;
+        p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme, false, bf.levels, bf.azim);
+    } else {
+        p->L = make_layout(p->nx, p->ny, Q, p->dtype, p->scheme,
+                           use_fused(p->dtype, p->scheme, opt.step_form, p->nx, p->ny, Q));
+    }
     const Layout& L = p->L;
     if (workspace) {
         if (workspace_bytes < L.total) {
@@ -598,6 +685,13 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                        p->stream) != hipSuccess ||
         hipMemcpyAsync(b + L.off_ktab, ktab.data(), ktab.size() * 4, hipMemcpyHostToDevice,
                        p->stream) != hipSuccess ||
+        (banded && (hipMemcpyAsync(b + L.off_band, bf.desc.data(), bf.desc.size() * 4,
+                                   hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                    hipMemcpyAsync(b + L.off_brange, bf.range.data(), bf.range.size() * 4,
+                                   hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                    hipMemcpyAsync(b + L.off_bcoef, bf.coef.data(), bf.coef.size() * 4,
+                                   hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                    asn::prepare_banded(bf.azim, p->band_lds()) != hipSuccess)) ||
         (L.lowp && hipMemcpyAsync(b + L.off_Klp, Klp.data(), Klp.size() * 2,
                                   hipMemcpyHostToDevice, p->stream) != hipSuccess) ||
         hipMemcpyAsync(b + L.off_coef, coef.data(), coef.size() * 16, hipMemcpyHostToDevice,
@@ -711,6 +805,7 @@ asn_status asn_get_state(asn_problem p, float* psi, int32_t on_device) {
 // The scheme the kernels are launched with: a separate-kernel step whose stencil
 // runs over flat cell chunks (Euler or Heun) has a launch form of its own.
 static int launch_scheme(asn_problem p) {
+    if (p->L.banded) return asn::SCHEME_EULER_BANDED;
     if (!p->L.flat) return p->scheme;
     return p->scheme == ASN_SCHEME_HEUN ? asn::SCHEME_HEUN_FLAT : asn::SCHEME_EULER_FLAT;
 }
@@ -733,9 +828,11 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
     }
     HIP_TRY(arm_single(p, n_steps));
     asn::BatchArgs b = single_batch(p);
+    const size_t lds = p->L.banded ? p->band_lds() : 0;
     for (int64_t i = 0; i < n_steps; ++i) {
         b.s_par = (int)(i & 1);
-        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, launch_scheme(p), p->stream));
+        HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, launch_scheme(p), p->stream, nullptr,
+                                 p->band_azim, lds));
     }
     p->cur ^= state_flip(p->scheme, n_steps);
     p->steps_done += n_steps;
@@ -776,8 +873,9 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     asn::BatchArgs bt = single_batch(p);
     for (int64_t i = 0; st == ASN_OK && i < n_steps; ++i) {
         bt.s_par = (int)(i & 1);
-        const hipError_t e =
-            asn::launch_step(bt, p->blocks, p->dtype, launch_scheme(p), p->stream, &ev[(size_t)i * per]);
+        const hipError_t e = asn::launch_step(
+            bt, p->blocks, p->dtype, launch_scheme(p), p->stream, &ev[(size_t)i * per], p->band_azim,
+            p->L.banded ? p->band_lds() : 0);
         if (e != hipSuccess) {
             st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
             break;
@@ -826,6 +924,10 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
             return fail(ASN_E_INVALID, "problems of a batch must share the kernel form "
                                        "(asn_step_form; ask for ASN_FORM_FUSED or ASN_FORM_SEPARATE "
                                        "when their sizes differ)");
+        if (probs[i]->L.banded != probs[0]->L.banded ||
+            probs[i]->band_azim != probs[0]->band_azim)
+            return fail(ASN_E_INVALID, "problems of a banded batch must share the azimuth count "
+                                       "(and a batch is banded for all its problems or none)");
         if (probs[i]->L.flat != probs[0]->L.flat)
             return fail(ASN_E_INVALID, std::string("problems of a batch must share the stencil form: ") +
                                        "separate-kernel steps use flat cell chunks up to nx = " +
@@ -842,6 +944,10 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
     b->dtype = probs[0]->dtype;
     b->scheme = probs[0]->scheme;
     b->launch_scheme = launch_scheme(probs[0]);
+    b->band_az = probs[0]->band_azim;
+    for (int32_t i = 0; i < n; ++i)
+        if (probs[i]->L.banded)
+            b->band_lds = std::max(b->band_lds, probs[i]->band_lds());
     b->stream = probs[0]->stream;
     b->tab.resize(2 * (size_t)n);
     b->off.assign((size_t)asn::KT_COUNT * (n + 1), 0);
@@ -905,7 +1011,8 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
             hipError_t e = hipSuccess;
             for (int64_t j = 0; j < n_steps && e == hipSuccess; ++j) {
                 args.s_par = (int)(j & 1);
-                e = asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream);
+                e = asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream, nullptr,
+                                     b->band_az, b->band_lds);
             }
             const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -923,7 +1030,8 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
     } else {
         for (int64_t j = 0; j < n_steps; ++j) {
             args.s_par = (int)(j & 1);
-            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream));
+            HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream, nullptr,
+                                     b->band_az, b->band_lds));
         }
     }
     for (int i = 0; i < b->n; ++i) {
@@ -999,7 +1107,7 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
 
 asn_status asn_step_form(asn_problem p, int32_t* form) {
     if (!p || !form) return fail(ASN_E_INVALID, "NULL argument");
-    *form = p->L.fused ? ASN_FORM_FUSED : ASN_FORM_SEPARATE;
+    *form = p->L.banded ? ASN_FORM_BANDED : p->L.fused ? ASN_FORM_FUSED : ASN_FORM_SEPARATE;
     return ASN_OK;
 }
 
@@ -1091,6 +1199,41 @@ asn_status asn_build_kernel_lowp(int32_t q, const double* k_in, int32_t gemm_dty
     if (gemm_dtype != ASN_GEMM_BF16 && gemm_dtype != ASN_GEMM_F16)
         return fail(ASN_E_INVALID, "gemm_dtype must be ASN_GEMM_BF16 or ASN_GEMM_F16");
     quantise_kernel(q, k_in, gemm_dtype, q, k_bits, row_defect);
+    return ASN_OK;
+}
+
+asn_status asn_band_expand(int32_t n_polar, int32_t n_azim, const double* k_in, float* k_out,
+                           int32_t* reach) {
+    if (n_polar < 1 || n_azim < 1 || (int64_t)n_polar * n_azim > 16384 || !k_in || !k_out || !reach)
+        return fail(ASN_E_INVALID, "invalid band request");
+    const int Q = n_polar * n_azim;
+    std::vector<float> K32((size_t)Q * Q);
+    for (size_t i = 0; i < K32.size(); ++i) K32[i] = (float)k_in[i];
+    asn::BandForm bf;
+    if (!asn::band_form(n_polar, n_azim, K32.data(), asn::kBandMaxReach, asn::kBandNarrow, bf))
+        return fail(ASN_E_UNSUPPORTED, "K has no banded form");
+    // decode the per-level descriptors the kernel reads
+    std::fill(k_out, k_out + (size_t)Q * Q, 0.f);
+    auto put_run = [&](int i, int k, int lo, int len, int first) {
+        const int j = i + k - bf.reach;
+        for (int t = 0; t < len; ++t) {
+            const int delta = lo + t;
+            for (int kk = 0; kk < n_azim; ++kk) {
+                const int kp = ((kk + delta) % n_azim + n_azim) % n_azim;
+                k_out[(size_t)(i * n_azim + kk) * Q + j * n_azim + kp] = bf.coef[first + t];
+            }
+        }
+    };
+    for (int i = 0; i < n_polar; ++i) {
+        const int n = (int)bf.desc[(size_t)i * 8];
+        for (int p = 0; p < n; ++p) {
+            const uint32_t c = bf.desc[(size_t)i * 8 + 1 + p];
+            int lo = 0, len = 0;
+            asn::band_run(c, n_azim, lo, len);
+            put_run(i, (int)((c >> 8) & 7u), lo, len, bf.range[2 * (size_t)i] + 4 * (int)(c >> 11));
+        }
+    }
+    *reach = bf.reach;
     return ASN_OK;
 }
 

@@ -337,3 +337,67 @@ float half_to_float(uint16_t h) {
 }
 
 }  // namespace asn
+
+namespace asn {
+
+bool band_form(int levels, int azim, const float* K32, int max_reach, int narrow_max,
+               BandForm& out) {
+    if (levels < 1 || azim < 2 || azim % 2 || azim > 126 || max_reach > 3) return false;
+    const int Q = levels * azim;
+    auto wrap = [azim](int d) { return ((d % azim) + azim) % azim; };
+    // every row equals the first row of its level, shifted by the row's azimuth
+    for (int i = 0; i < levels; ++i)
+        for (int k = 1; k < azim; ++k) {
+            const float* r0 = K32 + (size_t)(i * azim) * Q;
+            const float* rk = K32 + (size_t)(i * azim + k) * Q;
+            for (int j = 0; j < levels; ++j)
+                for (int kp = 0; kp < azim; ++kp)
+                    if (rk[j * azim + kp] != r0[j * azim + wrap(kp - k)]) return false;
+        }
+    int reach = 0;
+    for (int i = 0; i < levels; ++i)
+        for (int j = 0; j < levels; ++j)
+            for (int kp = 0; kp < azim; ++kp)
+                if (K32[(size_t)(i * azim) * Q + j * azim + kp] != 0.f)
+                    reach = std::max(reach, std::abs(i - j));
+    if (reach > max_reach) return false;
+    out.levels = levels;
+    out.azim = azim;
+    out.reach = reach;
+    out.cmax = 0;
+    out.desc.assign((size_t)levels * 8, 0u);
+    out.range.assign((size_t)levels * 2, 0);
+    out.coef.clear();
+    for (int i = 0; i < levels; ++i) {
+        const int base = (int)out.coef.size();
+        int n = 0;
+        for (int k = 0; k < 2 * reach + 1; ++k) {
+            const int j = i + k - reach;
+            if (j < 0 || j >= levels) continue;
+            const float* r0 = K32 + (size_t)(i * azim) * Q + j * azim;
+            int s = -1;
+            for (int kp = 0; kp < azim; ++kp)
+                if (r0[kp] != 0.f) s = std::max(s, std::min(kp, azim - kp));
+            if (s < 0) continue;
+            const bool ring = 2 * s + 1 >= azim;
+            const int start4 = ((int)out.coef.size() - base) / 4;
+            if (start4 > 127) return false;
+            const uint32_t c = (uint32_t)(ring ? azim / 2 : s) | (ring || s > narrow_max ? 64u : 0u) |
+                               (ring ? 128u : 0u) | ((uint32_t)k << 8) | ((uint32_t)start4 << 11);
+            out.desc[(size_t)i * 8 + 1 + n] = c;
+            ++n;
+            int lo = 0, len = 0;
+            band_run(c, azim, lo, len);
+            for (int t = 0; t < len; ++t) out.coef.push_back(r0[wrap(lo + t)]);
+            while (out.coef.size() % 4) out.coef.push_back(0.f);
+        }
+        out.desc[(size_t)i * 8] = (uint32_t)n;
+        out.range[2 * (size_t)i] = base;
+        out.range[2 * (size_t)i + 1] = (int)out.coef.size() - base;
+        if ((int)out.coef.size() - base > 508) return false;
+        out.cmax = std::max(out.cmax, (int)out.coef.size() - base);
+    }
+    return true;
+}
+
+}  // namespace asn

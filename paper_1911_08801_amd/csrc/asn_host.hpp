@@ -29,6 +29,42 @@ void icosahedron_quadrature(int order, std::vector<double>& omega, std::vector<d
 bool kernel_matrix(int Q, const double* omega, const double* w, double eps, int mode,
                    std::vector<double>& K, std::string& err);
 
+// Banded form of K for a product set of `levels` polar levels times `azim` azimuths
+// (ordinate q = i * azim + k).  The set is invariant under rotations by 2 pi / azim
+// about the polar axis, so K[(i, k), (j, k')] depends on i, j and (k' - k) mod azim
+// only: per pair of levels one run of coefficients c_ij(delta) over azimuth offsets,
+// nonzero for |delta| <= s_ij (cyclic distance).  Pair k of level i is level
+// j = i + k - reach, k = 0 .. 2 reach.  A run either is symmetric, delta = -s .. s
+// (2 s + 1 < azim), or covers the whole ring, delta = 1 - azim/2 .. azim/2; the runs
+// of a level are stored one after the other, each zero-padded to a multiple of 4, at
+// coef[range[2 i] .. range[2 i] + range[2 i + 1]).  desc[8 i .. 8 i + 7] describes
+// level i: desc[8 i] is the number n of coupled pairs, desc[8 i + 1 + p] (p < n) the
+// code of pair p:
+//   bits 0-5   s (azim / 2 for a whole ring)       bit 6  wide: whole ring or s > narrow_max
+//   bit 7      whole ring                          bits 8-10  k
+//   bits 11-17 the run's start within the level, in units of 4 coefficients.
+// cmax is the largest coefficient count of a level; reach the largest |i - j| with a
+// nonzero.
+struct BandForm {
+    int levels = 0, azim = 0, reach = 0, cmax = 0;
+    std::vector<uint32_t> desc;
+    std::vector<int32_t> range;
+    std::vector<float> coef;
+};
+// From the FP32 values K32[Q][Q] (row-major); false when the stored values are not
+// exactly of that form (every row of a level equal to the level's first row shifted),
+// when reach exceeds max_reach (at most 3) or a level has more than 508 coefficients.
+// Even azim up to 126.
+bool band_form(int levels, int azim, const float* K32, int max_reach, int narrow_max,
+               BandForm& out);
+// The run of a pair code: first offset and length.
+inline void band_run(uint32_t code, int azim, int& lo, int& len) {
+    const int s = (int)(code & 63u);
+    const bool ring = (code & 128u) != 0;
+    lo = ring ? 1 - azim / 2 : -s;
+    len = ring ? azim : 2 * s + 1;
+}
+
 // dt = t_final / n with n = ceil(t_final / dt_max), dt_max = cfl / max(|xi|/dx + |eta|/dy).
 void cfl_time_step(int Q, const double* omega, double dx, double dy, double cfl, double t_final,
                    double& dt, int64_t& n);

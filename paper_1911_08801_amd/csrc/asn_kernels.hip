@@ -1860,25 +1860,412 @@ __global__ void broadcast_kernel(float* psi, const float* cell, int Q, int64_t C
 }
 
 // ---------------------------------------------------------------------------
+// 5. Banded forward-Euler step for product ordinate sets (FP32).
+//    The set is invariant under rotations by 2 pi / n_az about the polar axis, so
+//    Y_(i,k) = sum_j sum_delta c_ij(delta) psi_(j, k + delta): per output level a
+//    short circular convolution along the azimuth with each of the levels within
+//    `reach`.  Block = kBandCells consecutive cells (flat index) x every ordinate,
+//    walking the levels in order.  Ring slot l % (2 reach + 2) holds level l of the
+//    block's cells (and the cell before and after them); while output level i is
+//    computed, level i + reach + 1 is written into the slot level i - reach - 1 left
+//    and level i + reach + 2 is loaded into registers, so one LDS barrier per level
+//    suffices and each cell-ordinate of psi^n is read from memory once.  Level i's
+//    coefficients sit in one of two LDS buffers (written a level ahead); its
+//    descriptor is a scalar load made a level ahead.  A lane's outputs of a level are
+//    kBandO consecutive azimuths of one cell.  Narrow pairs (coupling azimuths at
+//    most kBandNarrow apart) are unrolled per width with their LDS rows at
+//    compile-time offsets (the slot carries wrapped copies of the rows at either end);
+//    wide pairs go in steps of four offsets from the wrapped start row.  The epilogue is the stream + collide update of
+//    stream_collide_flat_kernel (same arithmetic); the x-upwind value comes from the
+//    slot, the y-upwind value from memory (loaded a level ahead).  The block writes
+//    each cell's complete Phi^{n+1} (one partial, G = 1) and its defect and outflow
+//    partials, in a fixed order.
+// ---------------------------------------------------------------------------
+// The band tables are written by the host before any step and only read by the
+// kernels: reached through the constant address space, their uniform loads are scalar
+// (SMEM) loads, which do not wait behind the vector memory counter.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ASN_K __attribute__((address_space(4)))
+#else
+#define ASN_K
+#endif
+template <typename T>
+__device__ __forceinline__ const ASN_K T* kp(const T* p) {
+    return (const ASN_K T*)p;
+}
+
+// A narrow pair: offsets -S .. S.  row: the lane's column in the row of its first
+// output azimuth; cf: the run's coefficients in LDS (16-byte aligned, the same words
+// for every lane).
+template <int S>
+__device__ __forceinline__ void band_narrow(float (&acc)[kBandO], const float* row,
+                                            const float* cf) {
+    constexpr int O = kBandO, N = O + 2 * S, NC = (2 * S + 4) / 4;
+    float in[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) in[j] = row[(j - S) * kBandStride];
+    float k[4 * NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        const float4 v = reinterpret_cast<const float4*>(cf)[t];
+        k[4 * t] = v.x;
+        k[4 * t + 1] = v.y;
+        k[4 * t + 2] = v.z;
+        k[4 * t + 3] = v.w;
+    }
+#pragma unroll
+    for (int d = 0; d <= 2 * S; ++d)
+#pragma unroll
+        for (int o = 0; o < O; ++o) acc[o] = fmaf(k[d], in[o + d], acc[o]);
+}
+
+// A wide pair: offsets lo .. lo + len - 1 in steps of four (coefficients past len are
+// zero) from the slot row of azimuth a0 + lo wrapped into [0, A).  slot: the lane's
+// column in row 0 of the slot.
+template <int A>
+__device__ __forceinline__ void band_wide(float (&acc)[kBandO], const float* slot, int a0, int lo,
+                                          int len, const float* cf) {
+    constexpr int O = kBandO;
+    for (int j0 = 0; j0 < len; j0 += 4) {
+        int m = a0 + lo + j0;
+        m = m < 0 ? m + A : (m >= A ? m - A : m);
+        const float* r = slot + (m + kBandLead) * kBandStride;
+        float in[O + 3];
+#pragma unroll
+        for (int u = 0; u < O + 3; ++u) in[u] = r[u * kBandStride];
+        const float4 k = reinterpret_cast<const float4*>(cf)[j0 / 4];
+        const float kk[4] = {k.x, k.y, k.z, k.w};
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int o = 0; o < O; ++o) acc[o] = fmaf(kk[d], in[o + d], acc[o]);
+    }
+}
+
+template <int A>
+__global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
+    constexpr int O = kBandO, NW = A / (2 * O), ROWS = kBandLead + A + kBandTrail;
+    constexpr int SLOT = ROWS * kBandStride;
+    extern __shared__ float ring[];
+    int pi, local;
+    if (!locate(B, KT_SC, xcd_remap(blockIdx.x, gridDim.x), pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int tid = threadIdx.x, wave = tid >> 6, h = (tid >> 5) & 1, c = tid & 31;
+    const int a0 = (2 * wave + h) * O;
+    const int nx = a.nx, ny = a.ny, L = a.n_lev, R = a.reach, NS = 2 * R + 2;
+    const int C = (int)a.C, CM = a.bcmax;
+    const int64_t P = a.P;
+    const int c0 = local * kBandCells, cell = c0 + c;
+    const bool in = cell < C;
+    float* stage = ring + NS * SLOT;   // two buffers of CM coefficients
+    const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    const ASN_K QInfo* qk = kp(a.qi);
+    const ASN_K uint4* ldesc = kp(a.band);
+    const ASN_K int2* lrange = kp(a.brange);
+    const ASN_G float* __restrict__ bcoef = gp(a.bcoef);
+
+    float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
+    float isov = 0.f;
+    if (in) {
+        cf = gp(a.coef)[cell];
+        isov = gp(a.iso)[cell];
+    }
+    const int y = cell / nx, x = cell - y * nx;
+    const int e = in ? ((x == 0 ? 1 : 0) | (x == nx - 1 ? 2 : 0) | (y == 0 ? 4 : 0) |
+                        (y == ny - 1 ? 8 : 0))
+                     : 0;
+    const bool wedge = __ballot(e != 0) != 0;   // some lane of the wave is on the boundary
+    // Memory is reached through one buffer descriptor per level (uniform; the two
+    // halves of a wave hold different azimuths) and a per-lane byte offset within the
+    // level, (a0 + o) P + cell floats; offsets at or beyond the level read 0.
+    const uint32_t lvl_bytes = (uint32_t)(A * P * 4);
+    const uint32_t pb = (uint32_t)(P * 4);   // bytes of an azimuth plane
+    // the lane's cell in its first azimuth plane (plane o: + o pb)
+    const uint32_t off0 = 4u * (uint32_t)(a0 * P) + 4u * (uint32_t)cell;
+    uint32_t yoff[O];    // its y-upwind cell (kOOB below the grid; masked at ghosts anyway)
+    uint32_t dirs = 0;   // 4 bits per azimuth: the direction is the same on every level
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+        const int d = qtab[a0 + o].dir;
+        dirs |= (uint32_t)d << (4 * o);
+        const int yc = (d & 4) ? cell - nx : cell + nx;
+        yoff[o] = (yc >= 0) ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
+    }
+    auto level_in = [&](int l) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.psi) + (size_t)l * A * P, 0,
+                                                 (int)lvl_bytes, kRsrcWord3);
+    };
+
+    // Ring fill: the lane's kBandO azimuths of level l, cell c.  Lanes 0 and 31 also
+    // fetch the cell before / after the block (the other lanes' halo offsets lie
+    // outside the level and read 0) into column 0 / 33 of the row; the other lanes
+    // write theirs into a padding column.  The first kBandTrail and the last kBandLead
+    // azimuths are also written to their wrapped copy (other rows: to themselves
+    // again).  No branches.
+    struct Fill {
+        float v[O], lo[O];   // the cell, and the block's halo cell (lanes 0 and 31)
+    };
+    const int hcol = c == 0 ? 0 : (c == 31 ? 33 : 34);
+    // halo offset of the lane relative to its cell's (kOOB: reads 0)
+    const bool hvalid = (c == 0 && c0 > 0) || c == 31;
+    const uint32_t hdel = c == 0 ? (uint32_t)-4 : 4u;
+    // the lane's rows for azimuth a0 + o: own (rrow0 + o kBandStride), wrapped copies
+    // after the last and before the first azimuth (at most one unless A < lead + trail)
+    constexpr bool kTwoCopies = A < kBandLead + kBandTrail;
+    const int rrow0 = (a0 + kBandLead) * kBandStride;
+    auto fetch = [&](int l, Fill& f) {
+        const __amdgpu_buffer_rsrc_t r = level_in(l);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const uint32_t of = off0 + (uint32_t)o * pb;
+            f.v[o] = load_plane(r, of);
+            f.lo[o] = load_plane(r, hvalid ? of + hdel : kOOB);
+        }
+    };
+    auto put = [&](int slot, const Fill& f) {
+        float* s = ring + slot * SLOT;
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const int az = a0 + o, rr = rrow0 + o * kBandStride;
+            const int up = az < kBandTrail ? rr + A * kBandStride : rr;
+            const int dn = az >= A - kBandLead ? rr - A * kBandStride : rr;
+            s[rr + c + 1] = f.v[o];
+            s[rr + hcol] = f.lo[o];
+            const int w1 = kTwoCopies ? up : (up != rr ? up : dn);
+            s[w1 + c + 1] = f.v[o];
+            s[w1 + hcol] = f.lo[o];
+            if constexpr (kTwoCopies) {
+                s[dn + c + 1] = f.v[o];
+                s[dn + hcol] = f.lo[o];
+            }
+        }
+    };
+    // a level's coefficients: thread t holds number t (the count is below the block
+    // size: at most 2 reach + 1 runs of at most n_az)
+    auto fetch_coef = [&](int l) {
+        const int2 rg = lrange[l];
+        return bcoef[rg.x + min(tid, rg.y - 1)];
+    };
+    auto put_coef = [&](int l, float v) {
+        if (tid < CM) stage[(l & 1) * CM + tid] = v;
+    };
+    // per level, loaded one level ahead (after the level's stores, so that the wait
+    // for them in the next epilogue does not also wait for the prefetches, which are
+    // issued later): the y-upwind values and the ordinates' constants (the weight w_q
+    // of a product set depends on the level only: a scalar load)
+    struct Ahead {
+        float y[O], cx[O], cy[O];
+        double w;
+    };
+    auto fetch_ahead = [&](int l, Ahead& ah) {
+        const __amdgpu_buffer_rsrc_t r = level_in(l);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const int q = l * A + a0 + o;
+            ah.y[o] = load_plane(r, yoff[o]);
+            ah.cx[o] = qtab[q].cx;
+            ah.cy[o] = qtab[q].cy;
+        }
+        ah.w = qk[l * A].w;
+    };
+
+    {   // prologue: levels 0 .. reach into the ring, level 0's coefficients staged
+        Fill f;
+        for (int l = 0; l <= R && l < L; ++l) {
+            fetch(l, f);
+            put(l, f);   // slot l
+        }
+        put_coef(0, fetch_coef(0));
+    }
+    // The values loaded a level ahead alternate between two register sets (the loop
+    // body is written twice), and every load is unconditional (the last level again
+    // near the end), so no loop-carried copy of a load in flight forces a wait.
+    float cpre = fetch_coef(min(1, L - 1));
+    Fill pre;
+    fetch(min(R + 1, L - 1), pre);
+    Ahead ahA, ahB;
+    uint4 dA = ldesc[0], dB = ldesc[1];   // level 0's descriptor
+    uint4 eA, eB;                         // level 1's
+    fetch_ahead(0, ahA);
+    lds_barrier();
+
+    double phacc = 0.0, defect = 0.0, outflow = 0.0;
+    auto wrap_slot = [NS](int s) { return s < 0 ? s + NS : (s >= NS ? s - NS : s); };
+    // level i in ring slot si: `pre` holds level i + reach + 1 and is refilled with
+    // level i + reach + 2, `cpre` holds level i + 1's coefficients and is refilled with
+    // level i + 2's; `d0`, `d1` / `ah` hold level i's descriptor / constants and
+    // y-upwind values, `n0`, `n1` / `ah_next` receive level i + 1's
+    auto level = [&](int i, int si, const uint4& d0, const uint4& d1, uint4& n0, uint4& n1,
+                     const Ahead& ah, Ahead& ah_next) {
+        // into the slot level i - reach - 1 held and the buffer level i - 1's coefficients
+        // held (their last readers passed the barrier)
+        if (i + R + 1 < L) put(wrap_slot(si + R + 1), pre);
+        put_coef(i + 1, cpre);
+        cpre = fetch_coef(min(i + 2, L - 1));
+        fetch(min(i + R + 2, L - 1), pre);
+        n0 = ldesc[2 * min(i + 1, L - 1)];
+        n1 = ldesc[2 * min(i + 1, L - 1) + 1];
+        // contraction, one pair of levels at a time
+        const float* cbuf = stage + (i & 1) * CM;
+        float acc[O];
+#pragma unroll
+        for (int o = 0; o < O; ++o) acc[o] = 0.f;
+        const int n_pairs = (int)d0.x;
+        for (int p = 0; p < n_pairs; ++p) {
+            const uint32_t code = p == 0 ? d0.y : (p == 1 ? d0.z : (p == 2 ? d0.w :
+                                  (p == 3 ? d1.x : (p == 4 ? d1.y : (p == 5 ? d1.z : d1.w)))));
+            const int s = (int)(code & 63u);
+            const int k = (int)((code >> 8) & 7u);
+            const float* slot = ring + wrap_slot(si + k - R) * SLOT + c + 1;
+            const float* cfp = cbuf + 4 * (int)(code >> 11);
+            if (!(code & 64u)) {
+                const float* row = slot + (a0 + kBandLead) * kBandStride;
+                switch (s) {
+                    case 0: band_narrow<0>(acc, row, cfp); break;
+                    case 1: band_narrow<1>(acc, row, cfp); break;
+                    case 2: band_narrow<2>(acc, row, cfp); break;
+                    case 3: band_narrow<3>(acc, row, cfp); break;
+                    case 4: band_narrow<4>(acc, row, cfp); break;
+                    case 5: band_narrow<5>(acc, row, cfp); break;
+                    case 6: band_narrow<6>(acc, row, cfp); break;
+                    case 7: band_narrow<7>(acc, row, cfp); break;
+                    default: band_narrow<8>(acc, row, cfp); break;
+                }
+            } else {
+                const bool whole = (code & 128u) != 0;
+                band_wide<A>(acc, slot, a0, whole ? 1 - A / 2 : -s, whole ? A : 2 * s + 1, cfp);
+            }
+        }
+        // stream + collide of the lane's outputs
+        const float* own = ring + si * SLOT + (a0 + kBandLead) * kBandStride + c + 1;
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            a.psi_new + (size_t)i * A * P, 0, (int)lvl_bytes, kRsrcWord3);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+            const int dd = (int)((dirs >> (4 * o)) & 15u);
+            const float* pc = own + o * kBandStride;
+            const float v = pc[0];
+            const float ux = (dd & e & 3) ? 0.f : ((dd & 1) ? pc[-1] : pc[1]);
+            const float uy = (dd & e & 12) ? 0.f : ah.y[o];
+            const float col = cf.z * (acc[o] - v) + cf.y * (isov - v);
+            const float r = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
+            const float nv = in ? r : 0.f;   // padding cells stay zero
+            store_plane(nv, ro, off0 + (uint32_t)o * pb);
+            phacc += ah.w * (double)nv;
+            defect += ah.w * (double)(in ? col : 0.f);
+            if (wedge) {
+                const int dout = ((dd & 5) << 1) | ((dd & 10) >> 1);   // outflow faces of dd
+                const int go = dout & e;
+                const float ob = in ? ((go & 3) ? ah.cx[o] * v : 0.f) + ((go & 12) ? ah.cy[o] * v : 0.f)
+                                    : 0.f;
+                outflow += ah.w * (double)ob;
+            }
+        }
+        fetch_ahead(min(i + 1, L - 1), ah_next);
+        lds_barrier();
+    };
+    int si = 0;   // ring slot of level i
+    for (int i = 0; i < L; i += 2) {
+        level(i, si, dA, dB, eA, eB, ahA, ahB);
+        si = wrap_slot(si + 1);
+        if (i + 1 >= L) break;
+        level(i + 1, si, eA, eB, dA, dB, ahB, ahA);
+        si = wrap_slot(si + 1);
+    }
+
+    // Phi^{n+1} of each cell: the 2 NW lane groups' partials in a fixed order
+    double* red = reinterpret_cast<double*>(ring);
+    red[(2 * wave + h) * kBandCells + c] = phacc;
+    lds_barrier();
+    if (tid < kBandCells && in) {
+        double s = red[c];
+#pragma unroll
+        for (int g = 1; g < 2 * NW; ++g) s += red[g * kBandCells + c];
+        gp(a.phi_part)[cell] = s;
+    }
+    double sums[2] = {defect, outflow};
+    block_sum_waves<NW, 2>(sums, gp(a.blk_part) + 2 * (size_t)local);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
-    out[KT_GEMM] = (a.Qp / kGemmBM) * (int)(a.P / kGemmBN);
+    const bool banded = a.band != nullptr;
+    out[KT_GEMM] = banded ? 0 : (a.Qp / kGemmBM) * (int)(a.P / kGemmBN);
     out[KT_FIX] = (a.dtype != 0 && !a.fused) ? a.fin_blocks : 0;
     out[KT_SC] = a.fused ? 0 : a.tiles_x * a.tiles_y * a.G;
     out[KT_FIN] = a.fin_blocks;
     out[KT_BUDGET] = 1;
 }
 
-// One pass: contraction, stencil (kind 0 donor cell, 1 / 2 Heun stage), finalize, budget.
+template <int A>
+static void launch_banded_az(const BatchArgs& b, int blocks, size_t lds, hipStream_t s) {
+    banded_euler_kernel<A><<<blocks, 8 * A, lds, s>>>(b);
+}
+
+static hipError_t launch_banded(const BatchArgs& b, int blocks, int az, size_t lds, hipStream_t s) {
+    switch (az) {
+        case 8: launch_banded_az<8>(b, blocks, lds, s); break;
+        case 16: launch_banded_az<16>(b, blocks, lds, s); break;
+        case 24: launch_banded_az<24>(b, blocks, lds, s); break;
+        case 32: launch_banded_az<32>(b, blocks, lds, s); break;
+        case 40: launch_banded_az<40>(b, blocks, lds, s); break;
+        case 48: launch_banded_az<48>(b, blocks, lds, s); break;
+        case 56: launch_banded_az<56>(b, blocks, lds, s); break;
+        case 64: launch_banded_az<64>(b, blocks, lds, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
+template <int A>
+static hipError_t prepare_banded_az(size_t lds) {
+    return hipFuncSetAttribute((const void*)banded_euler_kernel<A>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t prepare_banded(int az, size_t lds) {
+    switch (az) {
+        case 8: return prepare_banded_az<8>(lds);
+        case 16: return prepare_banded_az<16>(lds);
+        case 24: return prepare_banded_az<24>(lds);
+        case 32: return prepare_banded_az<32>(lds);
+        case 40: return prepare_banded_az<40>(lds);
+        case 48: return prepare_banded_az<48>(lds);
+        case 56: return prepare_banded_az<56>(lds);
+        case 64: return prepare_banded_az<64>(lds);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Stencil kinds of a pass: 0 donor-cell strips, 1 / 2 Heun stages (strips), 3 donor-cell
+// flat chunks, 4 / 5 Heun stages (flat chunks), kStencilBanded the banded step (its
+// contraction and stencil are one kernel).
+constexpr int kStencilBanded = 16;
+
+// One pass: contraction, stencil, finalize, budget.
 static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, int stencil,
-                              int bud, hipStream_t s, hipEvent_t* ev) {
+                              int bud, hipStream_t s, hipEvent_t* ev, int band_az = 0,
+                              size_t band_lds = 0) {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
+    if (stencil == kStencilBanded) {   // contraction and stencil in one kernel
+        mark(0);
+        e = launch_banded(b, grid[KT_SC], band_az, band_lds, s);
+        mark(1);
+        mark(2);
+        if (e == hipSuccess) finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
+        mark(3);
+        if (e == hipSuccess) budget_kernel<<<grid[KT_BUDGET], kBudgetThreads, 0, s>>>(b, BUD_STEP);
+        mark(4);
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    }
     // a batch whose stencil grid is empty runs the stencil inside the contraction
     const bool fused = grid[KT_SC] == 0;
     mark(0);
@@ -1926,7 +2313,9 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
 }
 
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
-                       hipEvent_t* ev) {
+                       hipEvent_t* ev, int band_az, size_t band_lds) {
+    if (scheme == SCHEME_EULER_BANDED)
+        return launch_pass(b, grid, dtype, kStencilBanded, BUD_STEP, s, ev, band_az, band_lds);
     if (scheme != SCHEME_HEUN && scheme != SCHEME_HEUN_FLAT)
         return launch_pass(b, grid, dtype, scheme == SCHEME_EULER_FLAT ? 3 : 0, BUD_STEP, s, ev);
     const int st = scheme == SCHEME_HEUN_FLAT ? 4 : 1;   // stencil of the first pass

@@ -55,6 +55,34 @@ constexpr int SCHEME_HEUN_FLAT = 4;
 constexpr int kFlatResident = 512;
 constexpr int kFlatMaxNxM = (kFlatRounds * kFlatCells - kFlatCells - 8) / 3;
 
+// Banded forward-Euler step (product ordinate sets, FP32): one kernel per step does
+// the contraction, the stream + collide update, the moments and the budget partials.
+// A block owns kBandCells consecutive cells (flat index) and every ordinate: it walks
+// the polar levels in order with a ring of 2 reach + 2 level slots in LDS, each slot
+// kBandLead + n_az + kBandTrail azimuth rows (wrapped copies of the last kBandLead and
+// the first kBandTrail azimuths around the n_az rows) of kBandStride floats (the cells
+// plus one neighbour on each side, padded), and the current level's coefficients
+// staged in LDS.  Lane (wave w, half h, cell c) produces azimuths (2 w + h) kBandO ..
+// + kBandO - 1 of every level for cell c, so a block has n_az / (2 kBandO) waves.
+// Level pairs coupling azimuths at most kBandNarrow apart are unrolled per width;
+// wider ones run in steps of four offsets.
+constexpr int SCHEME_EULER_BANDED = 5;
+constexpr int kBandCells = 32;
+constexpr int kBandO = 4;
+constexpr int kBandNarrow = 8;
+constexpr int kBandLead = kBandNarrow;     // rows before azimuth 0 (narrow reach)
+constexpr int kBandTrail = kBandO + 2;     // rows after the last azimuth (a step of four)
+constexpr int kBandStride = 40;
+constexpr int kBandMaxReach = 3;
+// Azimuth counts with a kernel instance.
+inline bool band_azimuths_supported(int az) { return az >= 8 && az <= 64 && az % 8 == 0; }
+// Dynamic LDS of a banded block: the ring, then two level-coefficient buffers of cmax
+// floats (cmax a multiple of 4).
+inline size_t band_lds_bytes(int az, int reach, int cmax) {
+    return (size_t)(2 * reach + 2) * (kBandLead + az + kBandTrail) * kBandStride * 4 +
+           2 * (size_t)cmax * 4;
+}
+
 // Modes of the budget kernel.
 enum { BUD_STEP = 0, BUD_INIT = 1, BUD_STAGE1 = 2, BUD_STAGE2 = 3 };
 
@@ -117,6 +145,14 @@ struct StepArgs {
     unsigned* bmax_cur;     // block max |psi^n| (read by the GEMM), follows the psi buffer
     unsigned* bmax_next;    // block max |psi^{n+1}| (written by the stencil)
     double* rec;
+    // banded step (product ordinate sets): n_lev levels of n_az azimuths, coupling
+    // levels up to `reach` apart; per level the descriptor (band, two uint4), the
+    // coefficient range {first, count} (brange) and the coefficients (bcoef) as built by
+    // band_form (asn_host.hpp); bcmax the largest count of a level
+    const uint4* band;
+    const int2* brange;
+    const float* bcoef;
+    int n_lev, n_az, reach, bcmax;
 };
 
 // Kernel kinds of one step, each with its own block decomposition.
@@ -150,8 +186,12 @@ inline bool can_fuse(int dtype, int scheme) { (void)dtype; return scheme == SCHE
 // Heun: two such passes (s_par 0, then 1), so the state returns to its buffer.
 // If ev is given, ev[5 k .. 5 k + 4] are recorded before, between and after
 // the four kernels of pass k.
+// band_az / band_lds: the banded step's azimuth count and dynamic LDS bytes (every
+// problem of a banded batch has that azimuth count).
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
-                       hipEvent_t* ev = nullptr);
+                       hipEvent_t* ev = nullptr, int band_az = 0, size_t band_lds = 0);
+// Raise the dynamic LDS limit of the banded kernel for an azimuth count (once per device).
+hipError_t prepare_banded(int band_az, size_t band_lds);
 // Passes per step of a scheme.
 inline int passes_per_step(int scheme) {
     return scheme == SCHEME_HEUN || scheme == SCHEME_HEUN_FLAT ? 2 : 1;

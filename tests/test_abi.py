@@ -169,21 +169,31 @@ def test_create_rejects_unknown_scheme():
 
 
 def test_step_form_choice_by_size_and_operand_type():
-    # the automatic form: FP32 from 2^25 cell-ordinates runs separate kernels (its
-    # workspace holds the contraction output Y), smaller problems, 16-bit operands and
-    # grids wider than the flat stencil fuse; the explicit forms are taken as asked
-    def ws(nx, ny, n_polar, dtype="f32", unfused=None):
+    # the automatic form: FP32 forward Euler on a product set takes the banded step when
+    # K has that form (known once K is built), else, like every other case: FP32 from
+    # 2^25 cell-ordinates runs separate kernels (its workspace holds the contraction
+    # output Y), smaller problems, 16-bit operands and grids wider than the flat stencil
+    # fuse.  The automatic workspace size covers both candidates; explicit forms are
+    # taken as asked.
+    def ws(nx, ny, n_polar, dtype="f32", unfused=None, form=None):
         g = asn.make_grid(nx, ny, 0.0, 1.0, 0.0, 1.0)
         q = asn.asn_quadrature(n_polar, 2 * n_polar, 0, None, None, 0)
-        return asn.asn_workspace_size(g, q, asn.make_options(dtype=dtype, unfused=unfused))
+        return asn.asn_workspace_size(g, q, asn.make_options(dtype=dtype, unfused=unfused, form=form))
     for nx, ny, npol, dtype, sep in ((400, 400, 16, "f32", True), (128, 128, 16, "f32", False),
                                      (400, 400, 16, "bf16", False), (5000, 20, 16, "f32", False),
                                      (256, 256, 16, "f32", True), (255, 256, 16, "f32", False)):
         auto = ws(nx, ny, npol, dtype)
-        assert auto == ws(nx, ny, npol, dtype, unfused=sep)
-        assert auto != ws(nx, ny, npol, dtype, unfused=not sep)
+        fallback = ws(nx, ny, npol, dtype, unfused=sep)
+        if dtype == "f32":
+            assert auto == max(fallback, ws(nx, ny, npol, dtype, form="banded"))
+        else:
+            assert auto == fallback
+        assert fallback != ws(nx, ny, npol, dtype, unfused=not sep)
+    # the banded layout has no Y buffer and one Phi partial per cell
+    plane = 512 * 400 * 400 * 4
+    assert ws(400, 400, 16, form="separate") - ws(400, 400, 16, form="banded") > 0.99 * plane
     opt = asn.make_options()
-    opt.step_form = 3
+    opt.step_form = 4
     g = asn.make_grid(8, 8, 0.0, 1.0, 0.0, 1.0)
     q = asn.asn_quadrature(2, 4, 0, None, None, 0)
     with pytest.raises(asn.AsnError):
@@ -224,3 +234,40 @@ def test_binding_shares_torchs_hip_runtime():
     # pointers from torch would be foreign to the library.
     maps = {l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l}
     assert len(maps) == 1
+
+
+@pytest.mark.parametrize("n_polar,beta", [(4, 4.5), (8, 4.5), (12, 4.5), (16, 4.5), (24, 4.5),
+                                          (32, 4.5), (8, 2.0), (16, 9.0)])
+def test_banded_form_rebuilds_the_stored_kernel(n_polar, beta):
+    # The banded step applies K as per-level-pair rows of coefficients over azimuth
+    # offsets; expanded back they must give fp32(K) of the oracle entry for entry.
+    n_azim = 2 * n_polar
+    om, w = o.product_quadrature(n_polar, n_azim)
+    K = o.as_kernel_matrix(om, w, beta / w.size, "sym")
+    got, reach = asn.asn_band_expand(n_polar, n_azim, K)
+    assert np.array_equal(got, K.astype(np.float32))
+    lv = np.arange(w.size) // n_azim
+    nz = K.astype(np.float32) != 0
+    assert reach == np.max(np.abs(lv[:, None] - lv[None, :])[nz])
+
+
+def test_banded_form_refuses_kernels_without_it():
+    # an icosahedron set has no azimuthal rotation symmetry; a row-shuffled product
+    # K is no longer circulant; an odd azimuth count is refused
+    om, w = o.product_quadrature(4, 8)
+    K = o.as_kernel_matrix(om, w, 4.5 / 32, "sym")
+    perm = np.random.default_rng(0).permutation(32)
+    with pytest.raises(asn.AsnError) as e:
+        asn.asn_band_expand(4, 8, K[perm][:, perm])
+    assert e.value.status == asn.ASN_E_UNSUPPORTED
+    om, w = o.product_quadrature(3, 7)
+    K = o.as_kernel_matrix(om, w, 4.5 / 21, "sym")
+    with pytest.raises(asn.AsnError) as e:
+        asn.asn_band_expand(3, 7, K)
+    assert e.value.status == asn.ASN_E_UNSUPPORTED
+    # a wide kernel couples levels more than three apart
+    om, w = o.product_quadrature(16, 32)
+    K = o.as_kernel_matrix(om, w, 0.5, "sym")
+    with pytest.raises(asn.AsnError) as e:
+        asn.asn_band_expand(16, 32, K)
+    assert e.value.status == asn.ASN_E_UNSUPPORTED

@@ -1,0 +1,120 @@
+"""GPU parity of the banded forward-Euler step (product ordinate sets, FP32): one
+kernel applies K as circular convolutions along the azimuth between nearby polar
+levels together with the stream + collide update.  Checked against the FP64 oracle
+element by element on ragged grids and every azimuth count with a kernel instance,
+for narrow and whole-ring bands, both normalisations, multi-step runs with the
+particle budget, and batches (full-size sampled steps: test_gpu_parity.py)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import asn_oracle as o
+from gpu_util import fp32_budget_floor, gpu_run, oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1911_08801_amd import asn  # noqa: E402
+
+GRIDS = [(1, 1), (1, 7), (9, 1), (31, 1), (33, 2), (37, 9), (64, 16), (65, 17), (130, 67), (200, 3)]
+# (n_polar, n_azim, beta): every azimuth count 8 .. 64; wide beta gives whole-ring bands
+QUADS = [(1, 8, 4.5), (2, 8, 4.5), (4, 8, 4.5), (8, 16, 4.5), (3, 24, 4.5), (12, 24, 4.5),
+         (16, 32, 4.5), (5, 40, 6.0), (24, 48, 4.5), (7, 56, 4.5), (6, 64, 3.0), (8, 16, 9.0)]
+
+
+def _band_reach(n_polar, n_azim, beta):
+    om, w = o.product_quadrature(n_polar, n_azim)
+    K = o.as_kernel_matrix(om, w, beta / w.size, "sym").astype(np.float32)
+    lv = np.arange(w.size) // n_azim
+    return int(np.max(np.abs(lv[:, None] - lv[None, :])[K != 0]))
+
+
+@pytest.mark.parametrize("nx,ny", GRIDS)
+@pytest.mark.parametrize("n_polar,n_azim,beta", QUADS)
+def test_one_step_matches_oracle(nx, ny, n_polar, n_azim, beta):
+    assert _band_reach(n_polar, n_azim, beta) <= 3
+    spec = wl.random_problem(nx * 131 + ny + n_azim, nx, ny, n_polar=n_polar, n_azim=n_azim,
+                             beta=beta)
+    psi0 = wl.random_state(nx + 7 * ny + n_polar, spec.q, ny, nx)
+    print(f"banded one step {nx}x{ny}, {n_polar}x{n_azim}, beta {beta}", flush=True)
+    state, phi, bud, info = gpu_run(asn, spec, 1, psi0=psi0, form="banded")
+    ref, phi_ref, st = oracle_run(spec, 1, psi0=psi0)
+    scale = np.abs(ref).max()
+    assert np.max(np.abs(state - ref)) <= 4e-6 * scale
+    assert np.max(np.abs(phi - phi_ref)) <= 4e-6 * np.abs(phi_ref).max()
+
+
+@pytest.mark.parametrize("norm", ["sym", "row"])
+@pytest.mark.parametrize("n_polar,n_azim", [(4, 8), (8, 16), (16, 32)])
+def test_multi_step_with_budget(norm, n_polar, n_azim):
+    spec = wl.random_problem(5 + n_polar, 70, 33, n_polar=n_polar, n_azim=n_azim, beta=4.5,
+                             t_final=0.3)
+    psi0 = wl.random_state(3, spec.q, 33, 70)
+    state, phi, bud, _ = gpu_run(asn, spec, 12, psi0=psi0, norm=norm, form="banded")
+    ref, phi_ref, st = oracle_run(spec, 12, psi0=psi0, norm=norm)
+    assert rel_l2(phi, phi_ref) <= 1e-5
+    assert rel_l2(state, ref) <= 1e-5
+    # budget terms against the oracle's, measured on its own trajectory
+    _, _, hist = o.run(spec, n_steps=12, st=st, psi0=psi0.astype(np.float64), mode=norm,
+                       budget=True)
+    assert bud["steps"] == 12
+    assert bud["outflow"] == pytest.approx(sum(h["outflow"] for h in hist) * st.dt, rel=1e-5)
+    assert bud["absorption"] == pytest.approx(sum(h["absorption"] for h in hist) * st.dt, rel=1e-5)
+    assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
+
+
+def test_line_source_50_q128_full_run():
+    spec = wl.line_source(50, n_polar=8, sigma_as=1.0)
+    state, phi, bud, info = gpu_run(asn, spec, 24, form="banded")
+    ref, phi_ref, st = oracle_run(spec, 24)
+    assert rel_l2(phi, phi_ref) <= 1e-5
+    assert bud["steps"] == 24
+    assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
+
+
+def test_automatic_form_takes_the_banded_step_and_agrees_with_fused():
+    spec = wl.random_problem(8, 45, 38, n_polar=8, n_azim=16, beta=4.5)
+    psi0 = wl.random_state(4, spec.q, 38, 45)
+    p = asn.from_spec(spec, set_initial_state=False)
+    assert asn.asn_step_form(p) == "banded"
+    p.close()
+    a, phi_a, bud_a, _ = gpu_run(asn, spec, 5, psi0=psi0, form="auto")
+    f, phi_f, bud_f, _ = gpu_run(asn, spec, 5, psi0=psi0, form="fused")
+    assert np.max(np.abs(a - f)) <= 4e-6 * np.abs(f).max()
+    assert bud_a["mass"] == pytest.approx(bud_f["mass"], rel=1e-6)
+
+
+def test_bitwise_reproducible_and_batch_equals_alone():
+    specs = [wl.random_problem(s, nx, ny, n_polar=np_, n_azim=16, beta=4.5)
+             for s, nx, ny, np_ in ((1, 40, 30, 8), (2, 17, 5, 4), (3, 64, 64, 6))]
+    states = [wl.random_state(10 + i, sp.q, sp.ny, sp.nx) for i, sp in enumerate(specs)]
+    alone = []
+    for sp, s0 in zip(specs, states):
+        a1, _, _, _ = gpu_run(asn, sp, 4, psi0=s0, form="banded")
+        a2, _, _, _ = gpu_run(asn, sp, 4, psi0=s0, form="banded")
+        assert np.array_equal(a1, a2)
+        alone.append(a1)
+    probs = [asn.from_spec(sp, set_initial_state=False, form="banded") for sp in specs]
+    try:
+        for p, s0 in zip(probs, states):
+            asn.asn_set_state(p, s0)
+        asn.asn_step_batch(probs, 4)
+        for p, ref in zip(probs, alone):
+            assert np.array_equal(asn.asn_get_state(p), ref)
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_banded_request_refused_where_it_does_not_apply():
+    spec = wl.random_problem(1, 10, 10, n_polar=3, n_azim=6, beta=4.5)   # n_azim 6
+    with pytest.raises(asn.AsnError) as e:
+        asn.from_spec(spec, form="banded")
+    assert e.value.status == asn.ASN_E_UNSUPPORTED
+    spec = wl.random_problem(1, 10, 10, n_polar=4, n_azim=8, beta=4.5)
+    with pytest.raises(asn.AsnError):
+        asn.from_spec(spec, form="banded", dtype="bf16")
+    with pytest.raises(asn.AsnError):
+        asn.from_spec(spec, form="banded", scheme="heun")

@@ -1,5 +1,8 @@
 """Fused multi-problem stepping: every problem computes bitwise the same result
-alone and inside a batch, with eager launches and with replayed HIP graphs."""
+alone and inside a batch, with eager launches and with replayed HIP graphs.
+Problems of one batch share a kernel form; the mixed-size batches here ask for the
+fused form (the banded form batches problems of one azimuth count,
+test_gpu_banded.py)."""
 import numpy as np
 import pytest
 
@@ -20,8 +23,8 @@ def _specs():
             wl.line_source(64, n_polar=4, sigma_as=0.0, t_final=0.2)]
 
 
-def _alone(spec, n, dtype):
-    p = asn.from_spec(spec, dtype=dtype)
+def _alone(spec, n, dtype, form="fused"):
+    p = asn.from_spec(spec, dtype=dtype, form=form)
     asn.asn_step(p, n)
     out = (asn.asn_get_state(p), asn.asn_scalar_flux(p), asn.asn_mass_budget(p))
     p.close()
@@ -36,7 +39,7 @@ def test_batch_equals_alone_bitwise(dtype, side_stream):
     alone = [_alone(s, n, dtype) for s, n in zip(specs, limits)]
     stream = torch.cuda.Stream() if side_stream else torch.cuda.current_stream()
     with torch.cuda.stream(stream):
-        probs = [asn.from_spec(s, dtype=dtype) for s in specs]
+        probs = [asn.from_spec(s, dtype=dtype, form="fused") for s in specs]
         b = asn.asn_batch_create(probs)
         for k in range(3):                       # 3 chunks of 4 steps (graph replays)
             asn.asn_batch_step(b, 4, limits=[max(0, l - 4 * k) for l in limits])
@@ -82,29 +85,35 @@ def test_batch_rejects_mixed_separate_stencil_forms():
 
 
 def test_batch_of_sizes_with_different_automatic_forms():
-    # the automatic form follows the size: a 2^25 cell-ordinate problem runs separate
-    # kernels, a small one fused; they batch once both ask for the same form
+    # the automatic form follows the problem: a product set with an azimuth count the
+    # banded step covers takes it at any size, one without runs separate kernels from
+    # 2^25 cell-ordinates and fused below; problems batch once they share a form
     big = wl.line_source(256, n_polar=16, t_final=0.02)
     small = wl.line_source(48, n_polar=16, t_final=0.02)
-    a1, a2 = asn.from_spec(big), asn.from_spec(small)
-    f1, f2 = asn.from_spec(big, unfused=False), asn.from_spec(small, unfused=False)
+    odd = wl.line_source(48, n_polar=3, n_azim=6, t_final=0.02)
+    a1, a2, a3 = asn.from_spec(big), asn.from_spec(small), asn.from_spec(odd)
+    f1, f3 = asn.from_spec(big, unfused=False), asn.from_spec(odd, unfused=False)
     try:
+        assert [asn.asn_step_form(p) for p in (a1, a2, a3)] == ["banded", "banded", "fused"]
         with pytest.raises(asn.AsnError):
-            asn.asn_batch_create([a1, a2])
-        b = asn.asn_batch_create([f1, f2])
+            asn.asn_batch_create([a1, a3])
+        b = asn.asn_batch_create([a1, a2])           # both banded, 32 azimuths
         asn.asn_batch_step(b, 2)
         b.close()
-        asn.asn_step(a2, 2)                          # the small one fuses either way
-        assert np.array_equal(asn.asn_scalar_flux(f2), asn.asn_scalar_flux(a2))
+        b = asn.asn_batch_create([f1, f3])           # both fused
+        asn.asn_batch_step(b, 2)
+        b.close()
+        asn.asn_step(a3, 2)                          # the odd set fuses either way
+        assert np.array_equal(asn.asn_scalar_flux(f3), asn.asn_scalar_flux(a3))
     finally:
-        for p in (a1, a2, f1, f2):
+        for p in (a1, a2, a3, f1, f3):
             p.close()
 
 
 def test_step_batch_one_shot_matches_alone():
     specs = _specs()[:2]
     alone = [_alone(s, 6, "f32") for s in specs]
-    probs = [asn.from_spec(s) for s in specs]
+    probs = [asn.from_spec(s, form="fused") for s in specs]
     asn.asn_step_batch(probs, 6)
     for p, a in zip(probs, alone):
         assert np.array_equal(asn.asn_get_state(p), a[0])
@@ -140,7 +149,7 @@ def test_problem_can_step_alone_between_batch_steps():
     alone = [_alone(s, 7, "f32") for s in specs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        probs = [asn.from_spec(s) for s in specs]
+        probs = [asn.from_spec(s, form="fused") for s in specs]
         b = asn.asn_batch_create(probs)
         asn.asn_batch_step(b, 2)
         asn.asn_step(probs[1], 3)                # odd number of solo steps flips its buffer
@@ -155,7 +164,8 @@ def test_problem_can_step_alone_between_batch_steps():
 def test_step_form_reports_the_library_choice():
     big = wl.line_source(256, n_polar=16, t_final=0.02)      # 2^25 cell-ordinates
     small = wl.line_source(48, n_polar=8, t_final=0.05)
-    for spec, kw, want in ((big, {}, "separate"), (small, {}, "fused"),
+    big6 = wl.line_source(256, n_polar=86, n_azim=6, t_final=0.02)   # no banded instance
+    for spec, kw, want in ((big, {}, "banded"), (small, {}, "banded"), (big6, {}, "separate"),
                            (big, {"unfused": False}, "fused"), (small, {"unfused": True}, "separate"),
                            (big, {"dtype": "bf16"}, "fused"), (small, {"scheme": "heun"}, "separate")):
         p = asn.from_spec(spec, **kw)

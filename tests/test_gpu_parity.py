@@ -207,14 +207,16 @@ def test_cfl_above_one_is_rejected():
 
 # ---------------------------------------------------------------- full-size sampled parity
 
-def _sampled_one_step(spec, seed, n_samples=400, unfused=None):
+def _sampled_one_step(spec, seed, n_samples=400, form="auto"):
     """One step at full size on a structured anisotropic state; the oracle
     evaluates sampled entries one by one (plus every corner / edge class).
-    unfused: None takes the kernel form the library chooses (separate at these
-    sizes), False / True ask for the fused / separate form."""
+    form: the kernel form asked for ("auto" takes the banded step on these
+    product sets)."""
     rng = np.random.default_rng(seed)
     psi0 = structured_state(spec, rng)
-    p = asn.from_spec(spec, set_initial_state=False, unfused=unfused)
+    p = asn.from_spec(spec, set_initial_state=False, form=form)
+    if form == "auto":
+        assert asn.asn_step_form(p) == "banded"
     asn.asn_set_state(p, psi0)
     asn.asn_step(p, 1)
     got = asn.asn_get_state(p)
@@ -227,26 +229,26 @@ def _sampled_one_step(spec, seed, n_samples=400, unfused=None):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("unfused", [None, False])
-def test_full_size_400_q512_one_step_sampled(unfused):
+@pytest.mark.parametrize("form", ["auto", "fused", "separate"])
+def test_full_size_400_q512_one_step_sampled(form):
     spec = wl.line_source(400, n_polar=16, sigma_as=5.0)
-    assert _sampled_one_step(spec, 1, unfused=unfused) <= 4e-6
+    assert _sampled_one_step(spec, 1, form=form) <= 4e-6
 
 
 @pytest.mark.slow
-def test_full_size_700_q1152_checkerboard_one_step_sampled():
+@pytest.mark.parametrize("form", ["auto", "separate"])
+def test_full_size_700_q1152_checkerboard_one_step_sampled(form):
     spec = wl.checkerboard(700, n_polar=24, sigma_as=5.0)
     spec.psi0_cell[:] = wl.random_state(5, 1, 700, 700)[0]
-    assert _sampled_one_step(spec, 2, n_samples=300) <= 4e-6
+    assert _sampled_one_step(spec, 2, n_samples=300, form=form) <= 4e-6
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("unfused", [None, False])
-def test_full_size_1024_q2048_one_step_sampled(unfused):
-    # the largest configured problem (8 GiB a state copy): the separate kernels the
-    # library picks at this size and the fused form
+@pytest.mark.parametrize("form", ["auto", "separate", "fused"])
+def test_full_size_1024_q2048_one_step_sampled(form):
+    # the largest configured problem (8 GiB a state copy) in every FP32 kernel form
     spec = wl.line_source(1024, n_polar=32, sigma_as=5.0)
-    assert _sampled_one_step(spec, 3, n_samples=300, unfused=unfused) <= 4e-6
+    assert _sampled_one_step(spec, 3, n_samples=300, form=form) <= 4e-6
 
 
 def test_contraction_work_reports_skipped_zero_tiles():

@@ -272,3 +272,16 @@ def test_cfl_rule_values_for_the_workloads():
         om, w = o.product_quadrature(n_polar, 2 * n_polar)
         dt, k = o.cfl_time_step(om, L / n, L / n, 0.95, tf)
         assert k == steps and dt == pytest.approx(tf / steps, rel=1e-15)
+
+
+def test_windowed_entries_equal_the_full_run():
+    # run_entries advances each sampled cell on its own (2n + 1)^2 window; every entry
+    # (corners, edges, interior) must equal the full-grid run
+    spec = wl.random_problem(21, 13, 9, n_polar=2, n_azim=4, beta=4.5)
+    st = o.setup(spec)
+    psi0 = wl.random_state(5, spec.q, 9, 13).astype(np.float64)
+    n = 3
+    full, _, _ = o.run(spec, n_steps=n, st=st, psi0=psi0)
+    qs, js, iis = np.meshgrid(np.arange(spec.q), np.arange(9), np.arange(13), indexing="ij")
+    got = o.run_entries(psi0, st, n, qs.ravel(), js.ravel(), iis.ravel())
+    assert np.max(np.abs(got - full.ravel())) <= 1e-13 * np.abs(full).max()

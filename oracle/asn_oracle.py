@@ -487,19 +487,25 @@ def run_entries(psi: np.ndarray, st: Setup, n_steps: int, qs: np.ndarray, js: np
     """
     Q, ny, nx = psi.shape
     h = n_steps
-    pad = lambda a: np.pad(np.asarray(a, dtype=np.float64), [(0, 0)] * (a.ndim - 2) + [(h, h), (h, h)])
-    P = pad(psi)
-    inside = pad(np.ones((ny, nx)))
-    fields = {k: pad(getattr(st, k)) for k in ("sigma_s", "sigma_a", "sigma_as", "source")}
+    w = 2 * h + 1
+
+    def window(a, j, i):
+        """a[..., j - h .. j + h, i - h .. i + h] in FP64, zero outside the grid."""
+        out = np.zeros(a.shape[:-2] + (w, w))
+        j0, j1, i0, i1 = max(j - h, 0), min(j + h + 1, ny), max(i - h, 0), min(i + h + 1, nx)
+        out[..., j0 - (j - h):j1 - (j - h), i0 - (i - h):i1 - (i - h)] = a[..., j0:j1, i0:i1]
+        return out
+
     cache: Dict[Tuple[int, int], np.ndarray] = {}
     out = np.empty(len(qs))
     for n, (q, j, i) in enumerate(zip(qs, js, iis)):
         key = (int(j), int(i))
         if key not in cache:
-            win = (slice(j, j + 2 * h + 1), slice(i, i + 2 * h + 1))
-            sub = dataclasses.replace(st, **{k: v[win] for k, v in fields.items()})
-            mask = inside[win][None]
-            p = P[(slice(None),) + win]
+            j, i = key
+            sub = dataclasses.replace(st, **{k: window(getattr(st, k), j, i)
+                                             for k in ("sigma_s", "sigma_a", "sigma_as", "source")})
+            mask = window(np.ones((ny, nx)), j, i)[None]
+            p = window(psi, j, i)
             for _ in range(n_steps):
                 p, _ = step(p, sub, want_budget=False)
                 p = p * mask

@@ -1,0 +1,103 @@
+"""The configured workloads at their full size against the FP64 oracle:
+
+* line source 400^2, 16 x 32 = 512 ordinates, sigma_as in {0, 1, 5}, 197 steps to
+  t = 1 (paper Section 4.1 set-up), FP32 in every kernel form, against the oracle's
+  stored scalar flux (tests/golden/make_line_source_400.py) and against the
+  continuous transport reference (the error falls as sigma_as rises);
+* line source 1024^2, 32 x 64 = 2048 ordinates, sigma_as 5: ten steps, sampled
+  entries against the oracle's windowed evaluator;
+* lattice 700^2, 24 x 48 = 1152 ordinates, sigma_as 5, 475 steps to t = 3.2 (paper
+  Section 4.2 materials): the BF16 and FP16 contractions against the FP32 run.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import asn_oracle as o
+from oracle import linesource_ref as L
+from gpu_util import fp32_budget_floor, rel_l2, sampled_entries, structured_state
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+from paper_1911_08801_amd import asn  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "line_source_400_q512_phi.npz")
+_closed_form_errors = {}
+
+
+def _run(spec, steps, **kw):
+    p = asn.from_spec(spec, **kw)
+    try:
+        asn.asn_step(p, steps)
+        return asn.asn_scalar_flux(p), asn.asn_mass_budget(p), asn.asn_get_state(p)
+    finally:
+        p.close()
+
+
+@pytest.mark.parametrize("sigma_as,form", [(0.0, "auto"), (1.0, "auto"), (5.0, "auto"),
+                                           (5.0, "separate"), (5.0, "fused")])
+def test_line_source_400_q512_full_run_against_stored_oracle(sigma_as, form):
+    gold = np.load(GOLDEN)
+    spec = wl.line_source(400, n_polar=16, sigma_as=sigma_as)
+    st = o.setup(spec)
+    assert st.n_steps == int(gold["n_steps"]) == 197
+    phi, bud, state = _run(spec, st.n_steps, form=form)
+    ref = gold[f"phi_as{int(sigma_as)}"].astype(np.float64)
+    err = rel_l2(phi, ref)
+    print(f"400^2 x 512, sigma_as {sigma_as}, {form}: rel L2 vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-5
+    assert bud["steps"] == 197
+    assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
+    if form == "auto":
+        cont = 4 * math.pi * L.line_source_on_grid(400, 1.0, wl.LINE_SOURCE_DELTA, n_k=800,
+                                                   n_tau=1200)
+        e_gpu, e_orc = rel_l2(phi, cont), rel_l2(ref, cont)
+        print(f"   vs the continuous reference: {e_gpu:.4f} (oracle {e_orc:.4f})", flush=True)
+        assert abs(e_gpu - e_orc) <= 1e-4 * e_orc
+        _closed_form_errors[sigma_as] = e_gpu
+        if len(_closed_form_errors) == 3:     # artificial scattering lowers the error
+            e = _closed_form_errors
+            assert e[5.0] < e[1.0] < e[0.0]
+
+
+@pytest.mark.parametrize("form", ["auto", "separate"])
+def test_line_source_1024_q2048_ten_steps_sampled(form):
+    # an anisotropic state of the full size (2^31 cell-ordinates); the oracle advances
+    # each sampled cell on its own 21 x 21 window for ten steps
+    spec = wl.line_source(1024, n_polar=32, sigma_as=5.0)
+    rng = np.random.default_rng(2048)
+    psi0 = structured_state(spec, rng)
+    p = asn.from_spec(spec, set_initial_state=False, form=form)
+    try:
+        asn.asn_set_state(p, psi0)
+        asn.asn_step(p, 10)
+        got = asn.asn_get_state(p)
+    finally:
+        p.close()
+    st = o.setup(spec)
+    qs, js, iis = sampled_entries(rng, spec.q, 1024, 1024, 48)
+    ref = o.run_entries(psi0, st, 10, qs, js, iis)
+    scale = np.maximum(np.abs(ref), 1e-3 * np.abs(psi0).max())
+    err = np.abs(got[qs, js, iis].astype(np.float64) - ref) / scale
+    print(f"1024^2 x 2048, 10 steps, {form}: max scaled error {err.max():.2e}", flush=True)
+    assert err.max() <= 4e-5
+
+
+def test_lattice_700_q1152_reduced_precision_full_runs():
+    spec = wl.checkerboard(700, n_polar=24, sigma_as=5.0)
+    st = o.setup(spec)
+    assert st.n_steps == 475
+    phi32, _, _ = _run(spec, st.n_steps)
+    for dtype in ("bf16", "f16"):
+        phi, bud, _ = _run(spec, st.n_steps, dtype=dtype)
+        err = rel_l2(phi, phi32)
+        print(f"700^2 x 1152 lattice, t = 3.2: {dtype} vs FP32 rel L2 {err:.2e}", flush=True)
+        assert err <= 2e-3
+        assert bud["steps"] == 475

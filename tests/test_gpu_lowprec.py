@@ -107,7 +107,7 @@ def test_reduced_precision_runs_are_bitwise_reproducible():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
-@pytest.mark.parametrize("n,n_polar", [(400, 16), (1024, 32)])
+@pytest.mark.parametrize("n,n_polar", [(400, 16), (700, 24), (1024, 32)])
 def test_full_size_one_step_sampled_within_rounding_bound(dtype, n, n_polar):
     # Full size (up to 2^31 cell-ordinates): sampled entries of one step against the
     # exact FP64 oracle.  The reduced-precision Y differs from K psi by the rounding of
@@ -117,7 +117,12 @@ def test_full_size_one_step_sampled_within_rounding_bound(dtype, n, n_polar):
     # again.  8 u |K|_row max|dev| covers them twice over (FP16: plus the subnormal
     # spacing of the small K entries, 2^-25 each); a misplaced operand or output would
     # be off by about max|dev| itself.
-    spec = wl.line_source(n, n_polar=n_polar, sigma_as=5.0)
+    # (700: the configured lattice, on a random isotropic part)
+    if n == 700:
+        spec = wl.checkerboard(n, n_polar=n_polar, sigma_as=5.0)
+        spec.psi0_cell[:] = wl.random_state(7, 1, n, n)[0]
+    else:
+        spec = wl.line_source(n, n_polar=n_polar, sigma_as=5.0)
     rng = np.random.default_rng(n + n_polar)
     psi0 = structured_state(spec, rng)
     p = asn.from_spec(spec, dtype=dtype, set_initial_state=False)

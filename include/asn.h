@@ -280,13 +280,22 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
                     int32_t* q);
 
 /* Arithmetic of one contraction Y = K Psi: dense_flops = 2 Q^2 C; tile_flops =
- * 2 C times the number of K entries in the blocks the kernel multiplies.  K is
+ * 2 C times the number of K entries in the blocks the kernel multiplies (banded
+ * step: the runs it multiplies, see asn_contraction_nonzero).  K is
  * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
  * sparse matrix), so blocks whose entries are all zero in the stored operand type
  * are skipped: 128-row x 32-column tiles for BF16/FP16, and for FP32 the 16-row x
  * 4-column blocks (the K operand of one MFMA).  The skipped products are exact zeros
  * and the result is unchanged.  Either pointer may be NULL. */
 asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile_flops);
+
+/* The contraction's own arithmetic: nonzero_flops = 2 C times the number of nonzero
+ * entries of K in the stored operand type (FP32, or the BF16/FP16 copy), the products
+ * the method needs (paper Section 3.5: S_as^+ is sparse).  The banded step
+ * (ASN_FORM_BANDED) multiplies every stored nonzero of a pair's run plus the zeros that
+ * pad wide runs to a multiple of four, which asn_contraction_work reports as its
+ * tile_flops.  Errors: ASN_E_INVALID (NULL problem or pointer). */
+asn_status asn_contraction_nonzero(asn_problem p, double* nonzero_flops);
 
 /* Free the handle and any memory the library allocated.  NULL is accepted. */
 asn_status asn_destroy(asn_problem p);

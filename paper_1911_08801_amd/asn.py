@@ -104,6 +104,7 @@ _SIG = {
     "asn_step_form": [_P, ctypes.POINTER(ctypes.c_int32)],
     "asn_destroy": [_P],
     "asn_contraction_work": [_P, _D, _D],
+    "asn_contraction_nonzero": [_P, _D],
     "asn_stability": [_P, _D],
     "asn_iteration_counts": [_P, _I64, _I64],
     "asn_build_quadrature": [ctypes.c_int32, ctypes.c_int32, _D, _D],
@@ -378,6 +379,7 @@ def asn_step_batch(probs, n_steps: int = 1) -> None:
     _check(_lib.asn_step_batch(arr, len(probs), int(n_steps)), "asn_step_batch")
 
 
+
 class AsnBatch:
     """Problems stepped together with fused launches (wraps an asn_batch handle)."""
 
@@ -472,7 +474,9 @@ def asn_contraction_work(p: AsnProblem) -> dict:
     t = ctypes.c_double()
     _check(_lib.asn_contraction_work(p.handle, ctypes.byref(d), ctypes.byref(t)),
            "asn_contraction_work")
-    return {"dense_flops": d.value, "tile_flops": t.value}
+    nz = ctypes.c_double()
+    _check(_lib.asn_contraction_nonzero(p.handle, ctypes.byref(nz)), "asn_contraction_nonzero")
+    return {"dense_flops": d.value, "tile_flops": t.value, "nonzero_flops": nz.value}
 
 
 def asn_destroy(p: AsnProblem) -> None:

@@ -183,6 +183,7 @@ struct asn_problem_s {
     int cur = 0;  // which psi buffer holds the current state
     std::vector<double> w;
     double tile_entries = 0;  // K entries inside the multiplied tiles (real rows/cols)
+    double nonzero_entries = 0;   // nonzero entries of K in the stored operand type
     StepArgs tab[2];          // step arguments when psi buffer 0 / 1 holds the state
     int blocks[asn::KT_COUNT];
     std::unique_ptr<asn::ImplicitSolver> imp;   // the implicit scheme's solver (else null)
@@ -653,6 +654,27 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         std::copy(masks.begin(), masks.end(), ktab.begin() + mt_n + 1 + entries.size());
         p->tile_entries = cover;
     }
+    {   // the method's own products: nonzeros of the stored K
+        double nz = 0;
+        for (int q = 0; q < Q; ++q)
+            for (int k = 0; k < Q; ++k)
+                nz += L.lowp ? ((Klp[(size_t)q * L.Qp + k] & 0x7FFFu) != 0)
+                             : (Kt[(size_t)k * L.Qp + q] != 0.f);
+        p->nonzero_entries = nz;
+    }
+    if (banded) {   // the banded step multiplies each pair's run (wide runs padded to 4)
+        double ex = 0;
+        for (int i = 0; i < bf.levels; ++i) {
+            const int n = (int)bf.desc[(size_t)i * 8];
+            for (int t = 0; t < n; ++t) {
+                const uint32_t code = bf.desc[(size_t)i * 8 + 1 + t];
+                int lo = 0, len = 0;
+                asn::band_run(code, bf.azim, lo, len);
+                ex += (double)bf.azim * ((code & 64u) ? (len + 3) / 4 * 4 : len);
+            }
+        }
+        p->tile_entries = ex;
+    }
     std::vector<QInfo> qi(Q);
     for (int q = 0; q < Q; ++q) {
         const double xi = om[3 * q], eta = om[3 * q + 1];
@@ -907,9 +929,9 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
     return ASN_OK;
 }
 
-asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
-    if (!out) return fail(ASN_E_INVALID, "out is NULL");
-    *out = nullptr;
+// Whether problems may step together (shared operand type, scheme, kernel form,
+// stream; no repeats, no implicit problems).
+static asn_status check_batch(asn_problem* probs, int32_t n) {
     if (!probs || n < 1 || n > asn::kMaxArm)
         return fail(ASN_E_INVALID, "a batch holds 1 to 64 problems");
     for (int32_t i = 0; i < n; ++i) {
@@ -938,6 +960,14 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
         for (int32_t j = 0; j < i; ++j)
             if (probs[j] == probs[i]) return fail(ASN_E_INVALID, "a problem appears twice");
     }
+    return ASN_OK;
+}
+
+asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
+    if (!out) return fail(ASN_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const asn_status cs = check_batch(probs, n);
+    if (cs != ASN_OK) return cs;
     auto* b = new asn_batch_s();
     b->probs.assign(probs, probs + n);
     b->n = n;
@@ -1129,6 +1159,12 @@ asn_status asn_contraction_work(asn_problem p, double* dense_flops, double* tile
     const double C = (double)p->L.C, Q = (double)p->L.Q;
     if (dense_flops) *dense_flops = 2.0 * Q * Q * C;
     if (tile_flops) *tile_flops = 2.0 * p->tile_entries * C;
+    return ASN_OK;
+}
+
+asn_status asn_contraction_nonzero(asn_problem p, double* nonzero_flops) {
+    if (!p || !nonzero_flops) return fail(ASN_E_INVALID, "NULL argument");
+    *nonzero_flops = 2.0 * p->nonzero_entries * (double)p->L.C;
     return ASN_OK;
 }
 

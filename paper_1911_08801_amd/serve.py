@@ -29,7 +29,7 @@ class Job:
     arrival: float
     dtype: str = "f32"
     scheme: str = "euler"           # "euler" (donor cell) or "heun" (Heun + minmod)
-    form: str = ""                  # kernel form the library chose ("fused" / "separate")
+    form: str = ""                  # kernel form the library chose ("banded" / "fused" / ...)
     status: str = "queued"          # queued, active, done, failed, rejected, cancelled
     bytes: int = 0
     steps_total: int = 0
@@ -52,16 +52,25 @@ class GpuBackend:
 
     Requests get the stiff time-step rule by default: arbitrary requests include
     coarse, strongly absorbing problems for which the streaming CFL step alone
-    is outside the explicit schemes' stability interval."""
+    is outside the explicit schemes' stability interval.
 
-    def __init__(self, stream=None, dt_rule: str = "stiff"):
+    form: kernel form of forward-Euler requests.  "auto" (default) lets the library
+    choose per request (the banded step for FP32 product sets, whose batches group
+    requests of one azimuth count); "fused" puts every Euler request in the fused
+    GEMM form, so that all of them share one batch."""
+
+    def __init__(self, stream=None, dt_rule: str = "stiff", form: str = "auto"):
         import torch
 
         from . import asn
         self.torch = torch
         self.asn = asn
         self.dt_rule = dt_rule
+        self.form_asked = form
         self.stream = stream if stream is not None else torch.cuda.Stream()
+
+    def _form(self, scheme: str):
+        return self.form_asked if scheme == "euler" else None
 
     def bytes_needed(self, spec, dtype: str, scheme: str = "euler") -> int:
         a = self.asn
@@ -69,19 +78,15 @@ class GpuBackend:
         quad = a.asn_quadrature(spec.n_polar, spec.n_azim, 0, None, None,
                                 getattr(spec, "ico_order", 0))
         return a.asn_workspace_size(grid, quad, a.make_options(dtype, cfl=spec.cfl, scheme=scheme,
-                                                               unfused=False))
+                                                               form=self._form(scheme)))
 
     def free_bytes(self) -> int:
         return int(self.torch.cuda.mem_get_info()[0])
 
     def create(self, spec, dtype: str, scheme: str = "euler"):
         with self.torch.cuda.stream(self.stream):
-            # Euler requests take the fused form at every size: a batch then packs all
-            # its problems into one launch per kernel (a burst of 24 requests of up to
-            # 512^2 cells ran 3 % faster so than with each request in the form the
-            # library picks for it alone, split over two batches)
             p = self.asn.from_spec(spec, dtype=dtype, scheme=scheme, dt_rule=self.dt_rule,
-                                   unfused=False)
+                                   form=self._form(scheme))
         return p, self.asn.asn_info(p)["steps_to_tfinal"]
 
     def form(self, handle) -> str:
@@ -209,11 +214,12 @@ class Server:
                     self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
                 continue
 
-            # one batch per operand type, time scheme and kernel form; rebuilt when its
-            # members change
+            # one batch per operand type, time scheme and kernel form (banded: and azimuth
+            # count); rebuilt when its members change
             groups: Dict[Any, List[Job]] = {}
             for j in active:
-                groups.setdefault((j.dtype, j.scheme, j.form), []).append(j)
+                az = j.spec.n_azim if j.form == "banded" else 0
+                groups.setdefault((j.dtype, j.scheme, j.form, az), []).append(j)
             for dt in list(batches):
                 if dt not in groups:
                     self.b.drop_batch(batches.pop(dt))

@@ -45,12 +45,12 @@ def test_each_result_equals_the_request_alone(mixed):
 
 
 def test_large_and_small_requests_share_the_fused_form():
-    # a request of 2^25 cell-ordinates would run separate kernels alone; the server
-    # asks for the fused form so that it batches with the small ones
+    # asked for the fused form, requests of every size and azimuth count share one batch
     big = [wl.line_source(256, n_polar=16, sigma_as=5.0, t_final=0.02) for _ in range(2)]
     small = [wl.line_source(48, n_polar=8, sigma_as=5.0, t_final=0.05) for _ in range(3)]
     jobs = [Job(rid=k, spec=s, arrival=0.0) for k, s in enumerate(big + small)]
-    rep = Server(GpuBackend(), hbm_budget=4 * 1024 ** 3, max_slots=8, chunk=4).serve(jobs)
+    rep = Server(GpuBackend(form="fused"), hbm_budget=4 * 1024 ** 3, max_slots=8,
+                 chunk=4).serve(jobs)
     assert all(j.status == "done" for j in rep.jobs)
     assert [j.form for j in rep.jobs] == ["fused"] * 5
     for j in rep.jobs:
@@ -72,3 +72,20 @@ def test_unstable_request_fails_alone_and_others_finish():
     st = {j.rid: j.status for j in rep.jobs}
     assert st[bad.rid] == "failed"
     assert sum(v == "done" for v in st.values()) == 4
+
+
+def test_banded_requests_batch_by_azimuth_count():
+    # the automatic form: FP32 product sets take the banded step; requests of one
+    # azimuth count share a batch, and each result equals the request alone
+    specs = [wl.line_source(40 + 8 * k, n_polar=(4, 8)[k % 2], sigma_as=3.0, t_final=0.1)
+             for k in range(6)]
+    jobs = [Job(rid=k, spec=s, arrival=0.0) for k, s in enumerate(specs)]
+    rep = Server(GpuBackend(), hbm_budget=2 * 1024 ** 3, max_slots=8, chunk=4).serve(jobs)
+    assert all(j.status == "done" for j in rep.jobs)
+    assert {j.form for j in rep.jobs} == {"banded"}
+    for j in rep.jobs:
+        p = asn.from_spec(j.spec, dt_rule="stiff")
+        asn.asn_step(p, j.steps_total)
+        alone = asn.asn_scalar_flux(p)
+        p.close()
+        assert np.array_equal(j.phi, alone), j.rid

@@ -253,7 +253,7 @@ def test_full_size_1024_q2048_one_step_sampled(form):
 
 def test_contraction_work_reports_skipped_zero_tiles():
     spec = wl.line_source(16, n_polar=16, sigma_as=5.0)
-    p = asn.from_spec(spec)
+    p = asn.from_spec(spec, form="separate")
     work = asn.asn_contraction_work(p)
     p.close()
     assert work["dense_flops"] == 2.0 * 512 * 512 * 256
@@ -281,3 +281,27 @@ def test_contraction_work_reduced_precision_blocks(dtype):
     tiles = ((bits & 0x7FFF) != 0).reshape(4, 128, 16, 32).any(axis=(1, 3)).sum()
     assert work["tile_flops"] == 2.0 * tiles * 128 * 32 * 256
     assert work["tile_flops"] < 0.5 * work["dense_flops"]
+
+
+def test_contraction_work_of_the_banded_step():
+    # the banded step multiplies each pair's run of coefficients (wide runs padded to a
+    # multiple of four); the method's own work is 2 C nnz(fp32 K)
+    spec = wl.line_source(16, n_polar=16, sigma_as=5.0)
+    p = asn.from_spec(spec)
+    assert asn.asn_step_form(p) == "banded"
+    work = asn.asn_contraction_work(p)
+    p.close()
+    om, w = asn.asn_build_quadrature(16, 32)
+    K = asn.asn_build_kernel(om, w, spec.beta / 512).astype(np.float32)
+    C = 256
+    assert work["nonzero_flops"] == 2.0 * np.count_nonzero(K) * C
+    executed = 0
+    for i in range(16):
+        for j in range(16):
+            nz = np.nonzero(K[32 * i, 32 * j:32 * j + 32])[0]
+            if nz.size:
+                s = np.minimum(nz, 32 - nz).max()
+                run = 32 if 2 * s + 1 >= 32 else 2 * s + 1
+                executed += 32 * ((run + 3) // 4 * 4 if (s > 8 or run == 32) else run)
+    assert work["tile_flops"] == 2.0 * executed * C
+    assert 1.0 <= work["tile_flops"] / work["nonzero_flops"] < 1.3

@@ -203,6 +203,19 @@ asn_status asn_step(asn_problem p, int64_t n_steps);
  * Errors: those of asn_batch_create and asn_batch_step. */
 asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps);
 
+/* asn_step_batch for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same steps with
+ * the same results, bit for bit, and no hipMalloc, hipFree, graph instantiation or
+ * other allocating call.  The batch tables live in a static device array of 64 KiB
+ * per GPU (held until the process ends), which bounds the batch to what fits (every
+ * batch of up to 64 problems does).  Launches are eager on the problems' stream and
+ * the call waits for them before it returns.  Every call on one GPU shares that array
+ * and overwrites it: calls that overlap on one GPU (other host threads, or problems on
+ * another stream of the same device while a call runs) race and must not be issued.
+ * Errors: those of asn_batch_create (ASN_E_INVALID, ASN_E_UNSUPPORTED), ASN_E_INVALID
+ * (n_steps outside [0, 2^20]), ASN_E_HIP. */
+asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps);
+
 /* A batch groups 1..64 problems for fused stepping: every kernel of a step covers
  * all of them in one launch.  Problems keep their own grid, ordinates, kernel
  * matrix and buffers (ordinate counts may differ); they must share the operand

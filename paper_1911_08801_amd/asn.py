@@ -94,6 +94,7 @@ _SIG = {
     "asn_get_state": [_P, _P, ctypes.c_int32],
     "asn_step": [_P, ctypes.c_int64],
     "asn_step_batch": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int64],
+    "asn_step_batch_noalloc": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int64],
     "asn_step_timed": [_P, ctypes.c_int64, _D],
     "asn_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)],
     "asn_batch_step": [_P, ctypes.c_int64, _I64],
@@ -377,6 +378,11 @@ def asn_step_timed(p: AsnProblem, n_steps: int) -> dict:
 def asn_step_batch(probs, n_steps: int = 1) -> None:
     arr = (_P * len(probs))(*[p.handle for p in probs])
     _check(_lib.asn_step_batch(arr, len(probs), int(n_steps)), "asn_step_batch")
+
+def asn_step_batch_noalloc(probs, n_steps: int = 1) -> None:
+    """asn_step_batch without any device allocation (tables in a static device array)."""
+    arr = (_P * len(probs))(*[p.handle for p in probs])
+    _check(_lib.asn_step_batch_noalloc(arr, len(probs), int(n_steps)), "asn_step_batch_noalloc")
 
 
 

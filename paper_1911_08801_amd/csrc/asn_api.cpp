@@ -1085,6 +1085,93 @@ asn_status asn_batch_destroy(asn_batch b) {
     return st;
 }
 
+// asn_step_batch_noalloc: the batch tables (step arguments of both buffers, block
+// offsets per kernel kind, buffer bases, step counters) live in this file-scope device
+// array instead of a hipMalloc'd block.  In host code the array's name is no device
+// address: each device's copy is reached through the pointer hipGetSymbolAddress
+// returns for it (kept per device at the first call there).
+constexpr size_t kNoAllocBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch_ptr;
+
+static asn_status scratch_on_device(char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)));
+        it = g_scratch_ptr.emplace(dev, static_cast<char*>(ptr)).first;
+    }
+    *out = it->second;
+    return ASN_OK;
+}
+
+asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps) {
+    const asn_status cs = check_batch(probs, n);
+    if (cs != ASN_OK) return cs;
+    if (n_steps < 0 || n_steps > (1 << 20)) return fail(ASN_E_INVALID, "n_steps must be in [0, 2^20]");
+    // the tables, laid out as in asn_batch_create, in host arrays of fixed size
+    constexpr int kN = asn::kMaxArm;
+    StepArgs tab[2 * kN];
+    int off[asn::KT_COUNT * (kN + 1)];
+    const size_t tab_b = 2 * (size_t)n * sizeof(StepArgs);
+    const size_t off_b = (size_t)asn::KT_COUNT * (n + 1) * sizeof(int);
+    const size_t bytes = tab_b + off_b + 2 * (size_t)kN * sizeof(int);
+    if (bytes > kNoAllocBytes)
+        return fail(ASN_E_INVALID, "batch tables exceed the no-allocation scratch (" +
+                                       std::to_string(kNoAllocBytes) + " bytes)");
+    int grid[asn::KT_COUNT];
+    for (int k = 0; k < asn::KT_COUNT; ++k) off[k * (n + 1)] = 0;
+    size_t band_lds = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        tab[2 * i] = probs[i]->tab[0];
+        tab[2 * i + 1] = probs[i]->tab[1];
+        for (int k = 0; k < asn::KT_COUNT; ++k)
+            off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + probs[i]->blocks[k];
+        if (probs[i]->L.banded) band_lds = std::max(band_lds, probs[i]->band_lds());
+    }
+    for (int k = 0; k < asn::KT_COUNT; ++k) grid[k] = off[k * (n + 1) + n];
+    if (n_steps == 0) return ASN_OK;
+    char* dev = nullptr;
+    const asn_status ss = scratch_on_device(&dev);
+    if (ss != ASN_OK) return ss;
+    hipStream_t stream = probs[0]->stream;
+    // stream order: earlier work on this stream that read the tables has finished
+    // before the copies land; the host arrays must outlive the copies, hence the wait
+    HIP_TRY(hipMemcpyAsync(dev, tab, tab_b, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dev + tab_b, off, off_b, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    asn::BatchArgs args{};
+    args.tab = reinterpret_cast<const StepArgs*>(dev);
+    args.off = reinterpret_cast<const int*>(dev + tab_b);
+    args.base = reinterpret_cast<const int*>(dev + tab_b + off_b);
+    args.steps_left = reinterpret_cast<int*>(dev + tab_b + off_b + kN * sizeof(int));
+    args.n = n;
+    asn::ArmArgs v{};
+    for (int i = 0; i < n; ++i) {
+        v.limit[i] = (int)n_steps;
+        v.cur[i] = probs[i]->cur;
+    }
+    HIP_TRY(asn::launch_arm(args.steps_left, const_cast<int*>(args.base), n, v, stream));
+    const int scheme = launch_scheme(probs[0]);
+    for (int64_t j = 0; j < n_steps; ++j) {
+        args.s_par = (int)(j & 1);
+        HIP_TRY(asn::launch_step(args, grid, probs[0]->dtype, scheme, stream, nullptr,
+                                 probs[0]->band_azim, band_lds));
+    }
+    for (int i = 0; i < n; ++i) {
+        probs[i]->cur ^= state_flip(probs[i]->scheme, n_steps);
+        probs[i]->steps_done += n_steps;
+    }
+    // the next call overwrites the tables: let this one's kernels finish first
+    HIP_TRY(hipStreamSynchronize(stream));
+    return ASN_OK;
+}
+
 asn_status asn_step_batch(asn_problem* probs, int32_t n, int64_t n_steps) {
     asn_batch b = nullptr;
     asn_status s = asn_batch_create(probs, n, &b);

@@ -2,9 +2,13 @@
 
 One "step" is one pass of the whole per-step hot path over the workload: the
 ordinate contraction Y = K Psi, stream + collide, moment finalize and budget
-fold.  Workload: line source on 400 x 400 cells of [-1.5, 1.5]^2 with 16 x 32 =
-512 product ordinates, sigma_s = 1, sigma_as = 5, beta = 4.5, CFL 0.95 (197 steps
-to t = 1), FP32 contraction.  Inputs are resident on the GPU before timing.
+fold (for FP32 product sets one banded kernel does the contraction and the
+stencil).  Headline workload: the line source on 1024 x 1024 cells of
+[-1.5, 1.5]^2 with 32 x 64 = 2048 product ordinates, sigma_s = 1, sigma_as = 5,
+beta = 4.5, CFL 0.95 (507 steps to t = 1), FP32; the same step with the BF16 and
+FP16 contraction, the 400 x 400 x 512 line source, the Heun + minmod and implicit
+schemes, the serving stream and the FP64 oracle are reported beside it.  Inputs
+are resident on the GPU before timing.
 
 Prints ONE JSON line (rank 0, N = 1).
 """
@@ -15,6 +19,7 @@ import math
 import json
 import os
 import platform
+import statistics
 import sys
 import time
 
@@ -23,41 +28,62 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "cell-ordinate updates/s per as-S_N step (FP32 vs BF16-GEMM) + p99 solve latency"
-PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_VALU_TFLOPS = 78.6     # FMA on 16 lanes per SIMD, no packed FP32 (not used here)
+PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
+BYTES_PER_UPDATE = 8.0           # read psi^n and write psi^{n+1} once, FP32
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=400)
-    ap.add_argument("--n-polar", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="the timed steps are split into this many chunks (eager), and a "
+                         "graph of one chunk is replayed as often; medians are reported")
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--n-polar", type=int, default=32)
     ap.add_argument("--sigma-as", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
-    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--cpu-rows", type=int, default=32,
+                    help="rows of the headline grid (through the pulse) the oracle steps")
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 400 x 400 x 512 line (all FP32 forms, precision vs oracle)")
     ap.add_argument("--no-heun", action="store_true", help="skip the Heun + minmod line")
-    ap.add_argument("--no-separate", action="store_true",
-                    help="skip the FP32 Euler line in the other kernel form (fused or separate) "
-                         "than the one the library chooses")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit-scheme line")
-    ap.add_argument("--sweep", choices=["lattice700", "line1024"], default=None,
+    ap.add_argument("--sweep", choices=["lattice700", "line1024", "line400"], default=None,
                     help="precision sweep to t_final on a configured workload (one JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one elementwise copy of 1 GiB (read 1 GiB, write 1 GiB) so "
                          "hardware byte counters can be scaled against known traffic")
-    ap.add_argument("--serve-requests", type=int, default=48)
-    ap.add_argument("--serve-nmax", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-nmax", type=int, default=512)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the measured batch capacity")
     return ap.parse_args()
 
 
-def cpu_baseline(spec, steps):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def oracle_slab(spec, rows):
+    """`rows` rows of the workload's grid through its centre (same dx, dy, dt, fields)."""
+    import dataclasses
+    r0 = max(0, spec.ny // 2 - rows // 2)
+    dy = (spec.y_max - spec.y_min) / spec.ny
+    cut = lambda a: a[r0:r0 + rows].copy()
+    return dataclasses.replace(spec, name=f"{spec.name}_rows{r0}-{r0 + rows}", ny=rows,
+                               y_min=spec.y_min + r0 * dy, y_max=spec.y_min + (r0 + rows) * dy,
+                               sigma_s=cut(spec.sigma_s), sigma_a=cut(spec.sigma_a),
+                               sigma_as=cut(spec.sigma_as), source=cut(spec.source),
+                               psi0_cell=cut(spec.psi0_cell))
+
+
+def cpu_baseline(spec, rows, steps):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload: `rows` full
+    rows of its grid (same spacing, ordinates, K and dt), `steps` steps after one untimed."""
     import numpy as np
     from oracle import asn_oracle as o
     try:
@@ -65,58 +91,75 @@ def cpu_baseline(spec, steps):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = os.cpu_count() or 1
-    st = o.setup(spec)
-    psi = spec.psi0().astype(np.float64)
+    slab = oracle_slab(spec, rows)
+    st = o.setup(slab)
+    psi = slab.psi0().astype(np.float64)
     psi, _ = o.step(psi, st, want_budget=False)          # first touch outside the timing
     t0 = time.perf_counter()
     for _ in range(steps):
         psi, _ = o.step(psi, st, want_budget=False)
     dt = time.perf_counter() - t0
-    ups = spec.cells * spec.q * steps / dt
+    ups = slab.cells * slab.q * steps / dt
     return {"value": ups, "unit": "cell-ordinate updates/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps of the same {spec.nx}x{spec.ny}, Q={spec.q} "
-                      f"line-source workload ({dt:.1f} s, {platform.processor() or 'host cpu'})"}
+            "sample": f"{steps} FP64 oracle steps on {rows} rows ({slab.nx}x{rows} cells, "
+                      f"Q={slab.q}, dt={st.dt:.6g}) of the {spec.nx}x{spec.ny} line-source "
+                      f"workload ({dt:.1f} s, {platform.processor() or 'host cpu'})"}
 
 
-PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
-
-
-def timed_run(asn, spec, dtype, steps, warmup, scheme="euler", unfused=None):
-    """Warm up, time `steps` steps as the library runs them (no timing events between
-    the kernels), then run `steps` more with HIP events recorded on the problem's stream
-    between the kernels for the per-kernel durations.  The event markers themselves add
-    a few microseconds per kernel boundary, so the throughput comes from the first pass."""
+def measure(asn, spec, dtype, steps, warmup, reps, scheme="euler", form=None, graph=True):
+    """Time `steps` steps as the library runs them, bracketed by synchronisations; the
+    steps go in `reps` chunks with events between them on the problem's stream (median
+    chunk rate).  Then a HIP graph of one chunk (a batch of this one problem) is
+    replayed `reps` times (median rate), and one more pass records events between the
+    kernels of each step (per-kernel durations; the markers add a few us per kernel
+    boundary, so the throughput is not taken from that pass).  Runs on a side stream,
+    which the library captures into graphs."""
     import torch
-    p = asn.from_spec(spec, dtype=dtype, scheme=scheme, unfused=unfused)
-    info = asn.asn_info(p)
-    work = asn.asn_contraction_work(p)
-    asn.asn_step(p, warmup)
+    side = torch.cuda.Stream()
+    cq = spec.cells * spec.q
+    with torch.cuda.stream(side):
+        p = asn.from_spec(spec, dtype=dtype, scheme=scheme, form=form)
+        info = asn.asn_info(p)
+        work = asn.asn_contraction_work(p)
+        step_form = asn.asn_step_form(p)
+        asn.asn_step(p, warmup)
+        chunk = max(1, steps // reps)
+        sizes = [chunk] * (reps - 1) + [steps - chunk * (reps - 1)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, n in enumerate(sizes):
+            ev[r].record(side)
+            asn.asn_step(p, n)
+        ev[reps].record(side)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        eager = [cq * n / (ev[r].elapsed_time(ev[r + 1]) * 1e-3) for r, n in enumerate(sizes)]
+        graph_rates = []
+        if graph and scheme == "euler" and chunk >= 2:
+            b = asn.asn_batch_create([p])
+            asn.asn_batch_step(b, chunk)                # capture + first replay
+            torch.cuda.synchronize()
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(side)
+                asn.asn_batch_step(b, chunk)
+                e1.record(side)
+                torch.cuda.synchronize()
+                graph_rates.append(cq * chunk / (e0.elapsed_time(e1) * 1e-3))
+            b.close()
+        kms = asn.asn_step_timed(p, chunk)
+        torch.cuda.synchronize()
+        bud = asn.asn_mass_budget(p)
+        p.close()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    asn.asn_step(p, steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    kms = asn.asn_step_timed(p, steps)
-    torch.cuda.synchronize()
-    wall_events = time.perf_counter() - t1
-    bud = asn.asn_mass_budget(p)
-    p.close()
-    return {"wall": wall, "wall_events": wall_events, "kms": kms, "info": info, "work": work,
-            "budget": bud, "scheme": scheme}
+    return {"wall": wall, "kms": kms, "info": info, "work": work, "budget": bud,
+            "scheme": scheme, "form": step_form, "eager_chunk_rates": eager,
+            "graph_chunk_rates": graph_rates, "chunk": chunk, "steps": steps}
 
 
-# Stencil bytes per update per step: Euler reads psi and Y and writes psi^{n+1}; a Heun
-# step is two passes, the second also reading psi^n.
-STENCIL_BYTES = {"euler": 12.0, "heun": 28.0}
-# widest grid whose separate stencil runs over flat 2048-cell chunks (three staged
-# rounds of 2048 floats hold the chunk and its neighbour rows); column strips beyond
-FLAT_MAX_NX = {"euler": 3 * 2048 - 2048 - 8, "heun": (3 * 2048 - 2048 - 8) // 3}
-PASSES = {"euler": 1, "heun": 2}
-
-
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_line_source_400_q512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_line_source_1024_q2048.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1911_08801_amd", "csrc", "asn_kernels.hip")
 
 
@@ -139,97 +182,76 @@ def measured_traffic(kernel, spec):
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_code_sha256") != kernel_source_hash() or (spec.nx, spec.q) != (400, 512):
+    if rec.get("kernel_code_sha256") != kernel_source_hash() or \
+            [spec.nx, spec.ny, spec.q] != rec.get("workload_nx_ny_q"):
         return None
-    total = 0.0
-    for name in kernel if isinstance(kernel, (list, tuple)) else [kernel]:
-        k = rec["kernels"].get(name)
-        if k is None:
-            return None
-        total += k["fetch_bytes"] + k["write_bytes"]
-    return total
+    k = rec["kernels"].get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
-def contraction_roofline(res, spec, dtype):
-    """MFMA roofline of the contraction kernel (fused or separate) of a run."""
+# the dominant kernel of each kernel form (its event slot in asn_step_timed)
+def dominant_kernel(res, spec, dtype):
+    form = res["form"]
+    if form == "banded":
+        return f"banded_euler_kernel<{spec.n_azim}>", "contraction"
+    lp = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
+    if form == "fused":
+        name = "gemm_f32_kernel<true>" if lp == 0 else f"gemm_lp_kernel<{lp}, true>"
+        return name, "contraction"
     kms = res["kms"]
-    scheme = res.get("scheme", "euler")
-    t_gemm = kms["contraction"] * 1e-3
-    fused = fused_run(res, dtype)
-    flops = PASSES[scheme] * res["work"]["tile_flops"]
-    peak = PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS
-    ach = flops / t_gemm / 1e12
-    if dtype == "f32":
-        prof = "gemm_f32_kernel<true>" if fused else "gemm_f32_kernel<false>"
-    else:
-        prof = f"gemm_lp_kernel<{1 if dtype == 'bf16' else 2}, {'true' if fused else 'false'}>"
-    traffic = measured_traffic(prof, spec)
-    return {"bound": "mfma", "kernel": prof + (" (contraction + stream/collide)" if fused else ""),
-            "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-            "frac": ach / peak,
-            "traffic": None if traffic is None else PASSES[scheme] * traffic,
-            "algorithmic": f"2*C*(K entries in the multiplied sub-blocks) = {flops:.4g} flop per "
-                           f"step (dense 2*Q*Q*C = {res['work']['dense_flops']:.4g} per launch)",
-            "dense_equivalent_TFLOPs": PASSES[scheme] * res["work"]["dense_flops"] / t_gemm / 1e12}
-
-
-def stencil_roofline(res, spec, dtype):
-    """HBM roofline of the separate stencil kernel(s) of a run (None when fused)."""
-    if fused_run(res, dtype):
-        return None
-    C, Q = spec.cells, spec.q
-    scheme = res.get("scheme", "euler")
-    t_sc = res["kms"]["stream_collide"] * 1e-3
-    sc_bytes = STENCIL_BYTES[scheme] * Q * C
-    ach = sc_bytes / t_sc / 1e9
-    lp = "false" if dtype == "f32" else "true"
-    flat = "_flat" if spec.nx <= FLAT_MAX_NX[scheme] else ""
-    prof = [f"stream_collide{flat}_kernel<{lp}>"] if scheme == "euler" else \
-        [f"muscl{flat}_kernel<{lp}, 1>", f"muscl{flat}_kernel<{lp}, 2>"]
-    return {"bound": "hbm", "kernel": " + ".join(prof), "achieved": ach,
-            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
-            "traffic": measured_traffic(prof, spec),
-            "algorithmic": f"{STENCIL_BYTES[scheme]:g}*Q*C = {sc_bytes:.4g} bytes per step"}
+    if kms["contraction"] >= kms["stream_collide"]:
+        return ("gemm_f32_kernel<false>" if lp == 0 else f"gemm_lp_kernel<{lp}, false>"), "contraction"
+    return ("stream_collide_flat_kernel<false>" if lp == 0 else
+            "stream_collide_flat_kernel<true>"), "stream_collide"
 
 
 def roofline(res, spec, dtype):
-    """Roofline entry of the kernel with the largest share of the step."""
-    kms = res["kms"]
-    if kms["contraction"] >= kms["stream_collide"]:
-        return contraction_roofline(res, spec, dtype)
-    return stencil_roofline(res, spec, dtype)
+    """Roofline of the step's dominant kernel on the method's own work.  Bytes: each
+    update reads psi^n and writes psi^{n+1} once (8 B in FP32) -- the binding roof, since
+    the contraction's own arithmetic, 2 nnz(K) flop per cell over the stored nonzeros,
+    stays below the compute ridge.  Separate-kernel forms move Y through memory as well
+    (their contraction and stencil each reported against the same 8 B/update)."""
+    name, slot = dominant_kernel(res, spec, dtype)
+    t = res["kms"][slot] * 1e-3
+    cq = spec.cells * spec.q
+    bytes_ = BYTES_PER_UPDATE * cq
+    ach = bytes_ / t / 1e9
+    nz = res["work"]["nonzero_flops"]
+    executed = res["work"]["tile_flops"]
+    compute_peak = (PEAK_FP32_VALU_TFLOPS if res["form"] == "banded" else
+                    PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS)
+    traffic = measured_traffic(name, spec)
+    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": traffic,
+            "algorithmic": f"{BYTES_PER_UPDATE:g} B x Q x C = {bytes_:.4g} B per step "
+                           f"(Q={spec.q}, C={spec.cells}); kernel {t * 1e3:.4g} ms (HIP events, "
+                           f"mean of {res['chunk']} steps)",
+            "kernel_ms": t * 1e3,
+            "method_flops": nz,
+            "method_TFLOPs": nz / t / 1e12,
+            "compute_peak_TFLOPs": compute_peak,
+            "method_compute_frac": nz / t / 1e12 / compute_peak,
+            "intensity_flop_per_byte": nz / bytes_,
+            "ridge_flop_per_byte": compute_peak * 1e12 / (PEAK_HBM_GBS * 1e9),
+            "executed_over_nonzero": executed / nz,
+            "dense_equivalent_TFLOPs": res["work"]["dense_flops"] / t / 1e12,
+            "traffic_over_algorithmic": None if traffic is None else traffic / bytes_}
 
 
-def rooflines(res, spec, dtype):
-    """Both rooflines of a run: MFMA for the contraction, HBM for a separate stencil."""
-    out = {"contraction": contraction_roofline(res, spec, dtype)}
-    st = stencil_roofline(res, spec, dtype)
-    if st is not None:
-        out["stencil"] = st
+def summary(res, spec, dtype="f32"):
+    cq = spec.cells * spec.q
+    steps = res["steps"]
+    out = {"value": cq * steps / res["wall"], "ms_per_step": 1e3 * res["wall"] / steps,
+           "form": res["form"], "dtype": dtype,
+           "eager_chunk_median_updates_per_s": statistics.median(res["eager_chunk_rates"]),
+           "eager_chunk_rates": res["eager_chunk_rates"],
+           "chunk_steps": res["chunk"],
+           "kernels_ms": res["kms"],
+           "budget_max_residual": res["budget"]["max_residual"]}
+    if res["graph_chunk_rates"]:
+        out["graph_chunk_median_updates_per_s"] = statistics.median(res["graph_chunk_rates"])
+        out["graph_chunk_rates"] = res["graph_chunk_rates"]
     return out
-
-
-def fused_run(res, dtype):
-    """True when the stencil ran inside the contraction (forward Euler)."""
-    kms = res["kms"]
-    return res.get("scheme", "euler") == "euler" and \
-        kms["stream_collide"] < 0.05 * kms["contraction"]
-
-
-def summary(res, spec, steps, dtype="f32"):
-    C, Q = spec.cells, spec.q
-    kms = res["kms"]
-    scheme = res.get("scheme", "euler")
-    sc_bytes = STENCIL_BYTES[scheme] * Q * C
-    fused = fused_run(res, dtype)
-    return {"value": C * Q * steps / res["wall"], "ms_per_step": 1e3 * res["wall"] / steps,
-            "ms_per_step_with_kernel_events": 1e3 * res["wall_events"] / steps,
-            "kernels_ms": kms,
-            "contraction_TFLOPs": PASSES[scheme] * res["work"]["tile_flops"]
-            / (kms["contraction"] * 1e-3) / 1e12,
-            "stream_collide_GBs": None if fused else sc_bytes / (kms["stream_collide"] * 1e-3) / 1e9,
-            "fused_step": fused,
-            "budget_max_residual": res["budget"]["max_residual"]}
 
 
 def serving_run(args):
@@ -312,26 +334,33 @@ def implicit_run(steps=3):
             "steps_timed": steps}
 
 
+GOLDEN_400 = os.path.join(ROOT, "tests", "golden", "line_source_400_q512_phi.npz")
+
+
 def precision_sweep(name):
-    """Full runs to t_final with FP32, BF16 and FP16 contractions on one workload;
-    updates/s per form and each reduced form's scalar-flux error against FP32."""
+    """Full runs to t_final with FP32, BF16 and FP16 contractions on one workload:
+    updates/s per form and each result's scalar-flux error against the FP32 run and,
+    for the 400 x 400 line source, against the FP64 oracle's stored flux."""
     import numpy as np
     import torch
 
     import workloads as wl
     from paper_1911_08801_amd import asn
+    oracle_phi = None
     if name == "lattice700":
         spec = wl.checkerboard(700, n_polar=24, sigma_as=5.0)
-        forms = ("f32", "bf16")
+    elif name == "line400":
+        spec = wl.line_source(400, n_polar=16, sigma_as=5.0)
+        oracle_phi = np.load(GOLDEN_400)["phi_as5"].astype(np.float64)
     else:
         spec = wl.line_source(1024, n_polar=32, sigma_as=5.0)
-        forms = ("f32", "bf16", "f16")
+    forms = ("f32", "bf16", "f16")
     out = {"workload": spec.name, "cells": spec.cells, "ordinates": spec.q, "forms": {}}
     ref = None
     for dt in forms:
         p = asn.from_spec(spec, dtype=dt)
         n = asn.asn_info(p)["steps_to_tfinal"]
-        work = asn.asn_contraction_work(p)
+        form = asn.asn_step_form(p)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         asn.asn_step(p, n)
@@ -340,13 +369,17 @@ def precision_sweep(name):
         phi = asn.asn_scalar_flux(p)
         bud = asn.asn_mass_budget(p)
         p.close()
-        rec = {"steps": n, "seconds": wall, "updates_per_s": spec.cells * spec.q * n / wall,
-               "tile_flops_per_step": work["tile_flops"], "budget_max_residual": bud["max_residual"],
+        rec = {"form": form, "steps": n, "seconds": wall,
+               "updates_per_s": spec.cells * spec.q * n / wall,
+               "budget_max_residual": bud["max_residual"],
                "defect_over_mass": bud["defect"] / max(bud["mass"], bud["mass0"], 1e-300)}
         if ref is None:
             ref = phi
         else:
             rec["phi_rel_l2_vs_f32"] = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+        if oracle_phi is not None:
+            rec["phi_rel_l2_vs_fp64_oracle"] = float(np.linalg.norm(phi - oracle_phi) /
+                                                     np.linalg.norm(oracle_phi))
         out["forms"][dt] = rec
         print(f"# {name} {dt}: {rec}", file=sys.stderr, flush=True)
     return out
@@ -354,20 +387,22 @@ def precision_sweep(name):
 
 def main():
     args = parse()
-    if args.sweep:
-        import torch
-        torch.cuda.set_device(0)
-        print(json.dumps({"sweep": precision_sweep(args.sweep)}), flush=True)
-        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only (no collectives, no "
+                                   "multi-GPU path); run with --gpus 1"}), flush=True)
         sys.exit(2)
     import torch
+    torch.cuda.set_device(0)
+    if args.sweep:
+        print(json.dumps({"sweep": precision_sweep(args.sweep)}), flush=True)
+        return
 
     import workloads as wl
     from paper_1911_08801_amd import asn
 
-    torch.cuda.set_device(0)
+    def log(msg):
+        print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
     if args.calibrate_copy:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
@@ -376,8 +411,9 @@ def main():
         del x, y
     spec = wl.line_source(args.n, n_polar=args.n_polar, sigma_as=args.sigma_as)
     C, Q = spec.cells, spec.q
-    res = timed_run(asn, spec, "f32", args.steps, args.warmup)
-    head = summary(res, spec, args.steps)
+    log(f"headline: {args.n}^2 x {Q}, FP32, {args.steps} steps")
+    res = measure(asn, spec, "f32", args.steps, args.warmup, args.reps)
+    head = summary(res, spec)
     out = {
         "metric": METRIC, "value": head["value"], "unit": "cell-ordinate updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -385,40 +421,46 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"line source {args.n}x{args.n} on [-1.5,1.5]^2, "
                                f"{args.n_polar}x{2 * args.n_polar}={Q} ordinates, sigma_s=1, "
-                               f"sigma_as={args.sigma_as}, beta=4.5, CFL 0.95, FP32 contraction",
+                               f"sigma_as={args.sigma_as}, beta=4.5, CFL 0.95, FP32",
                    "cells": C, "ordinates": Q, "dt": res["info"]["dt"],
-                   "steps_to_tfinal": res["info"]["steps_to_tfinal"]},
+                   "steps_to_tfinal": res["info"]["steps_to_tfinal"],
+                   "kernel_form": head["form"]},
         "f32": head,
         "roofline": roofline(res, spec, "f32"),
     }
-    out["f32"]["rooflines"] = rooflines(res, spec, "f32")
-    if not args.no_separate:
-        # the same FP32 Euler step in the other kernel form than the library chose
-        # (separate: Y through memory and the stencil's own HBM roofline; fused: the
-        # stencil in the contraction's epilogue)
-        sep = head["fused_step"]
-        r = timed_run(asn, spec, "f32", args.steps, args.warmup, unfused=sep)
-        key = "f32_separate" if sep else "f32_fused"
-        out[key] = summary(r, spec, args.steps)
-        out[key]["rooflines"] = rooflines(r, spec, "f32")
     if not args.no_lowp:
         for dt in ("bf16", "f16"):
-            r = timed_run(asn, spec, dt, args.steps, args.warmup)
-            out[dt] = summary(r, spec, args.steps, dt)
+            log(f"headline workload, {dt}")
+            r = measure(asn, spec, dt, args.steps, args.warmup, args.reps)
+            out[dt] = summary(r, spec, dt)
             out[dt]["roofline"] = roofline(r, spec, dt)
-            out[dt]["rooflines"] = rooflines(r, spec, dt)
+    if not args.no_small:
+        # the 400 x 400 x 512 line source: every FP32 kernel form, and each precision's
+        # full run to t = 1 against the FP64 oracle's stored flux
+        small = wl.line_source(400, n_polar=16, sigma_as=5.0)
+        out["line400"] = {}
+        for form in ("auto", "separate", "fused"):
+            log(f"400^2 x 512, FP32 {form}")
+            r = measure(asn, small, "f32", 40, args.warmup, args.reps, form=form)
+            out["line400"][r["form"]] = summary(r, small)
+            out["line400"][r["form"]]["roofline"] = roofline(r, small, "f32")
+        log("400^2 x 512 precision vs oracle")
+        out["line400"]["precision_vs_oracle"] = precision_sweep("line400")["forms"]
     if not args.no_heun:
-        # the paper's own explicit scheme (Heun + minmod), same workload, FP32 contraction
-        r = timed_run(asn, spec, "f32", args.steps, args.warmup, scheme="heun")
-        out["heun_f32"] = summary(r, spec, args.steps)
-        out["heun_f32"]["roofline"] = roofline(r, spec, "f32")
-        out["heun_f32"]["rooflines"] = rooflines(r, spec, "f32")
+        # the paper's own explicit scheme (Heun + minmod), 400 x 400 x 512
+        small = wl.line_source(400, n_polar=16, sigma_as=5.0)
+        log("Heun + minmod 400^2 x 512")
+        r = measure(asn, small, "f32", 20, args.warmup, args.reps, scheme="heun", graph=False)
+        out["heun_f32_line400"] = summary(r, small)
     if not args.no_implicit:
+        log("implicit")
         out["implicit"] = implicit_run()
     if not args.no_serving:
+        log(f"serving {args.serve_requests} requests")
         out["serving"] = serving_run(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_rows, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--sigma-as", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
-    ap.add_argument("--cpu-rows", type=int, default=32,
+    ap.add_argument("--cpu-rows", type=int, default=64,
                     help="rows of the headline grid (through the pulse) the oracle steps")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the 400 x 400 x 512 line (all FP32 forms, precision vs oracle)")

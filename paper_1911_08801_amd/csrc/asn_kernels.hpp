@@ -70,8 +70,13 @@ constexpr int SCHEME_EULER_BANDED = 5;
 constexpr int kBandCells = 32;
 constexpr int kBandO = 4;
 constexpr int kBandNarrow = 8;
-constexpr int kBandLead = kBandNarrow;     // rows before azimuth 0 (narrow reach)
-constexpr int kBandTrail = kBandO + 2;     // rows after the last azimuth (a step of four)
+// Rows before azimuth 0 and after the last azimuth.  A narrow pair of width s reads
+// the azimuths a0 - s .. a0 + kBandO - 1 + s of outputs a0 .. a0 + kBandO - 1, a wide
+// step the rows m .. m + kBandO + 2 from a wrapped start m in [0, n_az).
+constexpr int kBandLead = kBandNarrow;
+constexpr int kBandTrail = kBandNarrow > kBandO + 2 ? kBandNarrow : kBandO + 2;
+static_assert(kBandLead >= kBandNarrow && kBandTrail >= kBandNarrow && kBandTrail >= kBandO + 2,
+              "banded ring rows must cover every narrow and wide read");
 constexpr int kBandStride = 40;
 constexpr int kBandMaxReach = 3;
 // Azimuth counts with a kernel instance.

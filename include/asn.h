@@ -143,7 +143,10 @@ typedef struct {
     double cfl;             /* 0 < cfl <= 1 bounds dt * max_q(|xi|/dx + |eta|/dy); default 0.95   */
     double eps_override;    /* > 0: kernel width eps used instead of beta / Q                     */
     double dt_override;     /* > 0: fixed dt (still subject to the CFL bound)                     */
-    int32_t budget_every;   /* reserved: the particle budget is folded every step (set 0 or 1)   */
+    int32_t scale_block;    /* ASN_GEMM_BF16 / _F16: cells per block of the operand's power-of-two
+                               scale (flat cell index c = y nx + x, blocks [b n, (b + 1) n));
+                               a power of two from 64 to 4096, default 256; 0 means 256.
+                               Ignored for FP32, still checked.                           */
     int32_t scheme;         /* ASN_SCHEME_EULER (default) or ASN_SCHEME_HEUN                     */
     int32_t dt_rule;        /* ASN_DT_STREAMING (default) or ASN_DT_STIFF                        */
     int32_t step_form;      /* ASN_FORM_AUTO (default), _SEPARATE, _FUSED or _BANDED:       

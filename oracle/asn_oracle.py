@@ -652,7 +652,8 @@ def heun_step_entries(psi: np.ndarray, st: Setup, qs: np.ndarray, js: np.ndarray
 # accumulation.  The recipe (fixed by the design, not by the paper) is:
 #   iso_c  = fp32(Phi_c / W)                        isotropic part, exact for K
 #   dev_qc = fp32(psi_qc - iso_c)                    only the deviation is rounded
-#   e_b    = frexp exponent of max_{q, c in b} |psi_qc| over 256-cell blocks b,
+#   e_b    = frexp exponent of max_{q, c in b} |psi_qc| over blocks b of n cells
+#            of the flattened grid (n = 256 unless chosen: a power of two 64..4096),
 #            at least -100 (0 for an all-zero block)
 #   s_qc   = dev_qc * 2^(E - e_b), E = 14            power-of-two block scale
 #   x_qc   = T(s_qc) for FP16;  for BF16 two terms   RNE throughout
@@ -709,7 +710,7 @@ def lowprec_kernel(K: np.ndarray, dtype: str) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def block_exponents(psi32: np.ndarray, block: int = SCALE_BLOCK) -> np.ndarray:
-    """Per-cell exponent e_b of the block max |psi| (flattened cells, blocks of 256)."""
+    """Per-cell exponent e_b of the block max |psi| (flattened cells, blocks of `block`)."""
     Q = psi32.shape[0]
     flat = np.abs(psi32.reshape(Q, -1)).max(axis=0)
     C = flat.size
@@ -733,8 +734,10 @@ def _weighted_ordinate_sum(w: np.ndarray, x: np.ndarray) -> np.ndarray:
 
 def lowprec_in_scattering(psi32: np.ndarray, st: Setup, dtype: str,
                           kq: Optional[np.ndarray] = None,
-                          r: Optional[np.ndarray] = None) -> np.ndarray:
-    """Y by the reduced-precision recipe above, for a float32 state [Q, ny, nx]."""
+                          r: Optional[np.ndarray] = None,
+                          block: int = SCALE_BLOCK) -> np.ndarray:
+    """Y by the reduced-precision recipe above, for a float32 state [Q, ny, nx], with
+    scale blocks of `block` cells."""
     if kq is None:
         kq, r = lowprec_kernel(st.K, dtype)
     Q = psi32.shape[0]
@@ -742,7 +745,7 @@ def lowprec_in_scattering(psi32: np.ndarray, st: Setup, dtype: str,
     phi = _weighted_ordinate_sum(st.w, p.astype(np.float64))
     iso = (phi / st.W).astype(np.float32)
     dev = (p - iso[None, :]).astype(np.float32)
-    e = block_exponents(p)
+    e = block_exponents(p, block)
     s_in = np.ldexp(np.float32(1.0), (SCALE_EXP - e)).astype(np.float32)
     x = operand_terms((dev * s_in[None, :]).astype(np.float32), dtype)
     acc = kq @ x
@@ -753,7 +756,8 @@ def lowprec_in_scattering(psi32: np.ndarray, st: Setup, dtype: str,
     return Y.reshape(psi32.shape)
 
 
-def lowprec_step(psi32: np.ndarray, st: Setup, dtype: str, kq=None, r=None):
+def lowprec_step(psi32: np.ndarray, st: Setup, dtype: str, kq=None, r=None,
+                 block: int = SCALE_BLOCK):
     """One step with the reduced-precision Y; the rest of the step stays FP64."""
-    Y = lowprec_in_scattering(psi32, st, dtype, kq, r)
+    Y = lowprec_in_scattering(psi32, st, dtype, kq, r, block)
     return step(np.asarray(psi32, dtype=np.float64), st, Y=Y)

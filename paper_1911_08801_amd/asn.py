@@ -72,7 +72,7 @@ class asn_quadrature(ctypes.Structure):
 class asn_options(ctypes.Structure):
     _fields_ = [("gemm_dtype", ctypes.c_int32), ("normalization", ctypes.c_int32),
                 ("cfl", ctypes.c_double), ("eps_override", ctypes.c_double),
-                ("dt_override", ctypes.c_double), ("budget_every", ctypes.c_int32),
+                ("dt_override", ctypes.c_double), ("scale_block", ctypes.c_int32),
                 ("scheme", ctypes.c_int32), ("dt_rule", ctypes.c_int32),
                 ("step_form", ctypes.c_int32), ("implicit_tol", ctypes.c_double),
                 ("source_tol", ctypes.c_double), ("source_test", ctypes.c_int32)]
@@ -228,10 +228,11 @@ def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
                  scheme: str = "euler", dt_rule: str = "streaming",
                  unfused: Optional[bool] = None, implicit_tol: float = 0.0,
                  source_tol: float = 0.0, source_test: str = "absolute",
-                 form: Optional[str] = None) -> asn_options:
+                 form: Optional[str] = None, scale_block: int = 256) -> asn_options:
     """Options for asn_create.  Kernel form of forward-Euler steps: form "auto",
     "separate", "fused" or "banded"; or unfused (when form is None): None lets the
-    library choose, True asks for separate kernels, False for the fused one."""
+    library choose, True asks for separate kernels, False for the fused one.
+    scale_block: cells per block of the BF16 / FP16 operand scale."""
     o = asn_options_default()
     o.gemm_dtype = DTYPES[dtype]
     o.normalization = NORMS[norm]
@@ -248,6 +249,7 @@ def make_options(dtype: str = "f32", norm: str = "sym", cfl: float = 0.95,
     o.cfl = cfl
     o.eps_override = eps_override
     o.dt_override = dt_override
+    o.scale_block = scale_block
     return o
 
 
@@ -494,12 +496,13 @@ def from_spec(spec, dtype: str = "f32", norm: str = "sym", device: str = "cuda",
               set_initial_state: bool = True, scheme: str = "euler",
               dt_rule: str = "streaming", unfused: Optional[bool] = None,
               implicit_tol: float = 0.0, source_tol: float = 0.0,
-              source_test: str = "absolute", form: Optional[str] = None) -> AsnProblem:
+              source_test: str = "absolute", form: Optional[str] = None,
+              scale_block: int = 256) -> AsnProblem:
     """Create a problem from any object with the attributes of a problem description
     (nx, ny, x/y extents, n_polar, n_azim, sigma_*, source, psi0_cell, beta, t_final, cfl)."""
     grid = make_grid(spec.nx, spec.ny, spec.x_min, spec.x_max, spec.y_min, spec.y_max)
     opt = make_options(dtype, norm, spec.cfl, eps_override, dt_override, scheme, dt_rule, unfused,
-                       implicit_tol, source_tol, source_test, form)
+                       implicit_tol, source_tol, source_test, form, scale_block)
     p = asn_create(grid, spec.n_polar, spec.n_azim, spec.sigma_s, spec.sigma_a, spec.sigma_as,
                    spec.source, spec.beta, spec.t_final, opt, device=device,
                    icosahedron_order=getattr(spec, "ico_order", 0))

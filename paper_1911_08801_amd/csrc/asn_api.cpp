@@ -61,6 +61,15 @@ static size_t band_coef_capacity(int levels, int azim) {
     return (size_t)levels * span * (size_t)round_up(azim, 4);
 }
 
+// log2 of an accepted operand scale block (0 selects the default), else -1.
+int scale_block_log(int32_t n) {
+    if (n == 0) n = asn::kScaleBlock;
+    if (n < asn::kScaleBlockMin || n > asn::kScaleBlockMax || (n & (n - 1)) != 0) return -1;
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
 Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int band_levels = 0,
                    int band_azim = 0) {
     Layout L;
@@ -142,8 +151,9 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
     L.off_ypart = take(L.lowp ? (size_t)(L.Qp / asn::kGemmBM) * plane * 8 : 0);
     L.off_fix = take(L.lowp && !fused ? plane * 4 : 0);
     L.off_delta = take(L.lowp && fused ? plane * 4 : 0);
-    L.off_bmax0 = take(plane / asn::kScaleBlock * 4);
-    L.off_bmax1 = take(plane / asn::kScaleBlock * 4);
+    // block maxima for the smallest scale block (any block size a problem takes fits)
+    L.off_bmax0 = take((size_t)asn::scale_blocks(L.P, scale_block_log(asn::kScaleBlockMin)) * 4);
+    L.off_bmax1 = take((size_t)asn::scale_blocks(L.P, scale_block_log(asn::kScaleBlockMin)) * 4);
     L.off_rec = take(asn::REC_LEN * 8);
     // the problem as a batch of one: step arguments for both buffers, block offsets,
     // buffer base and step counter
@@ -176,6 +186,7 @@ struct asn_problem_s {
     double dx = 0, dy = 0, dt = 0, W = 0, eps = 0, stability = 0;
     int64_t n_to_tfinal = 0, steps_done = 0;
     int dtype = 0, norm = 0, scheme = 0;
+    int sb_log = 8;   // log2 of the cells per operand scale block
     hipStream_t stream = nullptr;
     int device = 0;
     bool owns = false;
@@ -224,6 +235,7 @@ StepArgs make_args(asn_problem p, int cur) {
     a.tiles_y = L.tiles_y;
     a.fin_blocks = L.fin_blocks;
     a.dtype = p->dtype;
+    a.sb_log = p->sb_log;
     a.fused = L.fused ? 1 : 0;
     a.W = p->W;
     a.area = p->dx * p->dy;
@@ -423,7 +435,7 @@ asn_status asn_options_default(asn_options* opt) {
     opt->gemm_dtype = ASN_GEMM_F32;
     opt->normalization = ASN_NORM_SYM;
     opt->cfl = 0.95;
-    opt->budget_every = 1;
+    opt->scale_block = asn::kScaleBlock;
     return ASN_OK;
 }
 
@@ -439,6 +451,8 @@ asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
     const int dtype = opt ? opt->gemm_dtype : d.gemm_dtype;
     const int scheme = opt ? opt->scheme : d.scheme;
     const int form = opt ? opt->step_form : d.step_form;
+    if (scale_block_log(opt ? opt->scale_block : d.scale_block) < 0)
+        return fail(ASN_E_INVALID, "scale_block must be a power of two from 64 to 4096 (or 0)");
     if (form < ASN_FORM_AUTO || form > ASN_FORM_BANDED)
         return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, _SEPARATE, _FUSED or _BANDED");
     if (form == ASN_FORM_BANDED) {
@@ -475,6 +489,9 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         return fail(ASN_E_INVALID, "unknown gemm_dtype");
     if (opt.normalization != ASN_NORM_SYM && opt.normalization != ASN_NORM_ROW)
         return fail(ASN_E_INVALID, "unknown normalization");
+    const int sb_log = scale_block_log(opt.scale_block);
+    if (sb_log < 0)
+        return fail(ASN_E_INVALID, "scale_block must be a power of two from 64 to 4096 (or 0)");
     if (opt.scheme != ASN_SCHEME_EULER && opt.scheme != ASN_SCHEME_HEUN &&
         opt.scheme != ASN_SCHEME_IMPLICIT)
         return fail(ASN_E_INVALID, "unknown scheme");
@@ -508,6 +525,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     p->dx = (grid->x_max - grid->x_min) / grid->nx;
     p->dy = (grid->y_max - grid->y_min) / grid->ny;
     p->dtype = opt.gemm_dtype;
+    p->sb_log = sb_log;
     p->norm = opt.normalization;
     p->scheme = opt.scheme;
     p->stream = reinterpret_cast<hipStream_t>(hip_stream);

@@ -465,12 +465,17 @@ void gemm_lp_kernel(BatchArgs B) {
     const int Q = a.Q, Qp = a.Qp;
     const int64_t P = a.P;
 
-    const float bm = __uint_as_float(gp(a.bmax_cur)[n0 / kScaleBlock]);
-    int e = 0;
-    if (bm > 0.f) (void)frexpf(bm, &e);
-    e = max(e, -100);
-    const float s_in = ldexpf(1.f, kScaleExp - e);
-    const float s_out = ldexpf(1.f, e - kScaleExp);
+    // Operand scale 2^(E - e_b) of scale block b (at least 64 cells): the four cells a
+    // thread stages (n0 + 4 cg ..) lie in one block, and so do the 64 output cells of a
+    // wave (n0 + wn ..); with blocks of 128 or more the tile has one scale.
+    auto block_exp = [&](int64_t c) {
+        const float bm = __uint_as_float(gp(a.bmax_cur)[c >> a.sb_log]);
+        int e = 0;
+        if (bm > 0.f) (void)frexpf(bm, &e);
+        return max(e, -100);
+    };
+    const float s_in = ldexpf(1.f, kScaleExp - block_exp(n0 + 4 * (tid & 31)));
+    const float s_out = ldexpf(1.f, block_exp(n0 + __builtin_amdgcn_readfirstlane(wn)) - kScaleExp);
 
     // Staging of one k-step (32 ordinates).  A: thread t moves 16-byte pieces t and
     // t + 256 of the T(K) tile.  B: thread t loads ordinates k0 + 4 kg .. + 3 of cells
@@ -800,9 +805,10 @@ void gemm_lp_kernel(BatchArgs B) {
                 }
             }
         }
-        // block max |psi^{n+1}| of the next operand scale: the tile lies in one block
+        // block max |psi^{n+1}| of the next operand scale: the wave's 64 cells lie in
+        // one block
         const unsigned mbits = wave_max_u32(__float_as_uint(mx));
-        if (lane == 0 && mbits) atomicMax(&a.bmax_next[n0 / kScaleBlock], mbits);
+        if (lane == 0 && mbits) atomicMax(&a.bmax_next[(n0 + wn) >> a.sb_log], mbits);
         double sums[2] = {defect, outflow};
         block_sum_256<2>(sums, gp(a.blk_part) + 2 * (size_t)tile);   // synchronises the block
         if (tid < kGemmBN) {
@@ -1037,13 +1043,13 @@ __global__ __launch_bounds__(256) void stream_collide_kernel(BatchArgs B) {
     for (int r = 0; r < R; ++r)
         if (in[r]) gp(a.phi_part)[(size_t)g * P + (uint32_t)((ybase + r) * nx + x)] = phacc[r];
     if (LP) {
-        // The updating lanes of one row cover at most two 256-cell scale blocks.
+        // The updating lanes of one row (at most 62 cells) cover at most two scale blocks.
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = ybase + r;
             const int64_t c_first = (int64_t)y * nx + bx * kStripX;
-            const int64_t b0 = c_first / kScaleBlock;
-            const int64_t cb = ((int64_t)y * nx + x) / kScaleBlock;
+            const int64_t b0 = c_first >> a.sb_log;
+            const int64_t cb = ((int64_t)y * nx + x) >> a.sb_log;
             const unsigned bits = in[r] ? __float_as_uint(mx[r]) : 0u;
             const unsigned m0 = wave_max_u32(cb == b0 ? bits : 0u);
             const unsigned m1 = wave_max_u32(cb != b0 ? bits : 0u);
@@ -1212,7 +1218,7 @@ __global__ __launch_bounds__(kFlatThreads) void stream_collide_flat_kernel(Batch
         for (int j = 0; j < J; ++j) {
             const unsigned m = wave_max_u32(__float_as_uint(mx[j]));
             const int cw = b0 + (tid & ~63) + T * j;
-            if (lane == 0 && m && cw < Pi) atomicMax(&a.bmax_next[cw / kScaleBlock], m);
+            if (lane == 0 && m && cw < Pi) atomicMax(&a.bmax_next[cw >> a.sb_log], m);
         }
     }
     double sums[2] = {defect, outflow};
@@ -1417,8 +1423,8 @@ __global__ __launch_bounds__(256) void muscl_kernel(BatchArgs B) {
         for (int r = 0; r < R; ++r) {
             const int y = ybase + r;
             const int64_t c_first = (int64_t)y * nx + bx * kStripXM;
-            const int64_t b0 = c_first / kScaleBlock;
-            const int64_t cb = ((int64_t)y * nx + x) / kScaleBlock;
+            const int64_t b0 = c_first >> a.sb_log;
+            const int64_t cb = ((int64_t)y * nx + x) >> a.sb_log;
             const unsigned bits = in[r] ? __float_as_uint(mx[r]) : 0u;
             const unsigned m0 = wave_max_u32(cb == b0 ? bits : 0u);
             const unsigned m1 = wave_max_u32(cb != b0 ? bits : 0u);
@@ -1632,7 +1638,7 @@ __global__ __launch_bounds__(kFlatThreads) void muscl_flat_kernel(BatchArgs B) {
         for (int j = 0; j < J; ++j) {
             const unsigned m = wave_max_u32(__float_as_uint(mx[j]));
             const int cw = b0 + (tid & ~63) + T * j;
-            if (lane == 0 && m && cw < Pi) atomicMax(&a.bmax_next[cw / kScaleBlock], m);
+            if (lane == 0 && m && cw < Pi) atomicMax(&a.bmax_next[cw >> a.sb_log], m);
         }
     }
     double sums[2] = {defect, outflow};
@@ -1693,7 +1699,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(BatchArgs B, int init) {
         s[2] = (double)cf.w;
         s[3] = corr;
     }
-    if (bmax_zero != nullptr && c < a.P / kScaleBlock) bmax_zero[c] = 0u;
+    if (bmax_zero != nullptr && c < scale_blocks(a.P, a.sb_log)) bmax_zero[c] = 0u;
     block_sum_256<4>(s, gp(a.fin_part) + 4 * (size_t)local);
 }
 
@@ -1845,7 +1851,7 @@ __global__ __launch_bounds__(256) void moments_kernel(StepArgs a) {
         mx = fmaxf(mx, fabsf(v));
     }
     a.phi_part[c] = phi;
-    atomicMax(&a.bmax_cur[c / kScaleBlock], __float_as_uint(mx));
+    atomicMax(&a.bmax_cur[c >> a.sb_log], __float_as_uint(mx));
 }
 
 __global__ void fill_u32_kernel(unsigned* p, int64_t n, unsigned v) {
@@ -2342,7 +2348,7 @@ hipError_t launch_arm(int* steps_left, int* base, int n, const ArmArgs& v, hipSt
 }
 
 hipError_t launch_init(const StepArgs& a, const BatchArgs& one, hipStream_t s) {
-    const int64_t nb = a.P / kScaleBlock;
+    const int64_t nb = scale_blocks(a.P, a.sb_log);
     fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_cur, nb, 0u);
     fill_u32_kernel<<<div_up(nb, 256), 256, 0, s>>>(a.bmax_next, nb, 0u);
     moments_kernel<<<div_up(a.C, 256), 256, 0, s>>>(a);

@@ -91,8 +91,15 @@ inline size_t band_lds_bytes(int az, int reach, int cmax) {
 // Modes of the budget kernel.
 enum { BUD_STEP = 0, BUD_INIT = 1, BUD_STAGE1 = 2, BUD_STAGE2 = 3 };
 
-// Cells per block of the reduced-precision operand scale.
+// Cells per block of the reduced-precision operand scale: the default, and the range
+// of powers of two a problem may choose (StepArgs::sb_log).  A block holds at least 64
+// cells, so the 64 cells of one wave of the contraction's epilogue or of a flat-chunk
+// stencil lie in one block.
 constexpr int kScaleBlock = 256;
+constexpr int kScaleBlockMin = 64;
+constexpr int kScaleBlockMax = 4096;
+// Blocks of 2^sb_log cells covering a plane of P cells.
+__host__ __device__ inline int64_t scale_blocks(int64_t P, int sb_log) { return (P + (1 << sb_log) - 1) >> sb_log; }
 // Scaled operands satisfy |x| < 2^(kScaleExp + 1).
 constexpr int kScaleExp = 14;
 
@@ -121,6 +128,8 @@ struct StepArgs {
     int fin_blocks;
     // operand type: 0 FP32, 1 BF16, 2 FP16
     int dtype;
+    // log2 of the cells per block of the reduced-precision operand scale
+    int sb_log;
     // 1: the stencil runs in the contraction's epilogue (forward Euler); the
     // stencil decomposition is then the contraction's: tiles_x = P / kGemmBN cell
     // tiles, tiles_y = 1, G = Qp / kGemmBM ordinate tiles

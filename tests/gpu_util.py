@@ -11,12 +11,12 @@ from oracle import asn_oracle as o
 
 
 def gpu_run(asn, spec, n_steps, psi0=None, dtype="f32", norm="sym", eps_override=0.0,
-            scheme="euler", dt=0.0, unfused=False, form=None):
+            scheme="euler", dt=0.0, unfused=False, form=None, scale_block=256):
     """Advance ``spec`` on the GPU; returns (state, phi, budget, info).  The kernel
     form is ``form`` if given, else fused (unfused False) or separate (True)."""
     p = asn.from_spec(spec, dtype=dtype, norm=norm, eps_override=eps_override,
                       set_initial_state=psi0 is None, scheme=scheme, dt_override=dt,
-                      unfused=unfused, form=form)
+                      unfused=unfused, form=form, scale_block=scale_block)
     if form is not None:
         assert asn.asn_step_form(p) == (form if form != "auto" else asn.asn_step_form(p))
     try:

@@ -200,6 +200,19 @@ def test_step_form_choice_by_size_and_operand_type():
         asn.asn_workspace_size(g, q, opt)
 
 
+def test_scale_block_choices_checked():
+    g = asn.make_grid(40, 30, 0.0, 1.0, 0.0, 1.0)
+    q = asn.asn_quadrature(2, 4, 0, None, None, 0)
+    for dtype in ("f32", "bf16"):
+        sizes = [asn.asn_workspace_size(g, q, asn.make_options(dtype=dtype, scale_block=sb))
+                 for sb in (0, 64, 128, 256, 1024, 4096)]
+        assert len(set(sizes)) == 1          # block maxima are sized for the smallest block
+        for sb in (-64, 1, 32, 96, 100, 8192):
+            with pytest.raises(asn.AsnError):
+                asn.asn_workspace_size(g, q, asn.make_options(dtype=dtype, scale_block=sb))
+    assert asn.asn_options_default().scale_block == 256
+
+
 def test_destroy_accepts_null_and_status_strings():
     assert asn._lib.asn_destroy(None) == asn.ASN_OK
     for s in range(-6, 1):

@@ -19,12 +19,12 @@ if not torch.cuda.is_available():
 from paper_1911_08801_amd import asn  # noqa: E402
 
 
-def _emulated_run(spec, n, psi0, dtype):
+def _emulated_run(spec, n, psi0, dtype, block=o.SCALE_BLOCK):
     st = o.setup(spec)
     kq, r = o.lowprec_kernel(st.K, dtype)
     psi = psi0.astype(np.float32)
     for _ in range(n):
-        new, _ = o.lowprec_step(psi, st, dtype, kq, r)
+        new, _ = o.lowprec_step(psi, st, dtype, kq, r, block)
         psi = new.astype(np.float32)
     return psi, st
 
@@ -56,6 +56,34 @@ def test_separate_kernels_match_emulation(dtype, nx, ny, n_polar):
     fused3, _, _, _ = gpu_run(asn, spec, 3, psi0=psi0, dtype=dtype)
     assert rel_l2(state3, fused3) <= 1e-5
     assert bud3["max_residual"] <= max(64 * fp32_budget_floor(state3, st.w), 1e-10)
+
+
+@pytest.mark.parametrize("block", [64, 4096])
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("unfused", [False, True])
+def test_scale_block_matches_emulation(block, dtype, unfused):
+    # 128 x 70 cells (ragged last block of 4096), no source; rows 0-15 are 2^-50 times
+    # smaller than the rest, so blocks of 64 cells scale the two bands apart and blocks
+    # of 4096 put both under one scale: FP16 operands of the small band then round to
+    # zero and the two block sizes give different states (checked on the band).
+    nx, ny, n_polar = 128, 70, 4
+    spec = wl.random_problem(19, nx, ny, n_polar=n_polar, n_azim=2 * n_polar, beta=4.5)
+    spec.source[:] = 0.0
+    psi0 = wl.random_state(20, spec.q, ny, nx)
+    psi0[:, :16] *= np.float32(2.0 ** -50)
+    band = (slice(None), slice(0, 12))          # the small band, off its edge by more than 3 steps reach
+    for steps in (1, 3):
+        state, _, bud, _ = gpu_run(asn, spec, steps, psi0=psi0, dtype=dtype, unfused=unfused,
+                                   scale_block=block)
+        ref, st = _emulated_run(spec, steps, psi0, dtype, block)
+        # steps after the first take their scales from the block maxima the kernels
+        # produce; over several steps the forms round different FP32 sums
+        tol = 2e-6 if steps == 1 else 2e-5
+        assert np.max(np.abs(state - ref)) <= tol * np.abs(ref).max()
+        assert np.max(np.abs(state[band] - ref[band])) <= tol * np.abs(ref[band]).max()
+    if dtype == "f16":
+        other, _ = _emulated_run(spec, 3, psi0, dtype, 4096 if block == 64 else 64)
+        assert np.max(np.abs(other[band] - ref[band])) > 1e-3 * np.abs(ref[band]).max()
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])

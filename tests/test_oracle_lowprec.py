@@ -59,16 +59,50 @@ def test_particle_fix_and_accuracy(dtype):
         assert err > 2.0 ** -16 * dev          # the rounding is really applied
 
 
-def test_block_exponents_bound_block_maximum():
+@pytest.mark.parametrize("block", [64, 256, 4096])
+def test_block_exponents_bound_block_maximum(block):
+    # 23 x 211 = 4853 cells: a ragged last block at every size
     rng = np.random.default_rng(7)
-    psi = (rng.random((3, 5, 211)) * np.exp2(rng.integers(-20, 20, (1, 5, 211)))).astype(np.float32)
-    e = o.block_exponents(psi)
+    psi = (rng.random((3, 23, 211)) * np.exp2(rng.integers(-20, 20, (1, 23, 211)))).astype(np.float32)
+    e = o.block_exponents(psi, block)
     flat = np.abs(psi.reshape(3, -1)).max(axis=0)
-    for b in range(0, flat.size, 256):
-        m = flat[b:b + 256].max()
+    for b in range(0, flat.size, block):
+        m = flat[b:b + block].max()
         eb = e[b]
-        assert np.all(e[b:b + 256] == eb)
+        assert np.all(e[b:b + block] == eb)
         assert 2.0 ** (eb - 1) <= m < 2.0 ** eb
+
+
+def _banded_magnitude_state(st, seed, ratio_exp):
+    """A 32 x 128 state whose rows 0-15 are 2^ratio_exp times smaller than rows 16-31:
+    blocks of 64 cells (half a row) never mix the two bands, blocks of 4096 do."""
+    psi = wl.random_state(seed, st.q, 32, 128)
+    psi[:, :16] *= np.float32(2.0 ** ratio_exp)
+    return psi
+
+
+def test_scale_block_leaves_bf16_unchanged_and_sets_f16_subnormal_range():
+    # Scaling by a power of two commutes with rounding while the scaled operand stays a
+    # normal number: the two-term BF16 operand (8 exponent bits) gives the same Y for
+    # every block size.  FP16 (5 exponent bits) does not: with one scale for both bands
+    # the small band's operands fall below 2^-14 and lose bits to the subnormal spacing,
+    # with blocks of 64 each band keeps 11 significant bits.
+    prob = wl.random_problem(11, 128, 32, n_polar=4, n_azim=8, beta=4.5)
+    st = o.setup(prob)
+    psi = _banded_magnitude_state(st, 12, -30)
+    Yx = o.as_in_scattering(psi.astype(np.float64), st.K)
+    small = (slice(None), slice(0, 16))
+    phi = o.scalar_flux(psi.astype(np.float64), st.w)
+    dev_small = np.abs(psi[small] - (phi / st.W)[:16]).max()
+    y64 = o.lowprec_in_scattering(psi, st, "bf16", block=64)
+    y4k = o.lowprec_in_scattering(psi, st, "bf16", block=4096)
+    assert np.array_equal(y64, y4k)
+    f64 = o.lowprec_in_scattering(psi, st, "f16", block=64)
+    f4k = o.lowprec_in_scattering(psi, st, "f16", block=4096)
+    e64 = np.abs(f64[small] - Yx[small]).max()
+    e4k = np.abs(f4k[small] - Yx[small]).max()
+    assert e64 < 2.0 ** -10 * dev_small
+    assert e4k > 8 * e64
 
 
 def test_scaled_operands_fit_half_range():

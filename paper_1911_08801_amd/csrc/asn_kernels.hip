@@ -1926,25 +1926,30 @@ __device__ __forceinline__ void band_narrow(float (&acc)[kBandO], const float* r
 }
 
 // A wide pair: offsets lo .. lo + len - 1 in steps of four (coefficients past len are
-// zero) from the slot row of azimuth a0 + lo wrapped into [0, A).  slot: the lane's
-// column in row 0 of the slot.
+// zero), from the slot row of azimuth a0 + lo wrapped into [0, A).  A step reads the
+// rows m .. m + kBandO + 2 of its start m in [0, A) (the trailing copies cover those
+// past A - 1); the start advances by four rows and wraps once it passes the last
+// azimuth.  slot: the lane's column in row 0 of the slot.
 template <int A>
 __device__ __forceinline__ void band_wide(float (&acc)[kBandO], const float* slot, int a0, int lo,
                                           int len, const float* cf) {
     constexpr int O = kBandO;
+    const int m0 = a0 + lo;   // >= 1 - A / 2 - ... > -A
+    const float* r = slot + (m0 < 0 ? m0 + A + kBandLead : m0 + kBandLead) * kBandStride;
+    const float* const rend = slot + (A + kBandLead) * kBandStride;
+    const float4* k4 = reinterpret_cast<const float4*>(cf);
     for (int j0 = 0; j0 < len; j0 += 4) {
-        int m = a0 + lo + j0;
-        m = m < 0 ? m + A : (m >= A ? m - A : m);
-        const float* r = slot + (m + kBandLead) * kBandStride;
         float in[O + 3];
 #pragma unroll
         for (int u = 0; u < O + 3; ++u) in[u] = r[u * kBandStride];
-        const float4 k = reinterpret_cast<const float4*>(cf)[j0 / 4];
+        const float4 k = *k4++;
         const float kk[4] = {k.x, k.y, k.z, k.w};
 #pragma unroll
         for (int d = 0; d < 4; ++d)
 #pragma unroll
             for (int o = 0; o < O; ++o) acc[o] = fmaf(kk[d], in[o + d], acc[o]);
+        r += 4 * kBandStride;
+        r = r >= rend ? r - A * kBandStride : r;
     }
 }
 
@@ -1989,14 +1994,24 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     // the lane's cell in its first azimuth plane (plane o: + o pb)
     const uint32_t off0 = 4u * (uint32_t)(a0 * P) + 4u * (uint32_t)cell;
     uint32_t yoff[O];    // its y-upwind cell (kOOB below the grid; masked at ghosts anyway)
-    uint32_t dirs = 0;   // 4 bits per azimuth: the direction is the same on every level
+    // per output azimuth (the direction is the same on every level): the x-upwind value
+    // is the left neighbour (tl), the right one (tr) or a ghost (neither); gy: the
+    // y-upwind value is a ghost; ox / oy: the cell's x / y face is an outflow face
+    bool tl[O], tr[O], gy[O], ox[O], oy[O];
 #pragma unroll
     for (int o = 0; o < O; ++o) {
         const int d = qtab[a0 + o].dir;
-        dirs |= (uint32_t)d << (4 * o);
         const int yc = (d & 4) ? cell - nx : cell + nx;
         yoff[o] = (yc >= 0) ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
+        const bool gx = (d & e & 3) != 0;
+        tl[o] = !gx && (d & 1);
+        tr[o] = !gx && !(d & 1);
+        gy[o] = (d & e & 12) != 0;
+        const int go = (((d & 5) << 1) | ((d & 10) >> 1)) & e;   // outflow faces of d
+        ox[o] = in && (go & 3);
+        oy[o] = in && (go & 12);
     }
+
     auto level_in = [&](int l) {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.psi) + (size_t)l * A * P, 0,
                                                  (int)lvl_bytes, kRsrcWord3);
@@ -2091,7 +2106,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     fetch(min(R + 1, L - 1), pre);
     Ahead ahA, ahB;
     uint4 dA = ldesc[0], dB = ldesc[1];   // level 0's descriptor
-    uint4 eA, eB;                         // level 1's
+    uint4 eA = dA, eB = dB;               // level 1's (set in the loop)
     fetch_ahead(0, ahA);
     lds_barrier();
 
@@ -2142,30 +2157,45 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
                 band_wide<A>(acc, slot, a0, whole ? 1 - A / 2 : -s, whole ? A : 2 * s + 1, cfp);
             }
         }
-        // stream + collide of the lane's outputs
+        // stream + collide of the lane's outputs:
+        //   psi' = psi + [cx (ux - psi) + cy (uy - psi) - aa psi + gs (Y - psi) + bs (iso - psi) + ss]
+        // (aa = dt sigma_a, bs = dt sigma_s, gs = dt sigma_as, ss = dt q), the bracket
+        // in one chain of FMAs; no coefficient of psi is folded into a per-cell constant,
+        // whose rounding would bias every ordinate of the cell alike.  Phi takes each new
+        // value in FP64; the collision term's sum over the outputs, gs sum (Y - psi) +
+        // bs sum (iso - psi), is formed in FP32 (small terms) and added once per level.
         const float* own = ring + si * SLOT + (a0 + kBandLead) * kBandStride + c + 1;
         const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
             a.psi_new + (size_t)i * A * P, 0, (int)lvl_bytes, kRsrcWord3);
+        float sd = 0.f, si_ = 0.f;
 #pragma unroll
         for (int o = 0; o < O; ++o) {
-            const int dd = (int)((dirs >> (4 * o)) & 15u);
             const float* pc = own + o * kBandStride;
             const float v = pc[0];
-            const float ux = (dd & e & 3) ? 0.f : ((dd & 1) ? pc[-1] : pc[1]);
-            const float uy = (dd & e & 12) ? 0.f : ah.y[o];
-            const float col = cf.z * (acc[o] - v) + cf.y * (isov - v);
-            const float r = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
-            const float nv = in ? r : 0.f;   // padding cells stay zero
+            const float ux = tl[o] ? pc[-1] : (tr[o] ? pc[1] : 0.f);
+            const float uy = gy[o] ? 0.f : ah.y[o];
+            const float dy = acc[o] - v, di = isov - v;
+            float t = fmaf(cf.y, di, cf.w);
+            t = fmaf(cf.z, dy, t);
+            t = fmaf(-cf.x, v, t);
+            t = fmaf(ah.cy[o], uy - v, t);
+            t = fmaf(ah.cx[o], ux - v, t);
+            const float nv = in ? v + t : 0.f;   // padding cells stay zero
             store_plane(nv, ro, off0 + (uint32_t)o * pb);
             phacc += ah.w * (double)nv;
-            defect += ah.w * (double)(in ? col : 0.f);
-            if (wedge) {
-                const int dout = ((dd & 5) << 1) | ((dd & 10) >> 1);   // outflow faces of dd
-                const int go = dout & e;
-                const float ob = in ? ((go & 3) ? ah.cx[o] * v : 0.f) + ((go & 12) ? ah.cy[o] * v : 0.f)
-                                    : 0.f;
-                outflow += ah.w * (double)ob;
+            sd += dy;
+            si_ += di;
+        }
+        const float col = fmaf(cf.z, sd, cf.y * si_);
+        defect += ah.w * (double)(in ? col : 0.f);
+        if (wedge) {
+            float ob = 0.f;
+#pragma unroll
+            for (int o = 0; o < O; ++o) {
+                const float v = own[o * kBandStride];
+                ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
             }
+            outflow += ah.w * (double)ob;
         }
         fetch_ahead(min(i + 1, L - 1), ah_next);
         lds_barrier();

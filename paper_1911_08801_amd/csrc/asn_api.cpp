@@ -138,7 +138,9 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
         L.ktab_len = mt + 1 + 2 * mt * (L.Qp / bk);   // offsets, k-steps, sub-block masks
         L.off_ktab = take((size_t)L.ktab_len * 4);
     }
-    L.off_band = take(L.banded ? (size_t)band_levels * 32 : 0);     // level descriptors, 8 words
+    // level descriptors, 8 words, and 8 zero words after them (the kernel may read one
+    // descriptor word past the last level's)
+    L.off_band = take(L.banded ? (size_t)(band_levels + 1) * 32 : 0);
     L.off_brange = take(L.banded ? (size_t)band_levels * 8 : 0);    // coefficient ranges, int2
     L.off_bcoef = take(L.banded ? band_coef_capacity(band_levels, band_azim) * 4 : 0);
     L.off_qi = take((size_t)Q * sizeof(QInfo));
@@ -710,6 +712,15 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         coef[c].w = source ? (float)(p->dt * (double)source[c]) : 0.f;
     }
 
+    // the banded kernel's descriptors: counts as built, pair codes in its decoded form
+    std::vector<uint32_t> ddesc;
+    if (banded) {
+        ddesc = bf.desc;
+        for (int i = 0; i < bf.levels; ++i)
+            for (int t = 0; t < (int)bf.desc[(size_t)i * 8]; ++t)
+                ddesc[(size_t)i * 8 + 1 + t] =
+                    asn::band_device_code(bf.desc[(size_t)i * 8 + 1 + t], i, bf.reach, bf.azim);
+    }
     auto bail = [&](asn_status st) {
         if (p->owns) (void)hipFree(p->base);
         delete p;
@@ -725,7 +736,7 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                        p->stream) != hipSuccess ||
         hipMemcpyAsync(b + L.off_ktab, ktab.data(), ktab.size() * 4, hipMemcpyHostToDevice,
                        p->stream) != hipSuccess ||
-        (banded && (hipMemcpyAsync(b + L.off_band, bf.desc.data(), bf.desc.size() * 4,
+        (banded && (hipMemcpyAsync(b + L.off_band, ddesc.data(), ddesc.size() * 4,
                                    hipMemcpyHostToDevice, p->stream) != hipSuccess ||
                     hipMemcpyAsync(b + L.off_brange, bf.range.data(), bf.range.size() * 4,
                                    hipMemcpyHostToDevice, p->stream) != hipSuccess ||

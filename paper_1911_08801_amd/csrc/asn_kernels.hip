@@ -2012,9 +2012,10 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         oy[o] = in && (go & 12);
     }
 
+    const size_t lvl_floats = (size_t)A * (size_t)P;
     auto level_in = [&](int l) {
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.psi) + (size_t)l * A * P, 0,
-                                                 (int)lvl_bytes, kRsrcWord3);
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.psi) + (uint32_t)l * lvl_floats,
+                                                 0, (int)lvl_bytes, kRsrcWord3);
     };
 
     // Ring fill: the lane's kBandO azimuths of level l, cell c.  Lanes 0 and 31 also
@@ -2027,9 +2028,12 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         float v[O], lo[O];   // the cell, and the block's halo cell (lanes 0 and 31)
     };
     const int hcol = c == 0 ? 0 : (c == 31 ? 33 : 34);
-    // halo offset of the lane relative to its cell's (kOOB: reads 0)
+    // the halo cell's offset in plane o (kOOB: reads 0)
     const bool hvalid = (c == 0 && c0 > 0) || c == 31;
     const uint32_t hdel = c == 0 ? (uint32_t)-4 : 4u;
+    uint32_t hoff[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) hoff[o] = hvalid ? off0 + (uint32_t)o * pb + hdel : kOOB;
     // the lane's rows for azimuth a0 + o: own (rrow0 + o kBandStride), wrapped copies
     // after the last and before the first azimuth (at most one unless A < lead + trail)
     constexpr bool kTwoCopies = A < kBandLead + kBandTrail;
@@ -2038,9 +2042,8 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         const __amdgpu_buffer_rsrc_t r = level_in(l);
 #pragma unroll
         for (int o = 0; o < O; ++o) {
-            const uint32_t of = off0 + (uint32_t)o * pb;
-            f.v[o] = load_plane(r, of);
-            f.lo[o] = load_plane(r, hvalid ? of + hdel : kOOB);
+            f.v[o] = load_plane(r, off0 + (uint32_t)o * pb);
+            f.lo[o] = load_plane(r, hoff[o]);
         }
     };
     auto put = [&](int slot, const Fill& f) {
@@ -2132,16 +2135,21 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 #pragma unroll
         for (int o = 0; o < O; ++o) acc[o] = 0.f;
         const int n_pairs = (int)d0.x;
+        // pair codes in the kernel's form (band_device_code), scalar loads one pair ahead
+        // (the word after the last pair's lies in the table: it is padded by one level)
+        const ASN_K uint32_t* pw = reinterpret_cast<const ASN_K uint32_t*>(ldesc) + 8 * i + 1;
+        uint32_t code_next = pw[0];
         for (int p = 0; p < n_pairs; ++p) {
-            const uint32_t code = p == 0 ? d0.y : (p == 1 ? d0.z : (p == 2 ? d0.w :
-                                  (p == 3 ? d1.x : (p == 4 ? d1.y : (p == 5 ? d1.z : d1.w)))));
-            const int s = (int)(code & 63u);
-            const int k = (int)((code >> 8) & 7u);
-            const float* slot = ring + wrap_slot(si + k - R) * SLOT + c + 1;
-            const float* cfp = cbuf + 4 * (int)(code >> 11);
-            if (!(code & 64u)) {
+            const uint32_t code = code_next;
+            code_next = pw[p + 1];
+            const uint32_t w = code >> 24;
+            const float* slot =
+                reinterpret_cast<const float*>(reinterpret_cast<const char*>(ring) + (code & 0x1FFFFu)) +
+                c + 1;
+            const float* cfp = cbuf + 4 * ((code >> 17) & 127u);
+            if (w <= (uint32_t)kBandNarrow) {
                 const float* row = slot + (a0 + kBandLead) * kBandStride;
-                switch (s) {
+                switch (w) {
                     case 0: band_narrow<0>(acc, row, cfp); break;
                     case 1: band_narrow<1>(acc, row, cfp); break;
                     case 2: band_narrow<2>(acc, row, cfp); break;
@@ -2153,7 +2161,8 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
                     default: band_narrow<8>(acc, row, cfp); break;
                 }
             } else {
-                const bool whole = (code & 128u) != 0;
+                const bool whole = w == kBandRingTag;
+                const int s = (int)w - (int)kBandWideTag;
                 band_wide<A>(acc, slot, a0, whole ? 1 - A / 2 : -s, whole ? A : 2 * s + 1, cfp);
             }
         }

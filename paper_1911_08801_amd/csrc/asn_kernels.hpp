@@ -81,6 +81,24 @@ constexpr int kBandStride = 40;
 constexpr int kBandMaxReach = 3;
 // Azimuth counts with a kernel instance.
 inline bool band_azimuths_supported(int az) { return az >= 8 && az <= 64 && az % 8 == 0; }
+// Floats of one ring slot of the banded kernel.
+inline int band_slot_floats(int az) { return (kBandLead + az + kBandTrail) * kBandStride; }
+// The kernel's form of a pair code of band_form (asn_host.hpp), decoded on the host so the
+// kernel spends few scalar instructions per pair:
+//   bits 0-16   byte offset of the partner level's ring slot (level j sits in slot j mod
+//               (2 reach + 2); at most 8 slots of (16 + 64) x 40 floats: < 2^17)
+//   bits 17-23  start of the pair's run in the level's staged coefficients, in units of 4
+//   bits 24-31  narrow run: its half-width s (<= kBandNarrow); wider run: kBandWideTag + s;
+//               whole ring: kBandRingTag
+constexpr uint32_t kBandWideTag = 32, kBandRingTag = 128;
+inline uint32_t band_device_code(uint32_t code, int level, int reach, int az) {
+    const int s = (int)(code & 63u), k = (int)((code >> 8) & 7u);
+    const int j = level + k - reach;
+    const uint32_t slot = (uint32_t)(j % (2 * reach + 2)) * (uint32_t)band_slot_floats(az) * 4u;
+    const uint32_t w = (code & 128u) ? kBandRingTag : ((code & 64u) ? kBandWideTag + (uint32_t)s
+                                                                     : (uint32_t)s);
+    return slot | ((code >> 11) & 127u) << 17 | w << 24;
+}
 // Dynamic LDS of a banded block: the ring, then two level-coefficient buffers of cmax
 // floats (cmax a multiple of 4).
 inline size_t band_lds_bytes(int az, int reach, int cmax) {

@@ -2013,9 +2013,9 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     }
 
     const size_t lvl_floats = (size_t)A * (size_t)P;
-    auto level_in = [&](int l) {
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.psi) + (uint32_t)l * lvl_floats,
-                                                 0, (int)lvl_bytes, kRsrcWord3);
+    auto level_rsrc = [&](const float* base) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)lvl_bytes,
+                                                 kRsrcWord3);
     };
 
     // Ring fill: the lane's kBandO azimuths of level l, cell c.  Lanes 0 and 31 also
@@ -2038,8 +2038,8 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     // after the last and before the first azimuth (at most one unless A < lead + trail)
     constexpr bool kTwoCopies = A < kBandLead + kBandTrail;
     const int rrow0 = (a0 + kBandLead) * kBandStride;
-    auto fetch = [&](int l, Fill& f) {
-        const __amdgpu_buffer_rsrc_t r = level_in(l);
+    auto fetch = [&](const float* base, Fill& f) {
+        const __amdgpu_buffer_rsrc_t r = level_rsrc(base);
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             f.v[o] = load_plane(r, off0 + (uint32_t)o * pb);
@@ -2081,22 +2081,22 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         float y[O], cx[O], cy[O];
         double w;
     };
-    auto fetch_ahead = [&](int l, Ahead& ah) {
-        const __amdgpu_buffer_rsrc_t r = level_in(l);
+    // base: the level's planes; q0: its first ordinate
+    auto fetch_ahead = [&](const float* base, int q0, Ahead& ah) {
+        const __amdgpu_buffer_rsrc_t r = level_rsrc(base);
 #pragma unroll
         for (int o = 0; o < O; ++o) {
-            const int q = l * A + a0 + o;
             ah.y[o] = load_plane(r, yoff[o]);
-            ah.cx[o] = qtab[q].cx;
-            ah.cy[o] = qtab[q].cy;
+            ah.cx[o] = qtab[q0 + a0 + o].cx;
+            ah.cy[o] = qtab[q0 + a0 + o].cy;
         }
-        ah.w = qk[l * A].w;
+        ah.w = qk[q0].w;
     };
 
     {   // prologue: levels 0 .. reach into the ring, level 0's coefficients staged
         Fill f;
         for (int l = 0; l <= R && l < L; ++l) {
-            fetch(l, f);
+            fetch(a.psi + (uint32_t)l * lvl_floats, f);
             put(l, f);   // slot l
         }
         put_coef(0, fetch_coef(0));
@@ -2106,27 +2106,39 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     // near the end), so no loop-carried copy of a load in flight forces a wait.
     float cpre = fetch_coef(min(1, L - 1));
     Fill pre;
-    fetch(min(R + 1, L - 1), pre);
+    // level cursors (uniform), advanced once per level and held at the last level:
+    // pf the planes of the level fetched next, pa / qa those and the first ordinate of
+    // the level whose constants are loaded next, po the output planes of level i
+    const float* pf = a.psi + (uint32_t)min(R + 1, L - 1) * lvl_floats;
+    fetch(pf, pre);
+    pf += (R + 2 <= L - 1) ? lvl_floats : 0;
+    const float* pa = a.psi;
+    int qa = 0;
+    float* po = a.psi_new;
     Ahead ahA, ahB;
     uint4 dA = ldesc[0], dB = ldesc[1];   // level 0's descriptor
     uint4 eA = dA, eB = dB;               // level 1's (set in the loop)
-    fetch_ahead(0, ahA);
+    fetch_ahead(pa, qa, ahA);
+    const bool more_levels = L > 1;
+    pa += more_levels ? lvl_floats : 0;
+    qa += more_levels ? A : 0;
     lds_barrier();
 
     double phacc = 0.0, defect = 0.0, outflow = 0.0;
-    auto wrap_slot = [NS](int s) { return s < 0 ? s + NS : (s >= NS ? s - NS : s); };
-    // level i in ring slot si: `pre` holds level i + reach + 1 and is refilled with
-    // level i + reach + 2, `cpre` holds level i + 1's coefficients and is refilled with
-    // level i + 2's; `d0`, `d1` / `ah` hold level i's descriptor / constants and
-    // y-upwind values, `n0`, `n1` / `ah_next` receive level i + 1's
-    auto level = [&](int i, int si, const uint4& d0, const uint4& d1, uint4& n0, uint4& n1,
-                     const Ahead& ah, Ahead& ah_next) {
+    // level i in ring slot si, level i + reach + 1 goes into slot sp: `pre` holds level
+    // i + reach + 1 and is refilled with level i + reach + 2, `cpre` holds level i + 1's
+    // coefficients and is refilled with level i + 2's; `d0`, `d1` / `ah` hold level i's
+    // descriptor / constants and y-upwind values, `n0`, `n1` / `ah_next` receive level
+    // i + 1's
+    auto level = [&](int i, int si, int sp, const uint4& d0, const uint4& d1, uint4& n0,
+                     uint4& n1, const Ahead& ah, Ahead& ah_next) {
         // into the slot level i - reach - 1 held and the buffer level i - 1's coefficients
         // held (their last readers passed the barrier)
-        if (i + R + 1 < L) put(wrap_slot(si + R + 1), pre);
+        if (i + R + 1 < L) put(sp, pre);
         put_coef(i + 1, cpre);
         cpre = fetch_coef(min(i + 2, L - 1));
-        fetch(min(i + R + 2, L - 1), pre);
+        fetch(pf, pre);
+        pf += (i + R + 3 <= L - 1) ? lvl_floats : 0;
         n0 = ldesc[2 * min(i + 1, L - 1)];
         n1 = ldesc[2 * min(i + 1, L - 1) + 1];
         // contraction, one pair of levels at a time
@@ -2174,8 +2186,8 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         // value in FP64; the collision term's sum over the outputs, gs sum (Y - psi) +
         // bs sum (iso - psi), is formed in FP32 (small terms) and added once per level.
         const float* own = ring + si * SLOT + (a0 + kBandLead) * kBandStride + c + 1;
-        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
-            a.psi_new + (size_t)i * A * P, 0, (int)lvl_bytes, kRsrcWord3);
+        const __amdgpu_buffer_rsrc_t ro = level_rsrc(po);
+        po += lvl_floats;
         float sd = 0.f, si_ = 0.f;
 #pragma unroll
         for (int o = 0; o < O; ++o) {
@@ -2206,16 +2218,22 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
             }
             outflow += ah.w * (double)ob;
         }
-        fetch_ahead(min(i + 1, L - 1), ah_next);
+        fetch_ahead(pa, qa, ah_next);
+        const bool adv = i + 2 <= L - 1;
+        pa += adv ? lvl_floats : 0;
+        qa += adv ? A : 0;
         lds_barrier();
     };
-    int si = 0;   // ring slot of level i
+    int si = 0, sp = R + 1;   // ring slots of levels i and i + reach + 1
+    auto next_slot = [NS](int s) { return s + 1 == NS ? 0 : s + 1; };
     for (int i = 0; i < L; i += 2) {
-        level(i, si, dA, dB, eA, eB, ahA, ahB);
-        si = wrap_slot(si + 1);
+        level(i, si, sp, dA, dB, eA, eB, ahA, ahB);
+        si = next_slot(si);
+        sp = next_slot(sp);
         if (i + 1 >= L) break;
-        level(i + 1, si, eA, eB, dA, dB, ahB, ahA);
-        si = wrap_slot(si + 1);
+        level(i + 1, si, sp, eA, eB, dA, dB, ahB, ahA);
+        si = next_slot(si);
+        sp = next_slot(sp);
     }
 
     // Phi^{n+1} of each cell: the 2 NW lane groups' partials in a fixed order

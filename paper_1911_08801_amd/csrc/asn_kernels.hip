@@ -2188,12 +2188,29 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         const float* own = ring + si * SLOT + (a0 + kBandLead) * kBandStride + c + 1;
         const __amdgpu_buffer_rsrc_t ro = level_rsrc(po);
         po += lvl_floats;
+        // The cells and both x neighbours of every output read first (one LDS round
+        // trip), or each output's as it is updated (the upwind one only): the first is
+        // faster where a SIMD holds three waves of this kernel (n_az 32, 48), the second
+        // at four (n_az 64; measured)
+        constexpr bool kEarly = NW < 8;
+        float vl[O], vv[O], vr[O];
+        if constexpr (kEarly) {
+#pragma unroll
+            for (int o = 0; o < O; ++o) {
+                const float* pc = own + o * kBandStride;
+                vl[o] = pc[-1];
+                vv[o] = pc[0];
+                vr[o] = pc[1];
+            }
+        }
         float sd = 0.f, si_ = 0.f;
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             const float* pc = own + o * kBandStride;
-            const float v = pc[0];
-            const float ux = tl[o] ? pc[-1] : (tr[o] ? pc[1] : 0.f);
+            if constexpr (!kEarly) vv[o] = pc[0];
+            const float v = vv[o];
+            const float ux = kEarly ? (tl[o] ? vl[o] : (tr[o] ? vr[o] : 0.f))
+                                    : (tl[o] ? pc[-1] : (tr[o] ? pc[1] : 0.f));
             const float uy = gy[o] ? 0.f : ah.y[o];
             const float dy = acc[o] - v, di = isov - v;
             float t = fmaf(cf.y, di, cf.w);
@@ -2212,10 +2229,8 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         if (wedge) {
             float ob = 0.f;
 #pragma unroll
-            for (int o = 0; o < O; ++o) {
-                const float v = own[o * kBandStride];
-                ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
-            }
+            for (int o = 0; o < O; ++o)
+                ob += (ox[o] ? ah.cx[o] * vv[o] : 0.f) + (oy[o] ? ah.cy[o] * vv[o] : 0.f);
             outflow += ah.w * (double)ob;
         }
         fetch_ahead(pa, qa, ah_next);

@@ -18,7 +18,8 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 from paper_1911_08801_amd import asn  # noqa: E402
 
-GRIDS = [(1, 1), (1, 7), (9, 1), (31, 1), (33, 2), (37, 9), (64, 16), (65, 17), (130, 67), (200, 3)]
+GRIDS = [(1, 1), (1, 7), (9, 1), (31, 1), (33, 2), (37, 9), (64, 16), (65, 17), (130, 67), (200, 3),
+         (256, 16)]   # the last one: rows of whole 32-cell blocks
 # (n_polar, n_azim, beta): every azimuth count 8 .. 64; wide beta gives whole-ring bands
 QUADS = [(1, 8, 4.5), (2, 8, 4.5), (4, 8, 4.5), (8, 16, 4.5), (3, 24, 4.5), (12, 24, 4.5),
          (16, 32, 4.5), (5, 40, 6.0), (24, 48, 4.5), (7, 56, 4.5), (6, 64, 3.0), (8, 16, 9.0)]

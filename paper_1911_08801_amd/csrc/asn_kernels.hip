@@ -1875,17 +1875,18 @@ __global__ void broadcast_kernel(float* psi, const float* cell, int Q, int64_t C
 //    block's cells (and the cell before and after them); while output level i is
 //    computed, level i + reach + 1 is written into the slot level i - reach - 1 left
 //    and level i + reach + 2 is loaded into registers, so one LDS barrier per level
-//    suffices and each cell-ordinate of psi^n is read from memory once.  Level i's
-//    coefficients sit in one of two LDS buffers (written a level ahead); its
-//    descriptor is a scalar load made a level ahead.  A lane's outputs of a level are
-//    kBandO consecutive azimuths of one cell.  Narrow pairs (coupling azimuths at
-//    most kBandNarrow apart) are unrolled per width with their LDS rows at
-//    compile-time offsets (the slot carries wrapped copies of the rows at either end);
-//    wide pairs go in steps of four offsets from the wrapped start row.  The epilogue is the stream + collide update of
-//    stream_collide_flat_kernel (same arithmetic); the x-upwind value comes from the
-//    slot, the y-upwind value from memory (loaded a level ahead).  The block writes
-//    each cell's complete Phi^{n+1} (one partial, G = 1) and its defect and outflow
-//    partials, in a fixed order.
+//    suffices and each cell-ordinate of psi^n is read from memory once by its own
+//    block (the y-upwind values are read again by the block below or above).  Level
+//    i's coefficients sit in one of two LDS buffers (written a level ahead); its pair
+//    codes, decoded on the host (band_device_code), are scalar loads made one pair
+//    ahead.  A lane's outputs of a level are kBandO consecutive azimuths of one cell.
+//    Narrow pairs (coupling azimuths at most kBandNarrow apart) are unrolled per width
+//    with their LDS rows at compile-time offsets (the slot carries wrapped copies of
+//    the rows at either end); wide pairs go in steps of four offsets from the wrapped
+//    start row.  The epilogue is the donor-cell stream + collide update as one FMA
+//    chain; the x-upwind value comes from the slot, the y-upwind value from memory
+//    (loaded a level ahead).  The block writes each cell's complete Phi^{n+1} (one
+//    partial, G = 1) and its defect and outflow partials, in a fixed order.
 // ---------------------------------------------------------------------------
 // The band tables are written by the host before any step and only read by the
 // kernels: reached through the constant address space, their uniform loads are scalar

@@ -1994,20 +1994,20 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     const uint32_t pb = (uint32_t)(P * 4);   // bytes of an azimuth plane
     // the lane's cell in its first azimuth plane (plane o: + o pb)
     const uint32_t off0 = 4u * (uint32_t)(a0 * P) + 4u * (uint32_t)cell;
-    uint32_t yoff[O];    // its y-upwind cell (kOOB below the grid; masked at ghosts anyway)
+    // its y-upwind cell; kOOB (reads 0, the vacuum ghost) where that lies outside the grid
+    uint32_t yoff[O];
     // per output azimuth (the direction is the same on every level): the x-upwind value
-    // is the left neighbour (tl), the right one (tr) or a ghost (neither); gy: the
-    // y-upwind value is a ghost; ox / oy: the cell's x / y face is an outflow face
-    bool tl[O], tr[O], gy[O], ox[O], oy[O];
+    // is the left neighbour (tl), the right one (tr) or a ghost (neither); ox / oy: the
+    // cell's x / y face is an outflow face
+    bool tl[O], tr[O], ox[O], oy[O];
 #pragma unroll
     for (int o = 0; o < O; ++o) {
         const int d = qtab[a0 + o].dir;
         const int yc = (d & 4) ? cell - nx : cell + nx;
-        yoff[o] = (yc >= 0) ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
+        yoff[o] = (yc >= 0 && yc < C) ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
         const bool gx = (d & e & 3) != 0;
         tl[o] = !gx && (d & 1);
         tr[o] = !gx && !(d & 1);
-        gy[o] = (d & e & 12) != 0;
         const int go = (((d & 5) << 1) | ((d & 10) >> 1)) & e;   // outflow faces of d
         ox[o] = in && (go & 3);
         oy[o] = in && (go & 12);
@@ -2212,7 +2212,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
             const float v = vv[o];
             const float ux = kEarly ? (tl[o] ? vl[o] : (tr[o] ? vr[o] : 0.f))
                                     : (tl[o] ? pc[-1] : (tr[o] ? pc[1] : 0.f));
-            const float uy = gy[o] ? 0.f : ah.y[o];
+            const float uy = ah.y[o];
             const float dy = acc[o] - v, di = isov - v;
             float t = fmaf(cf.y, di, cf.w);
             t = fmaf(cf.z, dy, t);

@@ -235,7 +235,32 @@ def roofline(res, spec, dtype):
             "ridge_flop_per_byte": compute_peak * 1e12 / (PEAK_HBM_GBS * 1e9),
             "executed_over_nonzero": executed / nz,
             "dense_equivalent_TFLOPs": res["work"]["dense_flops"] / t / 1e12,
-            "traffic_over_algorithmic": None if traffic is None else traffic / bytes_}
+            "traffic_over_algorithmic": None if traffic is None else traffic / bytes_,
+            "kernels": per_kernel_rooflines(res, spec, dtype)}
+
+
+def per_kernel_rooflines(res, spec, dtype):
+    """Each kernel of the step against its own roof: a separate stencil against HBM on
+    its algorithmic bytes (psi^n and Y read, psi^{n+1} written: 12 B per update in FP32),
+    a contraction against its MFMA peak on the products it executes (the multiplied
+    blocks) and on the nonzeros of K."""
+    kms = res["kms"]
+    cq = spec.cells * spec.q
+    out = {}
+    if res["form"] == "separate" and kms.get("stream_collide", 0) > 0:
+        t = kms["stream_collide"] * 1e-3
+        out["stream_collide"] = {"bound": "hbm", "algorithmic_bytes": 12.0 * cq,
+                                 "achieved_GBs": 12.0 * cq / t / 1e9,
+                                 "frac": 12.0 * cq / t / 1e9 / PEAK_HBM_GBS}
+    if res["form"] in ("separate", "fused") and kms.get("contraction", 0) > 0:
+        t = kms["contraction"] * 1e-3
+        peak = PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS
+        ex = res["work"]["tile_flops"] / t / 1e12
+        nz = res["work"]["nonzero_flops"] / t / 1e12
+        out["contraction"] = {"bound": "mfma", "peak_TFLOPs": peak,
+                              "executed_TFLOPs": ex, "executed_frac": ex / peak,
+                              "nonzero_TFLOPs": nz, "nonzero_frac": nz / peak}
+    return out
 
 
 def summary(res, spec, dtype="f32"):

@@ -43,6 +43,11 @@ def test_separate_form_takes_the_slower_of_its_two_kernels():
     spec = types.SimpleNamespace(cells=400 * 400, q=512, nx=400, ny=400, n_azim=32)
     res = _res("separate", {"contraction": 0.24, "stream_collide": 0.19}, 1.0, 2.0, 4.0)
     assert bench.roofline(res, spec, "f32")["kernel"] == "gemm_f32_kernel<false>"
+    k = bench.roofline(res, spec, "f32")["kernels"]
+    cq = spec.cells * spec.q
+    assert k["stream_collide"]["frac"] == pytest.approx(12 * cq / 0.19e-3 / 8e12)
+    assert k["contraction"]["executed_frac"] == pytest.approx(2.0 / 0.24e-3 / 157.3e12)
+    assert k["contraction"]["nonzero_frac"] == pytest.approx(1.0 / 0.24e-3 / 157.3e12)
     res["kms"] = {"contraction": 0.10, "stream_collide": 0.19}
     assert bench.roofline(res, spec, "f32")["kernel"] == "stream_collide_flat_kernel<false>"
     assert bench.roofline(_res("fused", {"contraction": 0.4}, 1.0, 1.0, 1.0), spec,

@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--sigma-as", type=float, default=5.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-lowp", action="store_true", help="skip the BF16 / FP16 lines")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip the headline workload with separate FP32 kernels")
     ap.add_argument("--cpu-rows", type=int, default=64,
                     help="rows of the headline grid (through the pulse) the oracle steps")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -459,6 +461,13 @@ def main():
             r = measure(asn, spec, dt, args.steps, args.warmup, args.reps)
             out[dt] = summary(r, spec, dt)
             out[dt]["roofline"] = roofline(r, spec, dt)
+    if not args.no_separate:
+        # the same workload with the FP32 contraction and the stencil as separate kernels:
+        # the stencil against HBM and the contraction against MFMA at this size
+        log("headline workload, FP32 separate kernels")
+        r = measure(asn, spec, "f32", args.steps, args.warmup, args.reps, form="separate")
+        out["f32_separate"] = summary(r, spec)
+        out["f32_separate"]["roofline"] = roofline(r, spec, "f32")
     if not args.no_small:
         # the 400 x 400 x 512 line source: every FP32 kernel form, and each precision's
         # full run to t = 1 against the FP64 oracle's stored flux

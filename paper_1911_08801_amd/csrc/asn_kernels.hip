@@ -2004,8 +2004,9 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     for (int o = 0; o < O; ++o) {
         const int d = qtab[a0 + o].dir;
         const int yc = (d & 4) ? cell - nx : cell + nx;
-        yoff[o] = (yc >= 0 && yc < C) ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
-        const bool gx = (d & e & 3) != 0;
+        yoff[o] = (in && yc >= 0 && yc < C) ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell)
+                                             : kOOB;
+        const bool gx = !in || (d & e & 3) != 0;
         tl[o] = !gx && (d & 1);
         tr[o] = !gx && !(d & 1);
         const int go = (((d & 5) << 1) | ((d & 10) >> 1)) & e;   // outflow faces of d
@@ -2039,6 +2040,15 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     // after the last and before the first azimuth (at most one unless A < lead + trail)
     constexpr bool kTwoCopies = A < kBandLead + kBandTrail;
     const int rrow0 = (a0 + kBandLead) * kBandStride;
+    // byte distance from the row of azimuth a0 + o to its (first) wrapped copy
+    int cpy[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+        const int az = a0 + o;
+        const int up = az < kBandTrail ? A * kBandStride : 0;
+        const int dn = az >= A - kBandLead ? -A * kBandStride : 0;
+        cpy[o] = 4 * (kTwoCopies ? up : (up != 0 ? up : dn));
+    }
     auto fetch = [&](const float* base, Fill& f) {
         const __amdgpu_buffer_rsrc_t r = level_rsrc(base);
 #pragma unroll
@@ -2052,13 +2062,13 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             const int az = a0 + o, rr = rrow0 + o * kBandStride;
-            const int up = az < kBandTrail ? rr + A * kBandStride : rr;
             const int dn = az >= A - kBandLead ? rr - A * kBandStride : rr;
-            s[rr + c + 1] = f.v[o];
-            s[rr + hcol] = f.lo[o];
-            const int w1 = kTwoCopies ? up : (up != rr ? up : dn);
-            s[w1 + c + 1] = f.v[o];
-            s[w1 + hcol] = f.lo[o];
+            float* pv = s + rr + c + 1;
+            float* ph = s + rr + hcol;
+            *pv = f.v[o];
+            *ph = f.lo[o];
+            *reinterpret_cast<float*>(reinterpret_cast<char*>(pv) + cpy[o]) = f.v[o];
+            *reinterpret_cast<float*>(reinterpret_cast<char*>(ph) + cpy[o]) = f.lo[o];
             if constexpr (kTwoCopies) {
                 s[dn + c + 1] = f.v[o];
                 s[dn + hcol] = f.lo[o];
@@ -2204,7 +2214,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
                 vr[o] = pc[1];
             }
         }
-        float sd = 0.f, si_ = 0.f;
+        float sd = 0.f;
 #pragma unroll
         for (int o = 0; o < O; ++o) {
             const float* pc = own + o * kBandStride;
@@ -2213,20 +2223,20 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
             const float ux = kEarly ? (tl[o] ? vl[o] : (tr[o] ? vr[o] : 0.f))
                                     : (tl[o] ? pc[-1] : (tr[o] ? pc[1] : 0.f));
             const float uy = ah.y[o];
-            const float dy = acc[o] - v, di = isov - v;
-            float t = fmaf(cf.y, di, cf.w);
+            const float dy = acc[o] - v;
+            float t = fmaf(cf.y, isov - v, cf.w);
             t = fmaf(cf.z, dy, t);
             t = fmaf(-cf.x, v, t);
             t = fmaf(ah.cy[o], uy - v, t);
             t = fmaf(ah.cx[o], ux - v, t);
-            const float nv = in ? v + t : 0.f;   // padding cells stay zero
+            // a padding cell (not in) has psi = 0, zero coefficients and zero upwind
+            // values, so it stays zero
+            const float nv = v + t;
             store_plane(nv, ro, off0 + (uint32_t)o * pb);
             phacc += ah.w * (double)nv;
             sd += dy;
-            si_ += di;
         }
-        const float col = fmaf(cf.z, sd, cf.y * si_);
-        defect += ah.w * (double)(in ? col : 0.f);
+        defect += ah.w * (double)(in ? cf.z * sd : 0.f);
         if (wedge) {
             float ob = 0.f;
 #pragma unroll
@@ -2262,6 +2272,10 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         for (int g = 1; g < 2 * NW; ++g) s += red[g * kBandCells + c];
         gp(a.phi_part)[cell] = s;
     }
+    // the physical scattering's part of the collision defect, sum_q w_q bs (iso - psi_q)
+    // = bs (W iso - Phi), once per cell (Phi of psi^n in FP64)
+    if (wave == 0 && h == 0 && in)
+        defect += (double)cf.y * (a.W * (double)isov - gp(a.phi64)[cell]);
     double sums[2] = {defect, outflow};
     block_sum_waves<NW, 2>(sums, gp(a.blk_part) + 2 * (size_t)local);
 }

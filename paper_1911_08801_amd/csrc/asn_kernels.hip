@@ -1878,8 +1878,8 @@ __global__ void broadcast_kernel(float* psi, const float* cell, int Q, int64_t C
 //    suffices and each cell-ordinate of psi^n is read from memory once by its own
 //    block (the y-upwind values are read again by the block below or above).  Level
 //    i's coefficients sit in one of two LDS buffers (written a level ahead); its pair
-//    codes, decoded on the host (band_device_code), are scalar loads made one pair
-//    ahead.  A lane's outputs of a level are kBandO consecutive azimuths of one cell.
+//    codes, decoded on the host (band_device_code), come with its descriptor, a scalar
+//    load made a level ahead.  A lane's outputs of a level are kBandO consecutive azimuths of one cell.
 //    Narrow pairs (coupling azimuths at most kBandNarrow apart) are unrolled per width
 //    with their LDS rows at compile-time offsets (the slot carries wrapped copies of
 //    the rows at either end); wide pairs go in steps of four offsets from the wrapped
@@ -2150,21 +2150,24 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         cpre = fetch_coef(min(i + 2, L - 1));
         fetch(pf, pre);
         pf += (i + R + 3 <= L - 1) ? lvl_floats : 0;
-        n0 = ldesc[2 * min(i + 1, L - 1)];
-        n1 = ldesc[2 * min(i + 1, L - 1) + 1];
         // contraction, one pair of levels at a time
         const float* cbuf = stage + (i & 1) * CM;
         float acc[O];
 #pragma unroll
         for (int o = 0; o < O; ++o) acc[o] = 0.f;
         const int n_pairs = (int)d0.x;
-        // pair codes in the kernel's form (band_device_code), scalar loads one pair ahead
-        // (the word after the last pair's lies in the table: it is padded by one level)
-        const ASN_K uint32_t* pw = reinterpret_cast<const ASN_K uint32_t*>(ldesc) + 8 * i + 1;
-        uint32_t code_next = pw[0];
+        // pair codes in the kernel's form (band_device_code), loaded with the level's
+        // descriptor a level ahead and shifted through scalar registers (no scalar load
+        // in flight in the loop, so the waits for a pair's LDS rows can be partial)
+        uint32_t c0 = d0.y, c1 = d0.z, c2 = d0.w, c3 = d1.x, c4 = d1.y, c5 = d1.z, c6 = d1.w;
         for (int p = 0; p < n_pairs; ++p) {
-            const uint32_t code = code_next;
-            code_next = pw[p + 1];
+            const uint32_t code = c0;
+            c0 = c1;
+            c1 = c2;
+            c2 = c3;
+            c3 = c4;
+            c4 = c5;
+            c5 = c6;
             const uint32_t w = code >> 24;
             const float* slot =
                 reinterpret_cast<const float*>(reinterpret_cast<const char*>(ring) + (code & 0x1FFFFu)) +
@@ -2189,6 +2192,10 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
                 band_wide<A>(acc, slot, a0, whole ? 1 - A / 2 : -s, whole ? A : 2 * s + 1, cfp);
             }
         }
+        // level i + 1's descriptor, after the contraction: a scalar load in flight there
+        // would make every wait for LDS rows a full one
+        n0 = ldesc[2 * min(i + 1, L - 1)];
+        n1 = ldesc[2 * min(i + 1, L - 1) + 1];
         // stream + collide of the lane's outputs:
         //   psi' = psi + [cx (ux - psi) + cy (uy - psi) - aa psi + gs (Y - psi) + bs (iso - psi) + ss]
         // (aa = dt sigma_a, bs = dt sigma_s, gs = dt sigma_as, ss = dt q), the bracket

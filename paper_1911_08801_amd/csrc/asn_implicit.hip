@@ -165,6 +165,7 @@ constexpr int kSweepWinDoubles = 3 * 64 * kSweepWinPitch;        // inputs x 2, 
 __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a) {
     extern __shared__ double smem[];   // [2 parity][2 rows][nx], then [W][3][64][pitch]
     __shared__ double ring[kSweepWaves][2][kSweepRing];
+    __shared__ double spare[64];   // targets of the stores of lanes that keep nothing
     constexpr int D = kSweepAhead, DP = kSweepWinPitch;
     // the slot u = tau mod D is the same for every wave (kSweepLag is a multiple of D);
     // wave w - 1 writes ring column k + kSweepRing 23 block steps after wave w read k
@@ -243,22 +244,24 @@ __global__ __launch_bounds__(64 * kSweepWaves) void imp_sweep_kernel(SweepArgs a
                 yn2 = t62r[u];
             }
             y1prev = yn1;
-            // The history shifts every step once the lane has started, also past the
-            // end of its row: the lane two rows up reads this lane's previous value one
-            // step later than the lane just above.
-            if (k >= 0) {
-                double v = 0.0;
-                if (valid && k < nx)
-                    v = (er + ax * (2.0 * last1 - 0.5 * last2) + ay * (2.0 * yn1 - 0.5 * yn2)) /
-                        (dflux + es);
-                win_o[lane * DP + u] = v;
-                if (lane >= 62 && k < nx) {
-                    ring[w][lane - 62][k & (kSweepRing - 1)] = v;
-                    if (last_wave) cur_top[(size_t)(lane - 62) * nx + k] = v;
-                }
-                last2 = last1;
-                last1 = v;
-            }
+            // Branch-free: every lane computes (the window's inputs are staged for every
+            // lane, at clamped in-grid cells, so the division is well defined) and the
+            // results are selected.  A lane's slot of a step before its start is never
+            // stored to memory; rows 62 and 63 keep their results for the strip below,
+            // the other lanes write a spare slot.  The history shifts every step once the
+            // lane has started, also past the end of its row: the lane two rows up reads
+            // this lane's previous value one step later than the lane just above.
+            const bool started = k >= 0;
+            const bool live = valid && started && k < nx;
+            const double num = er + ax * (2.0 * last1 - 0.5 * last2) + ay * (2.0 * yn1 - 0.5 * yn2);
+            const double v = live ? num / (dflux + es) : 0.0;
+            win_o[lane * DP + u] = v;
+            const bool keep = lane >= 62 && started && k < nx;
+            const int kr = max(lane - 62, 0);
+            *(keep ? &ring[w][kr][k & (kSweepRing - 1)] : &spare[lane]) = v;
+            if (last_wave) *(keep ? &cur_top[(size_t)kr * nx + k] : &spare[lane]) = v;
+            last2 = started ? last1 : last2;
+            last1 = started ? v : last1;
         };
         // Block step t: wave w runs its step tau = t - 72 w (slot u = tau mod 8, fixed at
         // compile time in the unrolled loops since 72 w is a multiple of 8).  At a window

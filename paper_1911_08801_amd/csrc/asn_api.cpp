@@ -202,6 +202,7 @@ struct asn_problem_s {
     std::unique_ptr<asn::ImplicitSolver> imp;   // the implicit scheme's solver (else null)
     int band_levels = 0, band_azim = 0, band_reach = 0, band_cmax = 0;   // banded step (else 0)
     size_t band_lds() const { return asn::band_lds_bytes(band_azim, band_reach, band_cmax); }
+    bool band_wide_rows() const { return nx >= asn::kBandWideRowCells; }
 };
 
 struct asn_batch_s {
@@ -210,6 +211,7 @@ struct asn_batch_s {
     int launch_scheme = 0;   // scheme, or its flat-chunk stencil form
     int band_az = 0;         // banded batches: the azimuth count and LDS bytes per block
     size_t band_lds = 0;
+    bool band_wide = false;  // every problem's rows are wide (asn::kBandWideRowCells)
     hipStream_t stream = nullptr;
     std::vector<StepArgs> tab;
     std::vector<int> off;
@@ -883,7 +885,7 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
     for (int64_t i = 0; i < n_steps; ++i) {
         b.s_par = (int)(i & 1);
         HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, launch_scheme(p), p->stream, nullptr,
-                                 p->band_azim, lds));
+                                 p->band_azim, lds, p->band_wide_rows()));
     }
     p->cur ^= state_flip(p->scheme, n_steps);
     p->steps_done += n_steps;
@@ -926,7 +928,7 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
         bt.s_par = (int)(i & 1);
         const hipError_t e = asn::launch_step(
             bt, p->blocks, p->dtype, launch_scheme(p), p->stream, &ev[(size_t)i * per], p->band_azim,
-            p->L.banded ? p->band_lds() : 0);
+            p->L.banded ? p->band_lds() : 0, p->band_wide_rows());
         if (e != hipSuccess) {
             st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
             break;
@@ -1004,9 +1006,12 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
     b->scheme = probs[0]->scheme;
     b->launch_scheme = launch_scheme(probs[0]);
     b->band_az = probs[0]->band_azim;
-    for (int32_t i = 0; i < n; ++i)
+    b->band_wide = true;
+    for (int32_t i = 0; i < n; ++i) {
         if (probs[i]->L.banded)
             b->band_lds = std::max(b->band_lds, probs[i]->band_lds());
+        b->band_wide = b->band_wide && probs[i]->band_wide_rows();
+    }
     b->stream = probs[0]->stream;
     b->tab.resize(2 * (size_t)n);
     b->off.assign((size_t)asn::KT_COUNT * (n + 1), 0);
@@ -1071,7 +1076,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
             for (int64_t j = 0; j < n_steps && e == hipSuccess; ++j) {
                 args.s_par = (int)(j & 1);
                 e = asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream, nullptr,
-                                     b->band_az, b->band_lds);
+                                     b->band_az, b->band_lds, b->band_wide);
             }
             const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -1090,7 +1095,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
         for (int64_t j = 0; j < n_steps; ++j) {
             args.s_par = (int)(j & 1);
             HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream, nullptr,
-                                     b->band_az, b->band_lds));
+                                     b->band_az, b->band_lds, b->band_wide));
         }
     }
     for (int i = 0; i < b->n; ++i) {
@@ -1156,12 +1161,14 @@ asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps
     int grid[asn::KT_COUNT];
     for (int k = 0; k < asn::KT_COUNT; ++k) off[k * (n + 1)] = 0;
     size_t band_lds = 0;
+    bool band_wide = true;
     for (int32_t i = 0; i < n; ++i) {
         tab[2 * i] = probs[i]->tab[0];
         tab[2 * i + 1] = probs[i]->tab[1];
         for (int k = 0; k < asn::KT_COUNT; ++k)
             off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + probs[i]->blocks[k];
         if (probs[i]->L.banded) band_lds = std::max(band_lds, probs[i]->band_lds());
+        band_wide = band_wide && probs[i]->band_wide_rows();
     }
     for (int k = 0; k < asn::KT_COUNT; ++k) grid[k] = off[k * (n + 1) + n];
     if (n_steps == 0) return ASN_OK;
@@ -1190,7 +1197,7 @@ asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps
     for (int64_t j = 0; j < n_steps; ++j) {
         args.s_par = (int)(j & 1);
         HIP_TRY(asn::launch_step(args, grid, probs[0]->dtype, scheme, stream, nullptr,
-                                 probs[0]->band_azim, band_lds));
+                                 probs[0]->band_azim, band_lds, band_wide));
     }
     for (int i = 0; i < n; ++i) {
         probs[i]->cur ^= state_flip(probs[i]->scheme, n_steps);

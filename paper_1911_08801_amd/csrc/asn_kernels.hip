@@ -1965,7 +1965,7 @@ __device__ __forceinline__ void band_wide(float (&acc)[kBandO], const float* slo
     }
 }
 
-template <int A>
+template <int A, bool YNT>
 __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     constexpr int O = kBandO, NW = A / (2 * O), ROWS = kBandLead + A + kBandTrail;
     constexpr int SLOT = ROWS * kBandStride;
@@ -2104,11 +2104,19 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         double w;
     };
     // base: the level's planes; q0: its first ordinate
+    // The y-upwind row belongs to the block nx / kBandCells blocks away.  With YNT (rows
+    // of kBandWideRowCells or more) that block runs about half a block's time apart (an
+    // XCD holds 64 blocks) and its lines are no longer in the L2: they are read
+    // non-temporally, so they do not push out lines that are (1024^2 x 2048: -0.8 %, with
+    // the non-temporal stores -3.9 %; on narrower rows the L2 still serves them and the
+    // same reads cost 2 to 3 %; measured).
     auto fetch_ahead = [&](const float* base, int q0, Ahead& ah) {
         const __amdgpu_buffer_rsrc_t r = level_rsrc(base);
 #pragma unroll
+        for (int o = 0; o < O; ++o)
+            ah.y[o] = YNT ? load_plane_nt(r, yoff[o]) : load_plane(r, yoff[o]);
+#pragma unroll
         for (int o = 0; o < O; ++o) {
-            ah.y[o] = load_plane(r, yoff[o]);
             ah.cx[o] = qtab[q0 + a0 + o].cx;
             ah.cy[o] = qtab[q0 + a0 + o].cy;
         }
@@ -2250,7 +2258,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
             // a padding cell (not in) has psi = 0, zero coefficients and zero upwind
             // values, so it stays zero
             const float nv = v + t;
-            store_plane(nv, ro, off0 + (uint32_t)o * pb);
+            store_plane_nt(nv, ro, off0 + (uint32_t)o * pb);   // read next step, not from L2
             phacc += ah.w * (double)nv;
             sd += dy;
         }
@@ -2313,20 +2321,22 @@ void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
 }
 
 template <int A>
-static void launch_banded_az(const BatchArgs& b, int blocks, size_t lds, hipStream_t s) {
-    banded_euler_kernel<A><<<blocks, 8 * A, lds, s>>>(b);
+static void launch_banded_az(const BatchArgs& b, int blocks, size_t lds, hipStream_t s, bool wide) {
+    if (wide) banded_euler_kernel<A, true><<<blocks, 8 * A, lds, s>>>(b);
+    else banded_euler_kernel<A, false><<<blocks, 8 * A, lds, s>>>(b);
 }
 
-static hipError_t launch_banded(const BatchArgs& b, int blocks, int az, size_t lds, hipStream_t s) {
+static hipError_t launch_banded(const BatchArgs& b, int blocks, int az, size_t lds, hipStream_t s,
+                                bool wide) {
     switch (az) {
-        case 8: launch_banded_az<8>(b, blocks, lds, s); break;
-        case 16: launch_banded_az<16>(b, blocks, lds, s); break;
-        case 24: launch_banded_az<24>(b, blocks, lds, s); break;
-        case 32: launch_banded_az<32>(b, blocks, lds, s); break;
-        case 40: launch_banded_az<40>(b, blocks, lds, s); break;
-        case 48: launch_banded_az<48>(b, blocks, lds, s); break;
-        case 56: launch_banded_az<56>(b, blocks, lds, s); break;
-        case 64: launch_banded_az<64>(b, blocks, lds, s); break;
+        case 8: launch_banded_az<8>(b, blocks, lds, s, wide); break;
+        case 16: launch_banded_az<16>(b, blocks, lds, s, wide); break;
+        case 24: launch_banded_az<24>(b, blocks, lds, s, wide); break;
+        case 32: launch_banded_az<32>(b, blocks, lds, s, wide); break;
+        case 40: launch_banded_az<40>(b, blocks, lds, s, wide); break;
+        case 48: launch_banded_az<48>(b, blocks, lds, s, wide); break;
+        case 56: launch_banded_az<56>(b, blocks, lds, s, wide); break;
+        case 64: launch_banded_az<64>(b, blocks, lds, s, wide); break;
         default: return hipErrorInvalidValue;
     }
     return hipSuccess;
@@ -2334,7 +2344,10 @@ static hipError_t launch_banded(const BatchArgs& b, int blocks, int az, size_t l
 
 template <int A>
 static hipError_t prepare_banded_az(size_t lds) {
-    return hipFuncSetAttribute((const void*)banded_euler_kernel<A>,
+    const hipError_t e = hipFuncSetAttribute((const void*)banded_euler_kernel<A, false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)banded_euler_kernel<A, true>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -2360,14 +2373,14 @@ constexpr int kStencilBanded = 16;
 // One pass: contraction, stencil, finalize, budget.
 static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, int stencil,
                               int bud, hipStream_t s, hipEvent_t* ev, int band_az = 0,
-                              size_t band_lds = 0) {
+                              size_t band_lds = 0, bool band_wide_rows = false) {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
     if (stencil == kStencilBanded) {   // contraction and stencil in one kernel
         mark(0);
-        e = launch_banded(b, grid[KT_SC], band_az, band_lds, s);
+        e = launch_banded(b, grid[KT_SC], band_az, band_lds, s, band_wide_rows);
         mark(1);
         mark(2);
         if (e == hipSuccess) finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
@@ -2424,9 +2437,10 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
 }
 
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
-                       hipEvent_t* ev, int band_az, size_t band_lds) {
+                       hipEvent_t* ev, int band_az, size_t band_lds, bool band_wide_rows) {
     if (scheme == SCHEME_EULER_BANDED)
-        return launch_pass(b, grid, dtype, kStencilBanded, BUD_STEP, s, ev, band_az, band_lds);
+        return launch_pass(b, grid, dtype, kStencilBanded, BUD_STEP, s, ev, band_az, band_lds,
+                           band_wide_rows);
     if (scheme != SCHEME_HEUN && scheme != SCHEME_HEUN_FLAT)
         return launch_pass(b, grid, dtype, scheme == SCHEME_EULER_FLAT ? 3 : 0, BUD_STEP, s, ev);
     const int st = scheme == SCHEME_HEUN_FLAT ? 4 : 1;   // stencil of the first pass

@@ -219,9 +219,15 @@ inline bool can_fuse(int dtype, int scheme) { (void)dtype; return scheme == SCHE
 // If ev is given, ev[5 k .. 5 k + 4] are recorded before, between and after
 // the four kernels of pass k.
 // band_az / band_lds: the banded step's azimuth count and dynamic LDS bytes (every
-// problem of a banded batch has that azimuth count).
+// problem of a banded batch has that azimuth count); band_wide_rows: every problem's
+// rows hold at least band_wide_cells cells (selects the banded kernel's instance that
+// reads the y-upwind rows non-temporally).
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
-                       hipEvent_t* ev = nullptr, int band_az = 0, size_t band_lds = 0);
+                       hipEvent_t* ev = nullptr, int band_az = 0, size_t band_lds = 0,
+                       bool band_wide_rows = false);
+// Rows from this many cells on: the banded kernel's y-upwind row belongs to a block at
+// least 32 blocks away, which runs about half a block's time apart on its XCD.
+constexpr int kBandWideRowCells = 32 * kBandCells;
 // Raise the dynamic LDS limit of the banded kernel for an azimuth count (once per device).
 hipError_t prepare_banded(int band_az, size_t band_lds);
 // Passes per step of a scheme.

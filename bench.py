@@ -33,6 +33,7 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP32_VALU_TFLOPS = 78.6     # FMA on 16 lanes per SIMD, no packed FP32 (not used here)
 PEAK_LP_MFMA_TFLOPS = 2500.0     # dense BF16 / FP16 MFMA
 BYTES_PER_UPDATE = 8.0           # read psi^n and write psi^{n+1} once, FP32
+BAND_WIDE_ROW_CELLS = 1024       # rows from this width on take the banded kernel's wide-row instance
 
 
 def parse():
@@ -195,7 +196,8 @@ def measured_traffic(kernel, spec):
 def dominant_kernel(res, spec, dtype):
     form = res["form"]
     if form == "banded":
-        return f"banded_euler_kernel<{spec.n_azim}>", "contraction"
+        wide = "true" if spec.nx >= BAND_WIDE_ROW_CELLS else "false"
+        return f"banded_euler_kernel<{spec.n_azim}, {wide}>", "contraction"
     lp = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
     if form == "fused":
         name = "gemm_f32_kernel<true>" if lp == 0 else f"gemm_lp_kernel<{lp}, true>"

@@ -30,7 +30,7 @@ def test_roofline_is_eight_bytes_per_update_over_the_kernel_time():
     res = _res("banded", {"contraction": 7.2}, 1.546e11, 1.57e11, 2 * 2048.0 ** 2 * 1024 ** 2)
     r = bench.roofline(res, spec, "f32")
     cq = spec.cells * spec.q
-    assert r["kernel"] == "banded_euler_kernel<64>" and r["bound"] == "hbm"
+    assert r["kernel"] == "banded_euler_kernel<64, true>" and r["bound"] == "hbm"
     assert r["achieved"] == pytest.approx(8 * cq / 7.2e-3 / 1e9)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
     assert r["method_TFLOPs"] == pytest.approx(1.546e11 / 7.2e-3 / 1e12)
@@ -75,3 +75,11 @@ def test_traffic_record_is_void_once_the_kernel_code_changes(tmp_path, monkeypat
     monkeypatch.setattr(bench, "kernel_source_hash", lambda path=None: "other")
     assert bench.measured_traffic("k<1>", spec) is None
 
+
+
+def test_banded_kernel_instance_follows_the_row_width():
+    res = _res("banded", {"contraction": 0.3}, 1e9, 1e9, 1e12)
+    narrow = types.SimpleNamespace(cells=400 * 400, q=512, nx=400, ny=400, n_azim=32)
+    wide = types.SimpleNamespace(cells=1024 * 4, q=512, nx=1024, ny=4, n_azim=32)
+    assert bench.dominant_kernel(res, narrow, "f32")[0] == "banded_euler_kernel<32, false>"
+    assert bench.dominant_kernel(res, wide, "f32")[0] == "banded_euler_kernel<32, true>"

@@ -19,7 +19,8 @@ if not torch.cuda.is_available():
 from paper_1911_08801_amd import asn  # noqa: E402
 
 GRIDS = [(1, 1), (1, 7), (9, 1), (31, 1), (33, 2), (37, 9), (64, 16), (65, 17), (130, 67), (200, 3),
-         (256, 16)]   # the last one: rows of whole 32-cell blocks
+         (256, 16),   # rows of whole 32-cell blocks
+         (1024, 3), (1030, 2)]   # rows of 1024 cells or more: the kernel instance for wide rows
 # (n_polar, n_azim, beta): every azimuth count 8 .. 64; wide beta gives whole-ring bands
 QUADS = [(1, 8, 4.5), (2, 8, 4.5), (4, 8, 4.5), (8, 16, 4.5), (3, 24, 4.5), (12, 24, 4.5),
          (16, 32, 4.5), (5, 40, 6.0), (24, 48, 4.5), (7, 56, 4.5), (6, 64, 3.0), (8, 16, 9.0)]
@@ -66,6 +67,20 @@ def test_multi_step_with_budget(norm, n_polar, n_azim):
     assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
 
 
+@pytest.mark.parametrize("nx,ny", [(1024, 4), (1031, 3)])
+def test_wide_rows_multi_step_with_budget(nx, ny):
+    # rows of 1024 cells or more take the instance that reads the y-upwind row
+    # non-temporally; several steps, so both state buffers feed it
+    spec = wl.random_problem(nx + ny, nx, ny, n_polar=6, n_azim=16, beta=4.5, t_final=0.3)
+    psi0 = wl.random_state(nx - ny, spec.q, ny, nx)
+    state, phi, bud, _ = gpu_run(asn, spec, 6, psi0=psi0, form="banded")
+    ref, phi_ref, st = oracle_run(spec, 6, psi0=psi0)
+    assert rel_l2(phi, phi_ref) <= 1e-5
+    assert np.max(np.abs(state - ref)) <= 1e-5 * np.abs(ref).max()
+    assert bud["steps"] == 6
+    assert bud["max_residual"] <= max(1e-10, 64 * fp32_budget_floor(state, st.w))
+
+
 def test_line_source_50_q128_full_run():
     spec = wl.line_source(50, n_polar=8, sigma_as=1.0)
     state, phi, bud, info = gpu_run(asn, spec, 24, form="banded")
@@ -88,8 +103,10 @@ def test_automatic_form_takes_the_banded_step_and_agrees_with_fused():
 
 
 def test_bitwise_reproducible_and_batch_equals_alone():
+    # the last problem's rows hold 1024+ cells: alone it takes the wide-row instance, in
+    # this batch the other one (the two differ in cache policy only)
     specs = [wl.random_problem(s, nx, ny, n_polar=np_, n_azim=16, beta=4.5)
-             for s, nx, ny, np_ in ((1, 40, 30, 8), (2, 17, 5, 4), (3, 64, 64, 6))]
+             for s, nx, ny, np_ in ((1, 40, 30, 8), (2, 17, 5, 4), (3, 64, 64, 6), (4, 1040, 3, 4))]
     states = [wl.random_state(10 + i, sp.q, sp.ny, sp.nx) for i, sp in enumerate(specs)]
     alone = []
     for sp, s0 in zip(specs, states):
@@ -102,6 +119,23 @@ def test_bitwise_reproducible_and_batch_equals_alone():
         for p, s0 in zip(probs, states):
             asn.asn_set_state(p, s0)
         asn.asn_step_batch(probs, 4)
+        for p, ref in zip(probs, alone):
+            assert np.array_equal(asn.asn_get_state(p), ref)
+    finally:
+        for p in probs:
+            p.close()
+
+
+def test_batch_of_wide_rows_equals_alone():
+    specs = [wl.random_problem(s, nx, ny, n_polar=4, n_azim=16, beta=4.5)
+             for s, nx, ny in ((5, 1024, 2), (6, 1100, 3))]
+    states = [wl.random_state(20 + i, sp.q, sp.ny, sp.nx) for i, sp in enumerate(specs)]
+    alone = [gpu_run(asn, sp, 3, psi0=s0, form="banded")[0] for sp, s0 in zip(specs, states)]
+    probs = [asn.from_spec(sp, set_initial_state=False, form="banded") for sp in specs]
+    try:
+        for p, s0 in zip(probs, states):
+            asn.asn_set_state(p, s0)
+        asn.asn_step_batch(probs, 3)
         for p, ref in zip(probs, alone):
             assert np.array_equal(asn.asn_get_state(p), ref)
     finally:

@@ -48,7 +48,7 @@ struct Layout {
     bool banded = false; // banded step: one kernel per step for a product ordinate set
     int ktab_len = 0;
     size_t off_psi0, off_psi1, off_Y, off_Kt, off_Klp, off_rdef, off_ktab, off_qi, off_coef, off_iso,
-        off_band, off_brange, off_bcoef,
+        off_band, off_brange, off_bcoef, off_bfrag,
         off_phi64, off_phipart, off_blk, off_fin, off_ypart, off_fix, off_delta, off_bmax0, off_bmax1, off_rec,
         off_tab, off_off, off_base, off_left, off_imp,
         total;
@@ -74,7 +74,8 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
                    int band_azim = 0) {
     Layout L;
     L.banded = band_levels > 0;
-    if (L.banded) fused = false;
+    // the banded reduced-precision step keeps the fused form's pending correction
+    if (L.banded) fused = dtype != ASN_GEMM_F32;
     L.fused = fused;
     L.Q = Q;
     L.Qp = (int)round_up(Q, asn::kGemmBM);
@@ -94,8 +95,10 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
     }
     int tiles = L.tiles_x * L.tiles_y;
     if (L.banded) {
-        // one block per kBandCells cells, every ordinate: each cell's Phi complete
-        L.tiles_x = (int)((L.C + asn::kBandCells - 1) / asn::kBandCells);
+        // one block per kBandCells (kBandLpCells) cells, every ordinate: each cell's Phi
+        // complete
+        const int cells = L.lowp ? asn::kBandLpCells : asn::kBandCells;
+        L.tiles_x = (int)((L.C + cells - 1) / cells);
         L.tiles_y = 1;
         tiles = L.tiles_x;
         L.qchunk = Q;
@@ -142,7 +145,12 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
     // descriptor word past the last level's)
     L.off_band = take(L.banded ? (size_t)(band_levels + 1) * 32 : 0);
     L.off_brange = take(L.banded ? (size_t)band_levels * 8 : 0);    // coefficient ranges, int2
-    L.off_bcoef = take(L.banded ? band_coef_capacity(band_levels, band_azim) * 4 : 0);
+    L.off_bcoef = take(L.banded && !L.lowp ? band_coef_capacity(band_levels, band_azim) * 4 : 0);
+    // reduced-precision banded step: A operands, per level at most 2 kBandMaxReach + 1 pairs
+    // of n_az / 16 fragments of 1 KiB, and one zero fragment after them
+    L.off_bfrag = take(L.banded && L.lowp
+                           ? ((size_t)band_levels * (2 * asn::kBandMaxReach + 1) * (band_azim / 16) + 1) * 1024
+                           : 0);
     L.off_qi = take((size_t)Q * sizeof(QInfo));
     L.off_coef = take(plane * 16);
     L.off_iso = take(plane * 4);
@@ -201,7 +209,10 @@ struct asn_problem_s {
     int blocks[asn::KT_COUNT];
     std::unique_ptr<asn::ImplicitSolver> imp;   // the implicit scheme's solver (else null)
     int band_levels = 0, band_azim = 0, band_reach = 0, band_cmax = 0;   // banded step (else 0)
-    size_t band_lds() const { return asn::band_lds_bytes(band_azim, band_reach, band_cmax); }
+    size_t band_lds() const {
+        return dtype == ASN_GEMM_F32 ? asn::band_lds_bytes(band_azim, band_reach, band_cmax)
+                                     : asn::band_lp_lds_bytes(band_azim, band_reach, dtype);
+    }
     bool band_wide_rows() const { return nx >= asn::kBandWideRowCells; }
 };
 
@@ -211,6 +222,7 @@ struct asn_batch_s {
     int launch_scheme = 0;   // scheme, or its flat-chunk stencil form
     int band_az = 0;         // banded batches: the azimuth count and LDS bytes per block
     size_t band_lds = 0;
+    int band_reach = 0;      // the largest reach of a banded reduced-precision batch
     bool band_wide = false;  // every problem's rows are wide (asn::kBandWideRowCells)
     hipStream_t stream = nullptr;
     std::vector<StepArgs> tab;
@@ -271,6 +283,7 @@ StepArgs make_args(asn_problem p, int cur) {
         a.band = reinterpret_cast<const uint4*>(b + L.off_band);   // two per level
         a.brange = reinterpret_cast<const int2*>(b + L.off_brange);
         a.bcoef = reinterpret_cast<const float*>(b + L.off_bcoef);
+        a.bfrag = reinterpret_cast<const uint4*>(b + L.off_bfrag);
         a.n_lev = p->band_levels;
         a.n_az = p->band_azim;
         a.reach = p->band_reach;
@@ -416,17 +429,20 @@ bool use_fused(int dtype, int scheme, int form, int nx, int ny, int Q) {
     return !(nx <= asn::kFlatMaxNx && (double)nx * ny * Q >= 33554432.0);
 }
 
-// Whether a problem may take the banded step: FP32 forward Euler on a product set
-// whose azimuth count has a kernel instance (ASN_FORM_AUTO or ASN_FORM_BANDED); the
-// stored K must then also have the banded form (band_form).
+// Whether a problem may take the banded step: forward Euler on a product set whose
+// azimuth count has a kernel instance (FP32: 8 .. 64 in steps of 8; BF16 / FP16: 32 or
+// 64) (ASN_FORM_AUTO or ASN_FORM_BANDED); the stored K must then also have the banded
+// form (band_form).
 bool band_candidate(int dtype, int scheme, int form, const asn_quadrature* q, int64_t C) {
     // the kernel addresses one polar level of planes (n_azim * P floats) with byte
     // offsets below 2^31
     const int64_t P = round_up(C, asn::kScaleBlock);
-    return dtype == ASN_GEMM_F32 && scheme == ASN_SCHEME_EULER &&
+    const bool az_ok = dtype == ASN_GEMM_F32 ? asn::band_azimuths_supported(q->n_azim)
+                                             : asn::band_lp_azimuths_supported(q->n_azim);
+    return az_ok && scheme == ASN_SCHEME_EULER &&
            (int64_t)std::max(q->n_azim, 1) * P * 4 < ((int64_t)1 << 31) &&
            (form == ASN_FORM_AUTO || form == ASN_FORM_BANDED) && q->q_custom == 0 &&
-           q->icosahedron_order == 0 && q->n_polar >= 1 && asn::band_azimuths_supported(q->n_azim);
+           q->icosahedron_order == 0 && q->n_polar >= 1;
 }
 
 }  // namespace
@@ -461,8 +477,9 @@ asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
         return fail(ASN_E_INVALID, "step_form must be ASN_FORM_AUTO, _SEPARATE, _FUSED or _BANDED");
     if (form == ASN_FORM_BANDED) {
         if (!band_candidate(dtype, scheme, form, quad, (int64_t)grid->nx * grid->ny))
-            return fail(ASN_E_UNSUPPORTED, "ASN_FORM_BANDED needs FP32 forward Euler on a product "
-                                           "set with n_azim in {8, 16, ..., 64}");
+            return fail(ASN_E_UNSUPPORTED, "ASN_FORM_BANDED needs forward Euler on a product set "
+                                           "with n_azim in {8, 16, ..., 64} (FP32) or {32, 64} "
+                                           "(BF16, FP16)");
         *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme, false, quad->n_polar,
                              quad->n_azim).total;
         return ASN_OK;
@@ -572,17 +589,30 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
     asn::BandForm bf;
     bool banded = false;
     if (band_candidate(p->dtype, p->scheme, opt.step_form, quad, C)) {
+        // the values the kernel multiplies: FP32 K, or its BF16 / FP16 rounding
         std::vector<float> K32((size_t)Q * Q);
-        for (size_t i = 0; i < K32.size(); ++i) K32[i] = (float)K[i];
+        if (p->dtype == ASN_GEMM_F32) {
+            for (size_t i = 0; i < K32.size(); ++i) K32[i] = (float)K[i];
+        } else {
+            std::vector<uint16_t> kq((size_t)Q * Q);
+            std::vector<float> rd((size_t)Q);
+            quantise_kernel(Q, K.data(), p->dtype, Q, kq.data(), rd.data());
+            for (size_t i = 0; i < K32.size(); ++i)
+                K32[i] = p->dtype == ASN_GEMM_BF16 ? asn::bf16_to_float(kq[i]) : asn::half_to_float(kq[i]);
+        }
         banded = asn::band_form(quad->n_polar, quad->n_azim, K32.data(), asn::kBandMaxReach,
                                 asn::kBandNarrow, bf);
+        if (banded && p->dtype != ASN_GEMM_F32 &&
+            asn::band_lp_lds_bytes(bf.azim, bf.reach, p->dtype) > asn::kMaxBlockLds)
+            banded = false;
     }
     if (opt.step_form == ASN_FORM_BANDED && !banded) {
         delete p;
         return fail(ASN_E_UNSUPPORTED,
-                    "ASN_FORM_BANDED needs FP32 forward Euler on a product set with n_azim in "
-                    "{8, 16, ..., 64}, n_azim * cells below 2^29, and a K that couples polar "
-                    "levels at most 3 apart and is circulant along the azimuth in FP32");
+                    "ASN_FORM_BANDED needs forward Euler on a product set with n_azim in "
+                    "{8, 16, ..., 64} (FP32) or {32, 64} (BF16, FP16), n_azim * cells below 2^29, "
+                    "and a stored K that couples polar levels at most 3 apart (BF16 at 64 "
+                    "azimuths: 2) and is circulant along the azimuth");
     }
     if (banded) {
         p->band_levels = bf.levels;
@@ -684,7 +714,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                              : (Kt[(size_t)k * L.Qp + q] != 0.f);
         p->nonzero_entries = nz;
     }
-    if (banded) {   // the banded step multiplies each pair's run (wide runs padded to 4)
+    if (banded) {   // the banded step multiplies each pair's run (wide runs padded to 4);
+                    // the reduced-precision one each pair's whole n_az x n_az block
         double ex = 0;
         for (int i = 0; i < bf.levels; ++i) {
             const int n = (int)bf.desc[(size_t)i * 8];
@@ -692,7 +723,8 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                 const uint32_t code = bf.desc[(size_t)i * 8 + 1 + t];
                 int lo = 0, len = 0;
                 asn::band_run(code, bf.azim, lo, len);
-                ex += (double)bf.azim * ((code & 64u) ? (len + 3) / 4 * 4 : len);
+                ex += L.lowp ? (double)bf.azim * bf.azim
+                             : (double)bf.azim * ((code & 64u) ? (len + 3) / 4 * 4 : len);
             }
         }
         p->tile_entries = ex;
@@ -716,12 +748,30 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
 
     // the banded kernel's descriptors: counts as built, pair codes in its decoded form
     std::vector<uint32_t> ddesc;
-    if (banded) {
+    std::vector<uint16_t> bfrag;
+    if (banded && !L.lowp) {
         ddesc = bf.desc;
         for (int i = 0; i < bf.levels; ++i)
             for (int t = 0; t < (int)bf.desc[(size_t)i * 8]; ++t)
                 ddesc[(size_t)i * 8 + 1 + t] =
                     asn::band_device_code(bf.desc[(size_t)i * 8 + 1 + t], i, bf.reach, bf.azim);
+    } else if (banded) {
+        // per level {pairs, first fragment, the pairs' level offsets k (4 bits each), 0};
+        // per pair n_az / 16 A operands of MFMA 16x16x32 (band_lp_fragments)
+        ddesc.assign((size_t)bf.levels * 8, 0u);
+        int fcount = 0;
+        for (int i = 0; i < bf.levels; ++i) {
+            const int n = (int)bf.desc[(size_t)i * 8];
+            uint32_t kc = 0;
+            for (int t = 0; t < n; ++t) kc |= ((bf.desc[(size_t)i * 8 + 1 + t] >> 8) & 7u) << (4 * t);
+            ddesc[(size_t)i * 8] = (uint32_t)n;
+            ddesc[(size_t)i * 8 + 1] = (uint32_t)fcount;
+            ddesc[(size_t)i * 8 + 2] = kc;
+            for (int t = 0; t < n; ++t) {
+                asn::band_lp_fragments(bf, i, t, p->dtype, bfrag);
+                fcount += bf.azim / 16;
+            }
+        }
     }
     auto bail = [&](asn_status st) {
         if (p->owns) (void)hipFree(p->base);
@@ -738,13 +788,20 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                        p->stream) != hipSuccess ||
         hipMemcpyAsync(b + L.off_ktab, ktab.data(), ktab.size() * 4, hipMemcpyHostToDevice,
                        p->stream) != hipSuccess ||
-        (banded && (hipMemcpyAsync(b + L.off_band, ddesc.data(), ddesc.size() * 4,
-                                   hipMemcpyHostToDevice, p->stream) != hipSuccess ||
-                    hipMemcpyAsync(b + L.off_brange, bf.range.data(), bf.range.size() * 4,
-                                   hipMemcpyHostToDevice, p->stream) != hipSuccess ||
-                    hipMemcpyAsync(b + L.off_bcoef, bf.coef.data(), bf.coef.size() * 4,
-                                   hipMemcpyHostToDevice, p->stream) != hipSuccess ||
-                    asn::prepare_banded(bf.azim, p->band_lds()) != hipSuccess)) ||
+        (banded && !L.lowp &&
+         (hipMemcpyAsync(b + L.off_band, ddesc.data(), ddesc.size() * 4, hipMemcpyHostToDevice,
+                         p->stream) != hipSuccess ||
+          hipMemcpyAsync(b + L.off_brange, bf.range.data(), bf.range.size() * 4,
+                         hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+          hipMemcpyAsync(b + L.off_bcoef, bf.coef.data(), bf.coef.size() * 4, hipMemcpyHostToDevice,
+                         p->stream) != hipSuccess ||
+          asn::prepare_banded(bf.azim, p->band_lds()) != hipSuccess)) ||
+        (banded && L.lowp &&
+         (hipMemcpyAsync(b + L.off_band, ddesc.data(), ddesc.size() * 4, hipMemcpyHostToDevice,
+                         p->stream) != hipSuccess ||
+          hipMemcpyAsync(b + L.off_bfrag, bfrag.data(), bfrag.size() * 2, hipMemcpyHostToDevice,
+                         p->stream) != hipSuccess ||
+          asn::prepare_banded_lp(bf.azim, p->dtype, bf.reach, p->band_lds()) != hipSuccess)) ||
         (L.lowp && hipMemcpyAsync(b + L.off_Klp, Klp.data(), Klp.size() * 2,
                                   hipMemcpyHostToDevice, p->stream) != hipSuccess) ||
         hipMemcpyAsync(b + L.off_coef, coef.data(), coef.size() * 16, hipMemcpyHostToDevice,
@@ -885,7 +942,7 @@ asn_status asn_step(asn_problem p, int64_t n_steps) {
     for (int64_t i = 0; i < n_steps; ++i) {
         b.s_par = (int)(i & 1);
         HIP_TRY(asn::launch_step(b, p->blocks, p->dtype, launch_scheme(p), p->stream, nullptr,
-                                 p->band_azim, lds, p->band_wide_rows()));
+                                 p->band_azim, lds, p->band_wide_rows(), p->band_reach));
     }
     p->cur ^= state_flip(p->scheme, n_steps);
     p->steps_done += n_steps;
@@ -928,7 +985,7 @@ asn_status asn_step_timed(asn_problem p, int64_t n_steps, double kernel_ms[5]) {
         bt.s_par = (int)(i & 1);
         const hipError_t e = asn::launch_step(
             bt, p->blocks, p->dtype, launch_scheme(p), p->stream, &ev[(size_t)i * per], p->band_azim,
-            p->L.banded ? p->band_lds() : 0, p->band_wide_rows());
+            p->L.banded ? p->band_lds() : 0, p->band_wide_rows(), p->band_reach);
         if (e != hipSuccess) {
             st = fail(ASN_E_HIP, std::string("step launch failed: ") + hipGetErrorString(e));
             break;
@@ -1011,6 +1068,7 @@ asn_status asn_batch_create(asn_problem* probs, int32_t n, asn_batch* out) {
         if (probs[i]->L.banded)
             b->band_lds = std::max(b->band_lds, probs[i]->band_lds());
         b->band_wide = b->band_wide && probs[i]->band_wide_rows();
+        b->band_reach = std::max(b->band_reach, probs[i]->band_reach);
     }
     b->stream = probs[0]->stream;
     b->tab.resize(2 * (size_t)n);
@@ -1076,7 +1134,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
             for (int64_t j = 0; j < n_steps && e == hipSuccess; ++j) {
                 args.s_par = (int)(j & 1);
                 e = asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream, nullptr,
-                                     b->band_az, b->band_lds, b->band_wide);
+                                     b->band_az, b->band_lds, b->band_wide, b->band_reach);
             }
             const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -1095,7 +1153,7 @@ asn_status asn_batch_step(asn_batch b, int64_t n_steps, const int64_t* limit) {
         for (int64_t j = 0; j < n_steps; ++j) {
             args.s_par = (int)(j & 1);
             HIP_TRY(asn::launch_step(args, b->grid, b->dtype, b->launch_scheme, b->stream, nullptr,
-                                     b->band_az, b->band_lds, b->band_wide));
+                                     b->band_az, b->band_lds, b->band_wide, b->band_reach));
         }
     }
     for (int i = 0; i < b->n; ++i) {
@@ -1162,6 +1220,7 @@ asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps
     for (int k = 0; k < asn::KT_COUNT; ++k) off[k * (n + 1)] = 0;
     size_t band_lds = 0;
     bool band_wide = true;
+    int band_reach = 0;
     for (int32_t i = 0; i < n; ++i) {
         tab[2 * i] = probs[i]->tab[0];
         tab[2 * i + 1] = probs[i]->tab[1];
@@ -1169,6 +1228,7 @@ asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps
             off[k * (n + 1) + i + 1] = off[k * (n + 1) + i] + probs[i]->blocks[k];
         if (probs[i]->L.banded) band_lds = std::max(band_lds, probs[i]->band_lds());
         band_wide = band_wide && probs[i]->band_wide_rows();
+        band_reach = std::max(band_reach, probs[i]->band_reach);
     }
     for (int k = 0; k < asn::KT_COUNT; ++k) grid[k] = off[k * (n + 1) + n];
     if (n_steps == 0) return ASN_OK;
@@ -1197,7 +1257,7 @@ asn_status asn_step_batch_noalloc(asn_problem* probs, int32_t n, int64_t n_steps
     for (int64_t j = 0; j < n_steps; ++j) {
         args.s_par = (int)(j & 1);
         HIP_TRY(asn::launch_step(args, grid, probs[0]->dtype, scheme, stream, nullptr,
-                                 probs[0]->band_azim, band_lds, band_wide));
+                                 probs[0]->band_azim, band_lds, band_wide, band_reach));
     }
     for (int i = 0; i < n; ++i) {
         probs[i]->cur ^= state_flip(probs[i]->scheme, n_steps);

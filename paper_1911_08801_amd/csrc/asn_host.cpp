@@ -400,4 +400,22 @@ bool band_form(int levels, int azim, const float* K32, int max_reach, int narrow
     return true;
 }
 
+void band_lp_fragments(const BandForm& bf, int level, int pair, int dtype,
+                       std::vector<uint16_t>& out) {
+    const int azim = bf.azim;
+    const uint32_t code = bf.desc[(size_t)level * 8 + 1 + pair];
+    int lo = 0, len = 0;
+    band_run(code, azim, lo, len);
+    const int start = 4 * (int)((code >> 11) & 127u) + bf.range[2 * (size_t)level];
+    std::vector<float> c((size_t)azim, 0.f);   // c(delta), delta = 0 .. azim - 1
+    for (int t = 0; t < len; ++t) c[(size_t)(((lo + t) % azim + azim) % azim)] = bf.coef[(size_t)start + t];
+    for (int f = 0; f < azim / 16; ++f)
+        for (int l = 0; l < 64; ++l)
+            for (int t = 0; t < 8; ++t) {
+                const int m = l % 16, k = 8 * (l / 16) + t;
+                const float v = c[(size_t)(((16 * f + k - m) % azim + azim) % azim)];
+                out.push_back(dtype == 1 ? float_to_bf16_rne(v) : float_to_half_rne(v));
+            }
+}
+
 }  // namespace asn

@@ -57,6 +57,14 @@ struct BandForm {
 // Even azim up to 126.
 bool band_form(int levels, int azim, const float* K32, int max_reach, int narrow_max,
                BandForm& out);
+// The A operands of MFMA 16x16x32 for pair `pair` of level `level` of a banded form of
+// the BF16 (dtype 1) or FP16 (dtype 2) K: the pair's circulant block C[a][a'] =
+// c((a' - a) mod azim) sliced as 16 output x 32 input azimuths at the offsets 16 f,
+// f = 0 .. azim / 16 - 1 (slice f: rows m, columns k hold c((16 f + k - m) mod azim)),
+// each as 64 lanes x 8 values (lane l: row l % 16, columns 8 (l / 16) .. + 7), appended
+// to `out` as operand bits.  azim 32 or 64.
+void band_lp_fragments(const BandForm& bf, int level, int pair, int dtype,
+                       std::vector<uint16_t>& out);
 // The run of a pair code: first offset and length.
 inline void band_run(uint32_t code, int azim, int& lo, int& len) {
     const int s = (int)(code & 63u);

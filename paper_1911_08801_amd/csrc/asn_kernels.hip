@@ -2307,6 +2307,318 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 }
 
 // ---------------------------------------------------------------------------
+// 6. Banded reduced-precision step (BF16 / FP16 operands, FP32 accumulate) on product
+//    sets of 32 or 64 azimuths.  As in the fused reduced-precision form the state is
+//    stored without its pending per-cell particle correction delta (isotropic, so it
+//    drops out of the rounded deviation), and only the anisotropic part is rounded:
+//      x = T((psi^ - iso^) 2^(E - e_b))  (BF16: hi + lo),
+//      Y^ - iso^ = 2^(e_b - E) sum_j T(C_ij) x_j + r_q (psi^ - iso^),
+//    T(C_ij) the circulant block of level pair (i, j) of the stored K.  Block =
+//    kBandLpCells cells x every ordinate; wave (m-tile mt, n-tile nt) owns azimuths
+//    16 mt .. + 15 of cells 16 nt .. + 15, lane l the four azimuths 16 mt + 4 (l / 16) ..
+//    of cell 16 nt + l % 16, which is where MFMA 16x16x32 leaves them.  Per level pair
+//    and k-step of 32 azimuths one MFMA per operand term: A is the block's 16 x 32 slice
+//    at the wave's azimuth offset (host-built, staged in LDS a level ahead), B eight
+//    consecutive azimuths of one cell of the partner level from a ring of quantised
+//    levels ([cell][azimuth], 16-byte reads).  The ring is filled from registers loaded
+//    two levels ahead; the unrounded values of the lane's own cell wait in registers
+//    (reach + 1 levels) for the level's update; x neighbours come from the adjacent lanes
+//    (DPP) or, at the edges of a 16-cell tile, from a small ring the neighbouring waves
+//    (or the block's halo loads) fill at the same time.  Outputs as the fused form:
+//    psi^{n+1} without its correction, per cell Phi^ and sum_q w_q Y^, budget partials,
+//    block maxima of the next operand scale.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float dpp_from_left(float v) {   // lane l gets lane l - 1 (row of 16)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_from_right(float v) {  // lane l gets lane l + 1 (row of 16)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
+}
+
+template <int A, int DT, int R>
+__global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs B) {
+    constexpr int MT = A / 16, NT = kBandLpCells / 16, KS = A / 32, TERMS = DT == 1 ? 2 : 1;
+    constexpr int NW = MT * NT, T = NW * 64;
+    constexpr int XS = band_lp_row(A);        // 16-bit elements per cell row
+    constexpr int NS = 2 * R + 2, NE = R + 2, NP = 2 * R + 1;
+    constexpr int XSLOT = kBandLpCells * XS;  // elements per ring slot and term
+    constexpr int FR = NP * MT * 64;          // uint4 per fragment buffer
+    constexpr int CPT = (FR + T - 1) / T;     // fragment uint4 staged per thread
+    extern __shared__ __attribute__((aligned(16))) char lds_raw[];
+    uint16_t* xr = reinterpret_cast<uint16_t*>(lds_raw);
+    uint4* fr = reinterpret_cast<uint4*>(lds_raw + (size_t)NS * TERMS * XSLOT * 2);
+    float* edge = reinterpret_cast<float*>(lds_raw + (size_t)NS * TERMS * XSLOT * 2 + (size_t)2 * FR * 16);
+    int pi, local;
+    if (!locate(B, KT_SC, xcd_remap(blockIdx.x, gridDim.x), pi, local)) return;
+    const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mt = wave % MT, nt = wave / MT;
+    const int g = lane >> 4, cl = lane & 15;
+    const int a0 = 16 * mt + 4 * g;      // the lane's first azimuth
+    const int cc = 16 * nt + cl;         // its cell within the block
+    const int nx = a.nx, ny = a.ny, L = a.n_lev, RE = a.reach;
+    const int C = (int)a.C;
+    const int64_t P = a.P;
+    const int cell = local * kBandLpCells + cc;
+    const bool in = cell < C;
+    const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
+    const ASN_K QInfo* qk = kp(a.qi);
+    const ASN_K uint4* ldesc = kp(a.band);
+    const ASN_G uint4* __restrict__ frag = gp(a.bfrag);
+    const ASN_G float* __restrict__ rdef = gp(a.rdef);
+
+    float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ihv = 0.f, dv = 0.f;   // iso^ = Phi^ / W and the pending correction of the cell
+    if (in) {
+        cf = gp(a.coef)[cell];
+        ihv = gp(a.iso)[cell];
+        dv = gp(a.delta)[cell];
+    }
+    float s_in, s_out;   // the cell's operand scale 2^(E - e_b) and its inverse
+    {
+        const float bm = in ? __uint_as_float(gp(a.bmax_cur)[cell >> a.sb_log]) : 0.f;
+        int e = 0;
+        if (bm > 0.f) (void)frexpf(bm, &e);
+        e = max(e, -100);
+        s_in = ldexpf(1.f, kScaleExp - e);
+        s_out = ldexpf(1.f, e - kScaleExp);
+    }
+    const float ivs = ihv * s_in;
+    const int y = cell / nx, x = cell - y * nx;
+    const int e = in ? ((x == 0 ? 1 : 0) | (x == nx - 1 ? 2 : 0) | (y == 0 ? 4 : 0) |
+                        (y == ny - 1 ? 8 : 0))
+                     : 0;
+    const bool wedge = __ballot(e != 0) != 0;
+    const uint32_t lvl_bytes = (uint32_t)(A * P * 4), pb = (uint32_t)(P * 4);
+    const uint32_t off0 = 4u * (uint32_t)(a0 * P) + 4u * (uint32_t)cell;
+    uint32_t yoff[4];
+    float ydl[4];   // pending correction of the y-upwind cell
+    bool tl[4], tr[4], ox[4], oy[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const int d = qtab[a0 + o].dir;
+        const int yc = (d & 4) ? cell - nx : cell + nx;
+        const bool yv = in && yc >= 0 && yc < C;
+        yoff[o] = yv ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
+        ydl[o] = yv ? gp(a.delta)[yc] : 0.f;
+        const bool gx = !in || (d & e & 3) != 0;
+        tl[o] = !gx && (d & 1);
+        tr[o] = !gx && !(d & 1);
+        const int go = (((d & 5) << 1) | ((d & 10) >> 1)) & e;   // outflow faces of d
+        ox[o] = in && (go & 3);
+        oy[o] = in && (go & 12);
+    }
+    // the block's halo cells: lane 0 of tile 0 reads the cell before the block, lane 15
+    // of the last tile the cell after it (the other lanes' halo offsets read 0)
+    const bool hlo = nt == 0 && cl == 0, hhi = nt == NT - 1 && cl == 15;
+    const bool hvalid = (hlo && cell > 0) || (hhi && cell + 1 < (int)P);
+    const int hcell = hlo ? cell - 1 : cell + 1;
+    const float hdl = (hvalid && hcell < C) ? gp(a.delta)[hcell] : 0.f;
+    uint32_t hoff[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) hoff[o] = hvalid ? off0 + (uint32_t)o * pb + (hlo ? (uint32_t)-4 : 4u) : kOOB;
+    const size_t lvl_floats = (size_t)A * (size_t)P;
+    auto level_rsrc = [&](const float* base) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)lvl_bytes, kRsrcWord3);
+    };
+
+    struct Fill {
+        float v[4], h[4];
+    };
+    auto fetch = [&](int l, Fill& f) {
+        const __amdgpu_buffer_rsrc_t r = level_rsrc(a.psi + (size_t)l * lvl_floats);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            f.v[o] = load_plane(r, off0 + (uint32_t)o * pb);
+            f.h[o] = load_plane(r, hoff[o]);
+        }
+    };
+    // the lane's four azimuths of level l into the ring (rounded operand terms) and the
+    // tile-edge values (true state psi^ + delta) its neighbours need
+    auto put = [&](int l, const Fill& f) {
+        uint16_t* xs = xr + (size_t)(l % NS) * TERMS * XSLOT + cc * XS + a0;
+        float xv[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) xv[o] = __builtin_fmaf(f.v[o], s_in, -ivs);
+        uint2 pk;
+        pk.x = pack2<DT>(xv[0], xv[1]);
+        pk.y = pack2<DT>(xv[2], xv[3]);
+        *reinterpret_cast<uint2*>(xs) = pk;
+        if constexpr (DT == 1) {
+            uint2 pl;
+            pl.x = bf16_residual2(pk.x, xv[0], xv[1]);
+            pl.y = bf16_residual2(pk.y, xv[2], xv[3]);
+            *reinterpret_cast<uint2*>(xs + XSLOT) = pl;
+        }
+        float* es = edge + (size_t)(l % NE) * 2 * NT * A;
+        if (cl == 15) {   // the left neighbour of the next tile, or the block's right halo
+            float* d = hhi ? es + (NT + NT - 1) * A + a0 : es + (nt + 1) * A + a0;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) d[o] = hhi ? f.h[o] + hdl : f.v[o] + dv;
+        }
+        if (cl == 0) {    // the right neighbour of the previous tile, or the left halo
+            float* d = hlo ? es + a0 : es + (NT + nt - 1) * A + a0;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) d[o] = hlo ? f.h[o] + hdl : f.v[o] + dv;
+        }
+    };
+    // a level's A operands into fragment buffer l & 1 (thread t moves uint4 t and t + T;
+    // a level has at most 7 pairs of n_az / 16 fragments of 64 uint4, T >= 4 n_az / 16 x 64)
+    static_assert(CPT <= 2, "two staged uint4 per thread");
+    auto fetch_frag = [&](int l, uint4& f0, uint4& f1) {
+        const uint4 d = ldesc[2 * l];
+        const int last = max((int)d.x * MT * 64 - 1, 0);
+        const ASN_G uint4* src = frag + (size_t)d.y * 64;
+        f0 = src[min(tid, last)];
+        f1 = src[min(tid + T, last)];
+    };
+    auto put_frag = [&](int l, const uint4& f0, const uint4& f1) {
+        const int cnt = (int)ldesc[2 * l].x * MT * 64;
+        uint4* dst = fr + (size_t)(l & 1) * FR;
+        if (tid < cnt) dst[tid] = f0;
+        if (CPT > 1 && tid + T < cnt) dst[tid + T] = f1;
+    };
+    struct Ahead {
+        float y[4], cx[4], cy[4], rq[4];
+        double w;
+    };
+    auto fetch_ahead = [&](int l, Ahead& ah) {
+        const __amdgpu_buffer_rsrc_t r = level_rsrc(a.psi + (size_t)l * lvl_floats);
+        const int q0 = l * A;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            ah.y[o] = load_plane(r, yoff[o]);
+            ah.cx[o] = qtab[q0 + a0 + o].cx;
+            ah.cy[o] = qtab[q0 + a0 + o].cy;
+            ah.rq[o] = rdef[q0 + a0 + o];
+        }
+        ah.w = qk[q0].w;
+    };
+
+    // prologue: levels 0 .. R into the ring and the register queue, level 0's operands
+    float fifo[R + 1][4];
+    {
+        Fill f;
+#pragma unroll
+        for (int l = 0; l <= R; ++l) {
+            const int lc = min(l, L - 1);
+            fetch(lc, f);
+            if (l < L) put(l, f);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) fifo[l][o] = f.v[o];
+        }
+        uint4 f0, f1;
+        fetch_frag(0, f0, f1);
+        put_frag(0, f0, f1);
+    }
+    Fill pre;
+    fetch(min(R + 1, L - 1), pre);
+    uint4 fp0, fp1;
+    fetch_frag(min(1, L - 1), fp0, fp1);
+    Ahead ah;
+    fetch_ahead(0, ah);
+    lds_barrier();
+
+    double phacc = 0.0, ypacc = 0.0, defect = 0.0, outflow = 0.0;
+    float mx = 0.f;
+    const int mtk0 = ((0 - mt) % MT + MT) % MT;   // fragment of k-step 0: offset (32 kt - 16 mt) mod A
+    for (int i = 0; i < L; ++i) {
+        // level i + 1's A operands (its buffer's last readers passed the barrier)
+        if (i + 1 < L) put_frag(i + 1, fp0, fp1);
+        fetch_frag(min(i + 2, L - 1), fp0, fp1);
+        // contraction: every coupled level pair, k-steps of 32 azimuths, operand terms
+        const uint4 dsc = ldesc[2 * i];
+        const int n_pairs = (int)dsc.x;
+        uint32_t kcodes = dsc.z;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const uint4* fl = fr + (size_t)(i & 1) * FR;
+        for (int p = 0; p < n_pairs; ++p) {
+            const int j = i + (int)(kcodes & 15u) - RE;
+            kcodes >>= 4;
+            const uint16_t* xs = xr + (size_t)(j % NS) * TERMS * XSLOT + cc * XS + 8 * g;
+#pragma unroll
+            for (int kt = 0; kt < KS; ++kt) {
+                const int fi = (mtk0 + 2 * kt) % MT;
+                const uint4 av = fl[(p * MT + fi) * 64 + lane];
+#pragma unroll
+                for (int t = 0; t < TERMS; ++t) {
+                    const uint4 bv = *reinterpret_cast<const uint4*>(xs + t * XSLOT + 32 * kt);
+                    acc = mfma_lp<DT>(av, bv, acc);
+                }
+            }
+        }
+        // the update of the lane's four outputs (as the fused reduced-precision form):
+        //   v = psi^ + delta, dev = psi^ - iso^, Y^ - iso^ = s_out acc + r_q dev
+        //   col = gs ((iso^ + Y^ - iso^) - psi^) + bs (iso^ - psi^)
+        //   new = v - cx (v - ux) - cy (v - uy) - aa v + col + ss
+        const float* es = edge + (size_t)(i % NE) * 2 * NT * A;
+        const __amdgpu_buffer_rsrc_t ro = level_rsrc(a.psi_new + (size_t)i * lvl_floats);
+        float colsum = 0.f, ob = 0.f;
+        double ph = 0.0, yp = 0.0;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const float vh = fifo[0][o];
+            const float v = vh + dv;
+            float left = dpp_from_left(v), right = dpp_from_right(v);
+            if (cl == 0) left = es[nt * A + a0 + o];
+            if (cl == 15) right = es[(NT + nt) * A + a0 + o];
+            const float ux = tl[o] ? left : (tr[o] ? right : 0.f);
+            const float uy = ah.y[o] + ydl[o];
+            const float dev = vh - ihv;
+            const float ya = s_out * acc[o] + ah.rq[o] * dev;
+            const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
+            const float r = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
+            const float nv = in ? r : 0.f;
+            store_plane_nt(nv, ro, off0 + (uint32_t)o * pb);
+            ph += (double)nv;
+            yp += in ? (double)(ihv + dv) + (double)ya : 0.0;
+            colsum += in ? col : 0.f;
+            mx = fmaxf(mx, fabsf(nv));
+            if (wedge) ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
+        }
+        phacc += ah.w * ph;
+        ypacc += ah.w * yp;
+        defect += ah.w * (double)colsum;
+        outflow += ah.w * (double)ob;
+        // the queue advances; level i + R + 1 goes into the ring slot level i - R - 1 held
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) fifo[k][o] = fifo[k + 1][o];
+        if (i + R + 1 < L) put(i + R + 1, pre);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) fifo[R][o] = pre.v[o];
+        fetch(min(i + R + 2, L - 1), pre);
+        fetch_ahead(min(i + 1, L - 1), ah);
+        lds_barrier();
+    }
+
+    // per cell Phi^ and sum_q w_q Y^: the (n_az / 4) lane groups' partials in a fixed order
+    double* red = reinterpret_cast<double*>(lds_raw);
+    red[(4 * mt + g) * kBandLpCells + cc] = phacc;
+    red[(A / 4 + 4 * mt + g) * kBandLpCells + cc] = ypacc;
+    lds_barrier();
+    if (tid < kBandLpCells) {
+        const int c = local * kBandLpCells + tid;
+        if (c < C) {
+            double s = red[tid], sy = red[(A / 4) * kBandLpCells + tid];
+#pragma unroll
+            for (int k = 1; k < A / 4; ++k) {
+                s += red[k * kBandLpCells + tid];
+                sy += red[(A / 4 + k) * kBandLpCells + tid];
+            }
+            gp(a.phi_part)[c] = s;
+            gp(a.ypart)[c] = sy;
+        }
+    }
+    // block max |psi^{n+1}| of the next operand scale: the block's cells lie in one block
+    const unsigned mbits = wave_max_u32(__float_as_uint(mx));
+    if (lane == 0 && mbits) atomicMax(&a.bmax_next[(local * kBandLpCells) >> a.sb_log], mbits);
+    double sums[2] = {defect, outflow};
+    block_sum_waves<NW, 2>(sums, gp(a.blk_part) + 2 * (size_t)local);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static inline unsigned div_up(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -2315,7 +2627,7 @@ void blocks_per_kind(const StepArgs& a, int out[KT_COUNT]) {
     const bool banded = a.band != nullptr;
     out[KT_GEMM] = banded ? 0 : (a.Qp / kGemmBM) * (int)(a.P / kGemmBN);
     out[KT_FIX] = (a.dtype != 0 && !a.fused) ? a.fin_blocks : 0;
-    out[KT_SC] = a.fused ? 0 : a.tiles_x * a.tiles_y * a.G;
+    out[KT_SC] = (a.fused && !banded) ? 0 : a.tiles_x * a.tiles_y * a.G;
     out[KT_FIN] = a.fin_blocks;
     out[KT_BUDGET] = 1;
 }
@@ -2340,6 +2652,53 @@ static hipError_t launch_banded(const BatchArgs& b, int blocks, int az, size_t l
         default: return hipErrorInvalidValue;
     }
     return hipSuccess;
+}
+
+template <int A, int DT, int R>
+static void launch_banded_lp_r(const BatchArgs& b, int blocks, size_t lds, hipStream_t s) {
+    banded_lp_kernel<A, DT, R><<<blocks, band_lp_threads(A), lds, s>>>(b);
+}
+template <int A, int DT>
+static hipError_t launch_banded_lp_a(const BatchArgs& b, int blocks, size_t lds, hipStream_t s,
+                                     int reach) {
+    switch (reach) {
+        case 0: launch_banded_lp_r<A, DT, 0>(b, blocks, lds, s); break;
+        case 1: launch_banded_lp_r<A, DT, 1>(b, blocks, lds, s); break;
+        case 2: launch_banded_lp_r<A, DT, 2>(b, blocks, lds, s); break;
+        case 3: launch_banded_lp_r<A, DT, 3>(b, blocks, lds, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+static hipError_t launch_banded_lp(const BatchArgs& b, int blocks, int az, int dtype, size_t lds,
+                                   hipStream_t s, int reach) {
+    if (az == 32 && dtype == 1) return launch_banded_lp_a<32, 1>(b, blocks, lds, s, reach);
+    if (az == 32 && dtype == 2) return launch_banded_lp_a<32, 2>(b, blocks, lds, s, reach);
+    if (az == 64 && dtype == 1) return launch_banded_lp_a<64, 1>(b, blocks, lds, s, reach);
+    if (az == 64 && dtype == 2) return launch_banded_lp_a<64, 2>(b, blocks, lds, s, reach);
+    return hipErrorInvalidValue;
+}
+template <int A, int DT, int R>
+static hipError_t prepare_banded_lp_r(size_t lds) {
+    return hipFuncSetAttribute((const void*)banded_lp_kernel<A, DT, R>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+template <int A, int DT>
+static hipError_t prepare_banded_lp_a(int reach, size_t lds) {
+    switch (reach) {
+        case 0: return prepare_banded_lp_r<A, DT, 0>(lds);
+        case 1: return prepare_banded_lp_r<A, DT, 1>(lds);
+        case 2: return prepare_banded_lp_r<A, DT, 2>(lds);
+        case 3: return prepare_banded_lp_r<A, DT, 3>(lds);
+        default: return hipErrorInvalidValue;
+    }
+}
+hipError_t prepare_banded_lp(int band_az, int dtype, int reach, size_t band_lds) {
+    if (band_az == 32 && dtype == 1) return prepare_banded_lp_a<32, 1>(reach, band_lds);
+    if (band_az == 32 && dtype == 2) return prepare_banded_lp_a<32, 2>(reach, band_lds);
+    if (band_az == 64 && dtype == 1) return prepare_banded_lp_a<64, 1>(reach, band_lds);
+    if (band_az == 64 && dtype == 2) return prepare_banded_lp_a<64, 2>(reach, band_lds);
+    return hipErrorInvalidValue;
 }
 
 template <int A>
@@ -2373,14 +2732,16 @@ constexpr int kStencilBanded = 16;
 // One pass: contraction, stencil, finalize, budget.
 static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, int stencil,
                               int bud, hipStream_t s, hipEvent_t* ev, int band_az = 0,
-                              size_t band_lds = 0, bool band_wide_rows = false) {
+                              size_t band_lds = 0, bool band_wide_rows = false,
+                              int band_reach = 0) {
     hipError_t e = hipSuccess;
     auto mark = [&](int k) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[k], s);
     };
     if (stencil == kStencilBanded) {   // contraction and stencil in one kernel
         mark(0);
-        e = launch_banded(b, grid[KT_SC], band_az, band_lds, s, band_wide_rows);
+        e = dtype == 0 ? launch_banded(b, grid[KT_SC], band_az, band_lds, s, band_wide_rows)
+                       : launch_banded_lp(b, grid[KT_SC], band_az, dtype, band_lds, s, band_reach);
         mark(1);
         mark(2);
         if (e == hipSuccess) finalize_kernel<<<grid[KT_FIN], 256, 0, s>>>(b, 0);
@@ -2437,10 +2798,11 @@ static hipError_t launch_pass(const BatchArgs& b, const int* grid, int dtype, in
 }
 
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
-                       hipEvent_t* ev, int band_az, size_t band_lds, bool band_wide_rows) {
+                       hipEvent_t* ev, int band_az, size_t band_lds, bool band_wide_rows,
+                       int band_reach) {
     if (scheme == SCHEME_EULER_BANDED)
         return launch_pass(b, grid, dtype, kStencilBanded, BUD_STEP, s, ev, band_az, band_lds,
-                           band_wide_rows);
+                           band_wide_rows, band_reach);
     if (scheme != SCHEME_HEUN && scheme != SCHEME_HEUN_FLAT)
         return launch_pass(b, grid, dtype, scheme == SCHEME_EULER_FLAT ? 3 : 0, BUD_STEP, s, ev);
     const int st = scheme == SCHEME_HEUN_FLAT ? 4 : 1;   // stencil of the first pass

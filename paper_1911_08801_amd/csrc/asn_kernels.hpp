@@ -106,6 +106,30 @@ inline size_t band_lds_bytes(int az, int reach, int cmax) {
            2 * (size_t)cmax * 4;
 }
 
+// Banded reduced-precision step (BF16 / FP16 operands on MFMA 16x16x32, FP32 accumulate)
+// for product sets of 32 or 64 azimuths: a block owns kBandLpCells consecutive cells and
+// every ordinate; wave (m, n) produces azimuths 16 m .. 16 m + 15 of cells 16 n .. 16 n + 15.
+// Per level pair (i, j) the circulant block of the stored K is multiplied as A operands
+// of 16 x 32 (one per 16-azimuth offset, built on the host: band_lp_fragments) with the
+// quantised partner level as B operand.
+constexpr int kBandLpCells = 64;
+constexpr int kBandLpMaxReach = 3;
+inline bool band_lp_azimuths_supported(int az) { return az == 32 || az == 64; }
+__host__ __device__ constexpr int band_lp_threads(int az) { return (az / 16) * (kBandLpCells / 16) * 64; }
+// 16-bit elements per cell row of the quantised-level ring (16-byte reads conflict-free)
+__host__ __device__ constexpr int band_lp_row(int az) { return az + 8; }
+// Dynamic LDS of a banded reduced-precision block: the ring of 2 reach + 2 quantised
+// levels (two operand terms for BF16), two buffers of a level's A operands (at most
+// 2 reach + 1 pairs, n_az / 16 fragments of 1 KiB each), the ring of tile-edge values
+// (reach + 2 levels).
+inline size_t band_lp_lds_bytes(int az, int reach, int dtype) {
+    const int terms = dtype == 1 ? 2 : 1, mt = az / 16, nt = kBandLpCells / 16;
+    return (size_t)(2 * reach + 2) * terms * kBandLpCells * band_lp_row(az) * 2 +
+           (size_t)2 * (2 * reach + 1) * mt * 1024 + (size_t)(reach + 2) * 2 * nt * az * 4;
+}
+// Largest dynamic LDS a block may take.
+constexpr size_t kMaxBlockLds = 160 * 1024 - 1024;
+
 // Modes of the budget kernel.
 enum { BUD_STEP = 0, BUD_INIT = 1, BUD_STAGE1 = 2, BUD_STAGE2 = 3 };
 
@@ -185,6 +209,10 @@ struct StepArgs {
     const int2* brange;
     const float* bcoef;
     int n_lev, n_az, reach, bcmax;
+    // banded reduced-precision step: per level pair and 16-azimuth offset the A operand
+    // of MFMA 16x16x32 as 64 lanes x 8 16-bit values (band_lp_fragments); band then holds
+    // per level {pairs, first fragment, level offsets k of the pairs (4 bits each), 0}
+    const uint4* bfrag;
 };
 
 // Kernel kinds of one step, each with its own block decomposition.
@@ -220,16 +248,20 @@ inline bool can_fuse(int dtype, int scheme) { (void)dtype; return scheme == SCHE
 // the four kernels of pass k.
 // band_az / band_lds: the banded step's azimuth count and dynamic LDS bytes (every
 // problem of a banded batch has that azimuth count); band_wide_rows: every problem's
-// rows hold at least band_wide_cells cells (selects the banded kernel's instance that
-// reads the y-upwind rows non-temporally).
+// rows hold at least kBandWideRowCells cells (selects the FP32 banded kernel's instance
+// that reads the y-upwind rows non-temporally); band_reach: the reach the banded
+// reduced-precision kernel is instantiated for (at least every problem's).
 hipError_t launch_step(const BatchArgs& b, const int* grid, int dtype, int scheme, hipStream_t s,
                        hipEvent_t* ev = nullptr, int band_az = 0, size_t band_lds = 0,
-                       bool band_wide_rows = false);
+                       bool band_wide_rows = false, int band_reach = 0);
 // Rows from this many cells on: the banded kernel's y-upwind row belongs to a block at
 // least 32 blocks away, which runs about half a block's time apart on its XCD.
 constexpr int kBandWideRowCells = 32 * kBandCells;
 // Raise the dynamic LDS limit of the banded kernel for an azimuth count (once per device).
 hipError_t prepare_banded(int band_az, size_t band_lds);
+// The same for the banded reduced-precision kernel of an azimuth count, operand type
+// and reach.
+hipError_t prepare_banded_lp(int band_az, int dtype, int reach, size_t band_lds);
 // Passes per step of a scheme.
 inline int passes_per_step(int scheme) {
     return scheme == SCHEME_HEUN || scheme == SCHEME_HEUN_FLAT ? 2 : 1;

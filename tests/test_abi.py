@@ -287,17 +287,22 @@ def test_banded_form_refuses_kernels_without_it():
 
 
 def test_banded_form_size_and_scheme_limits():
-    # the banded kernel addresses a polar level's planes (n_azim * P floats) with 32-bit
-    # byte offsets: an explicit request beyond that, or for BF16 / Heun / an icosahedron
-    # set, is refused; the automatic form falls back to the MFMA forms without error
+    # the banded kernels address a polar level's planes (n_azim * P floats) with 32-bit
+    # byte offsets: an explicit request beyond that, for Heun or an icosahedron set, or in
+    # BF16 / FP16 at an azimuth count without a reduced-precision instance, is refused;
+    # the automatic form falls back to the MFMA forms without error
     q = asn.asn_quadrature(32, 64, 0, None, None, 0)
+    q48 = asn.asn_quadrature(24, 48, 0, None, None, 0)
     small = asn.make_grid(1024, 1024, -1.5, 1.5, -1.5, 1.5)
     big = asn.make_grid(2900, 2900, -1.5, 1.5, -1.5, 1.5)      # 64 x P x 4 >= 2^31
     assert asn.asn_workspace_size(small, q, asn.make_options(form="banded")) > 0
-    for grid, opts in ((big, dict(form="banded")), (small, dict(form="banded", dtype="bf16")),
-                       (small, dict(form="banded", scheme="heun"))):
+    for dt in ("bf16", "f16"):
+        assert asn.asn_workspace_size(small, q, asn.make_options(form="banded", dtype=dt)) > 0
+    for grid, quad, opts in ((big, q, dict(form="banded")), (small, q48, dict(form="banded", dtype="bf16")),
+                             (small, q48, dict(form="banded", dtype="f16")),
+                             (small, q, dict(form="banded", scheme="heun"))):
         with pytest.raises(asn.AsnError) as e:
-            asn.asn_workspace_size(grid, q, asn.make_options(**opts))
+            asn.asn_workspace_size(grid, quad, asn.make_options(**opts))
         assert e.value.status == asn.ASN_E_UNSUPPORTED
     assert asn.asn_workspace_size(big, q, asn.make_options(form="auto")) > 0
     ico = asn.asn_quadrature(0, 0, 0, None, None, 3)

@@ -165,9 +165,11 @@ def test_step_form_reports_the_library_choice():
     big = wl.line_source(256, n_polar=16, t_final=0.02)      # 2^25 cell-ordinates
     small = wl.line_source(48, n_polar=8, t_final=0.05)
     big6 = wl.line_source(256, n_polar=86, n_azim=6, t_final=0.02)   # no banded instance
+    # BF16 / FP16 take the banded form at 32 or 64 azimuths, else the fused one
     for spec, kw, want in ((big, {}, "banded"), (small, {}, "banded"), (big6, {}, "separate"),
                            (big, {"unfused": False}, "fused"), (small, {"unfused": True}, "separate"),
-                           (big, {"dtype": "bf16"}, "fused"), (small, {"scheme": "heun"}, "separate")):
+                           (big, {"dtype": "bf16"}, "banded"), (small, {"dtype": "f16"}, "fused"),
+                           (big6, {"dtype": "bf16"}, "fused"), (small, {"scheme": "heun"}, "separate")):
         p = asn.from_spec(spec, **kw)
         try:
             assert asn.asn_step_form(p) == want, (spec.name, kw)

@@ -272,7 +272,7 @@ def test_contraction_work_reduced_precision_blocks(dtype):
     # 16-bit operands: the kernel multiplies the whole 128 x 32 tiles of T(K) (128
     # ordinates x one 32-ordinate k-step) that hold a nonzero 16-bit pattern
     spec = wl.line_source(16, n_polar=16, sigma_as=5.0)
-    p = asn.from_spec(spec, dtype=dtype)
+    p = asn.from_spec(spec, dtype=dtype, form="fused")
     work = asn.asn_contraction_work(p)
     p.close()
     om, w = asn.asn_build_quadrature(16, 32)

@@ -602,9 +602,17 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         }
         banded = asn::band_form(quad->n_polar, quad->n_azim, K32.data(), asn::kBandMaxReach,
                                 asn::kBandNarrow, bf);
-        if (banded && p->dtype != ASN_GEMM_F32 &&
-            asn::band_lp_lds_bytes(bf.azim, bf.reach, p->dtype) > asn::kMaxBlockLds)
-            banded = false;
+        if (banded && p->dtype != ASN_GEMM_F32) {
+            // the reduced-precision kernel takes one row defect per level (the rows of a
+            // level hold the same values, so their FP64 sums agree; checked) and must fit
+            // its LDS
+            if (asn::band_lp_lds_bytes(bf.azim, bf.reach, p->dtype) > asn::kMaxBlockLds) banded = false;
+            std::vector<uint16_t> kq((size_t)Q * Q);
+            std::vector<float> rd((size_t)Q);
+            quantise_kernel(Q, K.data(), p->dtype, Q, kq.data(), rd.data());
+            for (int q = 0; banded && q < Q; ++q)
+                if (rd[(size_t)q] != rd[(size_t)(q / quad->n_azim) * quad->n_azim]) banded = false;
+        }
     }
     if (opt.step_form == ASN_FORM_BANDED && !banded) {
         delete p;

@@ -2328,11 +2328,12 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 //    psi^{n+1} without its correction, per cell Phi^ and sum_q w_q Y^, budget partials,
 //    block maxima of the next operand scale.
 // ---------------------------------------------------------------------------
+// (lanes at the row's edge get 0; the kernel takes their value from the edge ring)
 __device__ __forceinline__ float dpp_from_left(float v) {   // lane l gets lane l - 1 (row of 16)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x111, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float dpp_from_right(float v) {  // lane l gets lane l + 1 (row of 16)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x101, 0xF, 0xF, true));
 }
 
 template <int A, int DT, int R>
@@ -2365,7 +2366,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     const ASN_K QInfo* qk = kp(a.qi);
     const ASN_K uint4* ldesc = kp(a.band);
     const ASN_G uint4* __restrict__ frag = gp(a.bfrag);
-    const ASN_G float* __restrict__ rdef = gp(a.rdef);
+    const ASN_K float* rdk = kp(a.rdef);   // r_q, the same for every ordinate of a level
 
     float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
     float ihv = 0.f, dv = 0.f;   // iso^ = Phi^ / W and the pending correction of the cell
@@ -2391,16 +2392,23 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     const bool wedge = __ballot(e != 0) != 0;
     const uint32_t lvl_bytes = (uint32_t)(A * P * 4), pb = (uint32_t)(P * 4);
     const uint32_t off0 = 4u * (uint32_t)(a0 * P) + 4u * (uint32_t)cell;
+    // the lane's four azimuths lie in one quadrant (n_az / 4 is a multiple of 4): one
+    // y-upwind cell
     uint32_t yoff[4];
-    float ydl[4];   // pending correction of the y-upwind cell
+    float ydl;   // pending correction of the y-upwind cell
     bool tl[4], tr[4], ox[4], oy[4];
+    {
+        const int d = qtab[a0].dir;
+        const int yc = (d & 4) ? cell - nx : cell + nx;
+        const bool yv = in && yc >= 0 && yc < C;
+        ydl = yv ? gp(a.delta)[yc] : 0.f;
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            yoff[o] = yv ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
+    }
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         const int d = qtab[a0 + o].dir;
-        const int yc = (d & 4) ? cell - nx : cell + nx;
-        const bool yv = in && yc >= 0 && yc < C;
-        yoff[o] = yv ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
-        ydl[o] = yv ? gp(a.delta)[yc] : 0.f;
         const bool gx = !in || (d & e & 3) != 0;
         tl[o] = !gx && (d & 1);
         tr[o] = !gx && !(d & 1);
@@ -2462,24 +2470,29 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
             for (int o = 0; o < 4; ++o) d[o] = hlo ? f.h[o] + hdl : f.v[o] + dv;
         }
     };
-    // a level's A operands into fragment buffer l & 1 (thread t moves uint4 t and t + T;
-    // a level has at most 7 pairs of n_az / 16 fragments of 64 uint4, T >= 4 n_az / 16 x 64)
-    static_assert(CPT <= 2, "two staged uint4 per thread");
-    auto fetch_frag = [&](int l, uint4& f0, uint4& f1) {
+    // a level's A operands into fragment buffer l & 1 (thread t moves uint4 t, t + T, ..;
+    // at most 7 pairs of n_az / 16 fragments of 64 uint4)
+    static_assert(CPT <= 4, "at most four staged uint4 per thread");
+    auto fetch_frag = [&](int l, uint4& f0, uint4& f1, uint4& f2, uint4& f3) {
         const uint4 d = ldesc[2 * l];
         const int last = max((int)d.x * MT * 64 - 1, 0);
         const ASN_G uint4* src = frag + (size_t)d.y * 64;
         f0 = src[min(tid, last)];
-        f1 = src[min(tid + T, last)];
+        if constexpr (CPT > 1) f1 = src[min(tid + T, last)];
+        if constexpr (CPT > 2) f2 = src[min(tid + 2 * T, last)];
+        if constexpr (CPT > 3) f3 = src[min(tid + 3 * T, last)];
     };
-    auto put_frag = [&](int l, const uint4& f0, const uint4& f1) {
+    auto put_frag = [&](int l, const uint4& f0, const uint4& f1, const uint4& f2, const uint4& f3) {
         const int cnt = (int)ldesc[2 * l].x * MT * 64;
         uint4* dst = fr + (size_t)(l & 1) * FR;
         if (tid < cnt) dst[tid] = f0;
-        if (CPT > 1 && tid + T < cnt) dst[tid + T] = f1;
+        if constexpr (CPT > 1) if (tid + T < cnt) dst[tid + T] = f1;
+        if constexpr (CPT > 2) if (tid + 2 * T < cnt) dst[tid + 2 * T] = f2;
+        if constexpr (CPT > 3) if (tid + 3 * T < cnt) dst[tid + 3 * T] = f3;
     };
     struct Ahead {
-        float y[4], cx[4], cy[4], rq[4];
+        float y[4], cx[4], cy[4];
+        float rq;
         double w;
     };
     auto fetch_ahead = [&](int l, Ahead& ah) {
@@ -2490,8 +2503,8 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
             ah.y[o] = load_plane(r, yoff[o]);
             ah.cx[o] = qtab[q0 + a0 + o].cx;
             ah.cy[o] = qtab[q0 + a0 + o].cy;
-            ah.rq[o] = rdef[q0 + a0 + o];
         }
+        ah.rq = rdk[q0];
         ah.w = qk[q0].w;
     };
 
@@ -2507,14 +2520,14 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
 #pragma unroll
             for (int o = 0; o < 4; ++o) fifo[l][o] = f.v[o];
         }
-        uint4 f0, f1;
-        fetch_frag(0, f0, f1);
-        put_frag(0, f0, f1);
+        uint4 g0, g1, g2, g3;
+        fetch_frag(0, g0, g1, g2, g3);
+        put_frag(0, g0, g1, g2, g3);
     }
     Fill pre;
     fetch(min(R + 1, L - 1), pre);
-    uint4 fp0, fp1;
-    fetch_frag(min(1, L - 1), fp0, fp1);
+    uint4 fp0, fp1, fp2, fp3;
+    fetch_frag(min(1, L - 1), fp0, fp1, fp2, fp3);
     Ahead ah;
     fetch_ahead(0, ah);
     lds_barrier();
@@ -2524,27 +2537,33 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     const int mtk0 = ((0 - mt) % MT + MT) % MT;   // fragment of k-step 0: offset (32 kt - 16 mt) mod A
     for (int i = 0; i < L; ++i) {
         // level i + 1's A operands (its buffer's last readers passed the barrier)
-        if (i + 1 < L) put_frag(i + 1, fp0, fp1);
-        fetch_frag(min(i + 2, L - 1), fp0, fp1);
+        if (i + 1 < L) put_frag(i + 1, fp0, fp1, fp2, fp3);
+        fetch_frag(min(i + 2, L - 1), fp0, fp1, fp2, fp3);
         // contraction: every coupled level pair, k-steps of 32 azimuths, operand terms
         const uint4 dsc = ldesc[2 * i];
         const int n_pairs = (int)dsc.x;
         uint32_t kcodes = dsc.z;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const uint4* fl = fr + (size_t)(i & 1) * FR;
+        const uint4* fl = fr + (size_t)(i & 1) * FR + lane;
+        // ring slot of level i - RE (k = 0); a pair's partner i - RE + k sits k slots on
+        const int sb = ((i - RE) % NS + NS) % NS;
+        const uint16_t* xl = xr + cc * XS + 8 * g;
         for (int p = 0; p < n_pairs; ++p) {
-            const int j = i + (int)(kcodes & 15u) - RE;
+            int sl = sb + (int)(kcodes & 15u);
+            sl = sl >= NS ? sl - NS : sl;
             kcodes >>= 4;
-            const uint16_t* xs = xr + (size_t)(j % NS) * TERMS * XSLOT + cc * XS + 8 * g;
+            const uint16_t* xs = xl + (size_t)sl * TERMS * XSLOT;
+            uint4 av[KS];
 #pragma unroll
-            for (int kt = 0; kt < KS; ++kt) {
-                const int fi = (mtk0 + 2 * kt) % MT;
-                const uint4 av = fl[(p * MT + fi) * 64 + lane];
+            for (int kt = 0; kt < KS; ++kt) av[kt] = fl[(p * MT + (mtk0 + 2 * kt) % MT) * 64];
 #pragma unroll
-                for (int t = 0; t < TERMS; ++t) {
-                    const uint4 bv = *reinterpret_cast<const uint4*>(xs + t * XSLOT + 32 * kt);
-                    acc = mfma_lp<DT>(av, bv, acc);
-                }
+            for (int t = 0; t < TERMS; ++t) {
+                uint4 bv[KS];
+#pragma unroll
+                for (int kt = 0; kt < KS; ++kt)
+                    bv[kt] = *reinterpret_cast<const uint4*>(xs + t * XSLOT + 32 * kt);
+#pragma unroll
+                for (int kt = 0; kt < KS; ++kt) acc = mfma_lp<DT>(av[kt], bv[kt], acc);
             }
         }
         // the update of the lane's four outputs (as the fused reduced-precision form):
@@ -2553,31 +2572,39 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         //   new = v - cx (v - ux) - cy (v - uy) - aa v + col + ss
         const float* es = edge + (size_t)(i % NE) * 2 * NT * A;
         const __amdgpu_buffer_rsrc_t ro = level_rsrc(a.psi_new + (size_t)i * lvl_floats);
-        float colsum = 0.f, ob = 0.f;
-        double ph = 0.0, yp = 0.0;
+        float colsum = 0.f, ob = 0.f, yas = 0.f;
+        double ph = 0.0;
+        // the tile-edge values of the lane's four azimuths (used by lanes 0 and 15 of a row)
+        const float4 eL = *reinterpret_cast<const float4*>(es + nt * A + a0);
+        const float4 eR = *reinterpret_cast<const float4*>(es + (NT + nt) * A + a0);
+        const float eLv[4] = {eL.x, eL.y, eL.z, eL.w}, eRv[4] = {eR.x, eR.y, eR.z, eR.w};
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const float vh = fifo[0][o];
             const float v = vh + dv;
-            float left = dpp_from_left(v), right = dpp_from_right(v);
-            if (cl == 0) left = es[nt * A + a0 + o];
-            if (cl == 15) right = es[(NT + nt) * A + a0 + o];
+            // the row shifts run in every lane (a lane whose neighbour is inactive would
+            // read 0), then the row's edge lanes take the edge ring's value
+            const float dl = dpp_from_left(v), dr = dpp_from_right(v);
+            const float left = cl == 0 ? eLv[o] : dl;
+            const float right = cl == 15 ? eRv[o] : dr;
             const float ux = tl[o] ? left : (tr[o] ? right : 0.f);
-            const float uy = ah.y[o] + ydl[o];
+            const float uy = ah.y[o] + ydl;
             const float dev = vh - ihv;
-            const float ya = s_out * acc[o] + ah.rq[o] * dev;
+            const float ya = s_out * acc[o] + ah.rq * dev;
             const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
             const float r = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
             const float nv = in ? r : 0.f;
             store_plane_nt(nv, ro, off0 + (uint32_t)o * pb);
             ph += (double)nv;
-            yp += in ? (double)(ihv + dv) + (double)ya : 0.0;
+            yas += in ? ya : 0.f;
             colsum += in ? col : 0.f;
             mx = fmaxf(mx, fabsf(nv));
             if (wedge) ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
         }
         phacc += ah.w * ph;
-        ypacc += ah.w * yp;
+        // sum over the four outputs of Y^ = iso^ + delta + (Y^ - iso^); the deviations,
+        // small against iso^, summed in FP32
+        ypacc += ah.w * ((in ? 4.0 * (double)(ihv + dv) : 0.0) + (double)yas);
         defect += ah.w * (double)colsum;
         outflow += ah.w * (double)ob;
         // the queue advances; level i + R + 1 goes into the ring slot level i - R - 1 held

@@ -180,7 +180,8 @@ def kernel_source_hash(path=KERNEL_SOURCE):
 
 def measured_traffic(kernel, spec):
     """HBM bytes per dispatch (read + write) from the committed counter summary, or None
-    if the kernels changed since it was taken or the workload is not the one measured."""
+    if the kernels changed since it was taken or the workload is not the one measured.
+    A name ending in ", R>" stands for the instance of any reach R."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -189,16 +190,20 @@ def measured_traffic(kernel, spec):
             [spec.nx, spec.ny, spec.q] != rec.get("workload_nx_ny_q"):
         return None
     k = rec["kernels"].get(kernel)
+    if k is None and kernel.endswith(", R>"):
+        k = next((v for n, v in rec["kernels"].items() if n.startswith(kernel[:-2])), None)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
 # the dominant kernel of each kernel form (its event slot in asn_step_timed)
 def dominant_kernel(res, spec, dtype):
     form = res["form"]
+    lp = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
+    if form == "banded" and lp:   # instantiated per reach of K
+        return f"banded_lp_kernel<{spec.n_azim}, {lp}, R>", "contraction"
     if form == "banded":
         wide = "true" if spec.nx >= BAND_WIDE_ROW_CELLS else "false"
         return f"banded_euler_kernel<{spec.n_azim}, {wide}>", "contraction"
-    lp = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
     if form == "fused":
         name = "gemm_f32_kernel<true>" if lp == 0 else f"gemm_lp_kernel<{lp}, true>"
         return name, "contraction"
@@ -222,7 +227,7 @@ def roofline(res, spec, dtype):
     ach = bytes_ / t / 1e9
     nz = res["work"]["nonzero_flops"]
     executed = res["work"]["tile_flops"]
-    compute_peak = (PEAK_FP32_VALU_TFLOPS if res["form"] == "banded" else
+    compute_peak = (PEAK_FP32_VALU_TFLOPS if res["form"] == "banded" and dtype == "f32" else
                     PEAK_FP32_MFMA_TFLOPS if dtype == "f32" else PEAK_LP_MFMA_TFLOPS)
     traffic = measured_traffic(name, spec)
     return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -100,14 +100,18 @@ enum { ASN_DT_STREAMING = 0, ASN_DT_STIFF = 1 };
  * ASN_FORM_FUSED:    the stream + collide update runs in the contraction kernel's
  *                    epilogue; the contraction output Y never reaches memory.
  * ASN_FORM_SEPARATE: contraction, then a separate stencil kernel (Y through memory).
- * ASN_FORM_BANDED:   FP32 on a product set only: the set is invariant under rotation
- *                    by 2 pi / n_azim about the polar axis, so K restricted to two polar
+ * ASN_FORM_BANDED:   product sets only: the set is invariant under rotation by
+ *                    2 pi / n_azim about the polar axis, so K restricted to two polar
  *                    levels is circulant along the azimuth, and K couples only nearby
  *                    levels (forward peak, Section 3.5 notes S_as^+ is sparse).  One kernel
- *                    per step applies K as short circular convolutions and the update,
- *                    reading psi^n once.  Needs n_azim in {8, 16, ..., 64}, levels at most
- *                    3 apart coupled, and the FP32 K exactly circulant (checked at
- *                    asn_create; ASN_E_UNSUPPORTED otherwise).
+ *                    per step applies K level pair by level pair and the update, reading
+ *                    psi^n once.  FP32: short circular convolutions on the vector units,
+ *                    n_azim in {8, 16, ..., 64}.  BF16 / FP16: each coupled pair's
+ *                    n_azim x n_azim circulant block of the rounded K on the matrix
+ *                    cores, the update as ASN_FORM_FUSED (the same rounding recipe and
+ *                    pending per-cell correction), n_azim 32 or 64.  Needs levels at most
+ *                    3 apart coupled (BF16 at 64 azimuths: 2) and the stored K exactly
+ *                    circulant (checked at asn_create; ASN_E_UNSUPPORTED otherwise).
  * ASN_FORM_AUTO:     the banded form where it applies; else BF16/FP16 fuse, and FP32
  *                    runs separate kernels from 2^25 cell-ordinates (nx <= 4088) and
  *                    fuses smaller problems, the faster forms on MI355X at the sizes
@@ -297,7 +301,8 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
 
 /* Arithmetic of one contraction Y = K Psi: dense_flops = 2 Q^2 C; tile_flops =
  * 2 C times the number of K entries in the blocks the kernel multiplies (banded
- * step: the runs it multiplies, see asn_contraction_nonzero).  K is
+ * step: the runs it multiplies, see asn_contraction_nonzero; in BF16 / FP16 every
+ * coupled pair's whole n_azim x n_azim block).  K is
  * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
  * sparse matrix), so blocks whose entries are all zero in the stored operand type
  * are skipped: 128-row x 32-column tiles for BF16/FP16, and for FP32 the 16-row x

@@ -83,3 +83,12 @@ def test_banded_kernel_instance_follows_the_row_width():
     wide = types.SimpleNamespace(cells=1024 * 4, q=512, nx=1024, ny=4, n_azim=32)
     assert bench.dominant_kernel(res, narrow, "f32")[0] == "banded_euler_kernel<32, false>"
     assert bench.dominant_kernel(res, wide, "f32")[0] == "banded_euler_kernel<32, true>"
+
+
+def test_banded_reduced_precision_kernel_named_by_family():
+    spec = types.SimpleNamespace(cells=1024 * 1024, q=2048, nx=1024, ny=1024, n_azim=64)
+    res = _res("banded", {"contraction": 10.7}, 1.5e11, 8.8e12, 2 * 2048.0 ** 2 * 1024 ** 2)
+    r = bench.roofline(res, spec, "bf16")
+    assert r["kernel"] == "banded_lp_kernel<64, 1, R>"
+    assert r["compute_peak_TFLOPs"] == 2500.0
+    assert r["frac"] == pytest.approx(8 * spec.cells * spec.q / 10.7e-3 / 1e9 / 8000.0)

@@ -2594,7 +2594,9 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
             const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
             const float r = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
             const float nv = in ? r : 0.f;
-            store_plane_nt(nv, ro, off0 + (uint32_t)o * pb);
+            // a wave writes half of each 128-byte line, a sibling wave the other half: the
+            // L2 joins them (non-temporal stores wrote 1.4x the bytes)
+            store_plane(nv, ro, off0 + (uint32_t)o * pb);
             ph += (double)nv;
             yas += in ? ya : 0.f;
             colsum += in ? col : 0.f;

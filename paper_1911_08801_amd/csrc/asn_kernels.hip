@@ -2592,14 +2592,15 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
             const float dev = vh - ihv;
             const float ya = s_out * acc[o] + ah.rq * dev;
             const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
-            const float r = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
-            const float nv = in ? r : 0.f;
+            // a padding cell (not in) has psi^ = delta = iso^ = 0, zero coefficients, zero
+            // operands and ghosts: its update is 0 without a select
+            const float nv = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
             // a wave writes half of each 128-byte line, a sibling wave the other half: the
             // L2 joins them (non-temporal stores wrote 1.4x the bytes)
             store_plane(nv, ro, off0 + (uint32_t)o * pb);
             ph += (double)nv;
-            yas += in ? ya : 0.f;
-            colsum += in ? col : 0.f;
+            yas += ya;
+            colsum += col;
             mx = fmaxf(mx, fabsf(nv));
             if (wedge) ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
         }

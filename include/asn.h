@@ -109,8 +109,8 @@ enum { ASN_DT_STREAMING = 0, ASN_DT_STIFF = 1 };
  *                    n_azim in {8, 16, ..., 64}.  BF16 / FP16: each coupled pair's
  *                    n_azim x n_azim circulant block of the rounded K on the matrix
  *                    cores, the update as ASN_FORM_FUSED (the same rounding recipe and
- *                    pending per-cell correction), n_azim 32 or 64.  Needs levels at most
- *                    3 apart coupled (BF16 at 64 azimuths: 2) and the stored K exactly
+ *                    pending per-cell correction), n_azim 32, 48 or 64.  Needs levels at
+ *                    most 3 apart coupled (BF16 at 48 or 64 azimuths: 2) and the stored K exactly
  *                    circulant (checked at asn_create; ASN_E_UNSUPPORTED otherwise).
  * ASN_FORM_AUTO:     the banded form where it applies; else BF16/FP16 fuse, and FP32
  *                    runs separate kernels from 2^25 cell-ordinates (nx <= 4088) and

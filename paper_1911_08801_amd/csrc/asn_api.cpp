@@ -478,7 +478,7 @@ asn_status asn_workspace_size(const asn_grid* grid, const asn_quadrature* quad,
     if (form == ASN_FORM_BANDED) {
         if (!band_candidate(dtype, scheme, form, quad, (int64_t)grid->nx * grid->ny))
             return fail(ASN_E_UNSUPPORTED, "ASN_FORM_BANDED needs forward Euler on a product set "
-                                           "with n_azim in {8, 16, ..., 64} (FP32) or {32, 64} "
+                                           "with n_azim in {8, 16, ..., 64} (FP32) or {32, 48, 64} "
                                            "(BF16, FP16)");
         *bytes = make_layout(grid->nx, grid->ny, Q, dtype, scheme, false, quad->n_polar,
                              quad->n_azim).total;
@@ -618,9 +618,9 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
         delete p;
         return fail(ASN_E_UNSUPPORTED,
                     "ASN_FORM_BANDED needs forward Euler on a product set with n_azim in "
-                    "{8, 16, ..., 64} (FP32) or {32, 64} (BF16, FP16), n_azim * cells below 2^29, "
-                    "and a stored K that couples polar levels at most 3 apart (BF16 at 64 "
-                    "azimuths: 2) and is circulant along the azimuth");
+                    "{8, 16, ..., 64} (FP32) or {32, 48, 64} (BF16, FP16), n_azim * cells below 2^29, "
+                    "and a stored K that couples polar levels at most 3 apart (BF16 at 48 or "
+                    "64 azimuths: 2) and is circulant along the azimuth");
     }
     if (banded) {
         p->band_levels = bf.levels;

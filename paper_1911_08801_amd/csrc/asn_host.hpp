@@ -62,7 +62,8 @@ bool band_form(int levels, int azim, const float* K32, int max_reach, int narrow
 // c((a' - a) mod azim) sliced as 16 output x 32 input azimuths at the offsets 16 f,
 // f = 0 .. azim / 16 - 1 (slice f: rows m, columns k hold c((16 f + k - m) mod azim)),
 // each as 64 lanes x 8 values (lane l: row l % 16, columns 8 (l / 16) .. + 7), appended
-// to `out` as operand bits.  azim 32 or 64.
+// to `out` as operand bits.  azim 32, 48 or 64 (48: columns past the last azimuth meet
+// zero operands in the kernel).
 void band_lp_fragments(const BandForm& bf, int level, int pair, int dtype,
                        std::vector<uint16_t>& out);
 // The run of a pair code: first offset and length.

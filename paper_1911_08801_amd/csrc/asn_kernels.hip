@@ -2308,7 +2308,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 
 // ---------------------------------------------------------------------------
 // 6. Banded reduced-precision step (BF16 / FP16 operands, FP32 accumulate) on product
-//    sets of 32 or 64 azimuths.  As in the fused reduced-precision form the state is
+//    sets of 32, 48 or 64 azimuths.  As in the fused reduced-precision form the state is
 //    stored without its pending per-cell particle correction delta (isotropic, so it
 //    drops out of the rounded deviation), and only the anisotropic part is rounded:
 //      x = T((psi^ - iso^) 2^(E - e_b))  (BF16: hi + lo),
@@ -2338,7 +2338,7 @@ __device__ __forceinline__ float dpp_from_right(float v) {  // lane l gets lane 
 
 template <int A, int DT, int R>
 __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs B) {
-    constexpr int MT = A / 16, NT = kBandLpCells / 16, KS = A / 32, TERMS = DT == 1 ? 2 : 1;
+    constexpr int MT = A / 16, NT = kBandLpCells / 16, KS = band_lp_ksteps(A), TERMS = DT == 1 ? 2 : 1;
     constexpr int NW = MT * NT, T = NW * 64;
     constexpr int XS = band_lp_row(A);        // 16-bit elements per cell row
     constexpr int NS = 2 * R + 2, NE = R + 2, NP = 2 * R + 1;
@@ -2508,6 +2508,14 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         ah.w = qk[q0].w;
     };
 
+    // n_az not a multiple of 32: the last k-step reads azimuths past n_az, which the ring
+    // holds at zero (the A operands' wrapped values there multiply zeros)
+    if constexpr (A % 32 != 0) {
+        uint4* z = reinterpret_cast<uint4*>(xr);
+        constexpr int NZ = NS * TERMS * XSLOT * 2 / 16;
+        for (int t = tid; t < NZ; t += T) z[t] = make_uint4(0u, 0u, 0u, 0u);
+        lds_barrier();
+    }
     // prologue: levels 0 .. R into the ring and the register queue, level 0's operands
     float fifo[R + 1][4];
     {
@@ -2704,6 +2712,8 @@ static hipError_t launch_banded_lp(const BatchArgs& b, int blocks, int az, int d
                                    hipStream_t s, int reach) {
     if (az == 32 && dtype == 1) return launch_banded_lp_a<32, 1>(b, blocks, lds, s, reach);
     if (az == 32 && dtype == 2) return launch_banded_lp_a<32, 2>(b, blocks, lds, s, reach);
+    if (az == 48 && dtype == 1) return launch_banded_lp_a<48, 1>(b, blocks, lds, s, reach);
+    if (az == 48 && dtype == 2) return launch_banded_lp_a<48, 2>(b, blocks, lds, s, reach);
     if (az == 64 && dtype == 1) return launch_banded_lp_a<64, 1>(b, blocks, lds, s, reach);
     if (az == 64 && dtype == 2) return launch_banded_lp_a<64, 2>(b, blocks, lds, s, reach);
     return hipErrorInvalidValue;
@@ -2726,6 +2736,8 @@ static hipError_t prepare_banded_lp_a(int reach, size_t lds) {
 hipError_t prepare_banded_lp(int band_az, int dtype, int reach, size_t band_lds) {
     if (band_az == 32 && dtype == 1) return prepare_banded_lp_a<32, 1>(reach, band_lds);
     if (band_az == 32 && dtype == 2) return prepare_banded_lp_a<32, 2>(reach, band_lds);
+    if (band_az == 48 && dtype == 1) return prepare_banded_lp_a<48, 1>(reach, band_lds);
+    if (band_az == 48 && dtype == 2) return prepare_banded_lp_a<48, 2>(reach, band_lds);
     if (band_az == 64 && dtype == 1) return prepare_banded_lp_a<64, 1>(reach, band_lds);
     if (band_az == 64 && dtype == 2) return prepare_banded_lp_a<64, 2>(reach, band_lds);
     return hipErrorInvalidValue;

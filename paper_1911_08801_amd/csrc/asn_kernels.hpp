@@ -107,17 +107,20 @@ inline size_t band_lds_bytes(int az, int reach, int cmax) {
 }
 
 // Banded reduced-precision step (BF16 / FP16 operands on MFMA 16x16x32, FP32 accumulate)
-// for product sets of 32 or 64 azimuths: a block owns kBandLpCells consecutive cells and
+// for product sets of 32, 48 or 64 azimuths: a block owns kBandLpCells consecutive cells and
 // every ordinate; wave (m, n) produces azimuths 16 m .. 16 m + 15 of cells 16 n .. 16 n + 15.
 // Per level pair (i, j) the circulant block of the stored K is multiplied as A operands
 // of 16 x 32 (one per 16-azimuth offset, built on the host: band_lp_fragments) with the
 // quantised partner level as B operand.
 constexpr int kBandLpCells = 64;
 constexpr int kBandLpMaxReach = 3;
-inline bool band_lp_azimuths_supported(int az) { return az == 32 || az == 64; }
+inline bool band_lp_azimuths_supported(int az) { return az == 32 || az == 48 || az == 64; }
+// k-steps of 32 azimuths a level pair takes (48 azimuths: two, the second half-padded)
+__host__ __device__ constexpr int band_lp_ksteps(int az) { return (az + 31) / 32; }
 __host__ __device__ constexpr int band_lp_threads(int az) { return (az / 16) * (kBandLpCells / 16) * 64; }
-// 16-bit elements per cell row of the quantised-level ring (16-byte reads conflict-free)
-__host__ __device__ constexpr int band_lp_row(int az) { return az + 8; }
+// 16-bit elements per cell row of the quantised-level ring: every k-step's azimuths (the
+// padding past n_az held at zero) and 8 more (16-byte reads conflict-free)
+__host__ __device__ constexpr int band_lp_row(int az) { return 32 * band_lp_ksteps(az) + 8; }
 // Dynamic LDS of a banded reduced-precision block: the ring of 2 reach + 2 quantised
 // levels (two operand terms for BF16), two buffers of a level's A operands (at most
 // 2 reach + 1 pairs, n_az / 16 fragments of 1 KiB each), the ring of tile-edge values

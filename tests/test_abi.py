@@ -292,14 +292,14 @@ def test_banded_form_size_and_scheme_limits():
     # BF16 / FP16 at an azimuth count without a reduced-precision instance, is refused;
     # the automatic form falls back to the MFMA forms without error
     q = asn.asn_quadrature(32, 64, 0, None, None, 0)
-    q48 = asn.asn_quadrature(24, 48, 0, None, None, 0)
+    q40 = asn.asn_quadrature(20, 40, 0, None, None, 0)
     small = asn.make_grid(1024, 1024, -1.5, 1.5, -1.5, 1.5)
     big = asn.make_grid(2900, 2900, -1.5, 1.5, -1.5, 1.5)      # 64 x P x 4 >= 2^31
     assert asn.asn_workspace_size(small, q, asn.make_options(form="banded")) > 0
     for dt in ("bf16", "f16"):
         assert asn.asn_workspace_size(small, q, asn.make_options(form="banded", dtype=dt)) > 0
-    for grid, quad, opts in ((big, q, dict(form="banded")), (small, q48, dict(form="banded", dtype="bf16")),
-                             (small, q48, dict(form="banded", dtype="f16")),
+    for grid, quad, opts in ((big, q, dict(form="banded")), (small, q40, dict(form="banded", dtype="bf16")),
+                             (small, q40, dict(form="banded", dtype="f16")),
                              (small, q, dict(form="banded", scheme="heun"))):
         with pytest.raises(asn.AsnError) as e:
             asn.asn_workspace_size(grid, quad, asn.make_options(**opts))

@@ -21,9 +21,10 @@ if not torch.cuda.is_available():
 from paper_1911_08801_amd import asn  # noqa: E402
 
 GRIDS = [(1, 1), (9, 1), (1, 7), (33, 2), (65, 17), (130, 67), (200, 3)]
-# (n_polar, n_azim, beta): both azimuth counts; reach of the BF16 / FP16 K: 1/0, 2/1,
-# 3/2, 0/0, 2/1, 1/1
-QUADS = [(4, 32, 4.5), (16, 32, 4.5), (16, 32, 12.0), (2, 64, 4.5), (16, 64, 9.0), (12, 64, 6.0)]
+# (n_polar, n_azim, beta): every azimuth count; reach of the BF16 / FP16 K: 1/0, 2/1,
+# 3/2, 0/0, 2/1, 1/1, 2/1, -
+QUADS = [(4, 32, 4.5), (16, 32, 4.5), (16, 32, 12.0), (2, 64, 4.5), (16, 64, 9.0), (12, 64, 6.0),
+         (24, 48, 4.5), (4, 48, 4.5)]
 
 
 def _emulated(spec, n, psi0, dtype, block=o.SCALE_BLOCK):

@@ -146,10 +146,10 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
     L.off_band = take(L.banded ? (size_t)(band_levels + 1) * 32 : 0);
     L.off_brange = take(L.banded ? (size_t)band_levels * 8 : 0);    // coefficient ranges, int2
     L.off_bcoef = take(L.banded && !L.lowp ? band_coef_capacity(band_levels, band_azim) * 4 : 0);
-    // reduced-precision banded step: A operands, per level at most 2 kBandMaxReach + 1 pairs
+    // reduced-precision banded step: A operands, per level 2 kBandLpMaxReach + 1 pair slots
     // of n_az / 16 fragments of 1 KiB, and one zero fragment after them
     L.off_bfrag = take(L.banded && L.lowp
-                           ? ((size_t)band_levels * (2 * asn::kBandMaxReach + 1) * (band_azim / 16) + 1) * 1024
+                           ? ((size_t)band_levels * (2 * asn::kBandLpMaxReach + 1) * (band_azim / 16) + 1) * 1024
                            : 0);
     L.off_qi = take((size_t)Q * sizeof(QInfo));
     L.off_coef = take(plane * 16);
@@ -764,21 +764,25 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                 ddesc[(size_t)i * 8 + 1 + t] =
                     asn::band_device_code(bf.desc[(size_t)i * 8 + 1 + t], i, bf.reach, bf.azim);
     } else if (banded) {
-        // per level {pairs, first fragment, the pairs' level offsets k (4 bits each), 0};
-        // per pair n_az / 16 A operands of MFMA 16x16x32 (band_lp_fragments)
+        // per level {pairs, first fragment, the level offsets k of its pair slots (4 bits
+        // each), 0}; 2 kBandLpMaxReach + 1 pair slots of n_az / 16 A operands of MFMA
+        // 16x16x32 (band_lp_fragments), the coupled pairs first, then zero operands whose
+        // partner is the level itself (the kernel runs the first 2 reach + 1 slots of its
+        // launch's largest reach, with no count)
+        constexpr int slots = 2 * asn::kBandLpMaxReach + 1;
+        const int per_slot = bf.azim / 16;
         ddesc.assign((size_t)bf.levels * 8, 0u);
-        int fcount = 0;
         for (int i = 0; i < bf.levels; ++i) {
             const int n = (int)bf.desc[(size_t)i * 8];
             uint32_t kc = 0;
-            for (int t = 0; t < n; ++t) kc |= ((bf.desc[(size_t)i * 8 + 1 + t] >> 8) & 7u) << (4 * t);
+            for (int t = 0; t < slots; ++t)
+                kc |= (t < n ? ((bf.desc[(size_t)i * 8 + 1 + t] >> 8) & 7u) : (uint32_t)bf.reach)
+                      << (4 * t);
             ddesc[(size_t)i * 8] = (uint32_t)n;
-            ddesc[(size_t)i * 8 + 1] = (uint32_t)fcount;
+            ddesc[(size_t)i * 8 + 1] = (uint32_t)(i * slots * per_slot);
             ddesc[(size_t)i * 8 + 2] = kc;
-            for (int t = 0; t < n; ++t) {
-                asn::band_lp_fragments(bf, i, t, p->dtype, bfrag);
-                fcount += bf.azim / 16;
-            }
+            for (int t = 0; t < n; ++t) asn::band_lp_fragments(bf, i, t, p->dtype, bfrag);
+            bfrag.resize((size_t)(i + 1) * slots * per_slot * 512, 0);
         }
     }
     auto bail = [&](asn_status st) {

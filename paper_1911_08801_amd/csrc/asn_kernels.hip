@@ -2341,9 +2341,9 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     constexpr int MT = A / 16, NT = kBandLpCells / 16, KS = band_lp_ksteps(A), TERMS = DT == 1 ? 2 : 1;
     constexpr int NW = MT * NT, T = NW * 64;
     constexpr int XS = band_lp_row(A);        // 16-bit elements per cell row
-    constexpr int NS = 2 * R + 2, NE = R + 2, NP = 2 * R + 1;
+    constexpr int NS = 2 * R + 2, NE = R + 3, NP = 2 * R + 1;
     constexpr int XSLOT = kBandLpCells * XS;  // elements per ring slot and term
-    constexpr int FR = NP * MT * 64;          // uint4 per fragment buffer
+    constexpr int FR = NP * MT * 64;          // uint4 per fragment buffer (NP pair slots)
     constexpr int CPT = (FR + T - 1) / T;     // fragment uint4 staged per thread
     extern __shared__ __attribute__((aligned(16))) char lds_raw[];
     uint16_t* xr = reinterpret_cast<uint16_t*>(lds_raw);
@@ -2393,8 +2393,9 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     const uint32_t lvl_bytes = (uint32_t)(A * P * 4), pb = (uint32_t)(P * 4);
     const uint32_t off0 = 4u * (uint32_t)(a0 * P) + 4u * (uint32_t)cell;
     // the lane's four azimuths lie in one quadrant (n_az / 4 is a multiple of 4): one
-    // y-upwind cell
-    uint32_t yoff[4];
+    // y-upwind cell; its offsets yoff + o pb (from kOOB they stay past every plane: a
+    // level holds under 2^31 bytes, and 3 pb more stays below 2^32)
+    uint32_t yoff;
     float ydl;   // pending correction of the y-upwind cell
     bool tl[4], tr[4], ox[4], oy[4];
     {
@@ -2402,9 +2403,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         const int yc = (d & 4) ? cell - nx : cell + nx;
         const bool yv = in && yc >= 0 && yc < C;
         ydl = yv ? gp(a.delta)[yc] : 0.f;
-#pragma unroll
-        for (int o = 0; o < 4; ++o)
-            yoff[o] = yv ? off0 + (uint32_t)o * pb + 4u * (uint32_t)(yc - cell) : kOOB;
+        yoff = yv ? off0 + 4u * (uint32_t)(yc - cell) : kOOB;
     }
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
@@ -2416,30 +2415,29 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         ox[o] = in && (go & 3);
         oy[o] = in && (go & 12);
     }
-    // the block's halo cells: lane 0 of tile 0 reads the cell before the block, lane 15
-    // of the last tile the cell after it (the other lanes' halo offsets read 0)
-    const bool hlo = nt == 0 && cl == 0, hhi = nt == NT - 1 && cl == 15;
-    const bool hvalid = (hlo && cell > 0) || (hhi && cell + 1 < (int)P);
-    const int hcell = hlo ? cell - 1 : cell + 1;
+    // the block's halo cells, one value a lane: in tile 0 lanes 0 .. 3 of each row of 16
+    // read azimuth a0 + cl of the cell before the block, in the last tile lanes 12 .. 15
+    // azimuth a0 + cl - 12 of the cell after it (the other lanes' halo offsets read 0)
+    const bool hlo = nt == 0 && cl < 4, hhi = nt == NT - 1 && cl >= 12;
+    const int hcell = hlo ? local * kBandLpCells - 1 : local * kBandLpCells + kBandLpCells;
+    const int haz = a0 + (hlo ? cl : cl - 12);
+    const bool hvalid = (hlo || hhi) && hcell >= 0 && hcell < (int)P;
     const float hdl = (hvalid && hcell < C) ? gp(a.delta)[hcell] : 0.f;
-    uint32_t hoff[4];
-#pragma unroll
-    for (int o = 0; o < 4; ++o) hoff[o] = hvalid ? off0 + (uint32_t)o * pb + (hlo ? (uint32_t)-4 : 4u) : kOOB;
+    const uint32_t hoff = hvalid ? 4u * (uint32_t)(haz * P) + 4u * (uint32_t)hcell : kOOB;
+    const int hslot = hlo ? haz : (NT + NT - 1) * A + haz;   // its place in an edge slot
     const size_t lvl_floats = (size_t)A * (size_t)P;
     auto level_rsrc = [&](const float* base) {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, (int)lvl_bytes, kRsrcWord3);
     };
 
     struct Fill {
-        float v[4], h[4];
+        float v[4], h;
     };
     auto fetch = [&](int l, Fill& f) {
         const __amdgpu_buffer_rsrc_t r = level_rsrc(a.psi + (size_t)l * lvl_floats);
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            f.v[o] = load_plane(r, off0 + (uint32_t)o * pb);
-            f.h[o] = load_plane(r, hoff[o]);
-        }
+        for (int o = 0; o < 4; ++o) f.v[o] = load_plane(r, off0 + (uint32_t)o * pb);
+        f.h = load_plane(r, hoff);
     };
     // the lane's four azimuths of level l into the ring (rounded operand terms) and the
     // tile-edge values (true state psi^ + delta) its neighbours need
@@ -2459,39 +2457,36 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
             *reinterpret_cast<uint2*>(xs + XSLOT) = pl;
         }
         float* es = edge + (size_t)(l % NE) * 2 * NT * A;
-        if (cl == 15) {   // the left neighbour of the next tile, or the block's right halo
-            float* d = hhi ? es + (NT + NT - 1) * A + a0 : es + (nt + 1) * A + a0;
+        if (cl == 15 && nt < NT - 1) {   // the left neighbour of the next tile
+            float* d = es + (nt + 1) * A + a0;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) d[o] = hhi ? f.h[o] + hdl : f.v[o] + dv;
+            for (int o = 0; o < 4; ++o) d[o] = f.v[o] + dv;
         }
-        if (cl == 0) {    // the right neighbour of the previous tile, or the left halo
-            float* d = hlo ? es + a0 : es + (NT + nt - 1) * A + a0;
+        if (cl == 0 && nt > 0) {         // the right neighbour of the previous tile
+            float* d = es + (NT + nt - 1) * A + a0;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) d[o] = hlo ? f.h[o] + hdl : f.v[o] + dv;
+            for (int o = 0; o < 4; ++o) d[o] = f.v[o] + dv;
         }
+        if (hlo || hhi) es[hslot] = f.h + hdl;   // the block's halo
     };
-    // a level's A operands into fragment buffer l & 1 (thread t moves uint4 t, t + T, ..;
-    // at most 7 pairs of n_az / 16 fragments of 64 uint4)
-    static_assert(CPT <= 4, "at most four staged uint4 per thread");
-    auto fetch_frag = [&](int l, uint4& f0, uint4& f1, uint4& f2, uint4& f3) {
-        const uint4 d = ldesc[2 * l];
-        const int last = max((int)d.x * MT * 64 - 1, 0);
-        const ASN_G uint4* src = frag + (size_t)d.y * 64;
-        f0 = src[min(tid, last)];
-        if constexpr (CPT > 1) f1 = src[min(tid + T, last)];
-        if constexpr (CPT > 2) f2 = src[min(tid + 2 * T, last)];
-        if constexpr (CPT > 3) f3 = src[min(tid + 3 * T, last)];
+    // a level's A operands into fragment buffer l & 1 (thread t moves uint4 t and t + T).
+    // Every level holds 2 kBandLpMaxReach + 1 pair slots, the coupled pairs first; the
+    // kernel runs the first NP, those past a problem's pairs hold zero operands
+    static_assert(CPT <= 2, "at most two staged uint4 per thread");
+    auto fetch_frag = [&](int l, uint4& f0, uint4& f1) {
+        const ASN_G uint4* src = frag + (size_t)ldesc[2 * l].y * 64;
+        f0 = src[FR >= T ? tid : min(tid, FR - 1)];
+        if constexpr (CPT > 1) f1 = src[min(tid + T, FR - 1)];
     };
-    auto put_frag = [&](int l, const uint4& f0, const uint4& f1, const uint4& f2, const uint4& f3) {
-        const int cnt = (int)ldesc[2 * l].x * MT * 64;
+    auto put_frag = [&](int l, const uint4& f0, const uint4& f1) {
         uint4* dst = fr + (size_t)(l & 1) * FR;
-        if (tid < cnt) dst[tid] = f0;
-        if constexpr (CPT > 1) if (tid + T < cnt) dst[tid + T] = f1;
-        if constexpr (CPT > 2) if (tid + 2 * T < cnt) dst[tid + 2 * T] = f2;
-        if constexpr (CPT > 3) if (tid + 3 * T < cnt) dst[tid + 3 * T] = f3;
+        if (FR >= T || tid < FR) dst[tid] = f0;
+        if constexpr (CPT > 1) if (tid + T < FR) dst[tid + T] = f1;
     };
+    // the next update's inputs: the lane's own four values (from the register queue), the
+    // y-upwind values and the level's coefficients
     struct Ahead {
-        float y[4], cx[4], cy[4];
+        float v[4], y[4], cx[4], cy[4];
         float rq;
         double w;
     };
@@ -2500,7 +2495,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         const int q0 = l * A;
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
-            ah.y[o] = load_plane(r, yoff[o]);
+            ah.y[o] = load_plane(r, yoff + (uint32_t)o * pb);
             ah.cx[o] = qtab[q0 + a0 + o].cx;
             ah.cy[o] = qtab[q0 + a0 + o].cy;
         }
@@ -2516,119 +2511,216 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         for (int t = tid; t < NZ; t += T) z[t] = make_uint4(0u, 0u, 0u, 0u);
         lds_barrier();
     }
-    // prologue: levels 0 .. R into the ring and the register queue, level 0's operands
+    // The level loop runs one level behind in its update: pass i contracts level i and
+    // updates level i - 1 with the products of the pass before, two independent streams
+    // (LDS reads and MFMA; VALU, DPP and stores) interleaved in one schedule.  The edge
+    // ring is reach + 3 levels deep: a level's edges stay until its lagging update has
+    // read them.
+    // the lane's own unrounded values of the levels in the ring ahead of the update
+    // (levels i + 1 .. i + R + 1 at the end of pass i)
     float fifo[R + 1][4];
-    {
+    {   // prologue: levels 0 .. R into the ring and the queue, level 0's operands
         Fill f;
 #pragma unroll
         for (int l = 0; l <= R; ++l) {
-            const int lc = min(l, L - 1);
-            fetch(lc, f);
+            fetch(min(l, L - 1), f);
             if (l < L) put(l, f);
 #pragma unroll
             for (int o = 0; o < 4; ++o) fifo[l][o] = f.v[o];
         }
-        uint4 g0, g1, g2, g3;
-        fetch_frag(0, g0, g1, g2, g3);
-        put_frag(0, g0, g1, g2, g3);
+        uint4 g0, g1;
+        fetch_frag(0, g0, g1);
+        put_frag(0, g0, g1);
     }
     Fill pre;
     fetch(min(R + 1, L - 1), pre);
-    uint4 fp0, fp1, fp2, fp3;
-    fetch_frag(min(1, L - 1), fp0, fp1, fp2, fp3);
+    uint4 fp0, fp1;
+    fetch_frag(min(1, L - 1), fp0, fp1);
     Ahead ah;
-    fetch_ahead(0, ah);
     lds_barrier();
 
     double phacc = 0.0, ypacc = 0.0, defect = 0.0, outflow = 0.0;
     float mx = 0.f;
     const int mtk0 = ((0 - mt) % MT + MT) % MT;   // fragment of k-step 0: offset (32 kt - 16 mt) mod A
-    for (int i = 0; i < L; ++i) {
-        // level i + 1's A operands (its buffer's last readers passed the barrier)
-        if (i + 1 < L) put_frag(i + 1, fp0, fp1, fp2, fp3);
-        fetch_frag(min(i + 2, L - 1), fp0, fp1, fp2, fp3);
-        // contraction: every coupled level pair, k-steps of 32 azimuths, operand terms
-        const uint4 dsc = ldesc[2 * i];
-        const int n_pairs = (int)dsc.x;
-        uint32_t kcodes = dsc.z;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        const uint4* fl = fr + (size_t)(i & 1) * FR + lane;
+    const uint16_t* xl = xr + cc * XS + 8 * g;
+    // level i's products: every pair slot, k-steps of 32 azimuths, operand terms
+    struct Ops {
+        uint4 a[KS], b[KS];
+        const uint16_t* xs;
+    };
+    struct Pass {
+        uint32_t kcodes;
+        int sb;
+        const uint4* fl;
+    };
+    auto pass_of = [&](int i) {
+        Pass ps;
+        ps.kcodes = ldesc[2 * i].z;
+        ps.fl = fr + (size_t)(i & 1) * FR + lane;
         // ring slot of level i - RE (k = 0); a pair's partner i - RE + k sits k slots on
-        const int sb = ((i - RE) % NS + NS) % NS;
-        const uint16_t* xl = xr + cc * XS + 8 * g;
-        for (int p = 0; p < n_pairs; ++p) {
-            int sl = sb + (int)(kcodes & 15u);
-            sl = sl >= NS ? sl - NS : sl;
-            kcodes >>= 4;
-            const uint16_t* xs = xl + (size_t)sl * TERMS * XSLOT;
-            uint4 av[KS];
+        ps.sb = ((i - RE) % NS + NS) % NS;
+        return ps;
+    };
+    // a pair's A operands and its first operand term; the second term (BF16) is read
+    // into the same registers after the first term's products
+    auto load_pair = [&](const Pass& ps, int p, Ops& op) {
+        int sl = ps.sb + (int)((ps.kcodes >> (4 * p)) & 15u);
+        sl = sl >= NS ? sl - NS : sl;
+        op.xs = xl + (size_t)sl * TERMS * XSLOT;
 #pragma unroll
-            for (int kt = 0; kt < KS; ++kt) av[kt] = fl[(p * MT + (mtk0 + 2 * kt) % MT) * 64];
+        for (int kt = 0; kt < KS; ++kt) op.a[kt] = ps.fl[(p * MT + (mtk0 + 2 * kt) % MT) * 64];
 #pragma unroll
-            for (int t = 0; t < TERMS; ++t) {
-                uint4 bv[KS];
+        for (int kt = 0; kt < KS; ++kt) op.b[kt] = *reinterpret_cast<const uint4*>(op.xs + 32 * kt);
+    };
+    auto load_term = [&](int t, Ops& op) {
 #pragma unroll
-                for (int kt = 0; kt < KS; ++kt)
-                    bv[kt] = *reinterpret_cast<const uint4*>(xs + t * XSLOT + 32 * kt);
+        for (int kt = 0; kt < KS; ++kt)
+            op.b[kt] = *reinterpret_cast<const uint4*>(op.xs + t * XSLOT + 32 * kt);
+    };
+    auto mul_term = [&](const Ops& op, f32x4& acc) {
 #pragma unroll
-                for (int kt = 0; kt < KS; ++kt) acc = mfma_lp<DT>(av[kt], bv[kt], acc);
-            }
+        for (int kt = 0; kt < KS; ++kt) acc = mfma_lp<DT>(op.a[kt], op.b[kt], acc);
+    };
+    auto mul_pair = [&](Ops& op, f32x4& acc) {   // (no overlap with other work)
+        mul_term(op, acc);
+#pragma unroll
+        for (int t = 1; t < TERMS; ++t) {
+            load_term(t, op);
+            mul_term(op, acc);
         }
-        // the update of the lane's four outputs (as the fused reduced-precision form):
-        //   v = psi^ + delta, dev = psi^ - iso^, Y^ - iso^ = s_out acc + r_q dev
-        //   col = gs ((iso^ + Y^ - iso^) - psi^) + bs (iso^ - psi^)
-        //   new = v - cx (v - ux) - cy (v - uy) - aa v + col + ss
-        const float* es = edge + (size_t)(i % NE) * 2 * NT * A;
-        const __amdgpu_buffer_rsrc_t ro = level_rsrc(a.psi_new + (size_t)i * lvl_floats);
-        float colsum = 0.f, ob = 0.f, yas = 0.f;
-        double ph = 0.0;
-        // the tile-edge values of the lane's four azimuths (used by lanes 0 and 15 of a row)
-        const float4 eL = *reinterpret_cast<const float4*>(es + nt * A + a0);
-        const float4 eR = *reinterpret_cast<const float4*>(es + (NT + nt) * A + a0);
-        const float eLv[4] = {eL.x, eL.y, eL.z, eL.w}, eRv[4] = {eR.x, eR.y, eR.z, eR.w};
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const float vh = fifo[0][o];
-            const float v = vh + dv;
-            // the row shifts run in every lane (a lane whose neighbour is inactive would
-            // read 0), then the row's edge lanes take the edge ring's value
-            const float dl = dpp_from_left(v), dr = dpp_from_right(v);
-            const float left = cl == 0 ? eLv[o] : dl;
-            const float right = cl == 15 ? eRv[o] : dr;
-            const float ux = tl[o] ? left : (tr[o] ? right : 0.f);
-            const float uy = ah.y[o] + ydl;
-            const float dev = vh - ihv;
-            const float ya = s_out * acc[o] + ah.rq * dev;
-            const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
-            // a padding cell (not in) has psi^ = delta = iso^ = 0, zero coefficients, zero
-            // operands and ghosts: its update is 0 without a select
-            const float nv = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
-            // a wave writes half of each 128-byte line, a sibling wave the other half: the
-            // L2 joins them (non-temporal stores wrote 1.4x the bytes)
-            store_plane(nv, ro, off0 + (uint32_t)o * pb);
-            ph += (double)nv;
-            yas += ya;
-            colsum += col;
-            mx = fmaxf(mx, fabsf(nv));
-            if (wedge) ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
-        }
-        phacc += ah.w * ph;
+    };
+    // the update of the lane's four outputs of level j (as the fused reduced-precision form):
+    //   v = psi^ + delta, dev = psi^ - iso^, Y^ - iso^ = s_out acc + r_q dev
+    //   col = gs ((iso^ + Y^ - iso^) - psi^) + bs (iso^ - psi^)
+    //   new = v - cx (v - ux) - cy (v - uy) - aa v + col + ss
+    // (the look-ahead values hold level j)
+    struct Upd {
+        __amdgpu_buffer_rsrc_t ro;
+        const float* es;   // the level's edge slot at the lane's tile and azimuths
+        float colsum, yas;
+        double ph;
+    };
+    auto upd_begin = [&](int j, Upd& u) {
+        u.es = edge + (size_t)(j % NE) * 2 * NT * A + nt * A + a0;
+        u.ro = level_rsrc(a.psi_new + (size_t)j * lvl_floats);
+        u.colsum = 0.f;
+        u.yas = 0.f;
+        u.ph = 0.0;
+    };
+    auto upd_out = [&](int o, const f32x4& acc, Upd& u) {
+        const float vh = ah.v[o];
+        const float v = vh + dv;
+        // the row shifts run in every lane (a lane whose neighbour is inactive would read
+        // 0), then the row's edge lanes (0 and 15) take the edge ring's value
+        const float dl = dpp_from_left(v), dr = dpp_from_right(v);
+        const float left = cl == 0 ? u.es[o] : dl;
+        const float right = cl == 15 ? u.es[NT * A + o] : dr;
+        const float ux = tl[o] ? left : (tr[o] ? right : 0.f);
+        const float uy = ah.y[o] + ydl;
+        const float dev = vh - ihv;
+        const float ya = s_out * acc[o] + ah.rq * dev;
+        const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
+        // a padding cell (not in) has psi^ = delta = iso^ = 0, zero coefficients, zero
+        // operands and ghosts: its update is 0 without a select
+        const float nv = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
+        // a wave writes half of each 128-byte line, a sibling wave the other half: the L2
+        // joins them (non-temporal stores wrote 1.4x the bytes)
+        store_plane(nv, u.ro, off0 + (uint32_t)o * pb);
+        u.ph += (double)nv;
+        u.yas += ya;
+        u.colsum += col;
+        mx = fmaxf(mx, fabsf(nv));
+    };
+    auto upd_end = [&](const Upd& u) {
+        phacc += ah.w * u.ph;
         // sum over the four outputs of Y^ = iso^ + delta + (Y^ - iso^); the deviations,
         // small against iso^, summed in FP32
-        ypacc += ah.w * ((in ? 4.0 * (double)(ihv + dv) : 0.0) + (double)yas);
-        defect += ah.w * (double)colsum;
-        outflow += ah.w * (double)ob;
-        // the queue advances; level i + R + 1 goes into the ring slot level i - R - 1 held
+        ypacc += ah.w * ((in ? 4.0 * (double)(ihv + dv) : 0.0) + (double)u.yas);
+        defect += ah.w * (double)u.colsum;
+    };
+    // the outflow of the level just updated (the look-ahead values still hold it)
+    auto outflow_of = [&]() {
+        if (wedge) {
+            float ob = 0.f;
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-#pragma unroll
-            for (int o = 0; o < 4; ++o) fifo[k][o] = fifo[k + 1][o];
+            for (int o = 0; o < 4; ++o) {
+                const float v = ah.v[o] + dv;
+                ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
+            }
+            outflow += ah.w * (double)ob;
+        }
+    };
+    // the end of pass i: level i + R + 1 goes into the ring slot level i - R - 1 held and
+    // the queue, level i leaves the queue for the next pass's update, loads for the next
+    // passes
+    auto advance = [&](int i) {
         if (i + R + 1 < L) put(i + R + 1, pre);
+        fetch_ahead(i, ah);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) ah.v[o] = fifo[0][o];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) fifo[q][o] = fifo[q + 1][o];
 #pragma unroll
         for (int o = 0; o < 4; ++o) fifo[R][o] = pre.v[o];
         fetch(min(i + R + 2, L - 1), pre);
-        fetch_ahead(min(i + 1, L - 1), ah);
         lds_barrier();
+    };
+
+    f32x4 accp = {0.f, 0.f, 0.f, 0.f};
+    {   // pass 0: products only
+        if (1 < L) put_frag(1, fp0, fp1);
+        fetch_frag(min(2, L - 1), fp0, fp1);
+        const Pass ps = pass_of(0);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            Ops op;
+            load_pair(ps, p, op);
+            mul_pair(op, accp);
+        }
+        advance(0);
+    }
+    for (int i = 1; i < L; ++i) {
+        // level i + 1's A operands (its buffer's last readers passed the barrier)
+        if (i + 1 < L) put_frag(i + 1, fp0, fp1);
+        fetch_frag(min(i + 2, L - 1), fp0, fp1);
+        // pass i in chunks the scheduler may not merge: chunk p reads pair p's operands,
+        // updates output p of level i - 1 while they arrive, then multiplies pair p (the
+        // MFMAs run on while the next chunk issues)
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const Pass ps = pass_of(i);
+        Upd u;
+        upd_begin(i - 1, u);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            __builtin_amdgcn_sched_barrier(0);
+            Ops op;
+            load_pair(ps, p, op);
+            if (p < 4) upd_out(p, accp, u);
+            mul_term(op, acc);
+#pragma unroll
+            for (int t = 1; t < TERMS; ++t) {
+                __builtin_amdgcn_sched_barrier(0);
+                load_term(t, op);
+                mul_term(op, acc);
+            }
+        }
+#pragma unroll
+        for (int o = NP; o < 4; ++o) upd_out(o, accp, u);
+        __builtin_amdgcn_sched_barrier(0);
+        upd_end(u);
+        accp = acc;
+        outflow_of();
+        advance(i);
+    }
+    {
+        Upd u;
+        upd_begin(L - 1, u);
+#pragma unroll
+        for (int o = 0; o < 4; ++o) upd_out(o, accp, u);
+        upd_end(u);
+        outflow_of();
     }
 
     // per cell Phi^ and sum_q w_q Y^: the (n_az / 4) lane groups' partials in a fixed order

@@ -146,10 +146,13 @@ Layout make_layout(int nx, int ny, int Q, int dtype, int scheme, bool fused, int
     L.off_band = take(L.banded ? (size_t)(band_levels + 1) * 32 : 0);
     L.off_brange = take(L.banded ? (size_t)band_levels * 8 : 0);    // coefficient ranges, int2
     L.off_bcoef = take(L.banded && !L.lowp ? band_coef_capacity(band_levels, band_azim) * 4 : 0);
-    // reduced-precision banded step: A operands, per level 2 kBandLpMaxReach + 1 pair slots
-    // of n_az / 16 fragments of 1 KiB, and one zero fragment after them
+    // reduced-precision banded step: per level and one more, 2 kBandLpMaxReach + 1 pair
+    // slots of n_az / 16 A operands of 1 KiB and a (cx, cy) table of n_az float pairs, and
+    // 1 KiB after them
     L.off_bfrag = take(L.banded && L.lowp
-                           ? ((size_t)band_levels * (2 * asn::kBandLpMaxReach + 1) * (band_azim / 16) + 1) * 1024
+                           ? (size_t)(band_levels + 1) *
+                                     ((2 * asn::kBandLpMaxReach + 1) * (band_azim / 16) * 1024 + band_azim * 8) +
+                                 1024
                            : 0);
     L.off_qi = take((size_t)Q * sizeof(QInfo));
     L.off_coef = take(plane * 16);
@@ -764,25 +767,38 @@ asn_status asn_create(const asn_grid* grid, const asn_quadrature* quad, const fl
                 ddesc[(size_t)i * 8 + 1 + t] =
                     asn::band_device_code(bf.desc[(size_t)i * 8 + 1 + t], i, bf.reach, bf.azim);
     } else if (banded) {
-        // per level {pairs, first fragment, the level offsets k of its pair slots (4 bits
-        // each), 0}; 2 kBandLpMaxReach + 1 pair slots of n_az / 16 A operands of MFMA
-        // 16x16x32 (band_lp_fragments), the coupled pairs first, then zero operands whose
-        // partner is the level itself (the kernel runs the first 2 reach + 1 slots of its
-        // launch's largest reach, with no count)
+        // per level and one more {pairs, first uint4 of its block, the level offsets k of its
+        // pair slots (4 bits each), 0}.  Block l: 2 kBandLpMaxReach + 1 pair slots of
+        // n_az / 16 A operands of MFMA 16x16x32 (band_lp_fragments), the coupled pairs of
+        // level l first, then zero operands whose partner is the level itself (the kernel
+        // runs the first 2 reach + 1 slots of its launch's largest reach, with no count);
+        // then (cx, cy) of level l - 1's ordinates as FP32 pairs (its update runs a level
+        // behind); block n_lev holds only the last level's table
         constexpr int slots = 2 * asn::kBandLpMaxReach + 1;
         const int per_slot = bf.azim / 16;
-        ddesc.assign((size_t)bf.levels * 8, 0u);
-        for (int i = 0; i < bf.levels; ++i) {
-            const int n = (int)bf.desc[(size_t)i * 8];
+        const size_t block = (size_t)slots * per_slot * 512 + (size_t)bf.azim * 4;   // 16-bit words
+        ddesc.assign((size_t)(bf.levels + 1) * 8, 0u);
+        for (int i = 0; i <= bf.levels; ++i) {
+            const int n = i < bf.levels ? (int)bf.desc[(size_t)i * 8] : 0;
             uint32_t kc = 0;
             for (int t = 0; t < slots; ++t)
                 kc |= (t < n ? ((bf.desc[(size_t)i * 8 + 1 + t] >> 8) & 7u) : (uint32_t)bf.reach)
                       << (4 * t);
             ddesc[(size_t)i * 8] = (uint32_t)n;
-            ddesc[(size_t)i * 8 + 1] = (uint32_t)(i * slots * per_slot);
+            ddesc[(size_t)i * 8 + 1] = (uint32_t)(i * block / 8);
             ddesc[(size_t)i * 8 + 2] = kc;
             for (int t = 0; t < n; ++t) asn::band_lp_fragments(bf, i, t, p->dtype, bfrag);
-            bfrag.resize((size_t)(i + 1) * slots * per_slot * 512, 0);
+            bfrag.resize((size_t)i * block + (size_t)slots * per_slot * 512, 0);
+            for (int az = 0; az < bf.azim; ++az) {
+                float c[2] = {0.f, 0.f};
+                if (i > 0) {
+                    c[0] = qi[(size_t)(i - 1) * bf.azim + az].cx;
+                    c[1] = qi[(size_t)(i - 1) * bf.azim + az].cy;
+                }
+                uint16_t w[4];
+                std::memcpy(w, c, sizeof(c));
+                bfrag.insert(bfrag.end(), w, w + 4);
+            }
         }
     }
     auto bail = [&](asn_status st) {

@@ -2343,12 +2343,14 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     constexpr int XS = band_lp_row(A);        // 16-bit elements per cell row
     constexpr int NS = 2 * R + 2, NE = R + 3, NP = 2 * R + 1;
     constexpr int XSLOT = kBandLpCells * XS;  // elements per ring slot and term
-    constexpr int FR = NP * MT * 64;          // uint4 per fragment buffer (NP pair slots)
-    constexpr int CPT = (FR + T - 1) / T;     // fragment uint4 staged per thread
+    constexpr int FR = NP * MT * 64;          // uint4 of A operands (NP pair slots)
+    constexpr int FRX = FR + A / 2;           // and the (cx, cy) table: uint4 per buffer
+    constexpr int FSL = (2 * kBandLpMaxReach + 1) * MT * 64;   // uint4 of a level's slots
+    constexpr int CPT = (FRX + T - 1) / T;    // uint4 staged per thread
     extern __shared__ __attribute__((aligned(16))) char lds_raw[];
     uint16_t* xr = reinterpret_cast<uint16_t*>(lds_raw);
     uint4* fr = reinterpret_cast<uint4*>(lds_raw + (size_t)NS * TERMS * XSLOT * 2);
-    float* edge = reinterpret_cast<float*>(lds_raw + (size_t)NS * TERMS * XSLOT * 2 + (size_t)2 * FR * 16);
+    float* edge = reinterpret_cast<float*>(lds_raw + (size_t)NS * TERMS * XSLOT * 2 + (size_t)2 * FRX * 16);
     int pi, local;
     if (!locate(B, KT_SC, xcd_remap(blockIdx.x, gridDim.x), pi, local)) return;
     const StepArgs a = args_of(B, pi);   // by value: no reloads after stores
@@ -2469,24 +2471,27 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         }
         if (hlo || hhi) es[hslot] = f.h + hdl;   // the block's halo
     };
-    // a level's A operands into fragment buffer l & 1 (thread t moves uint4 t and t + T).
-    // Every level holds 2 kBandLpMaxReach + 1 pair slots, the coupled pairs first; the
-    // kernel runs the first NP, those past a problem's pairs hold zero operands
+    // block l of the operand table into buffer l & 1 (thread t moves uint4 t and t + T):
+    // level l's A operands (2 kBandLpMaxReach + 1 pair slots, the coupled pairs first; the
+    // kernel runs the first NP, those past a problem's pairs hold zero operands), then the
+    // (cx, cy) of level l - 1's ordinates, read by the update that runs one level behind.
+    // Block n_lev holds the last level's (cx, cy).
     static_assert(CPT <= 2, "at most two staged uint4 per thread");
+    auto src_of = [&](int x) { return x < FR ? x : FSL + (x - FR); };
     auto fetch_frag = [&](int l, uint4& f0, uint4& f1) {
-        const ASN_G uint4* src = frag + (size_t)ldesc[2 * l].y * 64;
-        f0 = src[FR >= T ? tid : min(tid, FR - 1)];
-        if constexpr (CPT > 1) f1 = src[min(tid + T, FR - 1)];
+        const ASN_G uint4* src = frag + ldesc[2 * l].y;
+        f0 = src[src_of(FRX >= T ? tid : min(tid, FRX - 1))];
+        if constexpr (CPT > 1) f1 = src[src_of(min(tid + T, FRX - 1))];
     };
     auto put_frag = [&](int l, const uint4& f0, const uint4& f1) {
-        uint4* dst = fr + (size_t)(l & 1) * FR;
-        if (FR >= T || tid < FR) dst[tid] = f0;
-        if constexpr (CPT > 1) if (tid + T < FR) dst[tid + T] = f1;
+        uint4* dst = fr + (size_t)(l & 1) * FRX;
+        if (FRX >= T || tid < FRX) dst[tid] = f0;
+        if constexpr (CPT > 1) if (tid + T < FRX) dst[tid + T] = f1;
     };
     // the next update's inputs: the lane's own four values (from the register queue), the
     // y-upwind values and the level's coefficients
     struct Ahead {
-        float v[4], y[4], cx[4], cy[4];
+        float v[4], y[4];
         float rq;
         double w;
     };
@@ -2496,8 +2501,6 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             ah.y[o] = load_plane(r, yoff + (uint32_t)o * pb);
-            ah.cx[o] = qtab[q0 + a0 + o].cx;
-            ah.cy[o] = qtab[q0 + a0 + o].cy;
         }
         ah.rq = rdk[q0];
         ah.w = qk[q0].w;
@@ -2535,7 +2538,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     Fill pre;
     fetch(min(R + 1, L - 1), pre);
     uint4 fp0, fp1;
-    fetch_frag(min(1, L - 1), fp0, fp1);
+    fetch_frag(1, fp0, fp1);
     Ahead ah;
     lds_barrier();
 
@@ -2556,7 +2559,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     auto pass_of = [&](int i) {
         Pass ps;
         ps.kcodes = ldesc[2 * i].z;
-        ps.fl = fr + (size_t)(i & 1) * FR + lane;
+        ps.fl = fr + (size_t)(i & 1) * FRX + lane;
         // ring slot of level i - RE (k = 0); a pair's partner i - RE + k sits k slots on
         ps.sb = ((i - RE) % NS + NS) % NS;
         return ps;
@@ -2597,11 +2600,13 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     struct Upd {
         __amdgpu_buffer_rsrc_t ro;
         const float* es;   // the level's edge slot at the lane's tile and azimuths
+        const float2* cxy;   // the level's (cx, cy) at the lane's azimuths
         float colsum, yas;
         double ph;
     };
     auto upd_begin = [&](int j, Upd& u) {
         u.es = edge + (size_t)(j % NE) * 2 * NT * A + nt * A + a0;
+        u.cxy = reinterpret_cast<const float2*>(fr + (size_t)((j + 1) & 1) * FRX + FR) + a0;
         u.ro = level_rsrc(a.psi_new + (size_t)j * lvl_floats);
         u.colsum = 0.f;
         u.yas = 0.f;
@@ -2622,7 +2627,8 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         const float col = cf.z * ((ihv + ya) - vh) + cf.y * (ihv - vh);
         // a padding cell (not in) has psi^ = delta = iso^ = 0, zero coefficients, zero
         // operands and ghosts: its update is 0 without a select
-        const float nv = v - ah.cx[o] * (v - ux) - ah.cy[o] * (v - uy) - cf.x * v + col + cf.w;
+        const float2 c = u.cxy[o];
+        const float nv = v - c.x * (v - ux) - c.y * (v - uy) - cf.x * v + col + cf.w;
         // a wave writes half of each 128-byte line, a sibling wave the other half: the L2
         // joins them (non-temporal stores wrote 1.4x the bytes)
         store_plane(nv, u.ro, off0 + (uint32_t)o * pb);
@@ -2639,13 +2645,14 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         defect += ah.w * (double)u.colsum;
     };
     // the outflow of the level just updated (the look-ahead values still hold it)
-    auto outflow_of = [&]() {
+    auto outflow_of = [&](const Upd& u) {
         if (wedge) {
             float ob = 0.f;
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
                 const float v = ah.v[o] + dv;
-                ob += (ox[o] ? ah.cx[o] * v : 0.f) + (oy[o] ? ah.cy[o] * v : 0.f);
+                const float2 c = u.cxy[o];
+                ob += (ox[o] ? c.x * v : 0.f) + (oy[o] ? c.y * v : 0.f);
             }
             outflow += ah.w * (double)ob;
         }
@@ -2670,8 +2677,8 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
 
     f32x4 accp = {0.f, 0.f, 0.f, 0.f};
     {   // pass 0: products only
-        if (1 < L) put_frag(1, fp0, fp1);
-        fetch_frag(min(2, L - 1), fp0, fp1);
+        put_frag(1, fp0, fp1);
+        fetch_frag(min(2, L), fp0, fp1);
         const Pass ps = pass_of(0);
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -2682,9 +2689,9 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         advance(0);
     }
     for (int i = 1; i < L; ++i) {
-        // level i + 1's A operands (its buffer's last readers passed the barrier)
-        if (i + 1 < L) put_frag(i + 1, fp0, fp1);
-        fetch_frag(min(i + 2, L - 1), fp0, fp1);
+        // block i + 1 of the operand table (its buffer's last readers passed the barrier)
+        put_frag(i + 1, fp0, fp1);
+        fetch_frag(min(i + 2, L), fp0, fp1);
         // pass i in chunks the scheduler may not merge: chunk p reads pair p's operands,
         // updates output p of level i - 1 while they arrive, then multiplies pair p (the
         // MFMAs run on while the next chunk issues)
@@ -2711,7 +2718,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         __builtin_amdgcn_sched_barrier(0);
         upd_end(u);
         accp = acc;
-        outflow_of();
+        outflow_of(u);
         advance(i);
     }
     {
@@ -2720,7 +2727,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
 #pragma unroll
         for (int o = 0; o < 4; ++o) upd_out(o, accp, u);
         upd_end(u);
-        outflow_of();
+        outflow_of(u);
     }
 
     // per cell Phi^ and sum_q w_q Y^: the (n_az / 4) lane groups' partials in a fixed order

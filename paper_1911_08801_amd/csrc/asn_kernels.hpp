@@ -128,7 +128,7 @@ __host__ __device__ constexpr int band_lp_row(int az) { return 32 * band_lp_kste
 inline size_t band_lp_lds_bytes(int az, int reach, int dtype) {
     const int terms = dtype == 1 ? 2 : 1, mt = az / 16, nt = kBandLpCells / 16;
     return (size_t)(2 * reach + 2) * terms * kBandLpCells * band_lp_row(az) * 2 +
-           (size_t)2 * (2 * reach + 1) * mt * 1024 + (size_t)(reach + 3) * 2 * nt * az * 4;
+           (size_t)2 * ((2 * reach + 1) * mt * 1024 + az * 8) + (size_t)(reach + 3) * 2 * nt * az * 4;
 }
 // Largest dynamic LDS a block may take.
 constexpr size_t kMaxBlockLds = 160 * 1024 - 1024;

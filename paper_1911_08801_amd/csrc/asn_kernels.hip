@@ -1981,6 +1981,8 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     const int c0 = local * kBandCells, cell = c0 + c;
     const bool in = cell < C;
     float* stage = ring + NS * SLOT;   // two buffers of CM coefficients
+    // then two (cx, cy) tables of the level's ordinates (8-byte aligned)
+    float2* cxys = reinterpret_cast<float2*>(stage + 2 * ((CM + 1) & ~1));
     const ASN_G QInfo* __restrict__ qtab = gp(a.qi);
     const ASN_K QInfo* qk = kp(a.qi);
     const ASN_K uint4* ldesc = kp(a.band);
@@ -2087,20 +2089,28 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         }
     };
     // a level's coefficients: thread t holds number t (the count is below the block
-    // size: at most 2 reach + 1 runs of at most n_az)
+    // size: at most 2 reach + 1 runs of at most n_az), and threads 0 .. 2 n_az - 1 the
+    // level's cx, cy (thread 2 m + k: component k of azimuth m)
+    struct Coef {
+        float k, c;
+    };
     auto fetch_coef = [&](int l) {
         const int2 rg = lrange[l];
-        return bcoef[rg.x + min(tid, rg.y - 1)];
+        Coef v;
+        v.k = bcoef[rg.x + min(tid, rg.y - 1)];
+        v.c = reinterpret_cast<const ASN_G float*>(qtab + l * A + min(tid >> 1, A - 1))[tid & 1];
+        return v;
     };
-    auto put_coef = [&](int l, float v) {
-        if (tid < CM) stage[(l & 1) * CM + tid] = v;
+    auto put_coef = [&](int l, const Coef& v) {
+        if (tid < CM) stage[(l & 1) * CM + tid] = v.k;
+        if (tid < 2 * A) reinterpret_cast<float*>(cxys + (l & 1) * A)[tid] = v.c;
     };
     // per level, loaded one level ahead (after the level's stores, so that the wait
     // for them in the next epilogue does not also wait for the prefetches, which are
     // issued later): the y-upwind values and the ordinates' constants (the weight w_q
     // of a product set depends on the level only: a scalar load)
     struct Ahead {
-        float y[O], cx[O], cy[O];
+        float y[O];
         double w;
     };
     // base: the level's planes; q0: its first ordinate
@@ -2115,11 +2125,6 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 #pragma unroll
         for (int o = 0; o < O; ++o)
             ah.y[o] = YNT ? load_plane_nt(r, yoff[o]) : load_plane(r, yoff[o]);
-#pragma unroll
-        for (int o = 0; o < O; ++o) {
-            ah.cx[o] = qtab[q0 + a0 + o].cx;
-            ah.cy[o] = qtab[q0 + a0 + o].cy;
-        }
         ah.w = qk[q0].w;
     };
 
@@ -2134,7 +2139,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
     // The values loaded a level ahead alternate between two register sets (the loop
     // body is written twice), and every load is unconditional (the last level again
     // near the end), so no loop-carried copy of a load in flight forces a wait.
-    float cpre = fetch_coef(min(1, L - 1));
+    Coef cpre = fetch_coef(min(1, L - 1));
     Fill pre;
     // level cursors (uniform), advanced once per level and held at the last level:
     // pf the planes of the level fetched next, pa / qa those and the first ordinate of
@@ -2223,6 +2228,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
         // value in FP64; the collision term's sum over the outputs, gs sum (Y - psi) +
         // bs sum (iso - psi), is formed in FP32 (small terms) and added once per level.
         const float* own = ring + si * SLOT + (a0 + kBandLead) * kBandStride + c + 1;
+        const float2* cxy = cxys + (i & 1) * A + a0;   // the outputs' (cx, cy)
         const __amdgpu_buffer_rsrc_t ro = level_rsrc(po);
         po += lvl_floats;
         // The cells and both x neighbours of every output read first (one LDS round
@@ -2253,8 +2259,9 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
             float t = fmaf(cf.y, isov - v, cf.w);
             t = fmaf(cf.z, dy, t);
             t = fmaf(-cf.x, v, t);
-            t = fmaf(ah.cy[o], uy - v, t);
-            t = fmaf(ah.cx[o], ux - v, t);
+            const float2 cc = cxy[o];
+            t = fmaf(cc.y, uy - v, t);
+            t = fmaf(cc.x, ux - v, t);
             // a padding cell (not in) has psi = 0, zero coefficients and zero upwind
             // values, so it stays zero
             const float nv = v + t;
@@ -2267,7 +2274,7 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
             float ob = 0.f;
 #pragma unroll
             for (int o = 0; o < O; ++o)
-                ob += (ox[o] ? ah.cx[o] * vv[o] : 0.f) + (oy[o] ? ah.cy[o] * vv[o] : 0.f);
+                ob += (ox[o] ? cxy[o].x * vv[o] : 0.f) + (oy[o] ? cxy[o].y * vv[o] : 0.f);
             outflow += ah.w * (double)ob;
         }
         fetch_ahead(pa, qa, ah_next);

@@ -100,10 +100,10 @@ inline uint32_t band_device_code(uint32_t code, int level, int reach, int az) {
     return slot | ((code >> 11) & 127u) << 17 | w << 24;
 }
 // Dynamic LDS of a banded block: the ring, then two level-coefficient buffers of cmax
-// floats (cmax a multiple of 4).
+// floats (cmax a multiple of 4) and two tables of the level's (cx, cy).
 inline size_t band_lds_bytes(int az, int reach, int cmax) {
     return (size_t)(2 * reach + 2) * (kBandLead + az + kBandTrail) * kBandStride * 4 +
-           2 * (size_t)cmax * 4;
+           2 * (size_t)((cmax + 1) & ~1) * 4 + 2 * (size_t)az * 8;
 }
 
 // Banded reduced-precision step (BF16 / FP16 operands on MFMA 16x16x32, FP32 accumulate)

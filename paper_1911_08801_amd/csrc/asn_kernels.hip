@@ -2347,9 +2347,10 @@ template <int A, int DT, int R>
 __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs B) {
     constexpr int MT = A / 16, NT = kBandLpCells / 16, KS = band_lp_ksteps(A), TERMS = DT == 1 ? 2 : 1;
     constexpr int NW = MT * NT, T = NW * 64;
-    constexpr int XS = band_lp_row(A);        // 16-bit elements per cell row
+    constexpr int KC = 4 * KS;                // 16-byte chunks of 8 azimuths a cell holds
     constexpr int NS = 2 * R + 2, NE = R + 3, NP = 2 * R + 1;
-    constexpr int XSLOT = kBandLpCells * XS;  // elements per ring slot and term
+    constexpr int XSLOT = band_lp_slot(A);    // elements per ring slot and term:
+                                              // [chunk][cell][8 azimuths]
     constexpr int FR = NP * MT * 64;          // uint4 of A operands (NP pair slots)
     constexpr int FRX = FR + A / 2;           // and the (cx, cy) table: uint4 per buffer
     constexpr int FSL = (2 * kBandLpMaxReach + 1) * MT * 64;   // uint4 of a level's slots
@@ -2451,7 +2452,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     // the lane's four azimuths of level l into the ring (rounded operand terms) and the
     // tile-edge values (true state psi^ + delta) its neighbours need
     auto put = [&](int l, const Fill& f) {
-        uint16_t* xs = xr + (size_t)(l % NS) * TERMS * XSLOT + cc * XS + a0;
+        uint16_t* xs = xr + (size_t)(l % NS) * TERMS * XSLOT + ((a0 >> 3) * kBandLpCells + cc) * 8 + (a0 & 7);
         float xv[4];
 #pragma unroll
         for (int o = 0; o < 4; ++o) xv[o] = __builtin_fmaf(f.v[o], s_in, -ivs);
@@ -2552,7 +2553,11 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
     double phacc = 0.0, ypacc = 0.0, defect = 0.0, outflow = 0.0;
     float mx = 0.f;
     const int mtk0 = ((0 - mt) % MT + MT) % MT;   // fragment of k-step 0: offset (32 kt - 16 mt) mod A
-    const uint16_t* xl = xr + cc * XS + 8 * g;
+    // B operand of k-step kt: chunk g + 4 kt of the lane's cell (16 lanes of a row read
+    // 256 contiguous bytes)
+    const uint16_t* xl = xr + (g * kBandLpCells + cc) * 8;
+    static_assert(KC * kBandLpCells * 8 == XSLOT, "ring slot layout");
+    static_assert(A * 256 <= NS * TERMS * XSLOT * 2, "the final partials fit in the ring");
     // level i's products: every pair slot, k-steps of 32 azimuths, operand terms
     struct Ops {
         uint4 a[KS], b[KS];
@@ -2580,12 +2585,13 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
 #pragma unroll
         for (int kt = 0; kt < KS; ++kt) op.a[kt] = ps.fl[(p * MT + (mtk0 + 2 * kt) % MT) * 64];
 #pragma unroll
-        for (int kt = 0; kt < KS; ++kt) op.b[kt] = *reinterpret_cast<const uint4*>(op.xs + 32 * kt);
+        for (int kt = 0; kt < KS; ++kt)
+            op.b[kt] = *reinterpret_cast<const uint4*>(op.xs + 4 * kBandLpCells * 8 * kt);
     };
     auto load_term = [&](int t, Ops& op) {
 #pragma unroll
         for (int kt = 0; kt < KS; ++kt)
-            op.b[kt] = *reinterpret_cast<const uint4*>(op.xs + t * XSLOT + 32 * kt);
+            op.b[kt] = *reinterpret_cast<const uint4*>(op.xs + t * XSLOT + 4 * kBandLpCells * 8 * kt);
     };
     auto mul_term = [&](const Ops& op, f32x4& acc) {
 #pragma unroll

@@ -118,16 +118,18 @@ inline bool band_lp_azimuths_supported(int az) { return az == 32 || az == 48 || 
 // k-steps of 32 azimuths a level pair takes (48 azimuths: two, the second half-padded)
 __host__ __device__ constexpr int band_lp_ksteps(int az) { return (az + 31) / 32; }
 __host__ __device__ constexpr int band_lp_threads(int az) { return (az / 16) * (kBandLpCells / 16) * 64; }
-// 16-bit elements per cell row of the quantised-level ring: every k-step's azimuths (the
-// padding past n_az held at zero) and 8 more (16-byte reads conflict-free)
-__host__ __device__ constexpr int band_lp_row(int az) { return 32 * band_lp_ksteps(az) + 8; }
+// 16-bit elements of a slot of the quantised-level ring (one level, one operand term): the
+// 8-azimuth chunks of every k-step (the padding past n_az held at zero), each chunk the
+// block's cells in a row ([chunk][cell][8]: 16 lanes reading one chunk of 16 cells read
+// 256 contiguous bytes)
+__host__ __device__ constexpr int band_lp_slot(int az) { return 4 * band_lp_ksteps(az) * kBandLpCells * 8; }
 // Dynamic LDS of a banded reduced-precision block: the ring of 2 reach + 2 quantised
 // levels (two operand terms for BF16), two buffers of a level's A operands (at most
-// 2 reach + 1 pairs, n_az / 16 fragments of 1 KiB each), the ring of tile-edge values
-// (reach + 2 levels).
+// 2 reach + 1 pairs, n_az / 16 fragments of 1 KiB each, and the previous level's
+// (cx, cy)), the ring of tile-edge values (reach + 3 levels).
 inline size_t band_lp_lds_bytes(int az, int reach, int dtype) {
     const int terms = dtype == 1 ? 2 : 1, mt = az / 16, nt = kBandLpCells / 16;
-    return (size_t)(2 * reach + 2) * terms * kBandLpCells * band_lp_row(az) * 2 +
+    return (size_t)(2 * reach + 2) * terms * band_lp_slot(az) * 2 +
            (size_t)2 * ((2 * reach + 1) * mt * 1024 + az * 8) + (size_t)(reach + 3) * 2 * nt * az * 4;
 }
 // Largest dynamic LDS a block may take.

@@ -1,5 +1,5 @@
 """GPU parity of the banded reduced-precision step (BF16 / FP16 operands on MFMA, FP32
-accumulate, product sets of 32 or 64 azimuths): each level pair's circulant block of
+accumulate, product sets of 32, 48 or 64 azimuths): each level pair's circulant block of
 the stored K multiplies the rounded partner level, the update follows the fused
 reduced-precision form (pending per-cell particle correction).  Checked against the
 oracle's emulation of the rounding recipe element by element on ragged grids (one

@@ -2327,11 +2327,12 @@ __global__ __launch_bounds__(8 * A) void banded_euler_kernel(BatchArgs B) {
 //    and k-step of 32 azimuths one MFMA per operand term: A is the block's 16 x 32 slice
 //    at the wave's azimuth offset (host-built, staged in LDS a level ahead), B eight
 //    consecutive azimuths of one cell of the partner level from a ring of quantised
-//    levels ([cell][azimuth], 16-byte reads).  The ring is filled from registers loaded
-//    two levels ahead; the unrounded values of the lane's own cell wait in registers
-//    (reach + 1 levels) for the level's update; x neighbours come from the adjacent lanes
-//    (DPP) or, at the edges of a 16-cell tile, from a small ring the neighbouring waves
-//    (or the block's halo loads) fill at the same time.  Outputs as the fused form:
+//    levels ([8-azimuth chunk][cell], 16-byte reads).  The ring is filled from registers
+//    loaded a level before; the unrounded values of the lane's own cell wait in registers
+//    (reach + 1 levels) for the level's update, which runs one level behind the products
+//    and is interleaved with them; x neighbours come from the adjacent lanes (DPP) or, at
+//    the edges of a 16-cell tile, from a small ring the neighbouring waves (or the block's
+//    halo loads) fill at the same time.  Outputs as the fused form:
 //    psi^{n+1} without its correction, per cell Phi^ and sum_q w_q Y^, budget partials,
 //    block maxima of the next operand scale.
 // ---------------------------------------------------------------------------

@@ -2498,7 +2498,7 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
         if constexpr (CPT > 1) if (tid + T < FRX) dst[tid + T] = f1;
     };
     // the next update's inputs: the lane's own four values (from the register queue), the
-    // y-upwind values and the level's coefficients
+    // y-upwind values and the level's r_q and weight (its (cx, cy) come from LDS)
     struct Ahead {
         float v[4], y[4];
         float rq;

@@ -302,7 +302,8 @@ asn_status asn_info(asn_problem p, double* dt, int64_t* steps_done, int64_t* ste
 /* Arithmetic of one contraction Y = K Psi: dense_flops = 2 Q^2 C; tile_flops =
  * 2 C times the number of K entries in the blocks the kernel multiplies (banded
  * step: the runs it multiplies, see asn_contraction_nonzero; in BF16 / FP16 every
- * coupled pair's whole n_azim x n_azim block).  K is
+ * coupled pair's whole n_azim x n_azim block, not counting the zero operands that fill a
+ * level's pair slots up to 2 reach + 1).  K is
  * forward peaked (paper Section 3.5: the discrete artificial in-scattering is a
  * sparse matrix), so blocks whose entries are all zero in the stored operand type
  * are skipped: 128-row x 32-column tiles for BF16/FP16, and for FP32 the 16-row x

@@ -735,9 +735,11 @@ def _weighted_ordinate_sum(w: np.ndarray, x: np.ndarray) -> np.ndarray:
 def lowprec_in_scattering(psi32: np.ndarray, st: Setup, dtype: str,
                           kq: Optional[np.ndarray] = None,
                           r: Optional[np.ndarray] = None,
-                          block: int = SCALE_BLOCK) -> np.ndarray:
+                          block: int = SCALE_BLOCK,
+                          e: Optional[np.ndarray] = None) -> np.ndarray:
     """Y by the reduced-precision recipe above, for a float32 state [Q, ny, nx], with
-    scale blocks of `block` cells."""
+    scale blocks of `block` cells (or the per-cell block exponents `e`, given when the
+    state passed is part of the grid)."""
     if kq is None:
         kq, r = lowprec_kernel(st.K, dtype)
     Q = psi32.shape[0]
@@ -745,7 +747,8 @@ def lowprec_in_scattering(psi32: np.ndarray, st: Setup, dtype: str,
     phi = _weighted_ordinate_sum(st.w, p.astype(np.float64))
     iso = (phi / st.W).astype(np.float32)
     dev = (p - iso[None, :]).astype(np.float32)
-    e = block_exponents(p, block)
+    if e is None:
+        e = block_exponents(p, block)
     s_in = np.ldexp(np.float32(1.0), (SCALE_EXP - e)).astype(np.float32)
     x = operand_terms((dev * s_in[None, :]).astype(np.float32), dtype)
     acc = kq @ x
@@ -761,3 +764,47 @@ def lowprec_step(psi32: np.ndarray, st: Setup, dtype: str, kq=None, r=None,
     """One step with the reduced-precision Y; the rest of the step stays FP64."""
     Y = lowprec_in_scattering(psi32, st, dtype, kq, r, block)
     return step(np.asarray(psi32, dtype=np.float64), st, Y=Y)
+
+
+def lowprec_step_entries(psi32: np.ndarray, st: Setup, dtype: str, qs: np.ndarray,
+                         js: np.ndarray, iis: np.ndarray, kq=None, r=None,
+                         block: int = SCALE_BLOCK) -> np.ndarray:
+    """psi^{n+1} of lowprec_step at the listed (q, j, i) only, for grids where a full
+    emulated step is too slow.
+
+    The recipe is per cell apart from the block exponent: each distinct cell's column
+    of Y is formed from its own ordinates with the exponent of its whole scale block,
+    and the step is taken on the 3 x 3 window around the cell (zero outside the grid),
+    whose centre needs the old values of its four neighbours and its own Y only.
+    """
+    if kq is None:
+        kq, r = lowprec_kernel(st.K, dtype)
+    Q, ny, nx = psi32.shape
+    flat = np.asarray(psi32, dtype=np.float32).reshape(Q, -1)
+    C = ny * nx
+
+    def window(a, j, i):
+        """a[..., j - 1 .. j + 1, i - 1 .. i + 1] in FP64, zero outside the grid."""
+        out = np.zeros(a.shape[:-2] + (3, 3))
+        j0, j1, i0, i1 = max(j - 1, 0), min(j + 2, ny), max(i - 1, 0), min(i + 2, nx)
+        out[..., j0 - (j - 1):j1 - (j - 1), i0 - (i - 1):i1 - (i - 1)] = a[..., j0:j1, i0:i1]
+        return out
+
+    cache: Dict[Tuple[int, int], np.ndarray] = {}
+    out = np.empty(len(qs))
+    for n, (q, j, i) in enumerate(zip(qs, js, iis)):
+        key = (int(j), int(i))
+        if key not in cache:
+            j, i = key
+            b0 = ((j * nx + i) // block) * block
+            eb = block_exponents(flat[:, b0:min(b0 + block, C)], block)[:1]
+            Yc = lowprec_in_scattering(psi32[:, j:j + 1, i:i + 1], st, dtype, kq, r, block, e=eb)
+            sub = dataclasses.replace(st, **{k: window(getattr(st, k), j, i)
+                                             for k in ("sigma_s", "sigma_a", "sigma_as", "source")})
+            p = window(psi32, j, i)
+            Y = np.zeros_like(p)
+            Y[:, 1, 1] = Yc[:, 0, 0]
+            new, _ = step(p, sub, Y=Y, want_budget=False)
+            cache[key] = new[:, 1, 1]
+        out[n] = cache[key][q]
+    return out

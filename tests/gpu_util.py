@@ -60,9 +60,10 @@ def structured_state(spec, rng):
     return psi0
 
 
-def sampled_entries(rng, Q, ny, nx, n_samples):
+def sampled_entries(rng, Q, ny, nx, n_samples, n_centre=0):
     """(q, j, i) sample: uniform entries plus every corner / edge-midpoint class at
-    four ordinates (first, two interior, last)."""
+    four ordinates (first, two interior, last), and n_centre more entries within six
+    cells of the grid's centre (where a centred pulse is large)."""
     qs = rng.integers(0, Q, n_samples)
     js = rng.integers(0, ny, n_samples)
     iis = rng.integers(0, nx, n_samples)
@@ -72,6 +73,10 @@ def sampled_entries(rng, Q, ny, nx, n_samples):
     js[:k] = np.repeat(edge[:, 0], 4)
     iis[:k] = np.repeat(edge[:, 1], 4)
     qs[:k] = np.tile([0, Q // 4 + 1, Q // 2 + 3, Q - 1], len(edge))
+    if n_centre:
+        qs = np.concatenate([qs, rng.integers(0, Q, n_centre)])
+        js = np.concatenate([js, np.clip(ny // 2 + rng.integers(-6, 7, n_centre), 0, ny - 1)])
+        iis = np.concatenate([iis, np.clip(nx // 2 + rng.integers(-6, 7, n_centre), 0, nx - 1)])
     return qs, js, iis
 
 

@@ -5,7 +5,9 @@
   stored scalar flux (tests/golden/make_line_source_400.py) and against the
   continuous transport reference (the error falls as sigma_as rises);
 * line source 1024^2, 32 x 64 = 2048 ordinates, sigma_as 5: ten steps, sampled
-  entries against the oracle's windowed evaluator;
+  entries against the oracle's windowed evaluator; one BF16 / FP16 banded step (the
+  kernels the bench times there), sampled entries against the oracle's entry-wise
+  emulation of the rounding recipe;
 * lattice 700^2, 24 x 48 = 1152 ordinates, sigma_as 5, 475 steps to t = 3.2 (paper
   Section 4.2 materials): the BF16 and FP16 contractions against the FP32 run.
 """
@@ -82,12 +84,35 @@ def test_line_source_1024_q2048_ten_steps_sampled(form):
     finally:
         p.close()
     st = o.setup(spec)
-    qs, js, iis = sampled_entries(rng, spec.q, 1024, 1024, 48)
+    qs, js, iis = sampled_entries(rng, spec.q, 1024, 1024, 48, n_centre=8)
     ref = o.run_entries(psi0, st, 10, qs, js, iis)
     scale = np.maximum(np.abs(ref), 1e-3 * np.abs(psi0).max())
     err = np.abs(got[qs, js, iis].astype(np.float64) - ref) / scale
     print(f"1024^2 x 2048, 10 steps, {form}: max scaled error {err.max():.2e}", flush=True)
     assert err.max() <= 4e-5
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_line_source_1024_q2048_reduced_precision_step_sampled(dtype):
+    spec = wl.line_source(1024, n_polar=32, sigma_as=5.0)
+    rng = np.random.default_rng(4096)
+    psi0 = structured_state(spec, rng)
+    p = asn.from_spec(spec, set_initial_state=False, form="banded", dtype=dtype)
+    try:
+        assert asn.asn_step_form(p) == "banded"
+        asn.asn_set_state(p, psi0)
+        asn.asn_step(p, 1)
+        got = asn.asn_get_state(p)
+    finally:
+        p.close()
+    st = o.setup(spec)
+    qs, js, iis = sampled_entries(rng, spec.q, 1024, 1024, 48, n_centre=24)
+    ref = o.lowprec_step_entries(psi0, st, dtype, qs, js, iis)
+    err = np.abs(got[qs, js, iis].astype(np.float64) - ref)
+    print(f"1024^2 x 2048, one {dtype} banded step: max error {err.max():.2e}, sampled "
+          f"|psi| up to {np.abs(ref).max():.3e} (max|psi0| {np.abs(psi0).max():.3e})", flush=True)
+    assert np.abs(ref).max() >= 0.1 * np.abs(psi0).max()   # the pulse is sampled
+    assert err.max() <= 2e-6 * np.abs(psi0).max()
 
 
 def test_lattice_700_q1152_reduced_precision_full_runs():

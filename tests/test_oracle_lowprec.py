@@ -177,3 +177,22 @@ def test_bf16_recipe_meets_bound_on_lattice_where_single_term_would_not():
     phi_ex = o.scalar_flux(ex, st.w)
     err = np.linalg.norm(o.scalar_flux(lp.astype(np.float64), st.w) - phi_ex) / np.linalg.norm(phi_ex)
     assert err < 2e-3
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_entrywise_step_equals_full_emulated_step(dtype):
+    # the sampled evaluator used at full size: the same recipe per cell, the exponent of
+    # each cell's whole scale block (blocks of 64 on a ragged 23 x 11 grid: 4 blocks, the
+    # last partial), the step on the cell's window; entries on the edges and corners too
+    prob = wl.random_problem(11, 23, 11, n_polar=4, n_azim=8, beta=4.5)
+    st = o.setup(prob)
+    psi = wl.random_state(12, st.q, 11, 23)
+    psi[:, :3] *= np.float32(2.0 ** -20)        # blocks of very different scale
+    full, _ = o.lowprec_step(psi, st, dtype, block=64)
+    rng = np.random.default_rng(13)
+    qs = rng.integers(0, st.q, 60)
+    js = np.concatenate([[0, 10, 0, 10], rng.integers(0, 11, 56)])
+    iis = np.concatenate([[0, 0, 22, 22], rng.integers(0, 23, 56)])
+    got = o.lowprec_step_entries(psi, st, dtype, qs, js, iis, block=64)
+    ref = full[qs, js, iis]
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(full).max()

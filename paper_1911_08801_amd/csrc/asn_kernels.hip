@@ -2722,7 +2722,6 @@ __global__ __launch_bounds__(band_lp_threads(A)) void banded_lp_kernel(BatchArgs
             mul_term(op, acc);
 #pragma unroll
             for (int t = 1; t < TERMS; ++t) {
-                __builtin_amdgcn_sched_barrier(0);
                 load_term(t, op);
                 mul_term(op, acc);
             }
